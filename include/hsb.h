@@ -1,0 +1,186 @@
+/*
+ * hsb.h -- C ABI of libhsb: heated simulated bifurcation on one AMD MI355X (gfx950).
+ *
+ * The library integrates many independent replicas of heated ballistic SB
+ * (HbSB) and heated discrete SB (HdSB) on a dense all-to-all Ising problem
+ * (T. Kanao and H. Goto, "Simulated bifurcation assisted by thermal
+ * fluctuation", arXiv:2203.08361):
+ *
+ *   problem   find s in {-1,+1}^N minimising E = -1/2 sum_ij J_ij s_i s_j     eq. (1)
+ *             with J symmetric and J_ii = 0
+ *   field     f = J x (bSB, eq. (4))  or  f = J sgn(x) (dSB, eq. (5))
+ *   step      y~ = y + {-[a0 - a(t_k)] x + c0 f} dt                          eq. (16)
+ *             x~ = x + a0 y~ dt                                             eq. (17)
+ *             x' = g(x~), y~~ = h(x~, y~)  (perfectly inelastic walls)        eqs. (18)-(21)
+ *             y' = y~~ + gamma y dt        (heating with the OLD y)          eq. (22)
+ *   pump      a(t_k) = a0 k / Ns, linear from 0 to a0 over the run (Results, after eq. (11))
+ *   readout   s = sgn(x) with sgn(0) = +1 (Results, after eq. (5)); the energy
+ *             is sampled every `energy_interval` steps and at the last step, and
+ *             the best sample is returned (Results, K2000 protocol)
+ *   init      x_i, y_i uniform in the open interval (-amp, amp) (Results, after
+ *             eq. (12) with amp = 1; the library default is amp = 0.1), drawn
+ *             from a counter-based generator: SplitMix64's output mixer
+ *             (Steele, Lea, Flood 2014) chained over (seed, stream, replica, spin)
+ *
+ * gamma = 0 gives the unheated bSB / dSB of the same equations.
+ *
+ * Conventions common to every entry point
+ *   - Every function returns an hsb_status; on failure hsb_last_error() holds
+ *     a message for the calling thread.  HSB_EINVAL is returned before any
+ *     device work is queued and nothing is written to any output.
+ *   - Matrices are row-major.  Spin/state arrays are replica-major:
+ *     element (r, i) of an [R][N] array is at offset r*N + i.
+ *   - Determinism: the same (J, arguments, seed, options) give bitwise the same
+ *     outputs.  Replica r depends only on (seed, r): its result is the same for
+ *     any R, apart from the effect of the precision plan on bSB (below).
+ *   - Precision: the state x, y is single precision (Methods, last sentence).
+ *     For dSB with integer-valued J the field is an exact integer, so the
+ *     trajectory is bitwise the same whichever plan runs it.  For bSB the
+ *     field is rounded differently by each plan (FP32 products or split
+ *     BF16 products); see hsb_set_option(HSB_OPT_PRECISION).
+ *   - Thread safety: one context may be used by one thread at a time.
+ */
+#ifndef HSB_H
+#define HSB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hsb_ctx hsb_ctx; /* opaque; owns the device copies of J */
+
+typedef enum {
+    HSB_BSB = 0, /* ballistic SB, field eq. (4) */
+    HSB_DSB = 1  /* discrete SB, field eq. (5) */
+} hsb_variant;
+
+typedef enum {
+    HSB_OK = 0,
+    HSB_EINVAL = -1,      /* invalid argument; nothing was written */
+    HSB_ENOMEM = -2,      /* device allocation failed */
+    HSB_EDEVICE = -3,     /* HIP runtime error or no usable gfx950 device */
+    HSB_ENUMERIC = -4,    /* a replica's state became non-finite; its energy is NaN,
+                             all other outputs are valid */
+    HSB_EUNSUPPORTED = -6 /* a requested precision plan cannot run this problem */
+} hsb_status;
+
+typedef enum {
+    HSB_OPT_INIT_AMP = 0,        /* amplitude of the uniform initial x, y; default 0.1, > 0 */
+    HSB_OPT_ENERGY_INTERVAL = 1, /* energy sampled every this many steps (and at the end);
+                                    default 100, >= 1 */
+    HSB_OPT_RETURN_BEST = 2,     /* 1 (default): return the best sampled spins and energy;
+                                    0: return the final state's */
+    HSB_OPT_PRECISION = 3,       /* hsb_precision; default HSB_PREC_AUTO */
+    HSB_OPT_TIMING = 4,          /* 1: bracket every launch of the dominant kernel (the
+                                    field+update kernel of the plan) with HIP events on the
+                                    run's stream; default 0 */
+    HSB_OPT_KERNEL_MS = 5,       /* read only: summed event time (ms) of those launches in
+                                    the last run with timing on (synchronises the events) */
+    HSB_OPT_KERNEL_LAUNCHES = 6  /* read only: number of those launches in that run */
+} hsb_option;
+
+typedef enum {
+    HSB_PREC_AUTO = 0,  /* dSB on J exact in FP4 (entries in {0, +-0.5, +-1, +-1.5, +-2, +-3,
+                           +-4, +-6}) and N <= 2048: FP4 field; otherwise FP32 */
+    HSB_PREC_FP32 = 1,  /* plain FP32 field products (the baseline form) */
+    HSB_PREC_MIXED = 2  /* dSB: FP4 operands with FP32 accumulation (exact);
+                           bSB: split BF16 products x = x_hi + x_lo, J_hi + J_lo */
+} hsb_precision;
+
+/*
+ * hsb_create -- validate J and build its device copies (the J store).
+ *
+ *   J    host pointer, N*N floats, row-major; read only during the call
+ *        (the caller keeps ownership and may free it afterwards).
+ *   N    number of spins, >= 1.
+ *   out  receives the new context.
+ *
+ * J must be finite, symmetric (J[i*N+j] == J[j*N+i] exactly) and have a zero
+ * diagonal (eq. (1)); otherwise HSB_EINVAL.  Uses the current HIP device.
+ */
+int hsb_create(const float *J, int N, hsb_ctx **out);
+
+/* hsb_destroy -- free the context and all its device memory.  NULL is ignored. */
+void hsb_destroy(hsb_ctx *h);
+
+/* hsb_last_error -- message of the last failure on this thread ("" if none). */
+const char *hsb_last_error(void);
+
+/*
+ * hsb_set_option / hsb_get_option -- run options kept in the context
+ * (hsb_option keys).  Invalid key or value: HSB_EINVAL, option unchanged.
+ */
+int hsb_set_option(hsb_ctx *h, int key, double value);
+int hsb_get_option(hsb_ctx *h, int key, double *value);
+
+/*
+ * hsb_run -- integrate R replicas for `steps` steps; host outputs.
+ *
+ *   variant  HSB_BSB or HSB_DSB
+ *   a0, c0, dt, gamma  constants of eqs. (10)-(11), (16)-(22); finite, dt > 0,
+ *            gamma >= 0 (gamma = 0: unheated).  a(t) rises from 0 to a0 over
+ *            the `steps` steps.
+ *   steps    Ns >= 0 (0 returns the initial state's spins and energy)
+ *   R        number of replicas >= 1
+ *   seed     initial-state seed; replica r draws from (seed, r)
+ *   spins    host, [R][N] int8, receives +-1 (best sample or final, per
+ *            HSB_OPT_RETURN_BEST)
+ *   energy   host, [R] double, receives eq. (1) of `spins` (FP64)
+ *
+ * Returns HSB_ENUMERIC if any replica became non-finite (its energy is NaN).
+ */
+int hsb_run(hsb_ctx *h, int variant, float a0, float c0, float dt, float gamma, int steps, int R,
+            uint64_t seed, int8_t *spins, double *energy);
+
+/*
+ * hsb_run_args -- arguments of hsb_run_ex.  All pointers are DEVICE pointers
+ * (memory of the context's device), all optional ones may be NULL.  Zero-fill
+ * the struct, then set what is needed; `struct_size` must be
+ * sizeof(hsb_run_args).
+ */
+typedef struct {
+    size_t struct_size;
+    int32_t variant;        /* HSB_BSB / HSB_DSB */
+    int32_t steps;          /* steps to run in this call, >= 0 */
+    int32_t R;              /* replicas, >= 1 */
+    int32_t start_step;     /* first step index k0 of this call, >= 0 (resume) */
+    int32_t schedule_steps; /* Ns defining a(t_k) = a0 k / Ns; 0 means start_step + steps */
+    int32_t reserved0;
+    float a0, c0, dt, gamma;
+    uint64_t seed;
+    const float *gamma_rep; /* optional [R] per-replica gamma (overrides gamma) */
+    const float *x0, *y0;   /* optional [R][N] initial state (both or neither);
+                               default: seeded draw */
+    float *x_out, *y_out;   /* optional [R][N] final state */
+    int8_t *spins;          /* [R][N] best or final spins (required) */
+    double *energy;         /* [R] energy of `spins` (required) */
+    double *best_energy;    /* optional [R] best sampled energy */
+    double *final_energy;   /* optional [R] energy of the final state */
+    int32_t *best_step;     /* optional [R] step count of the best sample */
+    void *stream;           /* hipStream_t; NULL = the null stream */
+} hsb_run_args;
+
+/*
+ * hsb_run_ex -- hsb_run with device buffers, a caller stream, per-replica gamma,
+ * a caller initial state and resumable scheduling.  Work is queued on
+ * `stream`; the call returns after queuing except that it synchronises the
+ * stream to report HSB_ENUMERIC.  Sample points are step counts m with
+ * start_step < m <= start_step + steps and m % energy_interval == 0, plus the
+ * state after the last step of the call (and the initial state when steps = 0).
+ */
+int hsb_run_ex(hsb_ctx *h, const hsb_run_args *args);
+
+/*
+ * hsb_plan_info -- the precision plan AUTO (or the forced option) would use
+ * for `variant` on this J: HSB_PREC_FP32 or HSB_PREC_MIXED.
+ */
+int hsb_plan_info(hsb_ctx *h, int variant, int *precision);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSB_H */

@@ -42,6 +42,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("R", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("interval", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("return_best", ctypes.c_int32),
+                ("start_step", ctypes.c_int32), ("schedule_steps", ctypes.c_int32),
                 ("reserved", ctypes.c_int32),
                 ("a0", ctypes.c_double), ("c0", ctypes.c_double), ("dt", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("gamma_rep", ctypes.c_void_p)]
@@ -81,6 +82,8 @@ def lib():
         L.orc_update32.argtypes = [i32, vp, f32, f32, f32, f32, f32, vp, vp]
         L.orc_num_samples.restype = i32
         L.orc_num_samples.argtypes = [i32, i32]
+        L.orc_num_samples_range.restype = i32
+        L.orc_num_samples_range.argtypes = [i32, i32, i32]
         L.orc_run.restype = i32
         L.orc_run.argtypes = [ctypes.POINTER(_Params), vp, vp, vp, ctypes.POINTER(_Outputs)]
         _lib = L
@@ -173,8 +176,12 @@ def num_samples(steps: int, interval: int) -> int:
 
 def run(J, variant: int, a0: float, c0: float, dt: float, gamma, steps: int, R: int,
         seed: int = 0, amp: float = 0.1, interval: int = 100, precision: int = FP64,
-        return_best: bool = True, x0=None, y0=None, r0: int = 0, traces: bool = False):
+        return_best: bool = True, x0=None, y0=None, r0: int = 0, traces: bool = False,
+        start_step: int = 0, schedule_steps: int = 0):
     """Run R replicas (replica ids r0 .. r0+R-1) for `steps` steps.
+
+    start_step/schedule_steps resume a run: steps k = start_step .. start_step+steps-1
+    of a pump schedule a(t_k) = a0 k / schedule_steps (0 means start_step + steps).
 
     gamma may be a scalar or a per-replica array of length R.  x0/y0 default to
     the seeded initial state.  Returns a dict of numpy arrays.
@@ -190,6 +197,7 @@ def run(J, variant: int, a0: float, c0: float, dt: float, gamma, steps: int, R: 
     P = _Params()
     P.N, P.R, P.steps, P.variant = N, R, steps, variant
     P.interval, P.precision, P.return_best = interval, precision, int(bool(return_best))
+    P.start_step, P.schedule_steps = start_step, schedule_steps
     P.a0, P.c0, P.dt = a0, c0, dt
     g_arr = None
     if np.ndim(gamma) == 0:
@@ -201,7 +209,7 @@ def run(J, variant: int, a0: float, c0: float, dt: float, gamma, steps: int, R: 
             raise ValueError("per-replica gamma must have length R")
         P.gamma = 0.0
         P.gamma_rep = g_arr.ctypes.data
-    ns = num_samples(steps, interval)
+    ns = int(lib().orc_num_samples_range(start_step, start_step + steps, interval))
     out = {
         "x": np.empty((R, N)), "y": np.empty((R, N)),
         "spins": np.empty((R, N), dtype=np.int8), "energy": np.empty(R),

@@ -206,7 +206,10 @@ void orc_update32(int N, const double *f, float p, float a0, float c0, float dt,
 typedef struct {
     int32_t N, R, steps, variant;       /* variant 0 = bSB, 1 = dSB */
     int32_t interval, precision;        /* precision 0 = FP64, 1 = FP32 mirror */
-    int32_t return_best, reserved;
+    int32_t return_best;
+    int32_t start_step;                 /* k0: first step index (resumed runs); 0 normally */
+    int32_t schedule_steps;             /* Ns of a(t_k) = a0 k / Ns; 0 means start_step + steps */
+    int32_t reserved;
     double a0, c0, dt, gamma;
     const double *gamma_rep;            /* optional per-replica gamma [R] */
 } orc_params;
@@ -222,24 +225,28 @@ typedef struct {
     double *trace_tinst;    /* [n_samples][R] T_inst at each sample (optional) */
 } orc_outputs;
 
-/* Sample points: step counts m in 1..Ns with m % interval == 0, plus m = Ns
- * (and m = 0 when Ns = 0). */
-int orc_num_samples(int steps, int interval)
+/* Sample points of a run over steps k0 .. k1-1: step counts m in (k0, k1]
+ * with m % interval == 0, plus m = k1 (which is m = k0 when no step runs). */
+int orc_num_samples_range(int k0, int k1, int interval)
 {
-    if (steps <= 0) return 1;
-    return steps / interval + (steps % interval ? 1 : 0);
+    int n = k1 / interval - k0 / interval;
+    if (k1 == k0 || k1 % interval) ++n;
+    return n;
 }
 
-static int is_sample(int m, int steps, int interval)
+int orc_num_samples(int steps, int interval) { return orc_num_samples_range(0, steps, interval); }
+
+static int is_sample(int m, int k0, int k1, int interval)
 {
-    return (m == steps) || (m >= 1 && m % interval == 0);
+    return (m == k1) || (m > k0 && m % interval == 0);
 }
 
 int orc_run(const orc_params *P, const double *J, const float *x0, const float *y0, orc_outputs *O)
 {
-    const int N = P->N, R = P->R, Ns = P->steps;
-    if (N < 1 || R < 1 || Ns < 0 || P->interval < 1) return -1;
-    const int ns = orc_num_samples(Ns, P->interval);
+    const int N = P->N, R = P->R;
+    const int k0 = P->start_step, k1 = P->start_step + P->steps;
+    const int Ns = P->schedule_steps > 0 ? P->schedule_steps : k1;
+    if (N < 1 || R < 1 || P->steps < 0 || k0 < 0 || P->interval < 1 || Ns < k1) return -1;
 
     int rc = 0;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -260,9 +267,9 @@ int orc_run(const orc_params *P, const double *J, const float *x0, const float *
         }
         double best = INFINITY, last = NAN;
         int best_m = -1, sample = 0;
-        for (int m = 0; m <= Ns; ++m) {
+        for (int m = k0; m <= k1; ++m) {
             /* state after m steps is in (xd,yd) or (xf,yf) */
-            if (is_sample(m, Ns, P->interval)) {
+            if (is_sample(m, k0, k1, P->interval)) {
                 const int is32 = P->precision == 1;
                 double t = 0.0;
                 for (int i = 0; i < N; ++i) {
@@ -282,7 +289,7 @@ int orc_run(const orc_params *P, const double *J, const float *x0, const float *
                 }
                 last = e;
             }
-            if (m == Ns) break;
+            if (m == k1) break;
             if (P->precision == 1) {
                 /* a(t_k) as a float: (a0*k)/Ns; p = a0 - a(t_k) */
                 float a0f = (float)P->a0;
@@ -316,6 +323,5 @@ int orc_run(const orc_params *P, const double *J, const float *x0, const float *
         }
         free(f); free(xd); free(yd); free(xf); free(yf); free(s); free(best_s);
     }
-    (void)ns;
     return rc;
 }

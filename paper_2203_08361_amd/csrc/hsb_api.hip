@@ -1,0 +1,433 @@
+// libhsb C ABI: argument validation, the J store, run orchestration.
+// Declarations and the contract of every entry point are in include/hsb.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hsb.h"
+#include "kernels.h"
+#include "persistent.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? HSB_ENOMEM : HSB_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return hip_fail(_e, #expr); \
+    } while (0)
+
+inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+// FP4 (E2M1) values: 0, 0.5, 1, 1.5, 2, 3, 4, 6 and their negatives.
+bool fp4_exact(float v) {
+    const float a = std::fabs(v);
+    return a == 0.0f || a == 0.5f || a == 1.0f || a == 1.5f || a == 2.0f || a == 3.0f ||
+           a == 4.0f || a == 6.0f;
+}
+
+}  // namespace
+
+struct hsb_ctx {
+    int N = 0, Npad = 0, device = 0;
+    float *dJ = nullptr;        // FP32 J, [Npad][Npad], zero padded
+    bool j_int_exact = false;   // integer J with small row sums: FP32 fields exact
+    bool j_fp4_exact = false;   // every entry representable in FP4 (E2M1)
+    hsb::PersistentJ *pj = nullptr;  // FP4 J store for the persistent dSB path (lazy)
+    std::vector<float> hJ;      // host copy kept for lazy device re-layouts
+    // options
+    double init_amp = 0.1;
+    int interval = 100;
+    int return_best = 1;
+    int precision = HSB_PREC_AUTO;
+    int timing = 0;
+    hsb::KernelTimer timer;
+    // workspace
+    int Rpad_cap = 0;
+    hsb::StateBufs b{};
+    int8_t *d_spins = nullptr;  // hsb_run staging
+    double *d_energy = nullptr;
+    size_t run_cap = 0;
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+void free_state(hsb_ctx *h) {
+    hsb::StateBufs &b = h->b;
+    void *ptrs[] = {b.X,      b.Y,         b.B[0],      b.B[1], b.gamma, b.epart,
+                    b.best_e, b.last_e,    b.best_step, b.bad,  b.best_s, b.status};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    b = hsb::StateBufs{};
+    h->Rpad_cap = 0;
+}
+
+int ensure_state(hsb_ctx *h, int Rpad) {
+    if (Rpad <= h->Rpad_cap) return HSB_OK;
+    free_state(h);
+    hsb::StateBufs &b = h->b;
+    const size_t nr = (size_t)Rpad, ns = (size_t)h->Npad * nr;
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void **p, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, bytes);
+    };
+    alloc((void **)&b.X, ns * sizeof(float));
+    alloc((void **)&b.Y, ns * sizeof(float));
+    alloc((void **)&b.B[0], ns * sizeof(float));
+    alloc((void **)&b.B[1], ns * sizeof(float));
+    alloc((void **)&b.gamma, nr * sizeof(float));
+    alloc((void **)&b.epart, (size_t)(h->Npad / 32) * nr * sizeof(double));
+    alloc((void **)&b.best_e, nr * sizeof(double));
+    alloc((void **)&b.last_e, nr * sizeof(double));
+    alloc((void **)&b.best_step, nr * sizeof(int32_t));
+    alloc((void **)&b.bad, nr * sizeof(int32_t));
+    alloc((void **)&b.best_s, ns);
+    alloc((void **)&b.status, sizeof(int32_t));
+    if (e != hipSuccess) {
+        free_state(h);
+        return hip_fail(e, "allocating run state");
+    }
+    h->Rpad_cap = Rpad;
+    return HSB_OK;
+}
+
+bool finite_f(float v) { return std::isfinite(v); }
+
+}  // namespace
+
+// --------------------------------------------------------------------- API
+
+extern "C" const char *hsb_last_error(void) { return g_err; }
+
+extern "C" int hsb_create(const float *J, int N, hsb_ctx **out) {
+    g_err[0] = 0;
+    if (!out) return fail(HSB_EINVAL, "hsb_create: out is NULL");
+    *out = nullptr;
+    if (!J) return fail(HSB_EINVAL, "hsb_create: J is NULL");
+    if (N < 1 || N > 32768) return fail(HSB_EINVAL, "hsb_create: N=%d outside [1, 32768]", N);
+    bool is_int = true, is_fp4 = true;
+    double max_row = 0.0;
+    for (int i = 0; i < N; ++i) {
+        double row = 0.0;
+        for (int j = 0; j < N; ++j) {
+            const float v = J[(size_t)i * N + j];
+            if (!finite_f(v)) return fail(HSB_EINVAL, "hsb_create: J[%d][%d] is not finite", i, j);
+            if (v != J[(size_t)j * N + i])
+                return fail(HSB_EINVAL, "hsb_create: J is not symmetric at (%d, %d)", i, j);
+            if (i == j && v != 0.0f)
+                return fail(HSB_EINVAL, "hsb_create: J[%d][%d] = %g, diagonal must be 0", i, i, v);
+            if (v != std::nearbyint(v)) is_int = false;
+            if (!fp4_exact(v)) is_fp4 = false;
+            row += std::fabs((double)v);
+        }
+        if (row > max_row) max_row = row;
+    }
+    int dev = 0, ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(HSB_EDEVICE, "hsb_create: no HIP device");
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(HSB_EDEVICE, "hsb_create: device %d is %s, libhsb is built for gfx950", dev,
+                    prop.gcnArchName);
+
+    hsb_ctx *h = new (std::nothrow) hsb_ctx;
+    if (!h) return fail(HSB_ENOMEM, "hsb_create: host allocation failed");
+    h->N = N;
+    h->Npad = round_up(N, hsb::kTile);
+    h->device = dev;
+    // integer products/sums stay below 2^24 in FP32 (32-row partial energies included)
+    h->j_int_exact = is_int && max_row * 32.0 < 16777216.0;
+    h->j_fp4_exact = is_fp4;
+    const size_t np = (size_t)h->Npad;
+    std::vector<float> padded(np * np, 0.0f);
+    for (int i = 0; i < N; ++i)
+        std::memcpy(&padded[(size_t)i * np], J + (size_t)i * N, sizeof(float) * N);
+    hipError_t e = hipMalloc((void **)&h->dJ, np * np * sizeof(float));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipMemcpy(h->dJ, padded.data(), np * np * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        int rc = hip_fail(e, "hsb_create: J store");
+        hsb_destroy(h);
+        return rc;
+    }
+    h->hJ.assign(J, J + (size_t)N * N);
+    *out = h;
+    return HSB_OK;
+}
+
+extern "C" void hsb_destroy(hsb_ctx *h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    free_state(h);
+    if (h->dJ) (void)hipFree(h->dJ);
+    if (h->d_spins) (void)hipFree(h->d_spins);
+    if (h->d_energy) (void)hipFree(h->d_energy);
+    if (h->pj) hsb::persistent_free(h->pj);
+    h->timer.release();
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+extern "C" int hsb_set_option(hsb_ctx *h, int key, double v) {
+    if (!h) return fail(HSB_EINVAL, "hsb_set_option: NULL context");
+    switch (key) {
+    case HSB_OPT_INIT_AMP:
+        if (!(std::isfinite(v) && v > 0.0 && v <= 1.0e6))
+            return fail(HSB_EINVAL, "INIT_AMP must be finite and > 0");
+        h->init_amp = v;
+        return HSB_OK;
+    case HSB_OPT_ENERGY_INTERVAL:
+        if (!(v >= 1.0 && v <= 2147483647.0 && v == std::floor(v)))
+            return fail(HSB_EINVAL, "ENERGY_INTERVAL must be an integer >= 1");
+        h->interval = (int)v;
+        return HSB_OK;
+    case HSB_OPT_RETURN_BEST:
+        if (!(v == 0.0 || v == 1.0)) return fail(HSB_EINVAL, "RETURN_BEST must be 0 or 1");
+        h->return_best = (int)v;
+        return HSB_OK;
+    case HSB_OPT_PRECISION:
+        if (!(v == HSB_PREC_AUTO || v == HSB_PREC_FP32 || v == HSB_PREC_MIXED))
+            return fail(HSB_EINVAL, "PRECISION must be AUTO (0), FP32 (1) or MIXED (2)");
+        h->precision = (int)v;
+        return HSB_OK;
+    case HSB_OPT_TIMING:
+        if (!(v == 0.0 || v == 1.0)) return fail(HSB_EINVAL, "TIMING must be 0 or 1");
+        h->timing = (int)v;
+        return HSB_OK;
+    case HSB_OPT_KERNEL_MS:
+    case HSB_OPT_KERNEL_LAUNCHES:
+        return fail(HSB_EINVAL, "option %d is read only", key);
+    default:
+        return fail(HSB_EINVAL, "unknown option key %d", key);
+    }
+}
+
+extern "C" int hsb_get_option(hsb_ctx *h, int key, double *v) {
+    if (!h || !v) return fail(HSB_EINVAL, "hsb_get_option: NULL argument");
+    switch (key) {
+    case HSB_OPT_INIT_AMP: *v = h->init_amp; return HSB_OK;
+    case HSB_OPT_ENERGY_INTERVAL: *v = h->interval; return HSB_OK;
+    case HSB_OPT_RETURN_BEST: *v = h->return_best; return HSB_OK;
+    case HSB_OPT_PRECISION: *v = h->precision; return HSB_OK;
+    case HSB_OPT_TIMING: *v = h->timing; return HSB_OK;
+    case HSB_OPT_KERNEL_MS: {
+        double ms = 0.0;
+        hipError_t e = h->timer.total_ms(&ms);
+        if (e != hipSuccess) return hip_fail(e, "reading kernel timing events");
+        *v = ms;
+        return HSB_OK;
+    }
+    case HSB_OPT_KERNEL_LAUNCHES: *v = (double)h->timer.used; return HSB_OK;
+    default: return fail(HSB_EINVAL, "unknown option key %d", key);
+    }
+}
+
+namespace {
+
+// Which plan runs (variant, this J, the precision option).  Returns HSB_OK and
+// sets *plan to HSB_PREC_FP32 or HSB_PREC_MIXED, or HSB_EUNSUPPORTED.
+int choose_plan(const hsb_ctx *h, int variant, int *plan) {
+    const bool mixed_ok = variant == HSB_DSB && h->j_fp4_exact && hsb::persistent_supported(h->N);
+    if (h->precision == HSB_PREC_FP32) {
+        *plan = HSB_PREC_FP32;
+    } else if (h->precision == HSB_PREC_MIXED) {
+        if (!mixed_ok)
+            return fail(HSB_EUNSUPPORTED,
+                        "MIXED precision needs dSB, J exact in FP4 and N <= %d",
+                        hsb::persistent_max_n());
+        *plan = HSB_PREC_MIXED;
+    } else {
+        *plan = mixed_ok ? HSB_PREC_MIXED : HSB_PREC_FP32;
+    }
+    return HSB_OK;
+}
+
+}  // namespace
+
+extern "C" int hsb_plan_info(hsb_ctx *h, int variant, int *precision) {
+    if (!h || !precision) return fail(HSB_EINVAL, "hsb_plan_info: NULL argument");
+    if (variant != HSB_BSB && variant != HSB_DSB)
+        return fail(HSB_EINVAL, "variant must be HSB_BSB (0) or HSB_DSB (1)");
+    return choose_plan(h, variant, precision);
+}
+
+extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
+    g_err[0] = 0;
+    if (!h || !a) return fail(HSB_EINVAL, "hsb_run_ex: NULL argument");
+    if (a->struct_size != sizeof(hsb_run_args))
+        return fail(HSB_EINVAL, "hsb_run_ex: struct_size %zu != %zu", a->struct_size,
+                    sizeof(hsb_run_args));
+    if (a->variant != HSB_BSB && a->variant != HSB_DSB)
+        return fail(HSB_EINVAL, "variant must be HSB_BSB (0) or HSB_DSB (1)");
+    if (a->steps < 0) return fail(HSB_EINVAL, "steps must be >= 0");
+    if (a->R < 1 || a->R > (1 << 22)) return fail(HSB_EINVAL, "R must be in [1, 4194304]");
+    if (a->start_step < 0) return fail(HSB_EINVAL, "start_step must be >= 0");
+    if ((long long)a->start_step + a->steps > 2147483647LL)
+        return fail(HSB_EINVAL, "start_step + steps overflows");
+    const int Ns = a->schedule_steps > 0 ? a->schedule_steps : a->start_step + a->steps;
+    if (a->schedule_steps < 0 || Ns < a->start_step + a->steps)
+        return fail(HSB_EINVAL, "schedule_steps must be 0 or >= start_step + steps");
+    if (!(std::isfinite(a->a0) && std::isfinite(a->c0) && std::isfinite(a->dt) &&
+          std::isfinite(a->gamma)))
+        return fail(HSB_EINVAL, "a0, c0, dt and gamma must be finite");
+    if (!(a->dt > 0.0f)) return fail(HSB_EINVAL, "dt must be > 0");
+    if (!(a->gamma >= 0.0f)) return fail(HSB_EINVAL, "gamma must be >= 0");
+    if (!a->spins || !a->energy) return fail(HSB_EINVAL, "spins and energy are required");
+    if ((a->x0 == nullptr) != (a->y0 == nullptr))
+        return fail(HSB_EINVAL, "x0 and y0 must be given together");
+    int plan = 0;
+    int rc = choose_plan(h, a->variant, &plan);
+    if (rc != HSB_OK) return rc;
+    HIP_TRY(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)a->stream;
+    const int N = h->N, Npad = h->Npad, R = a->R;
+    const int Rpad = round_up(R, hsb::kTile);
+    if (a->gamma_rep) {
+        std::vector<float> g(R);
+        HIP_TRY(hipMemcpyAsync(g.data(), a->gamma_rep, sizeof(float) * R, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int r = 0; r < R; ++r)
+            if (!(std::isfinite(g[r]) && g[r] >= 0.0f))
+                return fail(HSB_EINVAL, "gamma_rep[%d] = %g must be finite and >= 0", r, g[r]);
+    }
+    rc = ensure_state(h, Rpad);
+    if (rc != HSB_OK) return rc;
+    hsb::StateBufs &b = h->b;
+    const float amp = (float)h->init_amp;
+    const int interval = h->interval;
+
+    // state set-up (eq. (16)-(22) start from x(t_0), y(t_0))
+    if (a->x0)
+        HIP_TRY(hsb::launch_load_state(b.X, b.Y, a->x0, a->y0, N, R, Npad, Rpad, s));
+    else
+        HIP_TRY(hsb::launch_init_seeded(b.X, b.Y, N, R, Npad, Rpad, a->seed, amp, s));
+    HIP_TRY(hsb::launch_fill_gamma(b.gamma, a->gamma_rep, a->gamma, R, Rpad, s));
+    HIP_TRY(hsb::launch_reset_tracking(b, Rpad, s));
+
+    h->timer.reset(h->timing != 0);
+    const float a0 = a->a0, c0 = a->c0, dt = a->dt;
+    const float a0dt = a0 * dt;
+    const int k0 = a->start_step, k1 = a->start_step + a->steps;
+    auto is_sample = [&](int m) { return m == k1 || (m > k0 && m % interval == 0); };
+    auto sample = [&](int m) -> int {
+        int nblk;
+        if (h->j_int_exact) {
+            HIP_TRY(hsb::launch_energy_fp32(h->dJ, b.X, b.epart, Npad, Rpad, s));
+            nblk = Npad / 32;
+        } else {
+            HIP_TRY(hsb::launch_energy_f64(h->dJ, b.X, b.epart, Npad, Rpad, s));
+            nblk = Npad / 64;
+        }
+        HIP_TRY(hsb::launch_best(b, nblk, N, R, Rpad, m, s));
+        return HSB_OK;
+    };
+
+    if (plan == HSB_PREC_MIXED) {
+        if (!h->pj) {
+            rc = hsb::persistent_create(h->hJ.data(), N, &h->pj);
+            if (rc != HSB_OK) return fail(rc, "%s", hsb::persistent_error());
+        }
+        hsb::PersistentRun pr{};
+        pr.X = b.X; pr.Y = b.Y; pr.gamma = b.gamma;
+        pr.Npad = Npad; pr.Rpad = Rpad; pr.R = R;
+        pr.k0 = k0; pr.k1 = k1; pr.Ns = Ns; pr.interval = interval;
+        pr.a0 = a0; pr.c0 = c0; pr.dt = dt;
+        pr.epart = b.epart;
+        rc = hsb::persistent_run(h->pj, pr, b, N, s, h->timer);
+        if (rc != HSB_OK) return fail(rc, "%s", hsb::persistent_error());
+    } else {
+        if (a->steps == 0) {
+            rc = sample(k0);
+            if (rc) return rc;
+        } else {
+            HIP_TRY(hsb::launch_make_operand(b.B[0], b.X, a->variant, Npad, Rpad, s));
+            int cur = 0;
+            for (int k = k0; k < k1; ++k) {
+                // a(t_k) = a0 k / Ns in single precision; p = a0 - a(t_k)
+                const float ak = (a0 * (float)k) / (float)Ns;
+                const float p = a0 - ak;
+                HIP_TRY(h->timer.begin(s));
+                HIP_TRY(hsb::launch_step_fp32(a->variant, h->dJ, b.B[cur], b.B[cur ^ 1], b.X, b.Y,
+                                              b.gamma, Npad, Rpad, p, c0, dt, a0dt, s));
+                HIP_TRY(h->timer.end(s));
+                cur ^= 1;
+                if (is_sample(k + 1)) {
+                    rc = sample(k + 1);
+                    if (rc) return rc;
+                }
+            }
+        }
+    }
+    HIP_TRY(hsb::launch_output(b, N, R, Rpad, h->return_best, a->spins, a->energy, a->x_out,
+                               a->y_out, a->best_energy, a->final_energy, a->best_step, s));
+    int32_t status = 0;
+    HIP_TRY(hipMemcpyAsync(&status, b.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (status) return fail(HSB_ENUMERIC, "a replica's state became non-finite");
+    return HSB_OK;
+}
+
+extern "C" int hsb_run(hsb_ctx *h, int variant, float a0, float c0, float dt, float gamma,
+                       int steps, int R, uint64_t seed, int8_t *spins, double *energy) {
+    g_err[0] = 0;
+    if (!h) return fail(HSB_EINVAL, "hsb_run: NULL context");
+    if (!spins || !energy) return fail(HSB_EINVAL, "hsb_run: spins and energy are required");
+    if (R < 1 || R > (1 << 22)) return fail(HSB_EINVAL, "R must be in [1, 4194304]");
+    HIP_TRY(hipSetDevice(h->device));
+    const size_t need = (size_t)R * h->N;
+    if (need > h->run_cap) {
+        if (h->d_spins) (void)hipFree(h->d_spins);
+        if (h->d_energy) (void)hipFree(h->d_energy);
+        h->d_spins = nullptr;
+        h->d_energy = nullptr;
+        h->run_cap = 0;
+        HIP_TRY(hipMalloc((void **)&h->d_spins, need));
+        HIP_TRY(hipMalloc((void **)&h->d_energy, sizeof(double) * (size_t)R));
+        h->run_cap = need;
+    }
+    hsb_run_args a;
+    std::memset(&a, 0, sizeof(a));
+    a.struct_size = sizeof(a);
+    a.variant = variant;
+    a.steps = steps;
+    a.R = R;
+    a.a0 = a0;
+    a.c0 = c0;
+    a.dt = dt;
+    a.gamma = gamma;
+    a.seed = seed;
+    a.spins = h->d_spins;
+    a.energy = h->d_energy;
+    a.stream = h->stream;
+    const int rc = hsb_run_ex(h, &a);
+    if (rc != HSB_OK && rc != HSB_ENUMERIC) return rc;
+    HIP_TRY(hipMemcpyAsync(spins, h->d_spins, need, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(energy, h->d_energy, sizeof(double) * R, hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return rc;
+}

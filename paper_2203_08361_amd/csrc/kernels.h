@@ -1,0 +1,99 @@
+// Launch wrappers of the libhsb kernels (host side).  Every device array of
+// the state uses the spin-major layout [Npad][Rpad]: element (i, r) at
+// i*Rpad + r, replicas contiguous.  Padding rows/columns hold zeros.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace hsb {
+
+// HIP-event brackets around launches of a run's dominant kernel.
+struct KernelTimer {
+    bool on = false;
+    size_t used = 0;
+    std::vector<hipEvent_t> ev;  // pairs: begin, end
+    void reset(bool enable) {
+        on = enable;
+        used = 0;
+    }
+    hipError_t begin(hipStream_t s) {
+        if (!on) return hipSuccess;
+        if (ev.size() < 2 * (used + 1)) {
+            for (int q = 0; q < 2; ++q) {
+                hipEvent_t e;
+                hipError_t rc = hipEventCreate(&e);
+                if (rc != hipSuccess) return rc;
+                ev.push_back(e);
+            }
+        }
+        return hipEventRecord(ev[2 * used], s);
+    }
+    hipError_t end(hipStream_t s) {
+        if (!on) return hipSuccess;
+        hipError_t rc = hipEventRecord(ev[2 * used + 1], s);
+        ++used;
+        return rc;
+    }
+    hipError_t total_ms(double *ms) const {
+        double t = 0.0;
+        for (size_t i = 0; i < used; ++i) {
+            float f = 0.0f;
+            hipError_t rc = hipEventSynchronize(ev[2 * i + 1]);
+            if (rc == hipSuccess) rc = hipEventElapsedTime(&f, ev[2 * i], ev[2 * i + 1]);
+            if (rc != hipSuccess) return rc;
+            t += f;
+        }
+        *ms = t;
+        return hipSuccess;
+    }
+    void release() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        used = 0;
+    }
+};
+
+// Tile sizes of the per-step FP32 path: Npad and Rpad are multiples of 64.
+constexpr int kTile = 64;
+
+struct StateBufs {
+    float *X, *Y;         // [Npad][Rpad]
+    float *B[2];          // field operand ping-pong: x (bSB) or sgn(x) (dSB)
+    float *gamma;         // [Rpad] per-replica gamma
+    double *epart;        // [Npad/32][Rpad] energy partial sums
+    double *best_e;       // [Rpad]
+    double *last_e;       // [Rpad]
+    int32_t *best_step;   // [Rpad]
+    int32_t *bad;         // [Rpad] non-finite flag per replica
+    int8_t *best_s;       // [Npad][Rpad]
+    int32_t *status;      // [1] any replica non-finite
+};
+
+hipError_t launch_init_seeded(float *X, float *Y, int N, int R, int Npad, int Rpad, uint64_t seed,
+                              float amp, hipStream_t s);
+hipError_t launch_load_state(float *X, float *Y, const float *x0, const float *y0, int N, int R,
+                             int Npad, int Rpad, hipStream_t s);
+hipError_t launch_make_operand(float *B, const float *X, int variant, int Npad, int Rpad,
+                               hipStream_t s);
+hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int R, int Rpad,
+                             hipStream_t s);
+hipError_t launch_reset_tracking(const StateBufs &b, int Rpad, hipStream_t s);
+hipError_t launch_step_fp32(int variant, const float *J, const float *Bin, float *Bout, float *X,
+                            float *Y, const float *gamma, int Npad, int Rpad, float p, float c0,
+                            float dt, float a0dt, hipStream_t s);
+// energy partials: exact path (FP32 products, J integer-valued) -> nblk = Npad/32
+hipError_t launch_energy_fp32(const float *J, const float *X, double *epart, int Npad, int Rpad,
+                              hipStream_t s);
+// energy partials in FP64 (any J) -> nblk = Npad/64
+hipError_t launch_energy_f64(const float *J, const float *X, double *epart, int Npad, int Rpad,
+                             hipStream_t s);
+hipError_t launch_best(const StateBufs &b, int nblk, int N, int R, int Rpad, int step,
+                       hipStream_t s);
+hipError_t launch_output(const StateBufs &b, int N, int R, int Rpad, int return_best,
+                         int8_t *spins, double *energy, float *x_out, float *y_out,
+                         double *best_energy, double *final_energy, int32_t *best_step,
+                         hipStream_t s);
+
+}  // namespace hsb

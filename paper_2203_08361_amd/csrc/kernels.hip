@@ -1,0 +1,386 @@
+// libhsb kernels: state set-up, the per-step FP32 field GEMM with the fused
+// update, energy partial sums, best-sample tracking and output.
+//
+// The field of eqs. (4)/(5) is the dense product F = J B with B = x (bSB) or
+// B = sgn(x) (dSB), J: Npad x Npad, B: Npad x Rpad.  One launch performs one
+// time step: every workgroup computes a 64 x 64 tile of F on the FP32 matrix
+// cores (v_mfma_f32_32x32x2f32, LDS double-buffered K loop) and applies
+// eqs. (16)-(22) to the same tile of (x, y) in its epilogue, writing the next
+// step's operand into the other ping-pong buffer (synchronous update: every
+// f_i of step k reads x(t_k) only).
+#include "hsb_device.h"
+#include "kernels.h"
+
+namespace hsb {
+
+// ------------------------------------------------------------ state set-up
+
+__global__ void k_init_seeded(float *__restrict__ X, float *__restrict__ Y, int N, int R, int Npad,
+                              int Rpad, uint64_t seed, float amp) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (r >= Rpad) return;
+    float x = 0.0f, y = 0.0f;
+    if (i < N && r < R) {
+        x = amp * uniform_open(rng_key(seed, 0, (uint64_t)r, (uint64_t)i));
+        y = amp * uniform_open(rng_key(seed, 1, (uint64_t)r, (uint64_t)i));
+    }
+    X[(size_t)i * Rpad + r] = x;
+    Y[(size_t)i * Rpad + r] = y;
+}
+
+__global__ void k_load_state(float *__restrict__ X, float *__restrict__ Y,
+                             const float *__restrict__ x0, const float *__restrict__ y0, int N,
+                             int R, int Rpad) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (r >= Rpad) return;
+    const bool ok = i < N && r < R;
+    X[(size_t)i * Rpad + r] = ok ? x0[(size_t)r * N + i] : 0.0f;
+    Y[(size_t)i * Rpad + r] = ok ? y0[(size_t)r * N + i] : 0.0f;
+}
+
+__global__ void k_make_operand(float *__restrict__ B, const float *__restrict__ X, int variant,
+                               size_t n) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    B[e] = variant == 0 ? X[e] : sgnf(X[e]);
+}
+
+__global__ void k_fill_gamma(float *__restrict__ g, const float *__restrict__ gamma_rep,
+                             float gamma, int R, int Rpad) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= Rpad) return;
+    g[r] = r < R ? (gamma_rep ? gamma_rep[r] : gamma) : 0.0f;
+}
+
+__global__ void k_reset_tracking(double *best_e, double *last_e, int32_t *best_step, int32_t *bad,
+                                 int32_t *status, int Rpad) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0) status[0] = 0;
+    if (r >= Rpad) return;
+    best_e[r] = __builtin_huge_val();
+    last_e[r] = __builtin_nan("");
+    best_step[r] = -1;
+    bad[r] = 0;
+}
+
+// --------------------------------------------------- FP32 GEMM main loop
+// 256 threads, four waves in a 2 x 2 arrangement of 32 x 32 tiles.  LDS tiles
+// are stored K-major ([k][i] and [k][r]) so that each MFMA operand read is a
+// run of 32 consecutive floats.
+//
+// v_mfma_f32_32x32x2f32 operand layout (lane l of 64):
+//   A: A[l % 32][l / 32]     B: B[l / 32][l % 32]
+//   D: item v of lane l is D[8*(v/4) + 4*(l/32) + v%4][l % 32]
+
+template <bool SIGN_B>
+__device__ __forceinline__ v16f gemm_tile_fp32(const float *__restrict__ J,
+                                               const float *__restrict__ Bsrc, int Npad, int Rpad,
+                                               int i0, int r0, float (*As)[32][68],
+                                               float (*Bs)[32][68]) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int a_row = t >> 2, a_col = (t & 3) * 8;
+    const int b_row = t >> 3, b_col = (t & 7) * 8;
+    const float *Ap = J + (size_t)(i0 + a_row) * Npad + a_col;
+    const float *Bp = Bsrc + (size_t)b_row * Rpad + r0 + b_col;
+    v4f ra0 = *(const v4f *)(Ap), ra1 = *(const v4f *)(Ap + 4);
+    v4f rb0 = *(const v4f *)(Bp), rb1 = *(const v4f *)(Bp + 4);
+    v16f acc = {};
+    const int nk = Npad / 32;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[buf][a_col + q][a_row] = ra0[q];
+            As[buf][a_col + 4 + q][a_row] = ra1[q];
+        }
+        if (SIGN_B) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                rb0[q] = sgnf(rb0[q]);
+                rb1[q] = sgnf(rb1[q]);
+            }
+        }
+        *(v4f *)&Bs[buf][b_row][b_col] = rb0;
+        *(v4f *)&Bs[buf][b_row][b_col + 4] = rb1;
+        __syncthreads();
+        if (kt + 1 < nk) {
+            Ap += 32;
+            Bp += (size_t)32 * Rpad;
+            ra0 = *(const v4f *)(Ap);
+            ra1 = *(const v4f *)(Ap + 4);
+            rb0 = *(const v4f *)(Bp);
+            rb1 = *(const v4f *)(Bp + 4);
+        }
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const float a = As[buf][2 * kk + (lane >> 5)][32 * wr + (lane & 31)];
+            const float b = Bs[buf][2 * kk + (lane >> 5)][32 * wc + (lane & 31)];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
+// One time step (field + fused eqs. (16)-(22)).  Grid (Rpad/64, Npad/64).
+template <int VARIANT>
+__global__ __launch_bounds__(256) void k_step_fp32(const float *__restrict__ J,
+                                                   const float *__restrict__ Bin,
+                                                   float *__restrict__ Bout, float *__restrict__ X,
+                                                   float *__restrict__ Y,
+                                                   const float *__restrict__ gam, int Npad,
+                                                   int Rpad, float p, float c0, float dt,
+                                                   float a0dt) {
+    __shared__ float As[2][32][68];
+    __shared__ float Bs[2][32][68];
+    const int r0 = blockIdx.x * kTile, i0 = blockIdx.y * kTile;
+    const v16f acc = gemm_tile_fp32<false>(J, Bin, Npad, Rpad, i0, r0, As, Bs);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int r = r0 + 32 * wc + (lane & 31);
+    const float gdt = gam[r] * dt;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = i0 + 32 * wr + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const size_t idx = (size_t)i * Rpad + r;
+        float x = X[idx], y = Y[idx];
+        sb_update(acc[v], p, c0, dt, a0dt, gdt, x, y);
+        X[idx] = x;
+        Y[idx] = y;
+        Bout[idx] = VARIANT == 0 ? x : sgnf(x);
+    }
+}
+
+// Energy partials, exact for integer-valued J: F = J sgn(x) on FP32 matrix
+// cores (every product and sum is an integer below 2^24), then per 32-row
+// block sum_i s_i F_i.  epart[(Npad/32)][Rpad].
+__global__ __launch_bounds__(256) void k_energy_fp32(const float *__restrict__ J,
+                                                     const float *__restrict__ X,
+                                                     double *__restrict__ epart, int Npad,
+                                                     int Rpad) {
+    __shared__ float As[2][32][68];
+    __shared__ float Bs[2][32][68];
+    const int r0 = blockIdx.x * kTile, i0 = blockIdx.y * kTile;
+    const v16f acc = gemm_tile_fp32<true>(J, X, Npad, Rpad, i0, r0, As, Bs);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int r = r0 + 32 * wc + (lane & 31);
+    float part = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = i0 + 32 * wr + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        part += sgnf(X[(size_t)i * Rpad + r]) * acc[v];
+    }
+    part += __shfl_xor(part, 32);
+    if (lane < 32) epart[(size_t)(blockIdx.y * 2 + wr) * Rpad + r] = (double)part;
+}
+
+// Energy partials in FP64 for any J: 64 x 64 tile, each thread 4 x 4 outputs,
+// fixed summation order.  epart[(Npad/64)][Rpad].
+__global__ __launch_bounds__(256) void k_energy_f64(const float *__restrict__ J,
+                                                    const float *__restrict__ X,
+                                                    double *__restrict__ epart, int Npad,
+                                                    int Rpad) {
+    __shared__ double As[16][65];
+    __shared__ double Bs[16][65];
+    __shared__ double red[16][65];
+    const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
+    const int r0 = blockIdx.x * kTile, i0 = blockIdx.y * kTile;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < Npad; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + 256 * q;
+            const int ai = e >> 4, ak = e & 15;
+            As[ak][ai] = (double)J[(size_t)(i0 + ai) * Npad + k0 + ak];
+            const int bk = e >> 6, br = e & 63;
+            Bs[bk][br] = (double)sgnf(X[(size_t)(k0 + bk) * Rpad + r0 + br]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = As[k][tr + 16 * q];
+                b[q] = Bs[k][tc + 16 * q];
+            }
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) acc[ii][rr] = __fma_rn(a[ii], b[rr], acc[ii][rr]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        double part = 0.0;
+        const int r = r0 + tc + 16 * rr;
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+            const int i = i0 + tr + 16 * ii;
+            part += (double)sgnf(X[(size_t)i * Rpad + r]) * acc[ii][rr];
+        }
+        red[tr][tc + 16 * rr] = part;
+    }
+    __syncthreads();
+    if (t < 64) {
+        double s = 0.0;
+        for (int q = 0; q < 16; ++q) s += red[q][t];
+        epart[(size_t)blockIdx.y * Rpad + r0 + t] = s;
+    }
+}
+
+// Best-sample tracking after a sample point `step`: total energy per replica
+// in a fixed order, non-finite detection, strict-improvement best update
+// (ties keep the earliest sample) with a copy of the spins.
+__global__ void k_best(const double *__restrict__ epart, int nblk, const float *__restrict__ X,
+                       const float *__restrict__ Y, int N, int R, int Rpad,
+                       double *__restrict__ best_e, double *__restrict__ last_e,
+                       int32_t *__restrict__ best_step, int32_t *__restrict__ bad,
+                       int8_t *__restrict__ best_s, int32_t *__restrict__ status, int step) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double e = 0.0;
+    for (int b = 0; b < nblk; ++b) e += epart[(size_t)b * Rpad + r];
+    e = -0.5 * e;
+    bool finite = true;
+    for (int i = 0; i < N; ++i) {
+        const float x = X[(size_t)i * Rpad + r], y = Y[(size_t)i * Rpad + r];
+        finite = finite && isfinite(x) && isfinite(y);
+    }
+    if (!finite) {
+        bad[r] = 1;
+        status[0] = 1;
+        e = __builtin_nan("");
+    }
+    last_e[r] = e;
+    if (e < best_e[r]) {
+        best_e[r] = e;
+        best_step[r] = step;
+        for (int i = 0; i < N; ++i)
+            best_s[(size_t)i * Rpad + r] = X[(size_t)i * Rpad + r] >= 0.0f ? 1 : -1;
+    }
+}
+
+__global__ void k_output_spins(const float *__restrict__ X, const float *__restrict__ Y,
+                               const int8_t *__restrict__ best_s,
+                               const int32_t *__restrict__ best_step, int N, int R, int Rpad,
+                               int return_best, int8_t *__restrict__ spins,
+                               float *__restrict__ x_out, float *__restrict__ y_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int r = blockIdx.y; r < R; r += gridDim.y) {
+        const size_t src = (size_t)i * Rpad + r, dst = (size_t)r * N + i;
+        const float x = X[src];
+        spins[dst] = (return_best && best_step[r] >= 0) ? best_s[src] : (x >= 0.0f ? 1 : -1);
+        if (x_out) x_out[dst] = x;
+        if (y_out) y_out[dst] = Y[src];
+    }
+}
+
+__global__ void k_output_energy(const double *__restrict__ best_e,
+                                const double *__restrict__ last_e,
+                                const int32_t *__restrict__ best_step_in,
+                                const int32_t *__restrict__ bad, int R, int return_best,
+                                double *__restrict__ energy, double *__restrict__ best_energy,
+                                double *__restrict__ final_energy,
+                                int32_t *__restrict__ best_step) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const double nan = __builtin_nan("");
+    const bool b = bad[r] != 0;
+    energy[r] = b ? nan : (return_best ? best_e[r] : last_e[r]);
+    if (best_energy) best_energy[r] = b ? nan : best_e[r];
+    if (final_energy) final_energy[r] = b ? nan : last_e[r];
+    if (best_step) best_step[r] = best_step_in[r];
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+hipError_t launch_init_seeded(float *X, float *Y, int N, int R, int Npad, int Rpad, uint64_t seed,
+                              float amp, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_seeded, dim3(cdiv(Rpad, 256), Npad), dim3(256), 0, s, X, Y, N, R,
+                       Npad, Rpad, seed, amp);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_state(float *X, float *Y, const float *x0, const float *y0, int N, int R,
+                             int Npad, int Rpad, hipStream_t s) {
+    hipLaunchKernelGGL(k_load_state, dim3(cdiv(Rpad, 256), Npad), dim3(256), 0, s, X, Y, x0, y0,
+                       N, R, Rpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_operand(float *B, const float *X, int variant, int Npad, int Rpad,
+                               hipStream_t s) {
+    const size_t n = (size_t)Npad * Rpad;
+    hipLaunchKernelGGL(k_make_operand, dim3(cdiv(n, 256)), dim3(256), 0, s, B, X, variant, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int R, int Rpad,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_gamma, dim3(cdiv(Rpad, 256)), dim3(256), 0, s, g, gamma_rep, gamma,
+                       R, Rpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_tracking(const StateBufs &b, int Rpad, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_tracking, dim3(cdiv(Rpad, 256)), dim3(256), 0, s, b.best_e,
+                       b.last_e, b.best_step, b.bad, b.status, Rpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_fp32(int variant, const float *J, const float *Bin, float *Bout, float *X,
+                            float *Y, const float *gamma, int Npad, int Rpad, float p, float c0,
+                            float dt, float a0dt, hipStream_t s) {
+    const dim3 grid(Rpad / kTile, Npad / kTile);
+    if (variant == 0)
+        hipLaunchKernelGGL(k_step_fp32<0>, grid, dim3(256), 0, s, J, Bin, Bout, X, Y, gamma, Npad,
+                           Rpad, p, c0, dt, a0dt);
+    else
+        hipLaunchKernelGGL(k_step_fp32<1>, grid, dim3(256), 0, s, J, Bin, Bout, X, Y, gamma, Npad,
+                           Rpad, p, c0, dt, a0dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_fp32(const float *J, const float *X, double *epart, int Npad, int Rpad,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_fp32, dim3(Rpad / kTile, Npad / kTile), dim3(256), 0, s, J, X,
+                       epart, Npad, Rpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_f64(const float *J, const float *X, double *epart, int Npad, int Rpad,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_f64, dim3(Rpad / kTile, Npad / kTile), dim3(256), 0, s, J, X,
+                       epart, Npad, Rpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_best(const StateBufs &b, int nblk, int N, int R, int Rpad, int step,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_best, dim3(cdiv(R, 64)), dim3(64), 0, s, b.epart, nblk, b.X, b.Y, N, R,
+                       Rpad, b.best_e, b.last_e, b.best_step, b.bad, b.best_s, b.status, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_output(const StateBufs &b, int N, int R, int Rpad, int return_best,
+                         int8_t *spins, double *energy, float *x_out, float *y_out,
+                         double *best_energy, double *final_energy, int32_t *best_step,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_output_spins, dim3(cdiv(N, 256), R < 32768 ? R : 32768), dim3(256), 0, s,
+                       b.X, b.Y, b.best_s, b.best_step, N, R, Rpad, return_best, spins, x_out,
+                       y_out);
+    hipLaunchKernelGGL(k_output_energy, dim3(cdiv(R, 256)), dim3(256), 0, s, b.best_e, b.last_e,
+                       b.best_step, b.bad, R, return_best, energy, best_energy, final_energy,
+                       best_step);
+    return hipGetLastError();
+}
+
+}  // namespace hsb

@@ -1,0 +1,514 @@
+// Persistent discrete-SB path on FP4 matrix cores.
+//
+// Field (eq. (5)): f = J sgn(x).  sgn(x) is +-1 and, for this path, every J_ij
+// is exactly representable in FP4 (E2M1), so the products are exact and the
+// FP32 accumulation of at most 2048 of them is exact: the field -- and hence
+// the whole single-precision trajectory -- is bitwise that of any exact
+// evaluation of eq. (5).
+//
+// Work decomposition.  Replicas never interact, so a "team" of waves owns a
+// tile of 32 replicas for the whole run, and inside the team wave `rb` owns
+// spin rows [64 rb, 64 rb + 64).  Each wave keeps, for the whole launch,
+//   - its 64 rows of J as FP4 MFMA operands in registers (64 x Npad x 4 bit),
+//   - x and y of its 64 x 32 (row, replica) block in registers.
+// One step (Methods, eqs. (16)-(22)) is
+//   1. F^T = S^T J  with S = sgn(x(t_k)) of all Npad rows of the team's 32
+//      replicas, on v_mfma_scale_f32_32x32x64_f8f6f4 (FP4 x FP4, unit scales);
+//   2. the fused update of its 64 x 32 block in registers;
+//   3. publishing the new signs: per (32-row chunk, replica) one 32-bit word
+//      of sign bits, stored together with the step index as a 64-bit tagged
+//      word in a ping-pong exchange buffer (synchronous update, eq. (16):
+//      every f_i of step k reads x(t_k) only).
+// Readers spin on the tag of each word they need; there is no grid barrier.
+// Double buffering by step parity makes a word safe to overwrite: the writer
+// of step k+2 has read every word of step k+1, whose writers had finished
+// reading step k.
+//
+// Energy (eq. (1)) needs J sgn(x) of the sampled state -- exactly the field
+// already computed for that state -- so each wave stores per-replica partial
+// sums sum_i s_i f_i of its rows at every sample point, plus the sign words of
+// the sampled state; a small kernel then forms E, keeps the best sample
+// (strict improvement, earliest wins) and its spins.
+#include "hsb.h"
+#include "hsb_device.h"
+#include "persistent.h"
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+namespace hsb {
+
+constexpr int kMaxKB = 32;  // K blocks of 64 spins: N <= 2048
+constexpr uint32_t kNoTag = 0xFFFFFFFFu;
+constexpr uint64_t kTimeoutTicks = 400000000ull;  // 4 s of the 100 MHz wall clock
+
+struct PersistentJ {
+    int N = 0, Npad = 0, nkb = 0, nrb = 0;
+    v4i *jpk = nullptr;          // [nrb][2][nkb][64] FP4 fragments
+    uint64_t *xb = nullptr;      // [2][nchunk][Rpad] tagged sign words
+    size_t xb_words = 0;
+    uint32_t *snap = nullptr;    // [ns][nchunk][Rpad] sign words of sampled states
+    size_t snap_words = 0;
+    float *ep = nullptr;         // [ns][nrb][Rpad] energy partials
+    size_t ep_elems = 0;
+    float *ptab = nullptr;       // p_k = a0 - a(t_k) of the steps of one segment
+    size_t ptab_elems = 0;
+    int32_t *err = nullptr;      // [1] timeout flag
+    int waves_capacity = 0;
+};
+
+namespace {
+thread_local char p_err[256] = "";
+int perr(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(p_err, sizeof(p_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+}  // namespace
+
+const char *persistent_error() { return p_err; }
+int persistent_max_n() { return kMaxKB * 64; }
+bool persistent_supported(int N) { return N >= 1 && N <= kMaxKB * 64; }
+
+// ----------------------------------------------------------------- device
+
+__device__ __forceinline__ uint64_t ld_tagged(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_tagged(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// Replace lane L of `old` by the wave-uniform value `val`.
+template <int L>
+__device__ __forceinline__ int write_lane(int old, int val) {
+    asm("v_writelane_b32 %0, %1, %2" : "+v"(old) : "s"(val), "n"(L));
+    return old;
+}
+
+// FP4 encoding of the values exact in E2M1.
+__device__ __forceinline__ uint32_t fp4_code(float v) {
+    const float a = fabsf(v);
+    uint32_t m = a == 0.5f ? 1u : a == 1.0f ? 2u : a == 1.5f ? 3u : a == 2.0f ? 4u
+               : a == 3.0f ? 5u : a == 4.0f ? 6u : a == 6.0f ? 7u : 0u;
+    return m | (v < 0.0f ? 8u : 0u);
+}
+
+// Packing convention shared by both MFMA operands.  Within a 32-spin chunk,
+// nibble n of fragment dword q holds spin t = 4n + 3 - q.  With sign words
+// (bit t set iff spin t is negative) this makes the +-1 operand of a chunk
+//   dword q = ((w << q) & 0x88888888) | 0x22222222
+// (0x2 = +1.0, 0xA = -1.0 in E2M1): seven integer operations per chunk.
+__device__ __forceinline__ v8i expand_signs(uint32_t w) {
+    v8i a = {};
+    a[0] = (int)((w & 0x88888888u) | 0x22222222u);
+    a[1] = (int)(((w << 1) & 0x88888888u) | 0x22222222u);
+    a[2] = (int)(((w << 2) & 0x88888888u) | 0x22222222u);
+    a[3] = (int)(((w << 3) & 0x88888888u) | 0x22222222u);
+    return a;
+}
+
+// J fragment for (row block rb, row tile rt, K block kb, lane): lane l holds
+// row 64 rb + 32 rt + l%32 and spins 64 kb + 32 (l/32) + t of the chunk.
+__global__ void k_pack_fp4(const float *__restrict__ J, v4i *__restrict__ jpk, int Npad, int nkb,
+                           int nrb) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)nrb * 2 * nkb * 64;
+    if (e >= total) return;
+    const int lane = (int)(e & 63);
+    const int kb = (int)((e >> 6) % nkb);
+    const int rt = (int)((e >> 6) / nkb % 2);
+    const int rb = (int)((e >> 6) / nkb / 2);
+    const int row = rb * 64 + rt * 32 + (lane & 31);
+    const int base = kb * 64 + (lane >> 5) * 32;
+    v4i out;
+    for (int q = 0; q < 4; ++q) {
+        uint32_t d = 0;
+        for (int n = 0; n < 8; ++n)
+            d |= fp4_code(J[(size_t)row * Npad + base + 4 * n + 3 - q]) << (4 * n);
+        out[q] = (int)d;
+    }
+    jpk[e] = out;
+}
+
+__global__ void k_zero_i32(int32_t *p) { p[0] = 0; }
+
+__global__ void k_fill_tags(uint64_t *xb, size_t n) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) xb[e] = ((uint64_t)kNoTag << 32);
+}
+
+struct SegArgs {
+    int seg_k0, seg_k1, final_k, interval, nmult;
+};
+
+__device__ __forceinline__ bool seg_is_sample(const SegArgs &g, int m) {
+    return m == g.final_k || (m > g.seg_k0 && m % g.interval == 0);
+}
+__device__ __forceinline__ int seg_sample_index(const SegArgs &g, int m) {
+    return (m > g.seg_k0 && m % g.interval == 0) ? (m / g.interval - g.seg_k0 / g.interval - 1)
+                                                 : g.nmult;
+}
+
+// Spin until every lane's word carries tag m.  Returns false on timeout or
+// when another wave has flagged an error.
+__device__ __forceinline__ bool wait_tag(uint64_t &v, const uint64_t *p, uint32_t m, int32_t *err) {
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        const bool ok = (uint32_t)(v >> 32) == m;
+        if (__all(ok)) return true;
+        __builtin_amdgcn_s_sleep(1);
+        if (!ok) v = ld_tagged(p);
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        if (wall_clock64() - t0 > kTimeoutTicks) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+}
+
+template <int NKB>
+__global__ __launch_bounds__(256, 1) void k_dsb_fp4(
+    const v4i *__restrict__ jpk, float *__restrict__ X, float *__restrict__ Y,
+    const float *__restrict__ gamma, uint64_t *xb, uint32_t *__restrict__ snap,
+    float *__restrict__ ep, const float *__restrict__ ptab, int32_t *__restrict__ bad,
+    int32_t *__restrict__ status, int32_t *err, int nkb, int nrb, int Rpad, int team0,
+    int nteams, SegArgs g, float c0, float dt, float a0dt) {
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int rb = gw % nrb;
+    const int team = team0 + gw / nrb;
+    if (gw / nrb >= nteams) return;  // uniform per wave
+    const int r0 = team * 32;
+    const int nchunk = 2 * nrb;
+    const int half = lane >> 5, l32 = lane & 31;
+
+    v4i jr0[NKB], jr1[NKB];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+        if (kb < nkb) {
+            jr0[kb] = jpk[((size_t)(rb * 2 + 0) * nkb + kb) * 64 + lane];
+            jr1[kb] = jpk[((size_t)(rb * 2 + 1) * nkb + kb) * 64 + lane];
+        } else {
+            jr0[kb] = v4i{0, 0, 0, 0};
+            jr1[kb] = v4i{0, 0, 0, 0};
+        }
+    }
+
+    // item v of an accumulator: replica r0 + 8(v/4) + 4(l/32) + v%4, row l%32 of the tile
+    float xs0[16], xs1[16], ys0[16], ys1[16], gdt[16];
+    const size_t row0 = (size_t)(rb * 64 + l32) * Rpad, row1 = row0 + (size_t)32 * Rpad;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int rep = r0 + 8 * (v >> 2) + 4 * half + (v & 3);
+        gdt[v] = gamma[rep] * dt;
+        xs0[v] = X[row0 + rep];
+        ys0[v] = Y[row0 + rep];
+        xs1[v] = X[row1 + rep];
+        ys1[v] = Y[row1 + rep];
+    }
+
+    // publish the sign words of the state x_m (tag m); snapshot at samples
+    auto publish = [&](int m) {
+        // ballot of item v: bits 0-31 are rows 0-31 of replica rho = 8(v/4) + v%4,
+        // bits 32-63 those of replica rho + 4; lane 32 rt + rho stores word (rt, rho)
+        int word = 0;
+        static_for<0, 16>([&](auto vc) {
+            constexpr int v = decltype(vc)::value;
+            constexpr int rho = 8 * (v >> 2) + (v & 3);
+            const uint64_t b0 = __ballot(!(xs0[v] >= 0.0f));
+            const uint64_t b1 = __ballot(!(xs1[v] >= 0.0f));
+            word = write_lane<rho>(word, (int)(uint32_t)b0);
+            word = write_lane<rho + 4>(word, (int)(uint32_t)(b0 >> 32));
+            word = write_lane<32 + rho>(word, (int)(uint32_t)b1);
+            word = write_lane<32 + rho + 4>(word, (int)(uint32_t)(b1 >> 32));
+        });
+        const size_t slot = (size_t)(rb * 2 + half) * Rpad + r0 + l32;
+        st_tagged(xb + (size_t)(m & 1) * nchunk * Rpad + slot,
+                  ((uint64_t)(uint32_t)m << 32) | (uint32_t)word);
+        if (seg_is_sample(g, m))
+            snap[(size_t)seg_sample_index(g, m) * nchunk * Rpad + slot] = (uint32_t)word;
+    };
+
+    publish(g.seg_k0);
+    for (int m = g.seg_k0;; ++m) {
+        v16f acc0 = {}, acc1 = {};
+        const uint64_t *src = xb + ((size_t)(m & 1) * nchunk + half) * Rpad + r0 + l32;
+        // exchange words of K blocks kb .. kb+kWin-1 are in flight
+        constexpr int kWin = NKB < 8 ? NKB : 8;
+        uint64_t wv[kWin];
+#pragma unroll
+        for (int q = 0; q < kWin; ++q)
+            if (q < nkb) wv[q] = ld_tagged(src + (size_t)2 * q * Rpad);
+        bool alive = true;
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+            if (kb < nkb && alive) {
+                uint64_t cur = wv[kb % kWin];
+                if (kb + kWin < nkb) wv[kb % kWin] = ld_tagged(src + (size_t)2 * (kb + kWin) * Rpad);
+                if (!__all((uint32_t)(cur >> 32) == (uint32_t)m))
+                    alive = wait_tag(cur, src + (size_t)2 * kb * Rpad, (uint32_t)m, err);
+                const v8i a = expand_signs((uint32_t)cur);
+                const v8i b0 = {jr0[kb][0], jr0[kb][1], jr0[kb][2], jr0[kb][3], 0, 0, 0, 0};
+                const v8i b1 = {jr1[kb][0], jr1[kb][1], jr1[kb][2], jr1[kb][3], 0, 0, 0, 0};
+                acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, acc0, 4, 4, 0, 127, 0,
+                                                                       127);
+                acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, acc1, 4, 4, 0, 127, 0,
+                                                                       127);
+            }
+        }
+        if (!alive) break;
+        if (seg_is_sample(g, m)) {
+            // eq. (1) partials: sum over this wave's rows of s_i f_i (exact integers/halves)
+            const int j = seg_sample_index(g, m);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                float part = sgnf(xs0[v]) * acc0[v] + sgnf(xs1[v]) * acc1[v];
+#pragma unroll
+                for (int off = 16; off >= 1; off >>= 1) part += __shfl_xor(part, off);
+                const int rep = r0 + 8 * (v >> 2) + 4 * half + (v & 3);
+                if (l32 == 0) ep[((size_t)j * nrb + rb) * Rpad + rep] = part;
+                const bool fin = isfinite(xs0[v]) && isfinite(xs1[v]) && isfinite(ys0[v]) &&
+                                 isfinite(ys1[v]);
+                if (!fin) {
+                    bad[rep] = 1;
+                    status[0] = 1;
+                }
+            }
+        }
+        if (m == g.seg_k1) break;
+        const float p = ptab[m - g.seg_k0];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            sb_update(acc0[v], p, c0, dt, a0dt, gdt[v], xs0[v], ys0[v]);
+            sb_update(acc1[v], p, c0, dt, a0dt, gdt[v], xs1[v], ys1[v]);
+        }
+        publish(m + 1);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int rep = r0 + 8 * (v >> 2) + 4 * half + (v & 3);
+        X[row0 + rep] = xs0[v];
+        Y[row0 + rep] = ys0[v];
+        X[row1 + rep] = xs1[v];
+        Y[row1 + rep] = ys1[v];
+    }
+}
+
+// Energies of the segment's samples, best-sample update and its spins.
+__global__ void k_fp4_best(const float *__restrict__ ep, const uint32_t *__restrict__ snap, int ns,
+                           int nrb, int N, int R, int Rpad, SegArgs g, double *__restrict__ best_e,
+                           double *__restrict__ last_e, int32_t *__restrict__ best_step,
+                           const int32_t *__restrict__ bad, int8_t *__restrict__ best_s) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int nchunk = 2 * nrb;
+    double best = best_e[r], last = 0.0;
+    int bj = -1;
+    for (int j = 0; j < ns; ++j) {
+        double e = 0.0;
+        for (int b = 0; b < nrb; ++b) e += (double)ep[((size_t)j * nrb + b) * Rpad + r];
+        e = -0.5 * e;
+        last = e;
+        if (e < best) {
+            best = e;
+            bj = j;
+        }
+    }
+    if (bad[r]) last = __builtin_nan("");
+    if (ns > 0) last_e[r] = last;
+    if (bj >= 0 && !bad[r]) {
+        best_e[r] = best;
+        best_step[r] = bj < g.nmult ? (g.seg_k0 / g.interval + 1 + bj) * g.interval : g.final_k;
+        for (int i = 0; i < N; ++i) {
+            const uint32_t w = snap[((size_t)bj * nchunk + (i >> 5)) * Rpad + r];
+            best_s[(size_t)i * Rpad + r] = ((w >> (i & 31)) & 1u) ? -1 : 1;
+        }
+    }
+}
+
+// ------------------------------------------------------------------- host
+
+namespace {
+
+template <int NKB>
+const void *kernel_ptr() {
+    return reinterpret_cast<const void *>(&k_dsb_fp4<NKB>);
+}
+
+const void *pick_kernel(int nkb) {
+    if (nkb <= 4) return kernel_ptr<4>();
+    if (nkb <= 8) return kernel_ptr<8>();
+    if (nkb <= 16) return kernel_ptr<16>();
+    return kernel_ptr<32>();
+}
+
+template <typename T>
+int grow(T **p, size_t *cap, size_t n) {
+    if (n <= *cap) return HSB_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e != hipSuccess)
+        return perr(e == hipErrorOutOfMemory ? HSB_ENOMEM : HSB_EDEVICE, "persistent scratch: %s",
+                    hipGetErrorString(e));
+    *cap = n;
+    return HSB_OK;
+}
+
+}  // namespace
+
+int persistent_create(const float *J, int N, PersistentJ **out) {
+    *out = nullptr;
+    if (!persistent_supported(N)) return perr(HSB_EUNSUPPORTED, "N=%d too large for FP4 path", N);
+    PersistentJ *pj = new PersistentJ;
+    pj->N = N;
+    pj->Npad = (N + 63) / 64 * 64;
+    pj->nkb = pj->Npad / 64;
+    pj->nrb = pj->Npad / 64;
+    const size_t np = (size_t)pj->Npad;
+    std::vector<float> padded(np * np, 0.0f);
+    for (int i = 0; i < N; ++i)
+        std::memcpy(&padded[(size_t)i * np], J + (size_t)i * N, sizeof(float) * N);
+    float *dJ = nullptr;
+    const size_t frags = (size_t)pj->nrb * 2 * pj->nkb * 64;
+    hipError_t e = hipMalloc((void **)&dJ, np * np * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&pj->jpk, frags * sizeof(v4i));
+    if (e == hipSuccess) e = hipMalloc((void **)&pj->err, sizeof(int32_t));
+    if (e == hipSuccess)
+        e = hipMemcpy(dJ, padded.data(), np * np * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_pack_fp4, dim3((unsigned)((frags + 255) / 256)), dim3(256), 0, 0, dJ,
+                           pj->jpk, pj->Npad, pj->nkb, pj->nrb);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (dJ) (void)hipFree(dJ);
+    int dev = 0, ncu = 0, nb = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(pj->nkb), 256, 0);
+    if (e != hipSuccess) {
+        persistent_free(pj);
+        return perr(e == hipErrorOutOfMemory ? HSB_ENOMEM : HSB_EDEVICE, "FP4 J store: %s",
+                    hipGetErrorString(e));
+    }
+    pj->waves_capacity = nb * ncu * 4;
+    if (pj->waves_capacity < pj->nrb) {
+        persistent_free(pj);
+        return perr(HSB_EUNSUPPORTED, "FP4 path: %d resident waves < %d row blocks",
+                    nb * ncu * 4, (N + 63) / 64);
+    }
+    *out = pj;
+    return HSB_OK;
+}
+
+void persistent_free(PersistentJ *pj) {
+    if (!pj) return;
+    void *ptrs[] = {pj->jpk, pj->xb, pj->snap, pj->ep, pj->ptab, pj->err};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete pj;
+}
+
+int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int N, hipStream_t s,
+                   KernelTimer &timer) {
+    const int Rpad = run.Rpad, nrb = pj->nrb, nkb = pj->nkb, nchunk = 2 * nrb;
+    const int nteams_total = Rpad / 32;
+    const int teams_per_launch = pj->waves_capacity / nrb;
+    const int interval = run.interval;
+    // samples per launch bounded by a 512 MiB snapshot budget (and 4096)
+    const size_t snap_per_sample = (size_t)nchunk * Rpad;
+    size_t seg_samples = ((size_t)512 << 20) / (snap_per_sample * 4);
+    if (seg_samples > 4096) seg_samples = 4096;
+    if (seg_samples < 1) seg_samples = 1;
+    int rc = grow(&pj->xb, &pj->xb_words, (size_t)2 * nchunk * Rpad);
+    if (!rc) rc = grow(&pj->snap, &pj->snap_words, (seg_samples + 1) * snap_per_sample);
+    if (!rc) rc = grow(&pj->ep, &pj->ep_elems, (seg_samples + 1) * (size_t)nrb * Rpad);
+    const long long max_seg_steps = (long long)seg_samples * interval;
+    const int ptab_need = (int)((long long)(run.k1 - run.k0) < max_seg_steps
+                                    ? (run.k1 - run.k0)
+                                    : max_seg_steps);
+    if (!rc) rc = grow(&pj->ptab, &pj->ptab_elems, (size_t)(ptab_need > 0 ? ptab_need : 1));
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, pj->err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
+    const float a0dt = run.a0 * run.dt;
+    const void *kfn = pick_kernel(nkb);
+    std::vector<float> ptab;
+    int a = run.k0;
+    for (;;) {
+        // segment [a, e]: at most seg_samples multiples of interval in (a, e]
+        long long e_ll = ((long long)a / interval + (long long)seg_samples) * interval;
+        const int e_k = e_ll < run.k1 ? (int)e_ll : run.k1;
+        SegArgs g;
+        g.seg_k0 = a;
+        g.seg_k1 = e_k;
+        g.final_k = run.k1;
+        g.interval = interval;
+        g.nmult = e_k / interval - a / interval;
+        const int ns = g.nmult + ((e_k == run.k1 && (e_k % interval != 0 || e_k == a)) ? 1 : 0);
+        ptab.resize((size_t)(e_k - a > 0 ? e_k - a : 1));
+        for (int k = a; k < e_k; ++k) {
+            // a(t_k) = a0 k / Ns in single precision; p = a0 - a(t_k)
+            const float ak = (run.a0 * (float)k) / (float)run.Ns;
+            ptab[k - a] = run.a0 - ak;
+        }
+        e = hipMemcpyAsync(pj->ptab, ptab.data(), sizeof(float) * (size_t)(e_k - a > 0 ? e_k - a : 0),
+                           hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
+        for (int t0 = 0; t0 < nteams_total; t0 += teams_per_launch) {
+            int nt = nteams_total - t0 < teams_per_launch ? nteams_total - t0 : teams_per_launch;
+            const size_t nxb = (size_t)2 * nchunk * Rpad;
+            hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((nxb + 255) / 256)), dim3(256), 0, s,
+                               pj->xb, nxb);
+            const int waves = nt * nrb;
+            const dim3 grid((waves + 3) / 4), block(256);
+            float c0 = run.c0, dt = run.dt, a0dtv = a0dt;
+            int nkb_v = nkb, nrb_v = nrb, Rpad_v = Rpad, t0_v = t0, nt_v = nt;
+            const float *gam = run.gamma;
+            void *args[] = {(void *)&pj->jpk, (void *)&run.X,   (void *)&run.Y,   (void *)&gam,
+                            (void *)&pj->xb,  (void *)&pj->snap, (void *)&pj->ep, (void *)&pj->ptab,
+                            (void *)&b.bad,   (void *)&b.status, (void *)&pj->err, (void *)&nkb_v,
+                            (void *)&nrb_v,   (void *)&Rpad_v,  (void *)&t0_v,  (void *)&nt_v,
+                            (void *)&g,       (void *)&c0,      (void *)&dt,    (void *)&a0dtv};
+            e = timer.begin(s);
+            if (e == hipSuccess) e = hipLaunchCooperativeKernel(kfn, grid, block, args, 0, s);
+            if (e == hipSuccess) e = timer.end(s);
+            if (e != hipSuccess)
+                return perr(HSB_EDEVICE, "FP4 persistent launch: %s", hipGetErrorString(e));
+        }
+        hipLaunchKernelGGL(k_fp4_best, dim3((run.R + 63) / 64), dim3(64), 0, s, pj->ep, pj->snap,
+                           ns, nrb, N, run.R, Rpad, g, b.best_e, b.last_e, b.best_step, b.bad,
+                           b.best_s);
+        e = hipGetLastError();
+        if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
+        if (e_k >= run.k1) break;
+        a = e_k;
+    }
+    int32_t herr = 0;
+    e = hipMemcpyAsync(&herr, pj->err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
+    if (herr) return perr(HSB_EDEVICE, "FP4 persistent kernel: exchange wait timed out");
+    return HSB_OK;
+}
+
+}  // namespace hsb

@@ -1,0 +1,245 @@
+"""Python binding of libhsb (include/hsb.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module converts
+numpy arrays / torch device tensors to pointers and back.  There is no CPU
+fallback: if libhsb.so is missing or the device is not usable, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhsb.so")
+
+HSB_BSB, HSB_DSB = 0, 1
+HSB_OK, HSB_EINVAL, HSB_ENOMEM, HSB_EDEVICE, HSB_ENUMERIC, HSB_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
+HSB_OPT_INIT_AMP, HSB_OPT_ENERGY_INTERVAL, HSB_OPT_RETURN_BEST, HSB_OPT_PRECISION = 0, 1, 2, 3
+HSB_OPT_TIMING, HSB_OPT_KERNEL_MS, HSB_OPT_KERNEL_LAUNCHES = 4, 5, 6
+HSB_PREC_AUTO, HSB_PREC_FP32, HSB_PREC_MIXED = 0, 1, 2
+
+EXPORTED = ("hsb_create", "hsb_destroy", "hsb_last_error", "hsb_set_option", "hsb_get_option",
+            "hsb_run", "hsb_run_ex", "hsb_plan_info")
+
+_lib = None
+
+
+class HSBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libhsb error {code}: {msg}")
+        self.code = code
+
+
+class hsb_run_args(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_size_t),
+        ("variant", ctypes.c_int32), ("steps", ctypes.c_int32), ("R", ctypes.c_int32),
+        ("start_step", ctypes.c_int32), ("schedule_steps", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("a0", ctypes.c_float), ("c0", ctypes.c_float), ("dt", ctypes.c_float),
+        ("gamma", ctypes.c_float),
+        ("seed", ctypes.c_uint64),
+        ("gamma_rep", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("y0", ctypes.c_void_p),
+        ("x_out", ctypes.c_void_p), ("y_out", ctypes.c_void_p),
+        ("spins", ctypes.c_void_p), ("energy", ctypes.c_void_p),
+        ("best_energy", ctypes.c_void_p), ("final_energy", ctypes.c_void_p),
+        ("best_step", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+def load_library():
+    """Load libhsb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, f32, f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
+    L.hsb_create.restype = i32
+    L.hsb_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    L.hsb_destroy.restype = None
+    L.hsb_destroy.argtypes = [vp]
+    L.hsb_last_error.restype = ctypes.c_char_p
+    L.hsb_last_error.argtypes = []
+    L.hsb_set_option.restype = i32
+    L.hsb_set_option.argtypes = [vp, i32, f64]
+    L.hsb_get_option.restype = i32
+    L.hsb_get_option.argtypes = [vp, i32, ctypes.POINTER(f64)]
+    L.hsb_run.restype = i32
+    L.hsb_run.argtypes = [vp, i32, f32, f32, f32, f32, i32, i32, ctypes.c_uint64, vp, vp]
+    L.hsb_run_ex.restype = i32
+    L.hsb_run_ex.argtypes = [vp, ctypes.POINTER(hsb_run_args)]
+    L.hsb_plan_info.restype = i32
+    L.hsb_plan_info.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    _lib = L
+    return L
+
+
+def hsb_last_error() -> str:
+    return load_library().hsb_last_error().decode()
+
+
+def _check(rc: int, allow=()):
+    if rc != HSB_OK and rc not in allow:
+        raise HSBError(rc, hsb_last_error())
+    return rc
+
+
+def hsb_create(J) -> ctypes.c_void_p:
+    J = np.ascontiguousarray(J, dtype=np.float32)
+    if J.ndim != 2 or J.shape[0] != J.shape[1]:
+        raise ValueError("J must be a square matrix")
+    h = ctypes.c_void_p()
+    _check(load_library().hsb_create(J.ctypes.data, J.shape[0], ctypes.byref(h)))
+    return h
+
+
+def hsb_destroy(h) -> None:
+    load_library().hsb_destroy(h)
+
+
+def hsb_set_option(h, key: int, value: float) -> None:
+    _check(load_library().hsb_set_option(h, key, float(value)))
+
+
+def hsb_get_option(h, key: int) -> float:
+    v = ctypes.c_double()
+    _check(load_library().hsb_get_option(h, key, ctypes.byref(v)))
+    return v.value
+
+
+def hsb_plan_info(h, variant: int) -> int:
+    p = ctypes.c_int()
+    _check(load_library().hsb_plan_info(h, variant, ctypes.byref(p)))
+    return p.value
+
+
+def hsb_run(h, variant, a0, c0, dt, gamma, steps, R, seed, allow_numeric=False):
+    """Host-output run: returns (spins int8 [R][N], energy float64 [R], status)."""
+    N = _ctx_n(h)
+    spins = np.empty((R, N), dtype=np.int8)
+    energy = np.empty(R, dtype=np.float64)
+    rc = load_library().hsb_run(h, variant, a0, c0, dt, gamma, steps, R, seed & (2**64 - 1),
+                                spins.ctypes.data, energy.ctypes.data)
+    _check(rc, (HSB_ENUMERIC,) if allow_numeric else ())
+    return spins, energy, rc
+
+
+_sizes = {}
+
+
+def _ctx_n(h) -> int:
+    return _sizes[h.value]
+
+
+def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=None, x0=None,
+               y0=None, start_step=0, schedule_steps=0, want_state=False, stream=None,
+               allow_numeric=False, out=None):
+    """Device run through hsb_run_ex.  Tensors are torch CUDA tensors.
+
+    Returns a dict of device tensors: spins [R][N] int8, energy/best_energy/
+    final_energy [R] float64, best_step [R] int32, and x/y [R][N] float32 when
+    want_state.  `out` may pass preallocated tensors under the same keys.
+    """
+    import torch
+
+    N = _ctx_n(h)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    o = dict(out) if out else {}
+    o.setdefault("spins", torch.empty((R, N), dtype=torch.int8, device=dev))
+    for k in ("energy", "best_energy", "final_energy"):
+        o.setdefault(k, torch.empty(R, dtype=torch.float64, device=dev))
+    o.setdefault("best_step", torch.empty(R, dtype=torch.int32, device=dev))
+    if want_state:
+        o.setdefault("x", torch.empty((R, N), dtype=torch.float32, device=dev))
+        o.setdefault("y", torch.empty((R, N), dtype=torch.float32, device=dev))
+    a = hsb_run_args()
+    a.struct_size = ctypes.sizeof(hsb_run_args)
+    a.variant, a.steps, a.R = variant, steps, R
+    a.start_step, a.schedule_steps = start_step, schedule_steps
+    a.a0, a.c0, a.dt, a.gamma = a0, c0, dt, gamma
+    a.seed = seed & (2**64 - 1)
+    keep = []
+
+    def dptr(t, dtype, shape):
+        if t is None:
+            return None
+        t = t.to(device=dev, dtype=dtype).contiguous()
+        if tuple(t.shape) != shape:
+            raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+        keep.append(t)
+        return t.data_ptr()
+
+    a.gamma_rep = dptr(gamma_rep, torch.float32, (R,))
+    a.x0 = dptr(x0, torch.float32, (R, N))
+    a.y0 = dptr(y0, torch.float32, (R, N))
+    a.x_out = o["x"].data_ptr() if want_state else None
+    a.y_out = o["y"].data_ptr() if want_state else None
+    a.spins = o["spins"].data_ptr()
+    a.energy = o["energy"].data_ptr()
+    a.best_energy = o["best_energy"].data_ptr()
+    a.final_energy = o["final_energy"].data_ptr()
+    a.best_step = o["best_step"].data_ptr()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    a.stream = s.cuda_stream
+    rc = load_library().hsb_run_ex(h, ctypes.byref(a))
+    _check(rc, (HSB_ENUMERIC,) if allow_numeric else ())
+    o["status"] = rc
+    return o
+
+
+class Context:
+    """Owns one hsb_ctx (the J store) and its options."""
+
+    def __init__(self, J, **options):
+        J = np.ascontiguousarray(J, dtype=np.float32)
+        self.N = J.shape[0]
+        self.h = hsb_create(J)
+        _sizes[self.h.value] = self.N
+        for k, v in options.items():
+            self.set_option(k, v)
+
+    _KEYS = {"init_amp": HSB_OPT_INIT_AMP, "energy_interval": HSB_OPT_ENERGY_INTERVAL,
+             "return_best": HSB_OPT_RETURN_BEST, "precision": HSB_OPT_PRECISION,
+             "timing": HSB_OPT_TIMING, "kernel_ms": HSB_OPT_KERNEL_MS,
+             "kernel_launches": HSB_OPT_KERNEL_LAUNCHES}
+    _PREC = {"auto": HSB_PREC_AUTO, "fp32": HSB_PREC_FP32, "mixed": HSB_PREC_MIXED}
+
+    def set_option(self, key, value):
+        if isinstance(value, str):
+            value = self._PREC[value]
+        hsb_set_option(self.h, self._KEYS.get(key, key), value)
+
+    def get_option(self, key):
+        return hsb_get_option(self.h, self._KEYS.get(key, key))
+
+    def plan(self, variant):
+        return {HSB_PREC_FP32: "fp32", HSB_PREC_MIXED: "mixed"}[hsb_plan_info(self.h, variant)]
+
+    def run(self, variant, a0, c0, dt, gamma, steps, R, seed, allow_numeric=False):
+        return hsb_run(self.h, variant, a0, c0, dt, gamma, steps, R, seed, allow_numeric)
+
+    def run_ex(self, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, **kw):
+        return hsb_run_ex(self.h, variant, steps, R, a0, c0, dt, gamma, seed, **kw)
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            _sizes.pop(self.h.value, None)
+            hsb_destroy(self.h)
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

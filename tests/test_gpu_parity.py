@@ -1,0 +1,243 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars (per the method's arithmetic):
+  - dSB with integer J: the field is exact, so the single-precision trajectory
+    is bitwise equal to the oracle's FP32 mirror (x, y, energies, spins), for
+    both the FP32 plan and the FP4 (mixed) plan.
+  - bSB: per replica ||x_gpu - x_ref|| / ||x_ref|| <= 1e-5 (and for y) against
+    the FP64 oracle after 1 and 50 steps.
+  - energies: eq. (1) of the returned spins, exact for integer J; FP64 with
+    relative error <= 1e-12 for real J.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2203_08361_amd import hsb  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    hsb.load_library()
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def gpu_run(J, variant, plan, steps, R, seed=1, a0=1.0, c0=None, dt=1.0, gamma=0.0, amp=0.1,
+            interval=100, return_best=1, **kw):
+    N = J.shape[0]
+    c0 = 0.5 / np.sqrt(N) if c0 is None else c0
+    with hsb.Context(J, precision=plan, init_amp=amp, energy_interval=interval,
+                     return_best=return_best) as ctx:
+        out = ctx.run_ex(variant, steps, R, a0, c0, dt, gamma, seed, want_state=True, **kw)
+        torch.cuda.synchronize()
+        res = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
+        res["plan"] = ctx.plan(variant)
+    return res
+
+
+def oracle_run(J, variant, precision, steps, R, seed=1, a0=1.0, c0=None, dt=1.0, gamma=0.0,
+               amp=0.1, interval=100, return_best=True, **kw):
+    N = J.shape[0]
+    c0 = 0.5 / np.sqrt(N) if c0 is None else c0
+    return oracle.run(J, variant, a0, np.float32(c0), dt, gamma, steps, R, seed=seed, amp=amp,
+                      interval=interval, precision=precision, return_best=return_best, **kw)
+
+
+def assert_bit_exact(g, o, what=""):
+    assert np.array_equal(g["x"].astype(np.float64), o["x"]), what + " x"
+    assert np.array_equal(g["y"].astype(np.float64), o["y"]), what + " y"
+    assert np.array_equal(g["best_energy"], o["best_e"]), what + " best E"
+    assert np.array_equal(g["final_energy"], o["final_e"]), what + " final E"
+    assert np.array_equal(g["best_step"], o["best_step"]), what + " best step"
+    assert np.array_equal(g["spins"], o["spins"]), what + " spins"
+    assert np.array_equal(g["energy"], o["energy"]), what + " energy"
+
+
+# ---------------------------------------------------------------- dSB exact
+
+@pytest.mark.parametrize("plan", ["fp32", "mixed"])
+@pytest.mark.parametrize("gamma", [0.0, 0.01])
+def test_dsb_small_sk_bit_exact(plan, gamma):
+    """SK N=100, R=16, 2000 steps, dt=1, c0=0.5/sqrt(N), x,y in [-0.1,0.1]."""
+    J = synth.sk_instance(100, 1)
+    say("dsb N=100 R=16 steps=2000", plan, gamma)
+    g = gpu_run(J, hsb.HSB_DSB, plan, 2000, 16, gamma=gamma)
+    assert g["plan"] == ("mixed" if plan == "mixed" else "fp32")
+    o = oracle_run(J, oracle.DSB, oracle.FP32, 2000, 16, gamma=gamma)
+    assert_bit_exact(g, o)
+    for s, e in zip(g["spins"], g["energy"]):
+        assert oracle.energy(J, s) == e
+
+
+@pytest.mark.parametrize("plan", ["fp32", "mixed"])
+@pytest.mark.parametrize("N,R,steps,interval", [(1, 3, 40, 7), (2, 5, 30, 10), (63, 33, 300, 50),
+                                                (65, 64, 250, 100), (130, 70, 120, 1),
+                                                (257, 40, 90, 30)])
+def test_dsb_ragged_shapes_bit_exact(plan, N, R, steps, interval):
+    J = synth.sk_instance(N, N + 3)
+    say("dsb ragged", plan, N, R, steps, interval)
+    g = gpu_run(J, hsb.HSB_DSB, plan, steps, R, seed=N, gamma=0.02, interval=interval)
+    o = oracle_run(J, oracle.DSB, oracle.FP32, steps, R, seed=N, gamma=0.02, interval=interval)
+    assert_bit_exact(g, o)
+
+
+@pytest.mark.parametrize("plan", ["fp32", "mixed"])
+def test_dsb_zero_steps_and_final_mode(plan):
+    J = synth.sk_instance(50, 2)
+    say("dsb zero steps", plan)
+    g = gpu_run(J, hsb.HSB_DSB, plan, 0, 8)
+    o = oracle_run(J, oracle.DSB, oracle.FP32, 0, 8)
+    assert_bit_exact(g, o)
+    say("dsb return final", plan)
+    g = gpu_run(J, hsb.HSB_DSB, plan, 333, 8, return_best=0, gamma=0.05)
+    o = oracle_run(J, oracle.DSB, oracle.FP32, 333, 8, return_best=False, gamma=0.05)
+    assert_bit_exact(g, o)
+
+
+@pytest.mark.parametrize("plan", ["fp32", "mixed"])
+def test_dsb_per_replica_gamma(plan):
+    J = synth.sk_instance(120, 5)
+    R = 24
+    gam = np.array([0.0, 0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.5] * 3, dtype=np.float32)
+    say("dsb gamma_rep", plan)
+    g = gpu_run(J, hsb.HSB_DSB, plan, 500, R, gamma_rep=torch.from_numpy(gam))
+    o = oracle_run(J, oracle.DSB, oracle.FP32, 500, R, gamma=gam.astype(np.float64))
+    assert_bit_exact(g, o)
+
+
+@pytest.mark.parametrize("plan", ["fp32", "mixed"])
+def test_dsb_resume_equals_one_run(plan):
+    J = synth.sk_instance(200, 9)
+    R, Ns, k = 32, 600, 250
+    say("dsb resume", plan)
+    full = gpu_run(J, hsb.HSB_DSB, plan, Ns, R, gamma=0.01)
+    a = gpu_run(J, hsb.HSB_DSB, plan, k, R, gamma=0.01, schedule_steps=Ns)
+    b = gpu_run(J, hsb.HSB_DSB, plan, Ns - k, R, gamma=0.01, start_step=k, schedule_steps=Ns,
+                x0=torch.from_numpy(a["x"]), y0=torch.from_numpy(a["y"]))
+    assert np.array_equal(b["x"], full["x"]) and np.array_equal(b["y"], full["y"])
+    assert np.array_equal(b["final_energy"], full["final_energy"])
+    o = oracle_run(J, oracle.DSB, oracle.FP32, Ns - k, R, gamma=0.01, start_step=k,
+                   schedule_steps=Ns, x0=a["x"], y0=a["y"])
+    assert_bit_exact(b, o)
+
+
+def test_dsb_plans_agree_and_are_deterministic():
+    J = synth.sk_instance(300, 4)
+    say("dsb determinism")
+    a = gpu_run(J, hsb.HSB_DSB, "mixed", 400, 64, gamma=0.03, seed=77)
+    b = gpu_run(J, hsb.HSB_DSB, "mixed", 400, 64, gamma=0.03, seed=77)
+    c = gpu_run(J, hsb.HSB_DSB, "fp32", 400, 64, gamma=0.03, seed=77)
+    for k in ("x", "y", "spins", "energy", "best_step"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+    # replica r depends only on (seed, r): a run of fewer replicas is a prefix
+    d = gpu_run(J, hsb.HSB_DSB, "mixed", 400, 37, gamma=0.03, seed=77)
+    assert np.array_equal(d["x"], a["x"][:37]) and np.array_equal(d["energy"], a["energy"][:37])
+
+
+# --------------------------------------------------- full-size (N=2000, R=1024)
+
+@pytest.mark.parametrize("plan", ["mixed", "fp32"])
+def test_dsb_full_size_sampled_replicas(plan):
+    """N=2000, R=1024 over the first 300 steps of the 10^4-step schedule; the
+    oracle recomputes sampled replicas one by one (replica r depends only on (seed, r))."""
+    J = synth.sk_instance(2000, 2000)
+    say("dsb full size", plan)
+    g = gpu_run(J, hsb.HSB_DSB, plan, 300, 1024, seed=3, gamma=0.01, schedule_steps=10000)
+    for r in (0, 1, 517, 1023):
+        o = oracle_run(J, oracle.DSB, oracle.FP32, 300, 1, seed=3, gamma=0.01, r0=r,
+                       schedule_steps=10000)
+        assert np.array_equal(g["x"][r].astype(np.float64), o["x"][0]), r
+        assert np.array_equal(g["y"][r].astype(np.float64), o["y"][0]), r
+        assert g["best_energy"][r] == o["best_e"][0] and g["final_energy"][r] == o["final_e"][0]
+    # every returned energy is eq. (1) of the returned spins (check a sample)
+    for r in range(0, 1024, 97):
+        assert oracle.energy(J, g["spins"][r]) == g["energy"][r]
+
+
+# ---------------------------------------------------------------- bSB 1e-5
+
+def rel_err(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+@pytest.mark.parametrize("steps", [1, 50])
+@pytest.mark.parametrize("gamma", [0.0, 0.01])
+def test_bsb_trajectory_within_1e5(steps, gamma):
+    J = synth.sk_instance(100, 1)
+    say("bsb N=100", steps, gamma)
+    g = gpu_run(J, hsb.HSB_BSB, "fp32", steps, 16, gamma=gamma, schedule_steps=2000)
+    o = oracle_run(J, oracle.BSB, oracle.FP64, steps, 16, gamma=gamma, schedule_steps=2000)
+    assert rel_err(g["x"], o["x"]).max() <= 1e-5
+    assert rel_err(g["y"], o["y"]).max() <= 1e-5
+
+
+def test_bsb_full_size_sampled_replicas():
+    J = synth.sk_instance(2000, 2000)
+    say("bsb full size")
+    g = gpu_run(J, hsb.HSB_BSB, "fp32", 50, 1024, seed=3, gamma=0.01, schedule_steps=10000)
+    for r in (0, 700, 1023):
+        o = oracle_run(J, oracle.BSB, oracle.FP64, 50, 1, seed=3, gamma=0.01, r0=r,
+                       schedule_steps=10000)
+        assert rel_err(g["x"][r:r + 1], o["x"]).max() <= 1e-5
+        assert rel_err(g["y"][r:r + 1], o["y"]).max() <= 1e-5
+
+
+def test_gaussian_bsb_and_fp64_energies():
+    J = synth.gaussian_instance(300, 3)
+    say("gaussian bsb")
+    c0 = 0.5  # c1 / (sigma_J sqrt(N)) with sigma_J = 1/sqrt(N)
+    g = gpu_run(J, hsb.HSB_BSB, "auto", 50, 32, c0=c0, gamma=0.01, schedule_steps=1000)
+    o = oracle_run(J, oracle.BSB, oracle.FP64, 50, 32, c0=c0, gamma=0.01, schedule_steps=1000)
+    assert g["plan"] == "fp32"
+    assert rel_err(g["x"], o["x"]).max() <= 1e-5 and rel_err(g["y"], o["y"]).max() <= 1e-5
+    g = gpu_run(J, hsb.HSB_BSB, "auto", 1000, 32, c0=c0, gamma=0.01)
+    for s, e in zip(g["spins"], g["energy"]):
+        ref = oracle.energy(J, s)
+        assert abs(e - ref) <= 1e-12 * abs(ref)
+
+
+# ---------------------------------------------------------------- errors
+
+def test_plan_selection_and_unsupported():
+    say("plans")
+    with hsb.Context(synth.sk_instance(64, 1)) as ctx:
+        assert ctx.plan(hsb.HSB_DSB) == "mixed" and ctx.plan(hsb.HSB_BSB) == "fp32"
+    with hsb.Context(synth.gaussian_instance(64, 1), precision="mixed") as ctx:
+        with pytest.raises(hsb.HSBError) as ei:
+            ctx.plan(hsb.HSB_DSB)
+        assert ei.value.code == hsb.HSB_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("plan", ["fp32", "mixed"])
+def test_non_finite_state_is_reported(plan):
+    """gamma*dt > 1 with walls: y grows geometrically (eq. (22)) until it overflows."""
+    J = synth.sk_instance(40, 1)
+    say("numeric", plan)
+    g = gpu_run(J, hsb.HSB_DSB, plan, 400, 8, gamma=8.0, dt=1.0, allow_numeric=True)
+    assert g["status"] == hsb.HSB_ENUMERIC
+    assert np.all(np.isnan(g["energy"]))
+
+
+def test_invalid_run_arguments():
+    J = synth.sk_instance(16, 1)
+    say("invalid args")
+    with hsb.Context(J) as ctx:
+        for kw in (dict(steps=-1), dict(R=0), dict(dt=0.0), dict(gamma=-0.1),
+                   dict(dt=float("nan")), dict(schedule_steps=5)):
+            args = dict(variant=hsb.HSB_DSB, steps=10, R=4, a0=1.0, c0=0.1, dt=1.0, gamma=0.0)
+            args.update(kw)
+            with pytest.raises(hsb.HSBError) as ei:
+                ctx.run_ex(args.pop("variant"), args.pop("steps"), args.pop("R"), args.pop("a0"),
+                           args.pop("c0"), args.pop("dt"), args.pop("gamma"), **args)
+            assert ei.value.code == hsb.HSB_EINVAL
