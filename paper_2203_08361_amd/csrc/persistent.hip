@@ -93,9 +93,18 @@ __device__ __forceinline__ void static_for(F &&f) {
 }
 
 // Replace lane L of `old` by the wave-uniform value `val`.
-template <int L>
-__device__ __forceinline__ int write_lane(int old, int val) {
-    asm("v_writelane_b32 %0, %1, %2" : "+v"(old) : "s"(val), "n"(L));
+// Write four wave-uniform values into lanes L0..L3 of `old`.  The leading
+// s_nop covers the wait states a v_writelane needs after a VALU write (here
+// the v_cmp of a ballot) of the SGPR it reads.
+template <int L0, int L1, int L2, int L3>
+__device__ __forceinline__ int write_lanes4(int old, int a, int b, int c, int d) {
+    asm("s_nop 4\n\t"
+        "v_writelane_b32 %0, %1, %5\n\t"
+        "v_writelane_b32 %0, %2, %6\n\t"
+        "v_writelane_b32 %0, %3, %7\n\t"
+        "v_writelane_b32 %0, %4, %8"
+        : "+v"(old)
+        : "s"(a), "s"(b), "s"(c), "s"(d), "n"(L0), "n"(L1), "n"(L2), "n"(L3));
     return old;
 }
 
@@ -112,8 +121,8 @@ __device__ __forceinline__ uint32_t fp4_code(float v) {
 // (bit t set iff spin t is negative) this makes the +-1 operand of a chunk
 //   dword q = ((w << q) & 0x88888888) | 0x22222222
 // (0x2 = +1.0, 0xA = -1.0 in E2M1): seven integer operations per chunk.
-__device__ __forceinline__ v8i expand_signs(uint32_t w) {
-    v8i a = {};
+__device__ __forceinline__ v4i expand_signs(uint32_t w) {
+    v4i a;
     a[0] = (int)((w & 0x88888888u) | 0x22222222u);
     a[1] = (int)(((w << 1) & 0x88888888u) | 0x22222222u);
     a[2] = (int)(((w << 2) & 0x88888888u) | 0x22222222u);
@@ -163,38 +172,77 @@ __device__ __forceinline__ int seg_sample_index(const SegArgs &g, int m) {
                                                  : g.nmult;
 }
 
-// Spin until every lane's word carries tag m.  Returns false on timeout or
-// when another wave has flagged an error.
-__device__ __forceinline__ bool wait_tag(uint64_t &v, const uint64_t *p, uint32_t m, int32_t *err) {
+// Gather, for state m, the tagged sign words of the K blocks this wave
+// expands (its share: every W-th block), wv[q] holding block w + W q.  All
+// words are loaded together; while some are stale the wave polls the first
+// stale one alone (cheap) and, once it has arrived, reloads every stale word
+// in one batch -- writers finish at nearly the same time, so this costs about
+// one memory round trip after the last writer instead of one per word.
+// Returns false on timeout (4 s) or when another wave has flagged an error.
+template <int NQ>
+__device__ __forceinline__ bool gather_words(uint64_t (&wv)[NQ], const uint64_t *src,
+                                             size_t stride, int nq, uint32_t m, int32_t *err) {
+    uint32_t stale = 0;  // bit q: some lane's word q is stale
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (q < nq) wv[q] = ld_tagged(src + q * stride);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (q < nq && __any((uint32_t)(wv[q] >> 32) != m)) stale |= 1u << q;
+    if (stale == 0) return true;
     const uint64_t t0 = wall_clock64();
-    for (;;) {
-        const bool ok = (uint32_t)(v >> 32) == m;
-        if (__all(ok)) return true;
-        __builtin_amdgcn_s_sleep(1);
-        if (!ok) v = ld_tagged(p);
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-        if (wall_clock64() - t0 > kTimeoutTicks) {
-            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
+    for (int it = 1;; ++it) {
+        const uint64_t *p = src + __builtin_ctz(stale) * stride;
+        uint64_t v = ld_tagged(p);
+        while (__any((uint32_t)(v >> 32) != m)) {
+            __builtin_amdgcn_s_sleep(1);
+            v = ld_tagged(p);
+            if ((++it & 31) == 0) {
+                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                    return false;
+                if (wall_clock64() - t0 > kTimeoutTicks) {
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    return false;
+                }
+            }
         }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if ((stale >> q) & 1u) wv[q] = ld_tagged(src + q * stride);
+        uint32_t still = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (((stale >> q) & 1u) && __any((uint32_t)(wv[q] >> 32) != m)) still |= 1u << q;
+        stale = still;
+        if (stale == 0) return true;
     }
 }
 
+// One workgroup = 4 waves = 4 consecutive row blocks of one team, so the four
+// waves need the same +-1 operand (the team's signs).  Each step every wave
+// gathers and expands a quarter of the K blocks into LDS (ping-pong by step
+// parity), one workgroup barrier publishes them, and each wave then runs its
+// MFMAs with the operand from LDS and its J rows from registers.
 template <int NKB>
 __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     const v4i *__restrict__ jpk, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, uint64_t *xb, uint32_t *__restrict__ snap,
     float *__restrict__ ep, const float *__restrict__ ptab, int32_t *__restrict__ bad,
-    int32_t *__restrict__ status, int32_t *err, int nkb, int nrb, int Rpad, int team0,
+    int32_t *__restrict__ status, int32_t *err, int N, int nkb, int nrb, int Rpad, int team0,
     int nteams, SegArgs g, float c0, float dt, float a0dt) {
-    const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int rb = gw % nrb;
-    const int team = team0 + gw / nrb;
-    if (gw / nrb >= nteams) return;  // uniform per wave
+    constexpr int NQ = (NKB + 3) / 4;
+    __shared__ v4i a_lds[2][NKB][64];
+    __shared__ int wg_abort;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wgs_per_team = nrb >> 2;
+    if ((int)blockIdx.x / wgs_per_team >= nteams) return;  // whole workgroup
+    const int team = team0 + blockIdx.x / wgs_per_team;
+    const int rb = (blockIdx.x % wgs_per_team) * 4 + w;
     const int r0 = team * 32;
     const int nchunk = 2 * nrb;
     const int half = lane >> 5, l32 = lane & 31;
+    const int nq = (nkb - w + 3) >> 2;  // K blocks w, w+4, ... below nkb
+    if (threadIdx.x == 0) wg_abort = 0;
 
     v4i jr0[NKB], jr1[NKB];
 #pragma unroll
@@ -210,15 +258,15 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
 
     // item v of an accumulator: replica r0 + 8(v/4) + 4(l/32) + v%4, row l%32 of the tile
     float xs0[16], xs1[16], ys0[16], ys1[16], gdt[16];
-    const size_t row0 = (size_t)(rb * 64 + l32) * Rpad, row1 = row0 + (size_t)32 * Rpad;
+    const int row0 = rb * 64 + l32, row1 = row0 + 32;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int rep = r0 + 8 * (v >> 2) + 4 * half + (v & 3);
         gdt[v] = gamma[rep] * dt;
-        xs0[v] = X[row0 + rep];
-        ys0[v] = Y[row0 + rep];
-        xs1[v] = X[row1 + rep];
-        ys1[v] = Y[row1 + rep];
+        xs0[v] = row0 < N ? X[(size_t)row0 * Rpad + rep] : 0.0f;
+        ys0[v] = row0 < N ? Y[(size_t)row0 * Rpad + rep] : 0.0f;
+        xs1[v] = row1 < N ? X[(size_t)row1 * Rpad + rep] : 0.0f;
+        ys1[v] = row1 < N ? Y[(size_t)row1 * Rpad + rep] : 0.0f;
     }
 
     // publish the sign words of the state x_m (tag m); snapshot at samples
@@ -231,10 +279,9 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
             constexpr int rho = 8 * (v >> 2) + (v & 3);
             const uint64_t b0 = __ballot(!(xs0[v] >= 0.0f));
             const uint64_t b1 = __ballot(!(xs1[v] >= 0.0f));
-            word = write_lane<rho>(word, (int)(uint32_t)b0);
-            word = write_lane<rho + 4>(word, (int)(uint32_t)(b0 >> 32));
-            word = write_lane<32 + rho>(word, (int)(uint32_t)b1);
-            word = write_lane<32 + rho + 4>(word, (int)(uint32_t)(b1 >> 32));
+            word = write_lanes4<rho, rho + 4, 32 + rho, 32 + rho + 4>(
+                word, (int)(uint32_t)b0, (int)(uint32_t)(b0 >> 32), (int)(uint32_t)b1,
+                (int)(uint32_t)(b1 >> 32));
         });
         const size_t slot = (size_t)(rb * 2 + half) * Rpad + r0 + l32;
         st_tagged(xb + (size_t)(m & 1) * nchunk * Rpad + slot,
@@ -244,33 +291,35 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     };
 
     publish(g.seg_k0);
+    __syncthreads();
     for (int m = g.seg_k0;; ++m) {
-        v16f acc0 = {}, acc1 = {};
-        const uint64_t *src = xb + ((size_t)(m & 1) * nchunk + half) * Rpad + r0 + l32;
-        // exchange words of K blocks kb .. kb+kWin-1 are in flight
-        constexpr int kWin = NKB < 8 ? NKB : 8;
-        uint64_t wv[kWin];
+        const int buf = m & 1;
+        // this wave's share: K block kb = w + 4q is chunk 2 kb + l/32
+        const uint64_t *src = xb + ((size_t)buf * nchunk + 2 * w + half) * Rpad + r0 + l32;
+        uint64_t wv[NQ];
+        if (gather_words<NQ>(wv, src, (size_t)8 * Rpad, nq, (uint32_t)m, err)) {
 #pragma unroll
-        for (int q = 0; q < kWin; ++q)
-            if (q < nkb) wv[q] = ld_tagged(src + (size_t)2 * q * Rpad);
-        bool alive = true;
+            for (int q = 0; q < NQ; ++q)
+                if (q < nq) a_lds[buf][w + 4 * q][lane] = expand_signs((uint32_t)wv[q]);
+        } else {
+            wg_abort = 1;
+        }
+        __syncthreads();
+        if (wg_abort) break;
+        v16f acc0 = {}, acc1 = {};
 #pragma unroll
         for (int kb = 0; kb < NKB; ++kb) {
-            if (kb < nkb && alive) {
-                uint64_t cur = wv[kb % kWin];
-                if (kb + kWin < nkb) wv[kb % kWin] = ld_tagged(src + (size_t)2 * (kb + kWin) * Rpad);
-                if (!__all((uint32_t)(cur >> 32) == (uint32_t)m))
-                    alive = wait_tag(cur, src + (size_t)2 * kb * Rpad, (uint32_t)m, err);
-                const v8i a = expand_signs((uint32_t)cur);
+            if (kb < nkb) {
+                const v4i a4 = a_lds[buf][kb][lane];
+                const v8i a = {a4[0], a4[1], a4[2], a4[3], 0, 0, 0, 0};
                 const v8i b0 = {jr0[kb][0], jr0[kb][1], jr0[kb][2], jr0[kb][3], 0, 0, 0, 0};
                 const v8i b1 = {jr1[kb][0], jr1[kb][1], jr1[kb][2], jr1[kb][3], 0, 0, 0, 0};
-                acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, acc0, 4, 4, 0, 127, 0,
-                                                                       127);
-                acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, acc1, 4, 4, 0, 127, 0,
-                                                                       127);
+                acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, acc0, 4, 4, 0, 127,
+                                                                       0, 127);
+                acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, acc1, 4, 4, 0, 127,
+                                                                       0, 127);
             }
         }
-        if (!alive) break;
         if (seg_is_sample(g, m)) {
             // eq. (1) partials: sum over this wave's rows of s_i f_i (exact integers/halves)
             const int j = seg_sample_index(g, m);
@@ -301,10 +350,14 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int rep = r0 + 8 * (v >> 2) + 4 * half + (v & 3);
-        X[row0 + rep] = xs0[v];
-        Y[row0 + rep] = ys0[v];
-        X[row1 + rep] = xs1[v];
-        Y[row1 + rep] = ys1[v];
+        if (row0 < N) {
+            X[(size_t)row0 * Rpad + rep] = xs0[v];
+            Y[(size_t)row0 * Rpad + rep] = ys0[v];
+        }
+        if (row1 < N) {
+            X[(size_t)row1 * Rpad + rep] = xs1[v];
+            Y[(size_t)row1 * Rpad + rep] = ys1[v];
+        }
     }
 }
 
@@ -377,7 +430,7 @@ int persistent_create(const float *J, int N, PersistentJ **out) {
     if (!persistent_supported(N)) return perr(HSB_EUNSUPPORTED, "N=%d too large for FP4 path", N);
     PersistentJ *pj = new PersistentJ;
     pj->N = N;
-    pj->Npad = (N + 63) / 64 * 64;
+    pj->Npad = (N + 255) / 256 * 256;  // four row blocks of 64 per workgroup
     pj->nkb = pj->Npad / 64;
     pj->nrb = pj->Npad / 64;
     const size_t np = (size_t)pj->Npad;
@@ -412,7 +465,7 @@ int persistent_create(const float *J, int N, PersistentJ **out) {
     if (pj->waves_capacity < pj->nrb) {
         persistent_free(pj);
         return perr(HSB_EUNSUPPORTED, "FP4 path: %d resident waves < %d row blocks",
-                    nb * ncu * 4, (N + 63) / 64);
+                    nb * ncu * 4, pj->nrb);
     }
     *out = pj;
     return HSB_OK;
@@ -479,18 +532,21 @@ int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int 
             const size_t nxb = (size_t)2 * nchunk * Rpad;
             hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((nxb + 255) / 256)), dim3(256), 0, s,
                                pj->xb, nxb);
-            const int waves = nt * nrb;
-            const dim3 grid((waves + 3) / 4), block(256);
+            const dim3 grid((unsigned)(nt * (nrb / 4))), block(256);
             float c0 = run.c0, dt = run.dt, a0dtv = a0dt;
-            int nkb_v = nkb, nrb_v = nrb, Rpad_v = Rpad, t0_v = t0, nt_v = nt;
+            int N_v = N, nkb_v = nkb, nrb_v = nrb, Rpad_v = Rpad, t0_v = t0, nt_v = nt;
             const float *gam = run.gamma;
-            void *args[] = {(void *)&pj->jpk, (void *)&run.X,   (void *)&run.Y,   (void *)&gam,
-                            (void *)&pj->xb,  (void *)&pj->snap, (void *)&pj->ep, (void *)&pj->ptab,
-                            (void *)&b.bad,   (void *)&b.status, (void *)&pj->err, (void *)&nkb_v,
-                            (void *)&nrb_v,   (void *)&Rpad_v,  (void *)&t0_v,  (void *)&nt_v,
-                            (void *)&g,       (void *)&c0,      (void *)&dt,    (void *)&a0dtv};
+            void *args[] = {(void *)&pj->jpk, (void *)&run.X,    (void *)&run.Y,   (void *)&gam,
+                            (void *)&pj->xb,  (void *)&pj->snap, (void *)&pj->ep,  (void *)&pj->ptab,
+                            (void *)&b.bad,   (void *)&b.status, (void *)&pj->err, (void *)&N_v,
+                            (void *)&nkb_v,   (void *)&nrb_v,    (void *)&Rpad_v,  (void *)&t0_v,
+                            (void *)&nt_v,    (void *)&g,        (void *)&c0,      (void *)&dt,
+                            (void *)&a0dtv};
+            // every workgroup of the grid is resident at once: the grid never exceeds
+            // the occupancy-derived capacity, and every wait inside the kernel is
+            // bounded, so a wave that cannot make progress ends the launch cleanly
             e = timer.begin(s);
-            if (e == hipSuccess) e = hipLaunchCooperativeKernel(kfn, grid, block, args, 0, s);
+            if (e == hipSuccess) e = hipLaunchKernel(kfn, grid, block, args, 0, s);
             if (e == hipSuccess) e = timer.end(s);
             if (e != hipSuccess)
                 return perr(HSB_EDEVICE, "FP4 persistent launch: %s", hipGetErrorString(e));
