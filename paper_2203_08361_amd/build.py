@@ -23,8 +23,6 @@ FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 arithmetic in generated device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # MFMA results in VGPRs, leaving the AGPR file to the register-resident J operand
-    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -47,7 +47,8 @@ __device__ __forceinline__ void sb_update(float f, float p, float c0, float dt, 
     const float yt = __fmaf_rn(u, dt, y);
     const float xt = __fmaf_rn(a0dt, yt, x);
     const bool wall = fabsf(xt) > 1.0f;
-    const float xn = wall ? (xt > 0.0f ? 1.0f : -1.0f) : xt;
+    // g(x~): x~ inside [-1, 1], else sgn(x~) -- the median of (x~, -1, 1)
+    const float xn = __builtin_amdgcn_fmed3f(xt, -1.0f, 1.0f);
     const float ytt = wall ? 0.0f : yt;
     y = __fmaf_rn(gdt, y, ytt);
     x = xn;

@@ -108,6 +108,31 @@ __device__ __forceinline__ int write_lanes4(int old, int a, int b, int c, int d)
     return old;
 }
 
+// F^T tile update on the FP4 matrix cores: acc (VGPRs) += a (+-1 operand, VGPRs)
+// x b (J fragment, AGPRs), unit block scales.  Written as inline assembly so
+// that the loop-invariant J fragments stay in the accumulation registers
+// file for the whole kernel and feed the MFMA directly (the compiler would
+// otherwise copy them back to VGPRs before every use).  Hazards: exactly
+// overlapping srcC/vdst chains are interlocked by the hardware; the first
+// product of a step uses an inline zero for srcC; VALU reads of the result
+// wait behind mfma_drain().
+__device__ __forceinline__ void mfma_fp4_first(v16f &acc, const v4i &a, const v4i &b, int one) {
+    asm volatile(
+        "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, 0, %3, %3 op_sel_hi:[0,0,0] cbsz:4 blgp:4"
+        : "=&v"(acc)
+        : "v"(a), "a"(b), "v"(one));
+}
+__device__ __forceinline__ void mfma_fp4(v16f &acc, const v4i &a, const v4i &b, int one) {
+    asm volatile(
+        "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, %0, %3, %3 op_sel_hi:[0,0,0] cbsz:4 blgp:4"
+        : "+v"(acc)
+        : "v"(a), "a"(b), "v"(one));
+}
+// 21 wait states: more than an XDL write needs before a VALU read of its vdst.
+__device__ __forceinline__ void mfma_drain(v16f &acc0, v16f &acc1) {
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 4" : "+v"(acc0), "+v"(acc1));
+}
+
 // FP4 encoding of the values exact in E2M1.
 __device__ __forceinline__ uint32_t fp4_code(float v) {
     const float a = fabsf(v);
@@ -230,8 +255,12 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     float *__restrict__ ep, const float *__restrict__ ptab, int32_t *__restrict__ bad,
     int32_t *__restrict__ status, int32_t *err, int N, int nkb, int nrb, int Rpad, int team0,
     int nteams, SegArgs g, float c0, float dt, float a0dt) {
-    constexpr int NQ = (NKB + 3) / 4;
+    static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
+    constexpr int NQ = NKB / 4;  // K blocks expanded by each wave
     __shared__ v4i a_lds[2][NKB][64];
+    // y and gamma*dt live in LDS (each read once per step), keeping registers for J
+    __shared__ float y_lds[4][32][64];
+    __shared__ float gdt_lds[4][16][2];
     __shared__ int wg_abort;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wgs_per_team = nrb >> 2;
@@ -241,32 +270,30 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     const int r0 = team * 32;
     const int nchunk = 2 * nrb;
     const int half = lane >> 5, l32 = lane & 31;
-    const int nq = (nkb - w + 3) >> 2;  // K blocks w, w+4, ... below nkb
     if (threadIdx.x == 0) wg_abort = 0;
 
     v4i jr0[NKB], jr1[NKB];
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
-        if (kb < nkb) {
-            jr0[kb] = jpk[((size_t)(rb * 2 + 0) * nkb + kb) * 64 + lane];
-            jr1[kb] = jpk[((size_t)(rb * 2 + 1) * nkb + kb) * 64 + lane];
-        } else {
-            jr0[kb] = v4i{0, 0, 0, 0};
-            jr1[kb] = v4i{0, 0, 0, 0};
-        }
+        jr0[kb] = jpk[((size_t)(rb * 2 + 0) * NKB + kb) * 64 + lane];
+        jr1[kb] = jpk[((size_t)(rb * 2 + 1) * NKB + kb) * 64 + lane];
     }
+    const int one = 127;  // E8M0 block scale 2^0
 
-    // item v of an accumulator: replica r0 + 8(v/4) + 4(l/32) + v%4, row l%32 of the tile
-    float xs0[16], xs1[16], ys0[16], ys1[16], gdt[16];
+    // item v of an accumulator: replica r0 + 4(l/32) + rep_off(v), row l%32 of the tile,
+    // with rep_off(v) = 8(v/4) + v%4 a compile-time offset from one base per row
+    float xs0[16], xs1[16];
     const int row0 = rb * 64 + l32, row1 = row0 + 32;
+    const int rbase = r0 + 4 * half;
+    const size_t s0 = (size_t)row0 * Rpad + rbase, s1 = (size_t)row1 * Rpad + rbase;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-        const int rep = r0 + 8 * (v >> 2) + 4 * half + (v & 3);
-        gdt[v] = gamma[rep] * dt;
-        xs0[v] = row0 < N ? X[(size_t)row0 * Rpad + rep] : 0.0f;
-        ys0[v] = row0 < N ? Y[(size_t)row0 * Rpad + rep] : 0.0f;
-        xs1[v] = row1 < N ? X[(size_t)row1 * Rpad + rep] : 0.0f;
-        ys1[v] = row1 < N ? Y[(size_t)row1 * Rpad + rep] : 0.0f;
+        const int ro = 8 * (v >> 2) + (v & 3);
+        if (l32 == 0) gdt_lds[w][v][half] = gamma[rbase + ro] * dt;
+        xs0[v] = row0 < N ? X[s0 + ro] : 0.0f;
+        xs1[v] = row1 < N ? X[s1 + ro] : 0.0f;
+        y_lds[w][v][lane] = row0 < N ? Y[s0 + ro] : 0.0f;
+        y_lds[w][16 + v][lane] = row1 < N ? Y[s1 + ro] : 0.0f;
     }
 
     // publish the sign words of the state x_m (tag m); snapshot at samples
@@ -282,6 +309,7 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
             word = write_lanes4<rho, rho + 4, 32 + rho, 32 + rho + 4>(
                 word, (int)(uint32_t)b0, (int)(uint32_t)(b0 >> 32), (int)(uint32_t)b1,
                 (int)(uint32_t)(b1 >> 32));
+            __builtin_amdgcn_sched_barrier(0);  // one pair of ballots live at a time
         });
         const size_t slot = (size_t)(rb * 2 + half) * Rpad + r0 + l32;
         st_tagged(xb + (size_t)(m & 1) * nchunk * Rpad + slot,
@@ -296,30 +324,35 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
         const int buf = m & 1;
         // this wave's share: K block kb = w + 4q is chunk 2 kb + l/32
         const uint64_t *src = xb + ((size_t)buf * nchunk + 2 * w + half) * Rpad + r0 + l32;
+        const float p = m < g.seg_k1 ? ptab[m - g.seg_k0] : 0.0f;  // issued early
         uint64_t wv[NQ];
-        if (gather_words<NQ>(wv, src, (size_t)8 * Rpad, nq, (uint32_t)m, err)) {
+        if (gather_words<NQ>(wv, src, (size_t)8 * Rpad, NQ, (uint32_t)m, err)) {
 #pragma unroll
-            for (int q = 0; q < NQ; ++q)
-                if (q < nq) a_lds[buf][w + 4 * q][lane] = expand_signs((uint32_t)wv[q]);
+            for (int q = 0; q < NQ; ++q) a_lds[buf][w + 4 * q][lane] = expand_signs((uint32_t)wv[q]);
         } else {
             wg_abort = 1;
         }
         __syncthreads();
         if (wg_abort) break;
-        v16f acc0 = {}, acc1 = {};
+        v16f acc0, acc1;
+        // operand reads from LDS run kPre K blocks ahead of the products
+        constexpr int kPre = 4;
+        v4i af[kPre];
+#pragma unroll
+        for (int q = 0; q < kPre; ++q) af[q] = a_lds[buf][q][lane];
 #pragma unroll
         for (int kb = 0; kb < NKB; ++kb) {
-            if (kb < nkb) {
-                const v4i a4 = a_lds[buf][kb][lane];
-                const v8i a = {a4[0], a4[1], a4[2], a4[3], 0, 0, 0, 0};
-                const v8i b0 = {jr0[kb][0], jr0[kb][1], jr0[kb][2], jr0[kb][3], 0, 0, 0, 0};
-                const v8i b1 = {jr1[kb][0], jr1[kb][1], jr1[kb][2], jr1[kb][3], 0, 0, 0, 0};
-                acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b0, acc0, 4, 4, 0, 127,
-                                                                       0, 127);
-                acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b1, acc1, 4, 4, 0, 127,
-                                                                       0, 127);
+            const v4i a = af[kb % kPre];
+            if (kb + kPre < NKB) af[kb % kPre] = a_lds[buf][kb + kPre][lane];
+            if (kb == 0) {
+                mfma_fp4_first(acc0, a, jr0[0], one);
+                mfma_fp4_first(acc1, a, jr1[0], one);
+            } else {
+                mfma_fp4(acc0, a, jr0[kb], one);
+                mfma_fp4(acc1, a, jr1[kb], one);
             }
         }
+        mfma_drain(acc0, acc1);
         if (seg_is_sample(g, m)) {
             // eq. (1) partials: sum over this wave's rows of s_i f_i (exact integers/halves)
             const int j = seg_sample_index(g, m);
@@ -328,10 +361,10 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
                 float part = sgnf(xs0[v]) * acc0[v] + sgnf(xs1[v]) * acc1[v];
 #pragma unroll
                 for (int off = 16; off >= 1; off >>= 1) part += __shfl_xor(part, off);
-                const int rep = r0 + 8 * (v >> 2) + 4 * half + (v & 3);
+                const int rep = rbase + 8 * (v >> 2) + (v & 3);
                 if (l32 == 0) ep[((size_t)j * nrb + rb) * Rpad + rep] = part;
-                const bool fin = isfinite(xs0[v]) && isfinite(xs1[v]) && isfinite(ys0[v]) &&
-                                 isfinite(ys1[v]);
+                const bool fin = isfinite(xs0[v]) && isfinite(xs1[v]) &&
+                                 isfinite(y_lds[w][v][lane]) && isfinite(y_lds[w][16 + v][lane]);
                 if (!fin) {
                     bad[rep] = 1;
                     status[0] = 1;
@@ -339,24 +372,32 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
             }
         }
         if (m == g.seg_k1) break;
-        const float p = ptab[m - g.seg_k0];
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            sb_update(acc0[v], p, c0, dt, a0dt, gdt[v], xs0[v], ys0[v]);
-            sb_update(acc1[v], p, c0, dt, a0dt, gdt[v], xs1[v], ys1[v]);
+            const float gdt = gdt_lds[w][v][half];
+            float y0 = y_lds[w][v][lane], y1 = y_lds[w][16 + v][lane];
+            sb_update(acc0[v], p, c0, dt, a0dt, gdt, xs0[v], y0);
+            sb_update(acc1[v], p, c0, dt, a0dt, gdt, xs1[v], y1);
+            y_lds[w][v][lane] = y0;
+            y_lds[w][16 + v][lane] = y1;
         }
         publish(m + 1);
     }
+    // write the state back (addresses recomputed here, not kept live through the loop)
+    {
+        const size_t t0 = (size_t)(rb * 64 + l32) * Rpad + r0 + 4 * half;
+        const size_t t1 = t0 + (size_t)32 * Rpad;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int rep = r0 + 8 * (v >> 2) + 4 * half + (v & 3);
-        if (row0 < N) {
-            X[(size_t)row0 * Rpad + rep] = xs0[v];
-            Y[(size_t)row0 * Rpad + rep] = ys0[v];
-        }
-        if (row1 < N) {
-            X[(size_t)row1 * Rpad + rep] = xs1[v];
-            Y[(size_t)row1 * Rpad + rep] = ys1[v];
+        for (int v = 0; v < 16; ++v) {
+            const int ro = 8 * (v >> 2) + (v & 3);
+            if (row0 < N) {
+                X[t0 + ro] = xs0[v];
+                Y[t0 + ro] = y_lds[w][v][lane];
+            }
+            if (row1 < N) {
+                X[t1 + ro] = xs1[v];
+                Y[t1 + ro] = y_lds[w][16 + v][lane];
+            }
         }
     }
 }
@@ -403,10 +444,16 @@ const void *kernel_ptr() {
 }
 
 const void *pick_kernel(int nkb) {
-    if (nkb <= 4) return kernel_ptr<4>();
-    if (nkb <= 8) return kernel_ptr<8>();
-    if (nkb <= 16) return kernel_ptr<16>();
-    return kernel_ptr<32>();
+    switch (nkb) {
+    case 4: return kernel_ptr<4>();
+    case 8: return kernel_ptr<8>();
+    case 12: return kernel_ptr<12>();
+    case 16: return kernel_ptr<16>();
+    case 20: return kernel_ptr<20>();
+    case 24: return kernel_ptr<24>();
+    case 28: return kernel_ptr<28>();
+    default: return kernel_ptr<32>();
+    }
 }
 
 template <typename T>
