@@ -36,7 +36,6 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <type_traits>
 #include <vector>
 
 namespace hsb {
@@ -57,6 +56,9 @@ struct PersistentJ {
     float *ptab = nullptr;       // p_k = a0 - a(t_k) of the steps of one segment
     size_t ptab_elems = 0;
     int32_t *err = nullptr;      // [1] timeout flag
+    uint64_t *xslot = nullptr;   // [grid] (launch epoch, XCD id) per workgroup
+    size_t xslot_n = 0;
+    uint32_t epoch = 0;          // launches so far
     int waves_capacity = 0;
 };
 
@@ -83,50 +85,34 @@ __device__ __forceinline__ uint64_t ld_tagged(const uint64_t *p) {
 __device__ __forceinline__ void st_tagged(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for<I + 1, N>(f);
-    }
+// Store for a team whose workgroups all run on one XCD: the word only has to
+// reach that XCD's L2, where the readers' device-scope loads find it (about
+// half the round trip of a device-scope store, which writes through).
+__device__ __forceinline__ void st_tagged_xcd(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+// Id of the XCD (accelerator complex die) this wave runs on.
+__device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20); }
 
-// Replace lane L of `old` by the wave-uniform value `val`.
-// Write four wave-uniform values into lanes L0..L3 of `old`.  The leading
-// s_nop covers the wait states a v_writelane needs after a VALU write (here
-// the v_cmp of a ballot) of the SGPR it reads.
-template <int L0, int L1, int L2, int L3>
-__device__ __forceinline__ int write_lanes4(int old, int a, int b, int c, int d) {
-    asm("s_nop 4\n\t"
-        "v_writelane_b32 %0, %1, %5\n\t"
-        "v_writelane_b32 %0, %2, %6\n\t"
-        "v_writelane_b32 %0, %3, %7\n\t"
-        "v_writelane_b32 %0, %4, %8"
-        : "+v"(old)
-        : "s"(a), "s"(b), "s"(c), "s"(d), "n"(L0), "n"(L1), "n"(L2), "n"(L3));
-    return old;
-}
-
-// F^T tile update on the FP4 matrix cores: acc (VGPRs) += a (+-1 operand, VGPRs)
-// x b (J fragment, AGPRs), unit block scales.  Written as inline assembly so
-// that the loop-invariant J fragments stay in the accumulation registers
-// file for the whole kernel and feed the MFMA directly (the compiler would
-// otherwise copy them back to VGPRs before every use).  Hazards: exactly
-// overlapping srcC/vdst chains are interlocked by the hardware; the first
-// product of a step uses an inline zero for srcC; VALU reads of the result
-// wait behind mfma_drain().
-__device__ __forceinline__ void mfma_fp4_first(v16f &acc, const v4i &a, const v4i &b, int one) {
+// F tile update on the FP4 matrix cores: acc (VGPRs) += j (J fragment, AGPRs)
+// x b (+-1 operand, VGPRs), 32 rows x 32 replicas x 64 spins, unit block
+// scales.  Inline assembly keeps the loop-invariant J fragments in the
+// accumulation register file for the whole kernel, feeding the MFMA directly
+// (the compiler would otherwise copy them to VGPRs before every use).
+// Hazards: exactly overlapping srcC/vdst chains are interlocked by the
+// hardware; the first product of a step uses an inline zero for srcC; VALU
+// reads of the results wait behind mfma_drain().
+__device__ __forceinline__ void mfma_fp4_first(v16f &acc, const v4i &j, const v4i &b, int one) {
     asm volatile(
         "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, 0, %3, %3 op_sel_hi:[0,0,0] cbsz:4 blgp:4"
         : "=&v"(acc)
-        : "v"(a), "a"(b), "v"(one));
+        : "a"(j), "v"(b), "v"(one));
 }
-__device__ __forceinline__ void mfma_fp4(v16f &acc, const v4i &a, const v4i &b, int one) {
+__device__ __forceinline__ void mfma_fp4(v16f &acc, const v4i &j, const v4i &b, int one) {
     asm volatile(
         "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, %0, %3, %3 op_sel_hi:[0,0,0] cbsz:4 blgp:4"
         : "+v"(acc)
-        : "v"(a), "a"(b), "v"(one));
+        : "a"(j), "v"(b), "v"(one));
 }
 // 21 wait states: more than an XDL write needs before a VALU read of its vdst.
 __device__ __forceinline__ void mfma_drain(v16f &acc0, v16f &acc1) {
@@ -141,9 +127,20 @@ __device__ __forceinline__ uint32_t fp4_code(float v) {
     return m | (v < 0.0f ? 8u : 0u);
 }
 
+// Sign words.  The word of (replica, 32-row chunk) holds one bit per row, set
+// iff x < 0.  Its bit order follows the accumulator layout of the writer
+// (lane l holds rows 8j + 4(l/32) + i, j, i = 0..3, of replica l%32): bit
+// b < 16 is row 8(b/4) + b%4, bit b >= 16 is row 8((b-16)/4) + 4 + b%4.
+__host__ __device__ constexpr int word_bit_row(int b) {
+    return b < 16 ? 8 * (b >> 2) + (b & 3) : 8 * ((b - 16) >> 2) + 4 + (b & 3);
+}
+__host__ __device__ constexpr int row_word_bit(int t) {
+    return (t & 4) ? 16 + 4 * (t >> 3) + (t & 3) : 4 * (t >> 3) + (t & 3);
+}
+
 // Packing convention shared by both MFMA operands.  Within a 32-spin chunk,
-// nibble n of fragment dword q holds spin t = 4n + 3 - q.  With sign words
-// (bit t set iff spin t is negative) this makes the +-1 operand of a chunk
+// nibble n of fragment dword q holds the spin of word bit 4n + 3 - q.  The
+// +-1 operand of a chunk is then
 //   dword q = ((w << q) & 0x88888888) | 0x22222222
 // (0x2 = +1.0, 0xA = -1.0 in E2M1): seven integer operations per chunk.
 __device__ __forceinline__ v4i expand_signs(uint32_t w) {
@@ -156,7 +153,8 @@ __device__ __forceinline__ v4i expand_signs(uint32_t w) {
 }
 
 // J fragment for (row block rb, row tile rt, K block kb, lane): lane l holds
-// row 64 rb + 32 rt + l%32 and spins 64 kb + 32 (l/32) + t of the chunk.
+// row 64 rb + 32 rt + l%32 and the 32 spins of chunk 2 kb + l/32, in the order
+// of the packing convention.
 __global__ void k_pack_fp4(const float *__restrict__ J, v4i *__restrict__ jpk, int Npad, int nkb,
                            int nrb) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -172,7 +170,7 @@ __global__ void k_pack_fp4(const float *__restrict__ J, v4i *__restrict__ jpk, i
     for (int q = 0; q < 4; ++q) {
         uint32_t d = 0;
         for (int n = 0; n < 8; ++n)
-            d |= fp4_code(J[(size_t)row * Npad + base + 4 * n + 3 - q]) << (4 * n);
+            d |= fp4_code(J[(size_t)row * Npad + base + word_bit_row(4 * n + 3 - q)]) << (4 * n);
         out[q] = (int)d;
     }
     jpk[e] = out;
@@ -198,39 +196,25 @@ __device__ __forceinline__ int seg_sample_index(const SegArgs &g, int m) {
 }
 
 // Gather, for state m, the tagged sign words of the K blocks this wave
-// expands (its share: every W-th block), wv[q] holding block w + W q.  All
-// words are loaded together; while some are stale the wave polls the first
-// stale one alone (cheap) and, once it has arrived, reloads every stale word
-// in one batch -- writers finish at nearly the same time, so this costs about
-// one memory round trip after the last writer instead of one per word.
-// Returns false on timeout (4 s) or when another wave has flagged an error.
+// expands (its share: every 4th block), wv[q] holding block w + 4q.  All
+// words are loaded together and every stale one is reloaded together until
+// all carry tag m, so the wait costs about one round trip after the last
+// writer.  Returns false on timeout (4 s) or when another wave has flagged an
+// error.
 template <int NQ>
 __device__ __forceinline__ bool gather_words(uint64_t (&wv)[NQ], const uint64_t *src,
                                              size_t stride, int nq, uint32_t m, int32_t *err) {
-    uint32_t stale = 0;  // bit q: some lane's word q is stale
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
         if (q < nq) wv[q] = ld_tagged(src + q * stride);
+    uint32_t stale = 0;  // bit q: some lane's word q is stale
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
         if (q < nq && __any((uint32_t)(wv[q] >> 32) != m)) stale |= 1u << q;
     if (stale == 0) return true;
     const uint64_t t0 = wall_clock64();
     for (int it = 1;; ++it) {
-        const uint64_t *p = src + __builtin_ctz(stale) * stride;
-        uint64_t v = ld_tagged(p);
-        while (__any((uint32_t)(v >> 32) != m)) {
-            __builtin_amdgcn_s_sleep(1);
-            v = ld_tagged(p);
-            if ((++it & 31) == 0) {
-                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-                    return false;
-                if (wall_clock64() - t0 > kTimeoutTicks) {
-                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    return false;
-                }
-            }
-        }
+        __builtin_amdgcn_s_sleep(1);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
             if ((stale >> q) & 1u) wv[q] = ld_tagged(src + q * stride);
@@ -240,6 +224,14 @@ __device__ __forceinline__ bool gather_words(uint64_t (&wv)[NQ], const uint64_t 
             if (((stale >> q) & 1u) && __any((uint32_t)(wv[q] >> 32) != m)) still |= 1u << q;
         stale = still;
         if (stale == 0) return true;
+        if ((it & 31) == 0) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                return false;
+            if (wall_clock64() - t0 > kTimeoutTicks) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+        }
     }
 }
 
@@ -247,30 +239,58 @@ __device__ __forceinline__ bool gather_words(uint64_t (&wv)[NQ], const uint64_t 
 // waves need the same +-1 operand (the team's signs).  Each step every wave
 // gathers and expands a quarter of the K blocks into LDS (ping-pong by step
 // parity), one workgroup barrier publishes them, and each wave then runs its
-// MFMAs with the operand from LDS and its J rows from registers.
+// MFMAs with its J rows from registers and the operand from LDS, followed by
+// the fused update of its 64 rows x 32 replicas.
 template <int NKB>
 __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     const v4i *__restrict__ jpk, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, uint64_t *xb, uint32_t *__restrict__ snap,
     float *__restrict__ ep, const float *__restrict__ ptab, int32_t *__restrict__ bad,
-    int32_t *__restrict__ status, int32_t *err, int N, int nkb, int nrb, int Rpad, int team0,
-    int nteams, SegArgs g, float c0, float dt, float a0dt) {
+    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, uint32_t epoch, int N, int nkb,
+    int nrb, int Rpad, int team0, int nteams, SegArgs g, float c0, float dt, float a0dt) {
     static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
     constexpr int NQ = NKB / 4;  // K blocks expanded by each wave
     __shared__ v4i a_lds[2][NKB][64];
-    // y and gamma*dt live in LDS (each read once per step), keeping registers for J
-    __shared__ float y_lds[4][32][64];
-    __shared__ float gdt_lds[4][16][2];
     __shared__ int wg_abort;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wgs_per_team = nrb >> 2;
-    if ((int)blockIdx.x / wgs_per_team >= nteams) return;  // whole workgroup
-    const int team = team0 + blockIdx.x / wgs_per_team;
-    const int rb = (blockIdx.x % wgs_per_team) * 4 + w;
+    // Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
+    // b % 8).  All workgroups of a team are placed on one XCD so that the sign
+    // words they exchange every step stay in that XCD's L2: team t uses the
+    // blocks b = 8 (wpt (t / 8) + k) + t % 8, k = 0 .. wpt-1.  (Correctness does
+    // not depend on the placement; only the exchange latency does.)
+    const int wpt = nrb >> 2;  // workgroups per team
+    const int xcd = blockIdx.x & 7, kx = blockIdx.x >> 3;
+    const int tl = (kx / wpt) * 8 + xcd;  // team within this launch
+    if (tl >= nteams) return;             // whole workgroup
+    const int team = team0 + tl;
+    const int rb = (kx % wpt) * 4 + w;
     const int r0 = team * 32;
     const int nchunk = 2 * nrb;
     const int half = lane >> 5, l32 = lane & 31;
     if (threadIdx.x == 0) wg_abort = 0;
+
+    // Are all workgroups of this team on one XCD?  Each records (launch epoch,
+    // XCD id) in its slot; lane k reads member k's slot.  Only then may the team
+    // publish with XCD-scoped stores (readers always load at device scope, and
+    // the step tags reject any stale word whatever the placement).
+    const int my_xcc = xcc_id();
+    if (threadIdx.x == 0) st_tagged(xslot + blockIdx.x, ((uint64_t)epoch << 32) | (uint32_t)my_xcc);
+    bool xcd_local;
+    {
+        const int mb = 8 * (wpt * (tl >> 3) + (lane < wpt ? lane : 0)) + (tl & 7);
+        uint64_t v = ld_tagged(xslot + mb);
+        const uint64_t t0 = wall_clock64();
+        bool ok = true;
+        while (__any((uint32_t)(v >> 32) != epoch)) {
+            __builtin_amdgcn_s_sleep(1);
+            v = ld_tagged(xslot + mb);
+            if (wall_clock64() - t0 > kTimeoutTicks) {
+                ok = false;
+                break;
+            }
+        }
+        xcd_local = ok && __all((int)(uint32_t)v == my_xcc);
+    }
 
     v4i jr0[NKB], jr1[NKB];
 #pragma unroll
@@ -280,42 +300,42 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     }
     const int one = 127;  // E8M0 block scale 2^0
 
-    // item v of an accumulator: replica r0 + 4(l/32) + rep_off(v), row l%32 of the tile,
-    // with rep_off(v) = 8(v/4) + v%4 a compile-time offset from one base per row
-    float xs0[16], xs1[16];
-    const int row0 = rb * 64 + l32, row1 = row0 + 32;
-    const int rbase = r0 + 4 * half;
-    const size_t s0 = (size_t)row0 * Rpad + rbase, s1 = (size_t)row1 * Rpad + rbase;
+    // item v of tile rt: replica r0 + l%32, row 64 rb + 32 rt + 8(v/4) + 4(l/32) + v%4
+    float xs0[16], xs1[16], ys0[16], ys1[16];
+    const int rep = r0 + l32;
+    const float gdt = gamma[rep] * dt;
+    const int rowb = rb * 64 + 4 * half;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-        const int ro = 8 * (v >> 2) + (v & 3);
-        if (l32 == 0) gdt_lds[w][v][half] = gamma[rbase + ro] * dt;
-        xs0[v] = row0 < N ? X[s0 + ro] : 0.0f;
-        xs1[v] = row1 < N ? X[s1 + ro] : 0.0f;
-        y_lds[w][v][lane] = row0 < N ? Y[s0 + ro] : 0.0f;
-        y_lds[w][16 + v][lane] = row1 < N ? Y[s1 + ro] : 0.0f;
+        const int row0 = rowb + 8 * (v >> 2) + (v & 3), row1 = row0 + 32;
+        // + 0.0f turns a caller's -0.0 into +0.0, so that the sign bit of x is its
+        // sgn (sgn(0) = +1); the update never produces -0.0 from a non-negative zero
+        xs0[v] = row0 < N ? X[(size_t)row0 * Rpad + rep] + 0.0f : 0.0f;
+        xs1[v] = row1 < N ? X[(size_t)row1 * Rpad + rep] + 0.0f : 0.0f;
+        ys0[v] = row0 < N ? Y[(size_t)row0 * Rpad + rep] : 0.0f;
+        ys1[v] = row1 < N ? Y[(size_t)row1 * Rpad + rep] : 0.0f;
     }
 
-    // publish the sign words of the state x_m (tag m); snapshot at samples
+    // publish the sign words of the state x_m (tag m); snapshot at samples.
+    // Lane l holds 16 rows of each tile for replica l%32: its bits form half a
+    // word, and lanes l, l+32 swap the halves they do not store.
     auto publish = [&](int m) {
-        // ballot of item v: bits 0-31 are rows 0-31 of replica rho = 8(v/4) + v%4,
-        // bits 32-63 those of replica rho + 4; lane 32 rt + rho stores word (rt, rho)
-        int word = 0;
-        static_for<0, 16>([&](auto vc) {
-            constexpr int v = decltype(vc)::value;
-            constexpr int rho = 8 * (v >> 2) + (v & 3);
-            const uint64_t b0 = __ballot(!(xs0[v] >= 0.0f));
-            const uint64_t b1 = __ballot(!(xs1[v] >= 0.0f));
-            word = write_lanes4<rho, rho + 4, 32 + rho, 32 + rho + 4>(
-                word, (int)(uint32_t)b0, (int)(uint32_t)(b0 >> 32), (int)(uint32_t)b1,
-                (int)(uint32_t)(b1 >> 32));
-            __builtin_amdgcn_sched_barrier(0);  // one pair of ballots live at a time
-        });
-        const size_t slot = (size_t)(rb * 2 + half) * Rpad + r0 + l32;
-        st_tagged(xb + (size_t)(m & 1) * nchunk * Rpad + slot,
-                  ((uint64_t)(uint32_t)m << 32) | (uint32_t)word);
+        uint32_t b0 = 0, b1 = 0;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            b0 |= (__float_as_uint(xs0[v]) >> 31) << v;
+            b1 |= (__float_as_uint(xs1[v]) >> 31) << v;
+        }
+        const uint32_t got = (uint32_t)__shfl_xor((int)(half ? b0 : b1), 32);
+        const uint32_t word = half ? (got | (b1 << 16)) : (b0 | (got << 16));
+        const size_t slot = (size_t)(rb * 2 + half) * Rpad + rep;
+        const uint64_t tagged = ((uint64_t)(uint32_t)m << 32) | word;
+        if (xcd_local)
+            st_tagged_xcd(xb + (size_t)(m & 1) * nchunk * Rpad + slot, tagged);
+        else
+            st_tagged(xb + (size_t)(m & 1) * nchunk * Rpad + slot, tagged);
         if (seg_is_sample(g, m))
-            snap[(size_t)seg_sample_index(g, m) * nchunk * Rpad + slot] = (uint32_t)word;
+            snap[(size_t)seg_sample_index(g, m) * nchunk * Rpad + slot] = word;
     };
 
     publish(g.seg_k0);
@@ -345,59 +365,51 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
             const v4i a = af[kb % kPre];
             if (kb + kPre < NKB) af[kb % kPre] = a_lds[buf][kb + kPre][lane];
             if (kb == 0) {
-                mfma_fp4_first(acc0, a, jr0[0], one);
-                mfma_fp4_first(acc1, a, jr1[0], one);
+                mfma_fp4_first(acc0, jr0[0], a, one);
+                mfma_fp4_first(acc1, jr1[0], a, one);
             } else {
-                mfma_fp4(acc0, a, jr0[kb], one);
-                mfma_fp4(acc1, a, jr1[kb], one);
+                mfma_fp4(acc0, jr0[kb], a, one);
+                mfma_fp4(acc1, jr1[kb], a, one);
             }
         }
         mfma_drain(acc0, acc1);
         if (seg_is_sample(g, m)) {
-            // eq. (1) partials: sum over this wave's rows of s_i f_i (exact integers/halves)
+            // eq. (1) partial over this wave's 64 rows of s_i f_i (exact integers/halves)
             const int j = seg_sample_index(g, m);
+            float part = 0.0f;
+            bool fin = true;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                float part = sgnf(xs0[v]) * acc0[v] + sgnf(xs1[v]) * acc1[v];
-#pragma unroll
-                for (int off = 16; off >= 1; off >>= 1) part += __shfl_xor(part, off);
-                const int rep = rbase + 8 * (v >> 2) + (v & 3);
-                if (l32 == 0) ep[((size_t)j * nrb + rb) * Rpad + rep] = part;
-                const bool fin = isfinite(xs0[v]) && isfinite(xs1[v]) &&
-                                 isfinite(y_lds[w][v][lane]) && isfinite(y_lds[w][16 + v][lane]);
-                if (!fin) {
-                    bad[rep] = 1;
-                    status[0] = 1;
-                }
+                part += sgnf(xs0[v]) * acc0[v] + sgnf(xs1[v]) * acc1[v];
+                fin = fin && isfinite(xs0[v]) && isfinite(xs1[v]) && isfinite(ys0[v]) &&
+                      isfinite(ys1[v]);
+            }
+            part += __shfl_xor(part, 32);
+            if (half == 0) ep[((size_t)j * nrb + rb) * Rpad + rep] = part;
+            if (!fin) {
+                bad[rep] = 1;
+                status[0] = 1;
             }
         }
         if (m == g.seg_k1) break;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const float gdt = gdt_lds[w][v][half];
-            float y0 = y_lds[w][v][lane], y1 = y_lds[w][16 + v][lane];
-            sb_update(acc0[v], p, c0, dt, a0dt, gdt, xs0[v], y0);
-            sb_update(acc1[v], p, c0, dt, a0dt, gdt, xs1[v], y1);
-            y_lds[w][v][lane] = y0;
-            y_lds[w][16 + v][lane] = y1;
+            sb_update(acc0[v], p, c0, dt, a0dt, gdt, xs0[v], ys0[v]);
+            sb_update(acc1[v], p, c0, dt, a0dt, gdt, xs1[v], ys1[v]);
         }
         publish(m + 1);
     }
-    // write the state back (addresses recomputed here, not kept live through the loop)
-    {
-        const size_t t0 = (size_t)(rb * 64 + l32) * Rpad + r0 + 4 * half;
-        const size_t t1 = t0 + (size_t)32 * Rpad;
+    // write the state back
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int ro = 8 * (v >> 2) + (v & 3);
-            if (row0 < N) {
-                X[t0 + ro] = xs0[v];
-                Y[t0 + ro] = y_lds[w][v][lane];
-            }
-            if (row1 < N) {
-                X[t1 + ro] = xs1[v];
-                Y[t1 + ro] = y_lds[w][16 + v][lane];
-            }
+    for (int v = 0; v < 16; ++v) {
+        const int row0 = rowb + 8 * (v >> 2) + (v & 3), row1 = row0 + 32;
+        if (row0 < N) {
+            X[(size_t)row0 * Rpad + rep] = xs0[v];
+            Y[(size_t)row0 * Rpad + rep] = ys0[v];
+        }
+        if (row1 < N) {
+            X[(size_t)row1 * Rpad + rep] = xs1[v];
+            Y[(size_t)row1 * Rpad + rep] = ys1[v];
         }
     }
 }
@@ -429,7 +441,7 @@ __global__ void k_fp4_best(const float *__restrict__ ep, const uint32_t *__restr
         best_step[r] = bj < g.nmult ? (g.seg_k0 / g.interval + 1 + bj) * g.interval : g.final_k;
         for (int i = 0; i < N; ++i) {
             const uint32_t w = snap[((size_t)bj * nchunk + (i >> 5)) * Rpad + r];
-            best_s[(size_t)i * Rpad + r] = ((w >> (i & 31)) & 1u) ? -1 : 1;
+            best_s[(size_t)i * Rpad + r] = ((w >> row_word_bit(i & 31)) & 1u) ? -1 : 1;
         }
     }
 }
@@ -520,7 +532,7 @@ int persistent_create(const float *J, int N, PersistentJ **out) {
 
 void persistent_free(PersistentJ *pj) {
     if (!pj) return;
-    void *ptrs[] = {pj->jpk, pj->xb, pj->snap, pj->ep, pj->ptab, pj->err};
+    void *ptrs[] = {pj->jpk, pj->xb, pj->snap, pj->ep, pj->ptab, pj->err, pj->xslot};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete pj;
@@ -530,7 +542,13 @@ int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int 
                    KernelTimer &timer) {
     const int Rpad = run.Rpad, nrb = pj->nrb, nkb = pj->nkb, nchunk = 2 * nrb;
     const int nteams_total = Rpad / 32;
-    const int teams_per_launch = pj->waves_capacity / nrb;
+    // teams per launch: a multiple of 8 (one slot per XCD) whose workgroups all
+    // fit on the device at once
+    const int wg_capacity = pj->waves_capacity / 4, wpt = nrb / 4;
+    const int teams_per_launch = 8 * (wg_capacity / (8 * wpt));
+    if (teams_per_launch < 8)
+        return perr(HSB_EUNSUPPORTED, "FP4 path: %d resident workgroups < 8 teams of %d",
+                    wg_capacity, wpt);
     const int interval = run.interval;
     // samples per launch bounded by a 512 MiB snapshot budget (and 4096)
     const size_t snap_per_sample = (size_t)nchunk * Rpad;
@@ -545,6 +563,14 @@ int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int 
                                     ? (run.k1 - run.k0)
                                     : max_seg_steps);
     if (!rc) rc = grow(&pj->ptab, &pj->ptab_elems, (size_t)(ptab_need > 0 ? ptab_need : 1));
+    if (!rc && pj->xslot_n < (size_t)wg_capacity + 8 * (size_t)wpt) {
+        rc = grow(&pj->xslot, &pj->xslot_n, (size_t)wg_capacity + 8 * (size_t)wpt);
+        if (!rc) {  // epoch 0xFFFFFFFF in every slot: never a launch's epoch
+            hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((pj->xslot_n + 255) / 256)), dim3(256), 0,
+                               s, pj->xslot, pj->xslot_n);
+            if (hipGetLastError() != hipSuccess) rc = perr(HSB_EDEVICE, "xslot fill failed");
+        }
+    }
     if (rc) return rc;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, pj->err);
     hipError_t e = hipGetLastError();
@@ -579,16 +605,19 @@ int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int 
             const size_t nxb = (size_t)2 * nchunk * Rpad;
             hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((nxb + 255) / 256)), dim3(256), 0, s,
                                pj->xb, nxb);
-            const dim3 grid((unsigned)(nt * (nrb / 4))), block(256);
+            // block b -> team (b/8)/wpt*8 + b%8: round the team count up to 8
+            const dim3 grid((unsigned)(8 * ((nt + 7) / 8) * (nrb / 4))), block(256);
             float c0 = run.c0, dt = run.dt, a0dtv = a0dt;
             int N_v = N, nkb_v = nkb, nrb_v = nrb, Rpad_v = Rpad, t0_v = t0, nt_v = nt;
+            uint32_t epoch = ++pj->epoch;
+            if (epoch == 0) epoch = ++pj->epoch;  // slots start zeroed: epoch 0 is never used
             const float *gam = run.gamma;
-            void *args[] = {(void *)&pj->jpk, (void *)&run.X,    (void *)&run.Y,   (void *)&gam,
-                            (void *)&pj->xb,  (void *)&pj->snap, (void *)&pj->ep,  (void *)&pj->ptab,
-                            (void *)&b.bad,   (void *)&b.status, (void *)&pj->err, (void *)&N_v,
-                            (void *)&nkb_v,   (void *)&nrb_v,    (void *)&Rpad_v,  (void *)&t0_v,
-                            (void *)&nt_v,    (void *)&g,        (void *)&c0,      (void *)&dt,
-                            (void *)&a0dtv};
+            void *args[] = {(void *)&pj->jpk,   (void *)&run.X,    (void *)&run.Y,   (void *)&gam,
+                            (void *)&pj->xb,    (void *)&pj->snap, (void *)&pj->ep,  (void *)&pj->ptab,
+                            (void *)&b.bad,     (void *)&b.status, (void *)&pj->err, (void *)&pj->xslot,
+                            (void *)&epoch,     (void *)&N_v,      (void *)&nkb_v,   (void *)&nrb_v,
+                            (void *)&Rpad_v,    (void *)&t0_v,     (void *)&nt_v,    (void *)&g,
+                            (void *)&c0,        (void *)&dt,       (void *)&a0dtv};
             // every workgroup of the grid is resident at once: the grid never exceeds
             // the occupancy-derived capacity, and every wait inside the kernel is
             // bounded, so a wave that cannot make progress ends the launch cleanly
