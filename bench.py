@@ -34,6 +34,29 @@ FP4_PEAK_TFLOPS = 10100.0   # MI355X dense FP4/FP6 matrix peak
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 matrix peak
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        src = os.path.join(ROOT, kv["source_file"])
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != kv["source_sha256"]:
+                return None
+        return float(kv["traffic_bytes_per_dispatch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -50,11 +73,14 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-replicas", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain FP32 copy of MIB MiB (read once, written once) three "
+                         "times: the reference dispatch for scaling HBM byte counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(replica sharding across GPUs is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (replicas are "
+              "independent, so several GPUs would each run a share of R)", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -64,6 +90,17 @@ def main() -> int:
     from paper_2203_08361_amd import hsb, metrics
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 4 * n, "kernel": "neg (FP32 elementwise)",
+                          "read_bytes": 4 * n, "write_bytes": 4 * n}), flush=True)
+        return 0
     N, R, Ns = N_SPINS, REPLICAS, args.sb_steps
     c0 = 0.5 / math.sqrt(N)
     variant = hsb.HSB_DSB if args.variant == "dsb" else hsb.HSB_BSB
@@ -105,9 +142,11 @@ def main() -> int:
     avg_launch_ms = kern_ms / max(kern_launches, 1)
     achieved = flops_per_run / launches_per_run / (avg_launch_ms * 1e-3) / 1e12
     peak = FP4_PEAK_TFLOPS if plan == "mixed" else FP32_PEAK_TFLOPS
+    kname = "k_dsb_fp4" if plan == "mixed" else "k_step_fp32"
+    traffic = measured_traffic(kname, f"N{N}_R{R}") if Ns == SB_STEPS else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 5), "traffic": None,
-                "kernel": "k_dsb_fp4" if plan == "mixed" else "k_step_fp32",
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 5), "traffic": traffic,
+                "kernel": kname,
                 "avg_launch_ms": round(avg_launch_ms, 4),
                 "launches_per_run": launches_per_run}
 

@@ -415,34 +415,60 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
 }
 
 // Energies of the segment's samples, best-sample update and its spins.
-__global__ void k_fp4_best(const float *__restrict__ ep, const uint32_t *__restrict__ snap, int ns,
-                           int nrb, int N, int R, int Rpad, SegArgs g, double *__restrict__ best_e,
-                           double *__restrict__ last_e, int32_t *__restrict__ best_step,
-                           const int32_t *__restrict__ bad, int8_t *__restrict__ best_s) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
+// Grid Rpad/32, 256 threads: lane group g = threadIdx.x / 32 scans samples
+// j = g, g + 8, ... of 32 replicas; the groups' minima are merged with the
+// earliest sample winning ties, then the winning sample's sign words are
+// decoded into best_s.  Every partial is a multiple of 1/2 below 2^23 in
+// magnitude, so the FP64 totals are exact in any order.
+__global__ __launch_bounds__(256) void k_fp4_best(
+    const float *__restrict__ ep, const uint32_t *__restrict__ snap, int ns, int nrb, int N, int R,
+    int Rpad, SegArgs g, double *__restrict__ best_e, double *__restrict__ last_e,
+    int32_t *__restrict__ best_step, const int32_t *__restrict__ bad, int8_t *__restrict__ best_s) {
+    __shared__ double s_e[8][32];
+    __shared__ int s_j[8][32];
+    const int rl = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int r = blockIdx.x * 32 + rl;
     const int nchunk = 2 * nrb;
-    double best = best_e[r], last = 0.0;
-    int bj = -1;
-    for (int j = 0; j < ns; ++j) {
-        double e = 0.0;
-        for (int b = 0; b < nrb; ++b) e += (double)ep[((size_t)j * nrb + b) * Rpad + r];
-        e = -0.5 * e;
-        last = e;
-        if (e < best) {
-            best = e;
-            bj = j;
+    double emin = __builtin_huge_val();
+    int jmin = -1;
+    if (r < R) {
+        for (int j = grp; j < ns; j += 8) {
+            double e = 0.0;
+            for (int b = 0; b < nrb; ++b) e += (double)ep[((size_t)j * nrb + b) * Rpad + r];
+            e = -0.5 * e;
+            if (j == ns - 1) last_e[r] = bad[r] ? __builtin_nan("") : e;
+            if (e < emin) {
+                emin = e;
+                jmin = j;
+            }
         }
     }
-    if (bad[r]) last = __builtin_nan("");
-    if (ns > 0) last_e[r] = last;
-    if (bj >= 0 && !bad[r]) {
-        best_e[r] = best;
-        best_step[r] = bj < g.nmult ? (g.seg_k0 / g.interval + 1 + bj) * g.interval : g.final_k;
-        for (int i = 0; i < N; ++i) {
-            const uint32_t w = snap[((size_t)bj * nchunk + (i >> 5)) * Rpad + r];
-            best_s[(size_t)i * Rpad + r] = ((w >> row_word_bit(i & 31)) & 1u) ? -1 : 1;
+    s_e[grp][rl] = emin;
+    s_j[grp][rl] = jmin;
+    __syncthreads();
+    if (grp == 0) {
+        for (int q = 1; q < 8; ++q) {
+            const double e = s_e[q][rl];
+            const int j = s_j[q][rl];
+            if (j >= 0 && (e < emin || (e == emin && j < jmin))) {
+                emin = e;
+                jmin = j;
+            }
         }
+        const bool take = r < R && jmin >= 0 && !bad[r] && emin < best_e[r];
+        if (take) {
+            best_e[r] = emin;
+            best_step[r] = jmin < g.nmult ? (g.seg_k0 / g.interval + 1 + jmin) * g.interval
+                                          : g.final_k;
+        }
+        s_j[0][rl] = take ? jmin : -1;
+    }
+    __syncthreads();
+    const int bj = s_j[0][rl];
+    if (r >= R || bj < 0) return;
+    for (int i = grp; i < N; i += 8) {
+        const uint32_t w = snap[((size_t)bj * nchunk + (i >> 5)) * Rpad + r];
+        best_s[(size_t)i * Rpad + r] = ((w >> row_word_bit(i & 31)) & 1u) ? -1 : 1;
     }
 }
 
@@ -627,9 +653,9 @@ int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int 
             if (e != hipSuccess)
                 return perr(HSB_EDEVICE, "FP4 persistent launch: %s", hipGetErrorString(e));
         }
-        hipLaunchKernelGGL(k_fp4_best, dim3((run.R + 63) / 64), dim3(64), 0, s, pj->ep, pj->snap,
-                           ns, nrb, N, run.R, Rpad, g, b.best_e, b.last_e, b.best_step, b.bad,
-                           b.best_s);
+        hipLaunchKernelGGL(k_fp4_best, dim3((unsigned)((run.R + 31) / 32)), dim3(256), 0, s,
+                           pj->ep, pj->snap, ns, nrb, N, run.R, Rpad, g, b.best_e, b.last_e,
+                           b.best_step, b.bad, b.best_s);
         e = hipGetLastError();
         if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
         if (e_k >= run.k1) break;
