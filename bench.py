@@ -12,6 +12,8 @@ per instance, outside it).
 Reported next to it:
   - the same run on the plain FP32 plan (the baseline form) and the
     time-to-target of both plans at the same target energy;
+  - the ballistic variant (bSB) on the same instance, mixed (integer-digit)
+    plan against FP32;
   - the roofline of the dominant kernel (FP4 MFMA field + fused update),
     its launch duration measured with HIP events on the run's stream;
   - the CPU oracle timed on a bounded sample of the same workload.
@@ -30,8 +32,13 @@ sys.path.insert(0, ROOT)
 
 N_SPINS, REPLICAS, SB_STEPS = 2000, 1024, 10000
 GAMMA, DT, A0 = 0.01, 1.0, 1.0
-FP4_PEAK_TFLOPS = 10100.0   # MI355X dense FP4/FP6 matrix peak
-FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 matrix peak
+# MI355X dense matrix-core peaks (TFLOP/s; TOP/s for int8)
+KERNELS = {"fp4": ("k_dsb_fp4", 10100.0, "fp4"),
+           "digits": ("k_i8_field", 5000.0, "int8"),
+           "fp32": ("k_step_fp32", 157.3, "fp32")}
+DTYPES = {"fp4": "fp4 x fp4 -> fp32 field (exact), fp32 state",
+          "digits": "int8 digits -> int32 field (exactly rounded), fp32 state",
+          "fp32": "fp32"}
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -71,6 +78,8 @@ def main() -> int:
     ap.add_argument("--plan", choices=["mixed", "fp32", "auto"], default="mixed")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-plan comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bsb", action="store_true",
+                    help="skip the ballistic-variant comparison of the default dSB run")
     ap.add_argument("--cpu-replicas", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -107,92 +116,99 @@ def main() -> int:
     J = synth.sk_instance(N, 2000)
     log(f"instance N={N} built; creating context")
     ctx = hsb.Context(J, precision=args.plan, init_amp=0.1, energy_interval=100)
-    plan = ctx.plan(variant)
 
-    def one_run(seed, timing=False):
-        ctx.set_option("timing", 1 if timing else 0)
-        out = ctx.run_ex(variant, Ns, R, A0, c0, DT, GAMMA, seed)
-        ms = ctx.get_option("kernel_ms") if timing else 0.0
-        nl = int(ctx.get_option("kernel_launches")) if timing else 0
-        return out, ms, nl
+    def measure(var, steps, warmup):
+        """Timed whole runs (no per-launch events), then one run with HIP-event
+        timing of the dominant kernel for the roofline."""
+        def run(seed):
+            return ctx.run_ex(var, Ns, R, A0, c0, DT, GAMMA, seed)
 
-    for w in range(args.warmup):
-        one_run(100 + w)
-        log(f"warmup {w + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    best = []
-    kern_ms, kern_launches = 0.0, 0
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        out, ms, nl = one_run(1 + i, timing=True)
-        kern_ms += ms
-        kern_launches += nl
-        best.append(out["best_energy"])
-        log(f"timed run {i + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_run = 1e3 * elapsed / args.steps
-    value = N * R * Ns / (elapsed / args.steps)
-    best_np = torch.stack(best).cpu().numpy()
-
-    # roofline of the dominant kernel: algorithmic work = (Ns + 1) fields of 2 N^2 R flops
-    # per run (Ns steps plus the field of the final sampled state)
-    flops_per_run = 2.0 * N * N * R * (Ns + 1)
-    launches_per_run = kern_launches / args.steps
-    avg_launch_ms = kern_ms / max(kern_launches, 1)
-    achieved = flops_per_run / launches_per_run / (avg_launch_ms * 1e-3) / 1e12
-    peak = FP4_PEAK_TFLOPS if plan == "mixed" else FP32_PEAK_TFLOPS
-    kname = "k_dsb_fp4" if plan == "mixed" else "k_step_fp32"
-    traffic = measured_traffic(kname, f"N{N}_R{R}") if Ns == SB_STEPS else None
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+        ctx.set_option("timing", 0)
+        for w in range(warmup):
+            run(100 + w)
+            log(f"warmup {w + 1}/{warmup} done")
+        torch.cuda.synchronize()
+        best = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            best.append(run(1 + i)["best_energy"])
+            log(f"timed run {i + 1}/{steps} done")
+        torch.cuda.synchronize()
+        ms_run = 1e3 * (time.perf_counter() - t0) / steps
+        plan_kind = ctx.last_plan()
+        ctx.set_option("timing", 1)
+        run(1)
+        kern_ms = ctx.get_option("kernel_ms")
+        launches = int(ctx.get_option("kernel_launches"))
+        ctx.set_option("timing", 0)
+        # algorithmic work of the timed kernel launches: 2 N^2 R flops per field;
+        # the persistent FP4 kernel also forms the field of the final sampled state
+        fields = Ns + 1 if plan_kind == "fp4" else Ns
+        flops = 2.0 * N * N * R * fields
+        avg_ms = kern_ms / max(launches, 1)
+        achieved = flops / (kern_ms * 1e-3) / 1e12
+        kname, peak, peak_dtype = KERNELS[plan_kind]
+        traffic = measured_traffic(kname, f"N{N}_R{R}") if Ns == SB_STEPS else None
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 5), "traffic": traffic,
-                "kernel": kname,
-                "avg_launch_ms": round(avg_launch_ms, 4),
-                "launches_per_run": launches_per_run}
+                "kernel": kname, "peak_dtype": peak_dtype, "avg_launch_ms": round(avg_ms, 5),
+                "launches_per_run": launches}
+        if plan_kind == "digits":
+            # int8 operations issued per algorithmic flop: one per x digit
+            roof["issued_per_algorithmic"] = 4 if var == hsb.HSB_BSB else 1
+        return {"ms_per_run": ms_run, "value": N * R * Ns / (ms_run * 1e-3), "plan": plan_kind,
+                "best": torch.stack(best).cpu().numpy(), "roofline": roof}
 
+    def fp32_compare(var, mixed):
+        """The same run on the FP32 plan (the baseline form) and time-to-target."""
+        ctx.set_option("precision", "fp32")
+        f = measure(var, 1, 0)
+        ctx.set_option("precision", args.plan)
+        best_np = mixed["best"]
+        e_star = float(min(best_np.min(), f["best"].min()))
+        tt = {}
+        for name, target in (("E_best", e_star), ("E_best+0.5%", e_star + 0.005 * abs(e_star))):
+            P = metrics.success_probability(best_np.ravel(), target)
+            P32 = metrics.success_probability(f["best"].ravel(), target)
+            S, S32 = metrics.step_to_solution(P, Ns), metrics.step_to_solution(P32, Ns)
+            tt[name] = {"target": target, "P": P,
+                        "P_ci95": metrics.wilson_interval(int(round(P * best_np.size)),
+                                                          best_np.size),
+                        "P_fp32": P32, "step_to_solution": S, "step_to_solution_fp32": S32,
+                        "tts_s_mixed": S * mixed["ms_per_run"] / 1e3 / Ns,
+                        "tts_s_fp32": S32 * f["ms_per_run"] / 1e3 / Ns}
+        same = bool(np.array_equal(f["best"][0], best_np[0]))
+        log(f"fp32 plan run: {f['ms_per_run']:.1f} ms")
+        return ({"value": f["value"], "ms_per_run": f["ms_per_run"],
+                 "speedup_mixed": f["ms_per_run"] / mixed["ms_per_run"],
+                 "identical_energies": same,
+                 "fp32_frac_of_peak": f["roofline"]["frac"]}, tt)
+
+    main_res = measure(variant, args.steps, args.warmup)
+    plan = main_res["plan"]
     result = {
         "metric": "spin-updates/s (N·R·steps/s) at N=2000,R=1024; mixed-prec vs FP32 "
                   "time-to-target",
-        "value": value, "unit": "spin-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_run, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp4xfp4->f32 field, f32 state" if plan == "mixed" else "f32",
-        "data": "synthetic",
+        "value": main_res["value"], "unit": "spin-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_res["ms_per_run"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPES[plan], "data": "synthetic",
         "config": {"workload": f"SK +-1 N={N}, R={R}, {Ns} steps, heated "
                                f"{args.variant} gamma={GAMMA}, dt={DT}, {plan} plan",
                    "N": N, "R": R, "sb_steps": Ns, "variant": args.variant, "plan": plan,
                    "gamma": GAMMA, "dt": DT, "c0": c0, "energy_interval": 100},
-        "roofline": roofline,
+        "roofline": main_res["roofline"],
     }
-
-    # same run on the FP32 plan and time-to-target at the pooled best energy
-    if not args.no_fp32 and plan == "mixed":
-        ctx.set_option("precision", "fp32")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        out32, ms32, nl32 = one_run(1, timing=True)
-        torch.cuda.synchronize()
-        ms_run32 = 1e3 * (time.perf_counter() - t1)
-        ctx.set_option("precision", args.plan)
-        same = bool(torch.equal(out32["best_energy"], best[0]))
-        e_star = float(best_np.min())
-        tt = {}
-        for name, target in (("E_best", e_star), ("E_best+0.5%", e_star + 0.005 * abs(e_star))):
-            P = metrics.success_probability(best_np.ravel(), target)
-            S = metrics.step_to_solution(P, Ns)
-            tt[name] = {"target": target, "P": P,
-                        "P_ci95": metrics.wilson_interval(int(round(P * best_np.size)),
-                                                          best_np.size),
-                        "step_to_solution": S,
-                        "tts_s_mixed": S * ms_per_run / 1e3 / Ns,
-                        "tts_s_fp32": S * ms_run32 / 1e3 / Ns}
-        result["fp32_plan"] = {"value": N * R * Ns / (ms_run32 / 1e3), "ms_per_run": ms_run32,
-                               "kernel_ms": ms32, "speedup_mixed": ms_run32 / ms_per_run,
-                               "identical_energies": same,
-                               "fp32_frac_of_peak": round(flops_per_run / (ms32 * 1e-3) / 1e12
-                                                          / FP32_PEAK_TFLOPS, 4)}
-        result["time_to_target"] = tt
-        log(f"fp32 plan run: {ms_run32:.1f} ms")
+    if not args.no_fp32 and plan != "fp32":
+        result["fp32_plan"], result["time_to_target"] = fp32_compare(variant, main_res)
+    if args.variant == "dsb" and not args.no_bsb:
+        # the ballistic variant on the same instance: mixed (digit) plan vs FP32
+        b = measure(hsb.HSB_BSB, 2, 1)
+        bsb = {"value": b["value"], "ms_per_run": b["ms_per_run"], "plan": b["plan"],
+               "dtype": DTYPES[b["plan"]], "roofline": b["roofline"]}
+        if not args.no_fp32 and b["plan"] != "fp32":
+            bsb["fp32_plan"], bsb["time_to_target"] = fp32_compare(hsb.HSB_BSB, b)
+        result["bsb"] = bsb
 
     if not args.no_cpu_baseline:
         import oracle

@@ -36,8 +36,9 @@
  *   - Precision: the state x, y is single precision (Methods, last sentence).
  *     For dSB with integer-valued J the field is an exact integer, so the
  *     trajectory is bitwise the same whichever plan runs it.  For bSB the
- *     field is rounded differently by each plan (FP32 products or split
- *     BF16 products); see hsb_set_option(HSB_OPT_PRECISION).
+ *     field is rounded differently by each plan (FP32 sums of FP32 products,
+ *     or the exactly rounded sum of the integer-digit plan); see
+ *     hsb_set_option(HSB_OPT_PRECISION).
  *   - Thread safety: one context may be used by one thread at a time.
  */
 #ifndef HSB_H
@@ -79,16 +80,35 @@ typedef enum {
                                     run's stream; default 0 */
     HSB_OPT_KERNEL_MS = 5,       /* read only: summed event time (ms) of those launches in
                                     the last run with timing on (synchronises the events) */
-    HSB_OPT_KERNEL_LAUNCHES = 6  /* read only: number of those launches in that run */
+    HSB_OPT_KERNEL_LAUNCHES = 6, /* read only: number of those launches in that run */
+    HSB_OPT_LAST_PLAN = 7        /* read only: plan of the last successful run, an hsb_plan */
 } hsb_option;
 
 typedef enum {
-    HSB_PREC_AUTO = 0,  /* dSB on J exact in FP4 (entries in {0, +-0.5, +-1, +-1.5, +-2, +-3,
-                           +-4, +-6}) and N <= 2048: FP4 field; otherwise FP32 */
+    HSB_PREC_AUTO = 0,  /* the FP4 plan where MIXED takes it; the digit plan for bSB and
+                           for dSB with integer J in [-127, 127]; FP32 otherwise */
     HSB_PREC_FP32 = 1,  /* plain FP32 field products (the baseline form) */
-    HSB_PREC_MIXED = 2  /* dSB: FP4 operands with FP32 accumulation (exact);
-                           bSB: split BF16 products x = x_hi + x_lo, J_hi + J_lo */
+    HSB_PREC_MIXED = 2  /* dSB with J exact in FP4 (entries in {0, +-0.5, +-1, +-1.5, +-2,
+                           +-3, +-4, +-6}) and N <= 2048: FP4 operands, FP32 accumulation
+                           (exact); otherwise, N <= 16384: the integer-digit plan */
 } hsb_precision;
+
+/*
+ * Execution plans (HSB_OPT_LAST_PLAN).  The field of eqs. (4)/(5) is
+ *   HSB_PLAN_FP32    FP32 matrix-core products, one launch per step;
+ *   HSB_PLAN_FP4     dSB only: FP4 x FP4 products, every step in one
+ *                    persistent launch; exact;
+ *   HSB_PLAN_DIGITS  int8 products of digits, one launch per step:
+ *                    x = rint(x 2^30) 2^-30 as four base-256 digits (exact for
+ *                    |x| >= 2^-6), sgn(x) as one digit, J as one digit when every
+ *                    entry is an integer in [-127, 127] (then the field is the
+ *                    exactly rounded FP32 value of sum_j J_ij x_j) or as four
+ *                    digits of a per-row power-of-two scaled J (real J: relative
+ *                    error about 2^-31 per entry).  bSB on this plan needs
+ *                    |x| <= 1 in the start state (eqs. (18)-(21) keep it so):
+ *                    otherwise MIXED returns HSB_EUNSUPPORTED and AUTO runs FP32.
+ */
+typedef enum { HSB_PLAN_FP32 = 0, HSB_PLAN_FP4 = 1, HSB_PLAN_DIGITS = 2 } hsb_plan;
 
 /*
  * hsb_create -- validate J and build its device copies (the J store).

@@ -1,0 +1,52 @@
+// Integer-digit field plan (host interface).
+//
+// The field of eqs. (4)/(5) is evaluated as an exact integer product on the
+// int8 matrix cores (v_mfma_i32_32x32x32_i8):
+//   x  -> q = rint(x 2^30), written as balanced base-256 digits
+//         q = d0 2^24 + d1 2^16 + d2 2^8 + d3 (d1..d3 in [-128, 127], d0 in
+//         [-64, 64]); for |x| >= 2^-6 this is x itself, otherwise x to within
+//         2^-31 (|x| <= 1 always holds after a step, eqs. (18)-(21));
+//   sgn(x) -> one digit +-1 (dSB);
+//   J  -> one digit when every entry is an integer in [-127, 127] (exact), else
+//         a per-row power-of-two scale s_i and four digits of rint(J_ij/s_i 2^30).
+// The products of digit pairs (a, b) with a + b <= 3 are summed in int32 per
+// weight a + b, combined exactly in FP64 and rounded once to FP32.  For
+// integer J the field is therefore fl32(sum_j J_ij q_j 2^-30) exactly.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace hsb {
+
+struct I8J;  // device J digit store and per-run digit buffers
+
+// Spins are padded to a multiple of this for the digit plan.
+constexpr int kI8SpinTile = 256;
+
+// Build the digit store of J (host N x N, row-major).  Returns an hsb_status.
+int i8_create(const float *hJ, int N, I8J **out);
+void i8_free(I8J *p);
+const char *i8_error();
+bool i8_exact(const I8J *p);  // J held exactly (one digit)
+int i8_max_n();
+
+struct I8Run {
+    int variant;          // HSB_BSB / HSB_DSB
+    int N, Nst, Rpad;     // spins, state rows (multiple of 64), padded replicas
+    int R;
+    int k0, k1, Ns, interval;
+    float a0, c0, dt;
+};
+
+// Whether every x of the state X ([n] FP32) satisfies |x| <= 1 (synchronises s).
+int i8_start_state_ok(I8J *p, const float *X, size_t n, hipStream_t s, bool *ok);
+
+// Run steps k0..k1-1 of the digit plan on the state in `b` (X, Y in
+// [Nst][Rpad]); samples energies at the sample points (as the FP32 plan).
+// `fp32J` is the FP32 J store ([Nst][Nst]) used for FP64 energies of real J.
+int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream_t s,
+           KernelTimer &timer);
+
+}  // namespace hsb

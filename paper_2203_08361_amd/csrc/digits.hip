@@ -1,0 +1,508 @@
+// Integer-digit field plan: the field of eqs. (4)/(5) as an exact integer
+// product on the int8 matrix cores, one launch per time step with the update
+// of eqs. (16)-(22) fused into its epilogue.
+//
+// Digits (see digits.h): x -> four balanced base-256 digits of rint(x 2^30),
+// sgn(x) -> one digit, J -> one digit (integer J) or four digits of a per-row
+// power-of-two scaled rint(J_ij / s_i 2^30).  Digit pairs (a, b) with
+// a + b <= 3 are multiplied; each weight w = a + b has its own int32
+// accumulator (exact), and the weights are combined exactly in FP64:
+//   T = sum_w 2^(8 (NW-1-w)) U_w,   f = fl32(T * rowscale_i * xscale).
+//
+// Layouts (16-spin K blocks, 16 bytes per record):
+//   J digits  jd[a][Npad/16][Npad][16]   record (kb, row) = J[row][16 kb .. 16 kb + 15]
+//   x digits  xd[b][Npad/16][Rpad][16]   record (kb, r)   = digit b of x[16 kb ..][r]
+// so every MFMA operand fragment (16 consecutive K of one row or one replica)
+// is one 16-byte load, and 32 lanes read 512 contiguous bytes.
+//
+// Work decomposition of one step: a workgroup (4 waves) computes the field of
+// 256 spins x 32 replicas; wave w owns spins [64 w, 64 w + 64) of the tile as
+// two 32 x 32 MFMA tiles.  The x digits of the 32 replicas are shared by the
+// four waves and staged through LDS (double-buffered, one barrier per stage);
+// each wave streams its own J rows from L2 straight into registers, one stage
+// ahead.  v_mfma_i32_32x32x32_i8 operand layout (lane l, half h = l / 32):
+//   A: A[l % 32][16 h .. 16 h + 15]   B: B[16 h .. 16 h + 15][l % 32]
+//   D: item v of lane l is D[8 (v / 4) + 4 h + v % 4][l % 32]
+#include "digits.h"
+#include "hsb.h"
+#include "hsb_device.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+namespace hsb {
+
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+struct I8J {
+    int N = 0, Npad = 0, njd = 1;
+    v4i *jd = nullptr;           // [njd][Npad/16][Npad] records
+    double *rowscale = nullptr;  // [Npad]: 1 (one digit) or s_i 2^-30
+    int8_t *xd = nullptr;        // [2][4][Npad/16][Rpad][16] digit ping-pong
+    size_t xd_bytes = 0;
+    int8_t *sd = nullptr;        // [Npad/16][Rpad][16] sign digits of sampled states
+    size_t sd_bytes = 0;
+    int32_t *flag = nullptr;     // start-state bound check
+};
+
+namespace {
+thread_local char d_err[256] = "";
+int derr(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(d_err, sizeof(d_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+constexpr int kMaxN = 16384;  // int32 digit sums stay below 2^31 for four-digit J
+}  // namespace
+
+const char *i8_error() { return d_err; }
+bool i8_exact(const I8J *p) { return p->njd == 1; }
+int i8_max_n() { return kMaxN; }
+
+// ----------------------------------------------------------------- device
+
+// Balanced base-256 digits of |q| <= 2^30: d3, d2, d1 in [-128, 127], d0 in [-64, 64].
+__device__ __forceinline__ void split4(int q, int (&d)[4]) {
+#pragma unroll
+    for (int b = 3; b > 0; --b) {
+        const int lo = (int)(int8_t)(q & 0xFF);
+        d[b] = lo;
+        q = (q - lo) >> 8;
+    }
+    d[0] = q;
+}
+
+__device__ __forceinline__ int x_fixed(float x) { return (int)rintf(x * 0x1p30f); }
+
+// Digits of the state X ([Nst][Rpad] FP32) into `nsets` consecutive digit
+// buffers.  Grid (Rpad / 64, Npad / 16), 64 threads: thread = replica.
+template <int NXD>
+__global__ __launch_bounds__(64) void k_i8_digits(const float *__restrict__ X,
+                                                  int8_t *__restrict__ xd, int Nst, int Npad,
+                                                  int Rpad, int nsets) {
+    const int r = blockIdx.x * 64 + threadIdx.x;
+    const int kb = blockIdx.y, nkb = Npad / 16;
+    uint32_t w[NXD][4];
+#pragma unroll
+    for (int b = 0; b < NXD; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[b][q] = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = kb * 16 + e;
+        if (i < Nst) {
+            const float x = X[(size_t)i * Rpad + r];
+            if (NXD == 1) {
+                w[0][e >> 2] |= (uint32_t)(uint8_t)(x >= 0.0f ? 1 : -1) << (8 * (e & 3));
+            } else {
+                int d[4];
+                split4(x_fixed(x), d);
+#pragma unroll
+                for (int b = 0; b < NXD; ++b)
+                    w[b][e >> 2] |= (uint32_t)(uint8_t)d[b] << (8 * (e & 3));
+            }
+        }
+    }
+    const size_t set = (size_t)NXD * nkb * Rpad;
+    for (int s = 0; s < nsets; ++s)
+#pragma unroll
+        for (int b = 0; b < NXD; ++b) {
+            v4i rec = {(int)w[b][0], (int)w[b][1], (int)w[b][2], (int)w[b][3]};
+            reinterpret_cast<v4i *>(xd)[s * set + ((size_t)b * nkb + kb) * Rpad + r] = rec;
+        }
+}
+
+__global__ void k_i8_clear_flag(int32_t *flag) { *flag = 0; }
+
+// 1 in *flag if any |x| > 1 or x is not finite (the digit plan's premise).
+__global__ void k_i8_bound(const float *__restrict__ X, size_t n, int32_t *flag) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float x = X[e];
+    if (!(fabsf(x) <= 1.0f)) atomicOr(flag, 1);
+}
+
+// One time step (ENERGY = false) or the energy partials of the current state
+// (ENERGY = true, sign digits, one-digit J).  Grid (Npad / 256, Rpad / 32).
+template <int NJD, int NXD, int KC, bool ENERGY>
+__global__ __launch_bounds__(256) void k_i8_field(
+    const v4i *__restrict__ jd, const double *__restrict__ rowscale, const v4i *__restrict__ xin,
+    int8_t *__restrict__ xout, float *__restrict__ X, float *__restrict__ Y,
+    const float *__restrict__ gam, double *__restrict__ epart, int Nst, int Npad, int Rpad,
+    float p, float c0, float dt, float a0dt) {
+    constexpr int NW = (NJD + NXD - 1) < 4 ? (NJD + NXD - 1) : 4;  // accumulated weights
+    constexpr int KB = 2 * KC;                                       // K blocks per stage
+    constexpr int BTOT = NXD * KB * 32;                              // B records per stage
+    constexpr int BPT = (BTOT + 255) / 256;                          // per thread
+    // x digits are 2^-30 units, sign digits units; truncating weights > 3 of a
+    // four-digit J shifts the combined sum by 2^24
+    constexpr double kXs = NXD == 4 ? 0x1p-30 : 1.0;
+    constexpr double kTrunc = (NJD + NXD - 1 - NW) == 3 ? 0x1p24 : 1.0;
+    __shared__ v4i bs[2][NXD][KB][32];
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, l32 = lane & 31;
+    // XCD-aware tile order: block L runs on XCD L % 8; each XCD takes a
+    // contiguous range of tiles in replica-major order, so the x digits of its
+    // replicas stay in its L2 across the spin blocks
+    const int gx = gridDim.x, T = gx * gridDim.y;
+    const int L = blockIdx.x + gx * blockIdx.y;
+    const int tile = (T & 7) == 0 ? (L & 7) * (T >> 3) + (L >> 3) : L;
+    const int sb = tile % gx, rb = tile / gx;
+    const int i0 = sb * 256 + w * 64, r0 = rb * 32;
+    const int nkb = Npad / 16;
+    const int S = Npad / (32 * KC);  // stages (even: Npad is a multiple of 256)
+
+    v16i acc[2][NW];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int q = 0; q < NW; ++q) acc[tt][q] = v16i{};
+
+    v4i a0r[2][NJD][KC], a1r[2][NJD][KC];
+    v4i breg[BPT];
+
+    auto loadA = [&](int s, v4i(&dst)[2][NJD][KC]) {
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+            for (int a = 0; a < NJD; ++a)
+#pragma unroll
+                for (int c = 0; c < KC; ++c)
+                    dst[tt][a][c] =
+                        jd[((size_t)a * nkb + s * KB + 2 * c + h) * Npad + i0 + tt * 32 + l32];
+    };
+    auto loadB = [&](int s) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int e = t + 256 * q;
+            if (BTOT % 256 == 0 || e < BTOT) {
+                const int b = e / (KB * 32), kb = (e / 32) % KB, r = e % 32;
+                breg[q] = xin[((size_t)b * nkb + s * KB + kb) * Rpad + r0 + r];
+            }
+        }
+    };
+    auto storeB = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int e = t + 256 * q;
+            if (BTOT % 256 == 0 || e < BTOT) {
+                const int b = e / (KB * 32), kb = (e / 32) % KB, r = e % 32;
+                bs[buf][b][kb][r] = breg[q];
+            }
+        }
+    };
+    auto compute = [&](int buf, const v4i(&A)[2][NJD][KC]) {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            v4i bf[NXD];
+#pragma unroll
+            for (int b = 0; b < NXD; ++b) bf[b] = bs[buf][b][2 * c + h][l32];
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+                for (int a = 0; a < NJD; ++a)
+#pragma unroll
+                    for (int b = 0; b < NXD; ++b)
+                        if (a + b < NW)
+                            acc[tt][a + b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                A[tt][a][c], bf[b], acc[tt][a + b], 0, 0, 0);
+        }
+    };
+
+    loadB(0);
+    storeB(0);
+    loadA(0, a0r);
+    __syncthreads();
+    for (int s = 0; s < S; s += 2) {
+        // stage s: operands in a0r / LDS buffer 0; prefetch stage s + 1
+        loadA(s + 1, a1r);
+        loadB(s + 1);
+        compute(0, a0r);
+        storeB(1);
+        __syncthreads();
+        // stage s + 1: a1r / buffer 1; prefetch stage s + 2
+        const bool more = s + 2 < S;
+        if (more) {
+            loadA(s + 2, a0r);
+            loadB(s + 2);
+        }
+        compute(1, a1r);
+        if (more) storeB(0);
+        __syncthreads();
+    }
+
+    const int r = r0 + l32;
+    if (ENERGY) {
+        // eq. (1): partial sum_i s_i f_i over this wave's 64 spins, exact in int32
+        int part = 0;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            const int ib = i0 + tt * 32;
+            if (ib >= Nst) continue;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = ib + 8 * (v >> 2) + 4 * h + (v & 3);
+                const int f = acc[tt][0][v];
+                part += X[(size_t)i * Rpad + r] >= 0.0f ? f : -f;
+            }
+        }
+        part += __shfl_xor(part, 32);
+        if (h == 0 && i0 < Nst) epart[(size_t)(i0 / 64) * Rpad + r] = (double)part;
+        return;
+    }
+
+    // every load of the tile's state is issued before the first store, so the
+    // 64 loads per lane overlap instead of each waiting behind a store
+    if (i0 >= Nst) return;  // Nst is a multiple of 64: a wave's rows are wholly in or out
+    const float gdt = gam[r] * dt;
+    float xs[2][16], ys[2][16];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const size_t idx = (size_t)(i0 + tt * 32 + 8 * (v >> 2) + 4 * h + (v & 3)) * Rpad + r;
+            xs[tt][v] = X[idx];
+            ys[tt][v] = Y[idx];
+        }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        const int ib = i0 + tt * 32;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            uint32_t dw[NXD];
+#pragma unroll
+            for (int b = 0; b < NXD; ++b) dw[b] = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int v = 4 * m + u;
+                const int i = ib + 8 * m + 4 * h + u;
+                double Tsum = (double)acc[tt][0][v];
+#pragma unroll
+                for (int q = 1; q < NW; ++q) Tsum = Tsum * 256.0 + (double)acc[tt][q][v];
+                const double sc = (NJD == 1 ? 1.0 : rowscale[i]) * (kXs * kTrunc);
+                const float f = (float)(Tsum * sc);
+                float &x = xs[tt][v], &y = ys[tt][v];
+                sb_update(f, p, c0, dt, a0dt, gdt, x, y);
+                if (NXD == 1) {
+                    dw[0] |= (uint32_t)(uint8_t)(x >= 0.0f ? 1 : -1) << (8 * u);
+                } else {
+                    int d[4];
+                    split4(x_fixed(x), d);
+#pragma unroll
+                    for (int b = 0; b < NXD; ++b) dw[b] |= (uint32_t)(uint8_t)d[b] << (8 * u);
+                }
+            }
+            const int ig = ib + 8 * m + 4 * h;  // first of the 4 consecutive spins
+#pragma unroll
+            for (int b = 0; b < NXD; ++b)
+                *reinterpret_cast<uint32_t *>(
+                    xout + (((size_t)b * nkb + (ig >> 4)) * Rpad + r) * 16 + (ig & 15)) = dw[b];
+        }
+    }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const size_t idx = (size_t)(i0 + tt * 32 + 8 * (v >> 2) + 4 * h + (v & 3)) * Rpad + r;
+            X[idx] = xs[tt][v];
+            Y[idx] = ys[tt][v];
+        }
+}
+
+// ------------------------------------------------------------------- host
+
+namespace {
+
+template <typename T>
+int grow(T **p, size_t *cap, size_t n) {
+    if (n <= *cap) return HSB_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e != hipSuccess)
+        return derr(e == hipErrorOutOfMemory ? HSB_ENOMEM : HSB_EDEVICE, "digit buffers: %s",
+                    hipGetErrorString(e));
+    *cap = n;
+    return HSB_OK;
+}
+
+// host balanced base-256 digits of |q| <= 2^30
+void split4_host(long long q, int d[4]) {
+    for (int b = 3; b > 0; --b) {
+        const int lo = (int)(int8_t)(uint8_t)(q & 0xFF);
+        d[b] = lo;
+        q = (q - lo) / 256;
+    }
+    d[0] = (int)q;
+}
+
+template <int NJD, int NXD, int KC, bool ENERGY>
+hipError_t launch_field(const I8J *p, const int8_t *xin, int8_t *xout, StateBufs &b, int Nst,
+                        int Rpad, float pk, float c0, float dt, float a0dt, hipStream_t s) {
+    const dim3 grid(p->Npad / 256, Rpad / 32);
+    hipLaunchKernelGGL((k_i8_field<NJD, NXD, KC, ENERGY>), grid, dim3(256), 0, s, p->jd,
+                       p->rowscale, reinterpret_cast<const v4i *>(xin), xout, b.X, b.Y, b.gamma,
+                       b.epart, Nst, p->Npad, Rpad, pk, c0, dt, a0dt);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int i8_create(const float *hJ, int N, I8J **out) {
+    *out = nullptr;
+    if (N < 1 || N > kMaxN) return derr(HSB_EUNSUPPORTED, "digit plan: N must be <= %d", kMaxN);
+    I8J *p = new (std::nothrow) I8J;
+    if (!p) return derr(HSB_ENOMEM, "digit plan: host allocation");
+    p->N = N;
+    p->Npad = (N + kI8SpinTile - 1) / kI8SpinTile * kI8SpinTile;
+    const int Np = p->Npad, nkb = Np / 16;
+    bool exact = true;
+    for (size_t e = 0; e < (size_t)N * N && exact; ++e) {
+        const float v = hJ[e];
+        exact = v == std::nearbyint(v) && std::fabs(v) <= 127.0f;
+    }
+    p->njd = exact ? 1 : 4;
+    const size_t rec = (size_t)p->njd * nkb * Np;  // 16-byte records
+    std::vector<int8_t> jd(rec * 16, 0);
+    std::vector<double> rs(Np, 1.0);
+    for (int i = 0; i < N; ++i) {
+        double sc = 1.0;
+        if (!exact) {
+            double m = 0.0;
+            for (int j = 0; j < N; ++j) m = std::fmax(m, std::fabs((double)hJ[(size_t)i * N + j]));
+            int ex = 0;
+            if (m > 0.0) (void)std::frexp(m, &ex);  // m < 2^ex
+            sc = std::ldexp(1.0, ex);
+            rs[i] = std::ldexp(sc, -30);
+        }
+        for (int j = 0; j < N; ++j) {
+            const double v = hJ[(size_t)i * N + j];
+            const size_t off = (((size_t)(j / 16)) * Np + i) * 16 + (j % 16);
+            if (exact) {
+                jd[off] = (int8_t)v;
+            } else {
+                int d[4];
+                split4_host((long long)std::nearbyint(std::ldexp(v / sc, 30)), d);
+                for (int a = 0; a < 4; ++a) jd[(size_t)a * nkb * Np * 16 + off] = (int8_t)d[a];
+            }
+        }
+    }
+    hipError_t e = hipMalloc((void **)&p->jd, rec * 16);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->rowscale, sizeof(double) * Np);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->flag, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpy(p->jd, jd.data(), rec * 16, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->rowscale, rs.data(), sizeof(double) * Np, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        i8_free(p);
+        return derr(e == hipErrorOutOfMemory ? HSB_ENOMEM : HSB_EDEVICE, "digit J store: %s",
+                    hipGetErrorString(e));
+    }
+    *out = p;
+    return HSB_OK;
+}
+
+void i8_free(I8J *p) {
+    if (!p) return;
+    void *ptrs[] = {p->jd, p->rowscale, p->xd, p->sd, p->flag};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+int i8_start_state_ok(I8J *p, const float *X, size_t n, hipStream_t s, bool *ok) {
+    hipLaunchKernelGGL(k_i8_clear_flag, dim3(1), dim3(1), 0, s, p->flag);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_i8_bound, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n,
+                           p->flag);
+        e = hipGetLastError();
+    }
+    int32_t f = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&f, p->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return derr(HSB_EDEVICE, "start-state check: %s", hipGetErrorString(e));
+    *ok = f == 0;
+    return HSB_OK;
+}
+
+int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream_t s,
+           KernelTimer &timer) {
+    const int Np = p->Npad, nkb = Np / 16, Rpad = run.Rpad, Nst = run.Nst;
+    const bool bsb = run.variant == HSB_BSB;
+    const int nxd = bsb ? 4 : 1;
+    int rc = grow(&p->xd, &p->xd_bytes, (size_t)2 * nxd * nkb * Rpad * 16);
+    if (!rc) rc = grow(&p->sd, &p->sd_bytes, (size_t)nkb * Rpad * 16);
+    if (rc) return rc;
+    // the caller has checked the premise of the x digits: |x| <= 1 in the start state
+    hipError_t e = hipSuccess;
+    const dim3 dgrid(Rpad / 64, nkb);
+    if (bsb)
+        hipLaunchKernelGGL(k_i8_digits<4>, dgrid, dim3(64), 0, s, b.X, p->xd, Nst, Np, Rpad, 2);
+    else
+        hipLaunchKernelGGL(k_i8_digits<1>, dgrid, dim3(64), 0, s, b.X, p->xd, Nst, Np, Rpad, 2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return derr(HSB_EDEVICE, "%s", hipGetErrorString(e));
+
+    const size_t set = (size_t)nxd * nkb * Rpad * 16;
+    const float a0 = run.a0, c0 = run.c0, dt = run.dt, a0dt = a0 * dt;
+    const int k0 = run.k0, k1 = run.k1, interval = run.interval;
+    auto is_sample = [&](int m) { return m == k1 || (m > k0 && m % interval == 0); };
+    auto sample = [&](int m) -> int {
+        hipError_t ee;
+        int nblk;
+        if (p->njd == 1) {
+            hipLaunchKernelGGL(k_i8_digits<1>, dgrid, dim3(64), 0, s, b.X, p->sd, Nst, Np, Rpad,
+                               1);
+            ee = hipGetLastError();
+            if (ee == hipSuccess)
+                ee = launch_field<1, 1, 4, true>(p, p->sd, nullptr, b, Nst, Rpad, 0.f, 0.f, 0.f,
+                                                 0.f, s);
+            nblk = Nst / 64;
+        } else {
+            ee = launch_energy_f64(fp32J, b.X, b.epart, Nst, Rpad, s);
+            nblk = Nst / 64;
+        }
+        if (ee == hipSuccess) ee = launch_best(b, nblk, run.N, run.R, Rpad, m, s);
+        if (ee != hipSuccess) return derr(HSB_EDEVICE, "%s", hipGetErrorString(ee));
+        return HSB_OK;
+    };
+    if (k1 == k0) return sample(k0);
+    int cur = 0;
+    for (int k = k0; k < k1; ++k) {
+        // a(t_k) = a0 k / Ns in single precision; p = a0 - a(t_k)
+        const float ak = (a0 * (float)k) / (float)run.Ns;
+        const float pk = a0 - ak;
+        const int8_t *xin = p->xd + cur * set;
+        int8_t *xout = p->xd + (cur ^ 1) * set;
+        e = timer.begin(s);
+        if (e == hipSuccess) {
+            if (p->njd == 1)
+                e = bsb ? launch_field<1, 4, 4, false>(p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                       a0dt, s)
+                        : launch_field<1, 1, 4, false>(p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                       a0dt, s);
+            else
+                e = bsb ? launch_field<4, 4, 2, false>(p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                       a0dt, s)
+                        : launch_field<4, 1, 2, false>(p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                       a0dt, s);
+        }
+        if (e == hipSuccess) e = timer.end(s);
+        if (e != hipSuccess) return derr(HSB_EDEVICE, "digit step: %s", hipGetErrorString(e));
+        cur ^= 1;
+        if (is_sample(k + 1)) {
+            rc = sample(k + 1);
+            if (rc) return rc;
+        }
+    }
+    return HSB_OK;
+}
+
+}  // namespace hsb

@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "digits.h"
 #include "hsb.h"
 #include "kernels.h"
 #include "persistent.h"
@@ -52,7 +53,9 @@ struct hsb_ctx {
     float *dJ = nullptr;        // FP32 J, [Npad][Npad], zero padded
     bool j_int_exact = false;   // integer J with small row sums: FP32 fields exact
     bool j_fp4_exact = false;   // every entry representable in FP4 (E2M1)
+    bool j_i8_exact = false;    // every entry an integer in [-127, 127]
     hsb::PersistentJ *pj = nullptr;  // FP4 J store for the persistent dSB path (lazy)
+    hsb::I8J *i8 = nullptr;          // integer-digit J store (lazy)
     std::vector<float> hJ;      // host copy kept for lazy device re-layouts
     // options
     double init_amp = 0.1;
@@ -60,6 +63,7 @@ struct hsb_ctx {
     int return_best = 1;
     int precision = HSB_PREC_AUTO;
     int timing = 0;
+    int last_plan = -1;
     hsb::KernelTimer timer;
     // workspace
     int Rpad_cap = 0;
@@ -125,7 +129,7 @@ extern "C" int hsb_create(const float *J, int N, hsb_ctx **out) {
     *out = nullptr;
     if (!J) return fail(HSB_EINVAL, "hsb_create: J is NULL");
     if (N < 1 || N > 32768) return fail(HSB_EINVAL, "hsb_create: N=%d outside [1, 32768]", N);
-    bool is_int = true, is_fp4 = true;
+    bool is_int = true, is_fp4 = true, is_i8 = true;
     double max_row = 0.0;
     for (int i = 0; i < N; ++i) {
         double row = 0.0;
@@ -138,6 +142,7 @@ extern "C" int hsb_create(const float *J, int N, hsb_ctx **out) {
                 return fail(HSB_EINVAL, "hsb_create: J[%d][%d] = %g, diagonal must be 0", i, i, v);
             if (v != std::nearbyint(v)) is_int = false;
             if (!fp4_exact(v)) is_fp4 = false;
+            if (v != std::nearbyint(v) || std::fabs(v) > 127.0f) is_i8 = false;
             row += std::fabs((double)v);
         }
         if (row > max_row) max_row = row;
@@ -160,6 +165,7 @@ extern "C" int hsb_create(const float *J, int N, hsb_ctx **out) {
     // integer products/sums stay below 2^24 in FP32 (32-row partial energies included)
     h->j_int_exact = is_int && max_row * 32.0 < 16777216.0;
     h->j_fp4_exact = is_fp4;
+    h->j_i8_exact = is_i8;
     const size_t np = (size_t)h->Npad;
     std::vector<float> padded(np * np, 0.0f);
     for (int i = 0; i < N; ++i)
@@ -187,6 +193,7 @@ extern "C" void hsb_destroy(hsb_ctx *h) {
     if (h->d_spins) (void)hipFree(h->d_spins);
     if (h->d_energy) (void)hipFree(h->d_energy);
     if (h->pj) hsb::persistent_free(h->pj);
+    if (h->i8) hsb::i8_free(h->i8);
     h->timer.release();
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -220,6 +227,7 @@ extern "C" int hsb_set_option(hsb_ctx *h, int key, double v) {
         return HSB_OK;
     case HSB_OPT_KERNEL_MS:
     case HSB_OPT_KERNEL_LAUNCHES:
+    case HSB_OPT_LAST_PLAN:
         return fail(HSB_EINVAL, "option %d is read only", key);
     default:
         return fail(HSB_EINVAL, "unknown option key %d", key);
@@ -242,26 +250,43 @@ extern "C" int hsb_get_option(hsb_ctx *h, int key, double *v) {
         return HSB_OK;
     }
     case HSB_OPT_KERNEL_LAUNCHES: *v = (double)h->timer.used; return HSB_OK;
+    case HSB_OPT_LAST_PLAN: *v = h->last_plan; return HSB_OK;
     default: return fail(HSB_EINVAL, "unknown option key %d", key);
     }
 }
 
 namespace {
 
-// Which plan runs (variant, this J, the precision option).  Returns HSB_OK and
-// sets *plan to HSB_PREC_FP32 or HSB_PREC_MIXED, or HSB_EUNSUPPORTED.
+// Execution plans (hsb_plan); the precision reported for both mixed plans is
+// HSB_PREC_MIXED.
+enum Plan { PLAN_FP32 = HSB_PLAN_FP32, PLAN_FP4 = HSB_PLAN_FP4, PLAN_DIGITS = HSB_PLAN_DIGITS };
+
+// Which plan runs (variant, this J, the precision option), or HSB_EUNSUPPORTED.
+//   FP32:  the plain FP32 per-step plan, always.
+//   MIXED: dSB with J exact in FP4 and N <= 2048 -> persistent FP4 plan;
+//          otherwise the integer-digit plan (N <= 16384).
+//   AUTO:  the FP4 plan where MIXED would take it; the digit plan for bSB and
+//          for dSB with integer J in [-127, 127] (both as accurate as FP32 or
+//          exact); FP32 otherwise.
 int choose_plan(const hsb_ctx *h, int variant, int *plan) {
-    const bool mixed_ok = variant == HSB_DSB && h->j_fp4_exact && hsb::persistent_supported(h->N);
+    const bool fp4_ok = variant == HSB_DSB && h->j_fp4_exact && hsb::persistent_supported(h->N);
+    const bool dig_ok = h->N <= hsb::i8_max_n();
     if (h->precision == HSB_PREC_FP32) {
-        *plan = HSB_PREC_FP32;
+        *plan = PLAN_FP32;
     } else if (h->precision == HSB_PREC_MIXED) {
-        if (!mixed_ok)
-            return fail(HSB_EUNSUPPORTED,
-                        "MIXED precision needs dSB, J exact in FP4 and N <= %d",
-                        hsb::persistent_max_n());
-        *plan = HSB_PREC_MIXED;
+        if (fp4_ok)
+            *plan = PLAN_FP4;
+        else if (dig_ok)
+            *plan = PLAN_DIGITS;
+        else
+            return fail(HSB_EUNSUPPORTED, "MIXED precision needs N <= %d", hsb::i8_max_n());
     } else {
-        *plan = mixed_ok ? HSB_PREC_MIXED : HSB_PREC_FP32;
+        if (fp4_ok)
+            *plan = PLAN_FP4;
+        else if (dig_ok && (variant == HSB_BSB || h->j_i8_exact))
+            *plan = PLAN_DIGITS;
+        else
+            *plan = PLAN_FP32;
     }
     return HSB_OK;
 }
@@ -272,7 +297,10 @@ extern "C" int hsb_plan_info(hsb_ctx *h, int variant, int *precision) {
     if (!h || !precision) return fail(HSB_EINVAL, "hsb_plan_info: NULL argument");
     if (variant != HSB_BSB && variant != HSB_DSB)
         return fail(HSB_EINVAL, "variant must be HSB_BSB (0) or HSB_DSB (1)");
-    return choose_plan(h, variant, precision);
+    int plan = 0;
+    const int rc = choose_plan(h, variant, &plan);
+    if (rc == HSB_OK) *precision = plan == PLAN_FP32 ? HSB_PREC_FP32 : HSB_PREC_MIXED;
+    return rc;
 }
 
 extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
@@ -346,7 +374,33 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
         return HSB_OK;
     };
 
-    if (plan == HSB_PREC_MIXED) {
+    if (plan == PLAN_DIGITS) {
+        if (!h->i8) {
+            rc = hsb::i8_create(h->hJ.data(), N, &h->i8);
+            if (rc != HSB_OK) return fail(rc, "%s", hsb::i8_error());
+        }
+        if (a->variant == HSB_BSB) {
+            // the x digits need |x| <= 1 in the start state (the walls keep it so)
+            bool ok = true;
+            rc = hsb::i8_start_state_ok(h->i8, b.X, (size_t)Npad * Rpad, s, &ok);
+            if (rc != HSB_OK) return fail(rc, "%s", hsb::i8_error());
+            if (!ok) {
+                if (h->precision == HSB_PREC_MIXED)
+                    return fail(HSB_EUNSUPPORTED,
+                                "MIXED bSB needs |x| <= 1 and finite in the start state");
+                plan = PLAN_FP32;
+            }
+        }
+    }
+    if (plan == PLAN_DIGITS) {
+        hsb::I8Run ir{};
+        ir.variant = a->variant;
+        ir.N = N; ir.Nst = Npad; ir.Rpad = Rpad; ir.R = R;
+        ir.k0 = k0; ir.k1 = k1; ir.Ns = Ns; ir.interval = interval;
+        ir.a0 = a0; ir.c0 = c0; ir.dt = dt;
+        rc = hsb::i8_run(h->i8, ir, b, h->dJ, s, h->timer);
+        if (rc != HSB_OK) return fail(rc, "%s", hsb::i8_error());
+    } else if (plan == PLAN_FP4) {
         if (!h->pj) {
             rc = hsb::persistent_create(h->hJ.data(), N, &h->pj);
             if (rc != HSB_OK) return fail(rc, "%s", hsb::persistent_error());
@@ -387,6 +441,7 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
     int32_t status = 0;
     HIP_TRY(hipMemcpyAsync(&status, b.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    h->last_plan = plan;
     if (status) return fail(HSB_ENUMERIC, "a replica's state became non-finite");
     return HSB_OK;
 }

@@ -141,11 +141,19 @@ __global__ __launch_bounds__(256) void k_step_fp32(const float *__restrict__ J,
     const int wr = w >> 1, wc = w & 1;
     const int r = r0 + 32 * wc + (lane & 31);
     const float gdt = gam[r] * dt;
+    // all loads of the tile's state before the first store (they overlap)
+    float xs[16], ys[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = i0 + 32 * wr + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        xs[v] = X[(size_t)i * Rpad + r];
+        ys[v] = Y[(size_t)i * Rpad + r];
+    }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int i = i0 + 32 * wr + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const size_t idx = (size_t)i * Rpad + r;
-        float x = X[idx], y = Y[idx];
+        float x = xs[v], y = ys[v];
         sb_update(acc[v], p, c0, dt, a0dt, gdt, x, y);
         X[idx] = x;
         Y[idx] = y;
@@ -235,34 +243,54 @@ __global__ __launch_bounds__(256) void k_energy_f64(const float *__restrict__ J,
 
 // Best-sample tracking after a sample point `step`: total energy per replica
 // in a fixed order, non-finite detection, strict-improvement best update
-// (ties keep the earliest sample) with a copy of the spins.
-__global__ void k_best(const double *__restrict__ epart, int nblk, const float *__restrict__ X,
-                       const float *__restrict__ Y, int N, int R, int Rpad,
-                       double *__restrict__ best_e, double *__restrict__ last_e,
-                       int32_t *__restrict__ best_step, int32_t *__restrict__ bad,
-                       int8_t *__restrict__ best_s, int32_t *__restrict__ status, int step) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    double e = 0.0;
-    for (int b = 0; b < nblk; ++b) e += epart[(size_t)b * Rpad + r];
-    e = -0.5 * e;
-    bool finite = true;
-    for (int i = 0; i < N; ++i) {
-        const float x = X[(size_t)i * Rpad + r], y = Y[(size_t)i * Rpad + r];
-        finite = finite && isfinite(x) && isfinite(y);
+// (ties keep the earliest sample) with a copy of the spins.  A workgroup of
+// 1024 threads owns 64 replicas (lane = replica); its 16 waves split the rows.
+__global__ __launch_bounds__(1024) void k_best(const double *__restrict__ epart, int nblk,
+                                               const float *__restrict__ X,
+                                               const float *__restrict__ Y, int N, int R,
+                                               int Rpad, double *__restrict__ best_e,
+                                               double *__restrict__ last_e,
+                                               int32_t *__restrict__ best_step,
+                                               int32_t *__restrict__ bad,
+                                               int8_t *__restrict__ best_s,
+                                               int32_t *__restrict__ status, int step) {
+    __shared__ int s_bad[16][64];
+    __shared__ int s_take[64];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = blockIdx.x * 64 + l;
+    int nf = 0;
+    if (r < R)
+        for (int i = w; i < N; i += 16) {
+            const float x = X[(size_t)i * Rpad + r], y = Y[(size_t)i * Rpad + r];
+            nf |= !(isfinite(x) && isfinite(y));
+        }
+    s_bad[w][l] = nf;
+    __syncthreads();
+    if (w == 0) {
+        int take = 0;
+        if (r < R) {
+            for (int q = 1; q < 16; ++q) nf |= s_bad[q][l];
+            double e = 0.0;
+            for (int b = 0; b < nblk; ++b) e += epart[(size_t)b * Rpad + r];
+            e = -0.5 * e;
+            if (nf) {
+                bad[r] = 1;
+                status[0] = 1;
+                e = __builtin_nan("");
+            }
+            last_e[r] = e;
+            if (e < best_e[r]) {
+                best_e[r] = e;
+                best_step[r] = step;
+                take = 1;
+            }
+        }
+        s_take[l] = take;
     }
-    if (!finite) {
-        bad[r] = 1;
-        status[0] = 1;
-        e = __builtin_nan("");
-    }
-    last_e[r] = e;
-    if (e < best_e[r]) {
-        best_e[r] = e;
-        best_step[r] = step;
-        for (int i = 0; i < N; ++i)
-            best_s[(size_t)i * Rpad + r] = X[(size_t)i * Rpad + r] >= 0.0f ? 1 : -1;
-    }
+    __syncthreads();
+    if (!s_take[l]) return;
+    for (int i = w; i < N; i += 16)
+        best_s[(size_t)i * Rpad + r] = X[(size_t)i * Rpad + r] >= 0.0f ? 1 : -1;
 }
 
 __global__ void k_output_spins(const float *__restrict__ X, const float *__restrict__ Y,
@@ -365,7 +393,7 @@ hipError_t launch_energy_f64(const float *J, const float *X, double *epart, int 
 
 hipError_t launch_best(const StateBufs &b, int nblk, int N, int R, int Rpad, int step,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_best, dim3(cdiv(R, 64)), dim3(64), 0, s, b.epart, nblk, b.X, b.Y, N, R,
+    hipLaunchKernelGGL(k_best, dim3(cdiv(R, 64)), dim3(1024), 0, s, b.epart, nblk, b.X, b.Y, N, R,
                        Rpad, b.best_e, b.last_e, b.best_step, b.bad, b.best_s, b.status, step);
     return hipGetLastError();
 }

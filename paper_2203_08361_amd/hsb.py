@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libhsb.so")
 HSB_BSB, HSB_DSB = 0, 1
 HSB_OK, HSB_EINVAL, HSB_ENOMEM, HSB_EDEVICE, HSB_ENUMERIC, HSB_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
 HSB_OPT_INIT_AMP, HSB_OPT_ENERGY_INTERVAL, HSB_OPT_RETURN_BEST, HSB_OPT_PRECISION = 0, 1, 2, 3
-HSB_OPT_TIMING, HSB_OPT_KERNEL_MS, HSB_OPT_KERNEL_LAUNCHES = 4, 5, 6
+HSB_OPT_TIMING, HSB_OPT_KERNEL_MS, HSB_OPT_KERNEL_LAUNCHES, HSB_OPT_LAST_PLAN = 4, 5, 6, 7
+HSB_PLAN_FP32, HSB_PLAN_FP4, HSB_PLAN_DIGITS = 0, 1, 2
+PLAN_NAMES = {HSB_PLAN_FP32: "fp32", HSB_PLAN_FP4: "fp4", HSB_PLAN_DIGITS: "digits"}
 HSB_PREC_AUTO, HSB_PREC_FP32, HSB_PREC_MIXED = 0, 1, 2
 
 EXPORTED = ("hsb_create", "hsb_destroy", "hsb_last_error", "hsb_set_option", "hsb_get_option",
@@ -206,7 +208,7 @@ class Context:
     _KEYS = {"init_amp": HSB_OPT_INIT_AMP, "energy_interval": HSB_OPT_ENERGY_INTERVAL,
              "return_best": HSB_OPT_RETURN_BEST, "precision": HSB_OPT_PRECISION,
              "timing": HSB_OPT_TIMING, "kernel_ms": HSB_OPT_KERNEL_MS,
-             "kernel_launches": HSB_OPT_KERNEL_LAUNCHES}
+             "kernel_launches": HSB_OPT_KERNEL_LAUNCHES, "last_plan": HSB_OPT_LAST_PLAN}
     _PREC = {"auto": HSB_PREC_AUTO, "fp32": HSB_PREC_FP32, "mixed": HSB_PREC_MIXED}
 
     def set_option(self, key, value):
@@ -219,6 +221,10 @@ class Context:
 
     def plan(self, variant):
         return {HSB_PREC_FP32: "fp32", HSB_PREC_MIXED: "mixed"}[hsb_plan_info(self.h, variant)]
+
+    def last_plan(self):
+        """Execution plan of the last successful run: "fp32", "fp4" or "digits"."""
+        return PLAN_NAMES.get(int(self.get_option("last_plan")))
 
     def run(self, variant, a0, c0, dt, gamma, steps, R, seed, allow_numeric=False):
         return hsb_run(self.h, variant, a0, c0, dt, gamma, steps, R, seed, allow_numeric)

@@ -3,7 +3,7 @@
 Bars (per the method's arithmetic):
   - dSB with integer J: the field is exact, so the single-precision trajectory
     is bitwise equal to the oracle's FP32 mirror (x, y, energies, spins), for
-    both the FP32 plan and the FP4 (mixed) plan.
+    the FP32 plan, the FP4 plan and the integer-digit plan.
   - bSB: per replica ||x_gpu - x_ref|| / ||x_ref|| <= 1e-5 (and for y) against
     the FP64 oracle after 1 and 50 steps.
   - energies: eq. (1) of the returned spins, exact for integer J; FP64 with
@@ -43,6 +43,7 @@ def gpu_run(J, variant, plan, steps, R, seed=1, a0=1.0, c0=None, dt=1.0, gamma=0
         torch.cuda.synchronize()
         res = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
         res["plan"] = ctx.plan(variant)
+        res["last_plan"] = ctx.last_plan()
     return res
 
 
@@ -145,6 +146,55 @@ def test_dsb_plans_agree_and_are_deterministic():
     assert np.array_equal(d["x"], a["x"][:37]) and np.array_equal(d["energy"], a["energy"][:37])
 
 
+def int_instance(N, seed, scale=5):
+    """Integer couplings +-scale: exact in int8 but not in FP4 (scale 5), so the
+    mixed precision option takes the integer-digit plan."""
+    return synth.sk_instance(N, seed) * np.float32(scale)
+
+
+@pytest.mark.parametrize("N,R,steps,interval", [(1, 3, 40, 7), (63, 33, 300, 50),
+                                                (65, 64, 250, 100), (300, 40, 400, 1),
+                                                (513, 96, 200, 60)])
+def test_dsb_digit_plan_bit_exact(N, R, steps, interval):
+    J = int_instance(N, N + 11)
+    c0 = 0.1 / np.sqrt(N)
+    say("dsb digits", N, R, steps, interval)
+    g = gpu_run(J, hsb.HSB_DSB, "mixed", steps, R, seed=N, c0=c0, gamma=0.02, interval=interval)
+    assert g["last_plan"] == ("fp4" if N == 1 else "digits")  # N = 1: J = 0 is FP4-exact
+    o = oracle_run(J, oracle.DSB, oracle.FP32, steps, R, seed=N, c0=c0, gamma=0.02,
+                   interval=interval)
+    assert_bit_exact(g, o)
+
+
+def test_dsb_digit_plan_beyond_fp4_size():
+    """N = 2100 > 2048: the FP4 plan does not apply, the digit plan is exact."""
+    J = synth.sk_instance(2100, 21)
+    say("dsb digits N=2100")
+    g = gpu_run(J, hsb.HSB_DSB, "mixed", 150, 40, seed=5, gamma=0.01, schedule_steps=2000,
+                interval=50)
+    assert g["last_plan"] == "digits"
+    o = oracle_run(J, oracle.DSB, oracle.FP32, 150, 40, seed=5, gamma=0.01, schedule_steps=2000,
+                   interval=50)
+    assert_bit_exact(g, o)
+
+
+def test_dsb_digit_plan_resume_and_gamma_rep():
+    J = int_instance(200, 8)
+    c0 = 0.1 / np.sqrt(200)
+    R, Ns, k = 32, 500, 170
+    gam = np.linspace(0.0, 0.1, R).astype(np.float32)
+    say("dsb digits resume")
+    full = gpu_run(J, hsb.HSB_DSB, "mixed", Ns, R, c0=c0, gamma_rep=torch.from_numpy(gam))
+    a = gpu_run(J, hsb.HSB_DSB, "mixed", k, R, c0=c0, schedule_steps=Ns,
+                gamma_rep=torch.from_numpy(gam))
+    b = gpu_run(J, hsb.HSB_DSB, "mixed", Ns - k, R, c0=c0, start_step=k, schedule_steps=Ns,
+                x0=torch.from_numpy(a["x"]), y0=torch.from_numpy(a["y"]),
+                gamma_rep=torch.from_numpy(gam))
+    assert np.array_equal(b["x"], full["x"]) and np.array_equal(b["y"], full["y"])
+    o = oracle_run(J, oracle.DSB, oracle.FP32, Ns, R, c0=c0, gamma=gam.astype(np.float64))
+    assert_bit_exact(full, o)
+
+
 # --------------------------------------------------- full-size (N=2000, R=1024)
 
 @pytest.mark.parametrize("plan", ["mixed", "fp32"])
@@ -171,21 +221,24 @@ def rel_err(a, b):
     return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
 
 
+@pytest.mark.parametrize("plan", ["fp32", "mixed"])
 @pytest.mark.parametrize("steps", [1, 50])
 @pytest.mark.parametrize("gamma", [0.0, 0.01])
-def test_bsb_trajectory_within_1e5(steps, gamma):
+def test_bsb_trajectory_within_1e5(plan, steps, gamma):
     J = synth.sk_instance(100, 1)
-    say("bsb N=100", steps, gamma)
-    g = gpu_run(J, hsb.HSB_BSB, "fp32", steps, 16, gamma=gamma, schedule_steps=2000)
+    say("bsb N=100", plan, steps, gamma)
+    g = gpu_run(J, hsb.HSB_BSB, plan, steps, 16, gamma=gamma, schedule_steps=2000)
+    assert g["last_plan"] == ("digits" if plan == "mixed" else "fp32")
     o = oracle_run(J, oracle.BSB, oracle.FP64, steps, 16, gamma=gamma, schedule_steps=2000)
     assert rel_err(g["x"], o["x"]).max() <= 1e-5
     assert rel_err(g["y"], o["y"]).max() <= 1e-5
 
 
-def test_bsb_full_size_sampled_replicas():
+@pytest.mark.parametrize("plan", ["mixed", "fp32"])
+def test_bsb_full_size_sampled_replicas(plan):
     J = synth.sk_instance(2000, 2000)
-    say("bsb full size")
-    g = gpu_run(J, hsb.HSB_BSB, "fp32", 50, 1024, seed=3, gamma=0.01, schedule_steps=10000)
+    say("bsb full size", plan)
+    g = gpu_run(J, hsb.HSB_BSB, plan, 50, 1024, seed=3, gamma=0.01, schedule_steps=10000)
     for r in (0, 700, 1023):
         o = oracle_run(J, oracle.BSB, oracle.FP64, 50, 1, seed=3, gamma=0.01, r0=r,
                        schedule_steps=10000)
@@ -193,18 +246,64 @@ def test_bsb_full_size_sampled_replicas():
         assert rel_err(g["y"][r:r + 1], o["y"]).max() <= 1e-5
 
 
-def test_gaussian_bsb_and_fp64_energies():
+@pytest.mark.parametrize("plan", ["fp32", "mixed"])
+def test_gaussian_bsb_and_fp64_energies(plan):
     J = synth.gaussian_instance(300, 3)
-    say("gaussian bsb")
+    say("gaussian bsb", plan)
     c0 = 0.5  # c1 / (sigma_J sqrt(N)) with sigma_J = 1/sqrt(N)
-    g = gpu_run(J, hsb.HSB_BSB, "auto", 50, 32, c0=c0, gamma=0.01, schedule_steps=1000)
+    g = gpu_run(J, hsb.HSB_BSB, plan, 50, 32, c0=c0, gamma=0.01, schedule_steps=1000)
     o = oracle_run(J, oracle.BSB, oracle.FP64, 50, 32, c0=c0, gamma=0.01, schedule_steps=1000)
-    assert g["plan"] == "fp32"
+    assert g["last_plan"] == ("digits" if plan == "mixed" else "fp32")
     assert rel_err(g["x"], o["x"]).max() <= 1e-5 and rel_err(g["y"], o["y"]).max() <= 1e-5
-    g = gpu_run(J, hsb.HSB_BSB, "auto", 1000, 32, c0=c0, gamma=0.01)
+    g = gpu_run(J, hsb.HSB_BSB, plan, 1000, 32, c0=c0, gamma=0.01)
     for s, e in zip(g["spins"], g["energy"]):
         ref = oracle.energy(J, s)
         assert abs(e - ref) <= 1e-12 * abs(ref)
+
+
+def test_gaussian_full_size_bsb_digits():
+    """N=2000 Gaussian couplings (four-digit J), R=1024, first 50 steps of 10^4."""
+    J = synth.gaussian_instance(2000, 3)
+    say("gaussian full size digits")
+    g = gpu_run(J, hsb.HSB_BSB, "mixed", 50, 1024, seed=4, c0=0.5, gamma=0.01,
+                schedule_steps=10000)
+    assert g["last_plan"] == "digits"
+    for r in (0, 333, 1023):
+        o = oracle_run(J, oracle.BSB, oracle.FP64, 50, 1, seed=4, c0=0.5, gamma=0.01, r0=r,
+                       schedule_steps=10000)
+        assert rel_err(g["x"][r:r + 1], o["x"]).max() <= 1e-5
+        assert rel_err(g["y"][r:r + 1], o["y"]).max() <= 1e-5
+
+
+def test_bsb_digits_deterministic_prefix_and_resume():
+    J = synth.sk_instance(300, 6)
+    R, Ns, k = 48, 400, 150
+    say("bsb digits determinism")
+    a = gpu_run(J, hsb.HSB_BSB, "mixed", Ns, R, gamma=0.02, seed=9)
+    b = gpu_run(J, hsb.HSB_BSB, "mixed", Ns, R, gamma=0.02, seed=9)
+    d = gpu_run(J, hsb.HSB_BSB, "mixed", Ns, 17, gamma=0.02, seed=9)
+    for key in ("x", "y", "spins", "energy", "best_step"):
+        assert np.array_equal(a[key], b[key]), key
+    assert np.array_equal(d["x"], a["x"][:17]) and np.array_equal(d["energy"], a["energy"][:17])
+    h1 = gpu_run(J, hsb.HSB_BSB, "mixed", k, R, gamma=0.02, seed=9, schedule_steps=Ns)
+    h2 = gpu_run(J, hsb.HSB_BSB, "mixed", Ns - k, R, gamma=0.02, start_step=k, schedule_steps=Ns,
+                 x0=torch.from_numpy(h1["x"]), y0=torch.from_numpy(h1["y"]))
+    assert np.array_equal(h2["x"], a["x"]) and np.array_equal(h2["y"], a["y"])
+    # energies are eq. (1) of the returned spins, exactly
+    for s_, e in zip(a["spins"], a["energy"]):
+        assert oracle.energy(J, s_) == e
+
+
+def test_bsb_digits_need_bounded_start_state():
+    J = synth.sk_instance(64, 2)
+    say("bsb digits start-state bound")
+    with pytest.raises(hsb.HSBError) as ei:
+        gpu_run(J, hsb.HSB_BSB, "mixed", 10, 8, amp=1.5)
+    assert ei.value.code == hsb.HSB_EUNSUPPORTED
+    g = gpu_run(J, hsb.HSB_BSB, "auto", 10, 8, amp=1.5)
+    assert g["last_plan"] == "fp32"
+    f = gpu_run(J, hsb.HSB_BSB, "fp32", 10, 8, amp=1.5)
+    assert np.array_equal(g["x"], f["x"])
 
 
 # ---------------------------------------------------------------- errors
@@ -212,19 +311,19 @@ def test_gaussian_bsb_and_fp64_energies():
 def test_plan_selection_and_unsupported():
     say("plans")
     with hsb.Context(synth.sk_instance(64, 1)) as ctx:
-        assert ctx.plan(hsb.HSB_DSB) == "mixed" and ctx.plan(hsb.HSB_BSB) == "fp32"
+        assert ctx.plan(hsb.HSB_DSB) == "mixed" and ctx.plan(hsb.HSB_BSB) == "mixed"
+    with hsb.Context(synth.gaussian_instance(64, 1)) as ctx:
+        assert ctx.plan(hsb.HSB_DSB) == "fp32" and ctx.plan(hsb.HSB_BSB) == "mixed"
     with hsb.Context(synth.gaussian_instance(64, 1), precision="mixed") as ctx:
-        with pytest.raises(hsb.HSBError) as ei:
-            ctx.plan(hsb.HSB_DSB)
-        assert ei.value.code == hsb.HSB_EUNSUPPORTED
+        assert ctx.plan(hsb.HSB_DSB) == "mixed"
 
 
-@pytest.mark.parametrize("plan", ["fp32", "mixed"])
-def test_non_finite_state_is_reported(plan):
+@pytest.mark.parametrize("variant,plan", [(1, "fp32"), (1, "mixed"), (0, "mixed")])
+def test_non_finite_state_is_reported(variant, plan):
     """gamma*dt > 1 with walls: y grows geometrically (eq. (22)) until it overflows."""
     J = synth.sk_instance(40, 1)
-    say("numeric", plan)
-    g = gpu_run(J, hsb.HSB_DSB, plan, 400, 8, gamma=8.0, dt=1.0, allow_numeric=True)
+    say("numeric", variant, plan)
+    g = gpu_run(J, variant, plan, 400, 8, gamma=8.0, dt=1.0, allow_numeric=True)
     assert g["status"] == hsb.HSB_ENUMERIC
     assert np.all(np.isnan(g["energy"]))
 
