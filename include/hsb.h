@@ -199,6 +199,52 @@ int hsb_run_ex(hsb_ctx *h, const hsb_run_args *args);
  */
 int hsb_plan_info(hsb_ctx *h, int variant, int *precision);
 
+/*
+ * hsb_run_batch -- many independent runs ("jobs") over several instances in
+ * one call: the parameter sweeps and instance sets of the Results section
+ * (each job is a set of trials of one instance at one heating rate).
+ *
+ *   hs      n_inst contexts (the instances), all on the current device
+ *   jobs    n_jobs job descriptions (host array); job j runs jobs[j].R replicas
+ *           of instance hs[jobs[j].instance] with its own c0, gamma and seed
+ *   args    what all jobs share: variant, steps (Ns), a0, dt, initial
+ *           amplitude, energy interval, best/final output, stream
+ *
+ * Job j gives exactly what hsb_run_ex on its instance gives with the same
+ * variant, steps, R, a0, c0, dt, gamma and seed (and the batch's amplitude,
+ * interval and return mode), under the plan its instance's precision option
+ * selects; dSB jobs whose J is exact in FP4 with N <= 2048 run together, one
+ * persistent launch per padded size for all their instances, so a batch of
+ * small instances fills the device.  Other jobs run one after another.
+ * Outputs are device pointers owned by the caller: jobs[j].spins [R][N] int8
+ * and jobs[j].energy [R] double.  Validation failures return HSB_EINVAL before
+ * any device work; HSB_ENUMERIC if any replica of any job became non-finite.
+ * Contexts' own options (amplitude, interval, return mode) are not changed.
+ */
+typedef struct {
+    int32_t instance; /* index into hs[] */
+    int32_t R;        /* replicas, >= 1 */
+    float c0;         /* c0 of eq. (16) for this job, finite */
+    float gamma;      /* heating rate of every replica of the job, finite, >= 0 */
+    uint64_t seed;    /* replica r of the job draws its initial state from (seed, r) */
+    int8_t *spins;    /* device, [R][N of the instance], receives +-1 */
+    double *energy;   /* device, [R], receives eq. (1) of spins */
+} hsb_job;
+
+typedef struct {
+    size_t struct_size;      /* sizeof(hsb_batch_args) */
+    int32_t variant;         /* HSB_BSB / HSB_DSB */
+    int32_t steps;           /* Ns >= 0 for every job */
+    float a0, dt;            /* finite, dt > 0 */
+    double init_amp;         /* > 0 (0 means 0.1) */
+    int32_t energy_interval; /* >= 1 (0 means 100) */
+    int32_t return_best;     /* 1: best sample, 0: final state */
+    void *stream;            /* hipStream_t, or NULL for the null stream */
+} hsb_batch_args;
+
+int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs, int n_jobs,
+                  const hsb_batch_args *args);
+
 #ifdef __cplusplus
 }
 #endif

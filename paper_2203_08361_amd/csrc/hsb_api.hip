@@ -2,8 +2,10 @@
 // Declarations and the contract of every entry point are in include/hsb.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -56,6 +58,7 @@ struct hsb_ctx {
     bool j_i8_exact = false;    // every entry an integer in [-127, 127]
     hsb::PersistentJ *pj = nullptr;  // FP4 J store for the persistent dSB path (lazy)
     hsb::I8J *i8 = nullptr;          // integer-digit J store (lazy)
+    hsb::PersistentWork *bwork = nullptr;  // scratch of batched FP4 runs led by this context
     std::vector<float> hJ;      // host copy kept for lazy device re-layouts
     // options
     double init_amp = 0.1;
@@ -77,40 +80,15 @@ struct hsb_ctx {
 namespace {
 
 void free_state(hsb_ctx *h) {
-    hsb::StateBufs &b = h->b;
-    void *ptrs[] = {b.X,      b.Y,         b.B[0],      b.B[1], b.gamma, b.epart,
-                    b.best_e, b.last_e,    b.best_step, b.bad,  b.best_s, b.status};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    b = hsb::StateBufs{};
+    hsb::free_state_bufs(h->b);
     h->Rpad_cap = 0;
 }
 
 int ensure_state(hsb_ctx *h, int Rpad) {
     if (Rpad <= h->Rpad_cap) return HSB_OK;
     free_state(h);
-    hsb::StateBufs &b = h->b;
-    const size_t nr = (size_t)Rpad, ns = (size_t)h->Npad * nr;
-    hipError_t e = hipSuccess;
-    auto alloc = [&](void **p, size_t bytes) {
-        if (e == hipSuccess) e = hipMalloc(p, bytes);
-    };
-    alloc((void **)&b.X, ns * sizeof(float));
-    alloc((void **)&b.Y, ns * sizeof(float));
-    alloc((void **)&b.B[0], ns * sizeof(float));
-    alloc((void **)&b.B[1], ns * sizeof(float));
-    alloc((void **)&b.gamma, nr * sizeof(float));
-    alloc((void **)&b.epart, (size_t)(h->Npad / 32) * nr * sizeof(double));
-    alloc((void **)&b.best_e, nr * sizeof(double));
-    alloc((void **)&b.last_e, nr * sizeof(double));
-    alloc((void **)&b.best_step, nr * sizeof(int32_t));
-    alloc((void **)&b.bad, nr * sizeof(int32_t));
-    alloc((void **)&b.best_s, ns);
-    alloc((void **)&b.status, sizeof(int32_t));
-    if (e != hipSuccess) {
-        free_state(h);
-        return hip_fail(e, "allocating run state");
-    }
+    hipError_t e = hsb::alloc_state(h->b, h->Npad, Rpad);
+    if (e != hipSuccess) return hip_fail(e, "allocating run state");
     h->Rpad_cap = Rpad;
     return HSB_OK;
 }
@@ -194,6 +172,7 @@ extern "C" void hsb_destroy(hsb_ctx *h) {
     if (h->d_energy) (void)hipFree(h->d_energy);
     if (h->pj) hsb::persistent_free(h->pj);
     if (h->i8) hsb::i8_free(h->i8);
+    if (h->bwork) hsb::persistent_work_free(h->bwork);
     h->timer.release();
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -352,7 +331,7 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
     if (a->x0)
         HIP_TRY(hsb::launch_load_state(b.X, b.Y, a->x0, a->y0, N, R, Npad, Rpad, s));
     else
-        HIP_TRY(hsb::launch_init_seeded(b.X, b.Y, N, R, Npad, Rpad, a->seed, amp, s));
+        HIP_TRY(hsb::launch_init_seeded(b.X, b.Y, N, R, Npad, Rpad, Rpad, a->seed, amp, s));
     HIP_TRY(hsb::launch_fill_gamma(b.gamma, a->gamma_rep, a->gamma, R, Rpad, s));
     HIP_TRY(hsb::launch_reset_tracking(b, Rpad, s));
 
@@ -485,4 +464,169 @@ extern "C" int hsb_run(hsb_ctx *h, int variant, float a0, float c0, float dt, fl
                            h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return rc;
+}
+
+extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs, int n_jobs,
+                             const hsb_batch_args *a) {
+    g_err[0] = 0;
+    if (!hs || !a || (n_jobs > 0 && !jobs)) return fail(HSB_EINVAL, "hsb_run_batch: NULL argument");
+    if (a->struct_size != sizeof(hsb_batch_args))
+        return fail(HSB_EINVAL, "hsb_run_batch: struct_size %zu != %zu", a->struct_size,
+                    sizeof(hsb_batch_args));
+    if (n_inst < 1 || n_jobs < 0) return fail(HSB_EINVAL, "n_inst must be >= 1, n_jobs >= 0");
+    if (a->variant != HSB_BSB && a->variant != HSB_DSB)
+        return fail(HSB_EINVAL, "variant must be HSB_BSB (0) or HSB_DSB (1)");
+    if (a->steps < 0) return fail(HSB_EINVAL, "steps must be >= 0");
+    if (!(std::isfinite(a->a0) && std::isfinite(a->dt) && a->dt > 0.0f))
+        return fail(HSB_EINVAL, "a0 must be finite and dt finite and > 0");
+    const double amp = a->init_amp == 0.0 ? 0.1 : a->init_amp;
+    if (!(std::isfinite(amp) && amp > 0.0 && amp <= 1.0e6))
+        return fail(HSB_EINVAL, "init_amp must be finite and > 0");
+    const int interval = a->energy_interval == 0 ? 100 : a->energy_interval;
+    if (interval < 1) return fail(HSB_EINVAL, "energy_interval must be >= 1");
+    if (a->return_best != 0 && a->return_best != 1)
+        return fail(HSB_EINVAL, "return_best must be 0 or 1");
+    for (int i = 0; i < n_inst; ++i) {
+        if (!hs[i]) return fail(HSB_EINVAL, "hs[%d] is NULL", i);
+        if (hs[i]->device != hs[0]->device)
+            return fail(HSB_EINVAL, "all contexts must be on one device");
+    }
+    // plan of every job (the instance's precision option), FP4 jobs grouped by padded size
+    std::map<int, std::vector<int>> classes;  // K blocks of 64 -> jobs
+    std::vector<int> singles;
+    for (int j = 0; j < n_jobs; ++j) {
+        const hsb_job &jb = jobs[j];
+        if (jb.instance < 0 || jb.instance >= n_inst)
+            return fail(HSB_EINVAL, "job %d: instance %d out of range", j, jb.instance);
+        if (jb.R < 1 || jb.R > (1 << 22)) return fail(HSB_EINVAL, "job %d: R out of range", j);
+        if (!std::isfinite(jb.c0)) return fail(HSB_EINVAL, "job %d: c0 must be finite", j);
+        if (!(std::isfinite(jb.gamma) && jb.gamma >= 0.0f))
+            return fail(HSB_EINVAL, "job %d: gamma must be finite and >= 0", j);
+        if (!jb.spins || !jb.energy) return fail(HSB_EINVAL, "job %d: spins and energy required", j);
+        int plan = 0;
+        const int rc = choose_plan(hs[jb.instance], a->variant, &plan);
+        if (rc != HSB_OK) return rc;
+        if (plan == PLAN_FP4)
+            classes[(hs[jb.instance]->N + 255) / 256 * 4].push_back(j);
+        else
+            singles.push_back(j);
+    }
+    hsb_ctx *lead = hs[0];
+    HIP_TRY(hipSetDevice(lead->device));
+    hipStream_t s = (hipStream_t)a->stream;
+    int any_bad = 0;
+
+    // jobs outside the FP4 plan: one run each (their contexts' own plans)
+    for (int j : singles) {
+        const hsb_job &jb = jobs[j];
+        hsb_ctx *h = hs[jb.instance];
+        const double amp0 = h->init_amp;
+        const int int0 = h->interval, rb0 = h->return_best, tim0 = h->timing;
+        h->init_amp = amp;
+        h->interval = interval;
+        h->return_best = a->return_best;
+        h->timing = 0;
+        hsb_run_args ra;
+        std::memset(&ra, 0, sizeof(ra));
+        ra.struct_size = sizeof(ra);
+        ra.variant = a->variant;
+        ra.steps = a->steps;
+        ra.R = jb.R;
+        ra.a0 = a->a0;
+        ra.c0 = jb.c0;
+        ra.dt = a->dt;
+        ra.gamma = jb.gamma;
+        ra.seed = jb.seed;
+        ra.spins = jb.spins;
+        ra.energy = jb.energy;
+        ra.stream = a->stream;
+        const int rc = hsb_run_ex(h, &ra);
+        h->init_amp = amp0;
+        h->interval = int0;
+        h->return_best = rb0;
+        h->timing = tim0;
+        if (rc == HSB_ENUMERIC)
+            any_bad = 1;
+        else if (rc != HSB_OK)
+            return rc;
+    }
+
+    // FP4 jobs: one persistent launch sequence per padded size; the lead
+    // context's timer (TIMING on) records those launches
+    lead->timer.reset(lead->timing != 0);
+    for (auto &cls : classes) {
+        const int nkb = cls.first, Nst = nkb * 64;
+        const std::vector<int> &cj = cls.second;
+        // columns: job j owns [col0, col0 + round_up(R, 32)), 32-replica teams
+        std::vector<int> col0(cj.size());
+        int used = 0;
+        for (size_t q = 0; q < cj.size(); ++q) {
+            col0[q] = used;
+            used += round_up(jobs[cj[q]].R, 32);
+        }
+        const int Rtot = round_up(used, hsb::kTile);
+        std::vector<hsb::FP4Team> teams;
+        for (size_t q = 0; q < cj.size(); ++q) {
+            const hsb_job &jb = jobs[cj[q]];
+            hsb_ctx *h = hs[jb.instance];
+            if (!h->pj) {
+                const int rc = hsb::persistent_create(h->hJ.data(), h->N, &h->pj);
+                if (rc != HSB_OK) return fail(rc, "%s", hsb::persistent_error());
+            }
+            for (int t = 0; t < round_up(jb.R, 32) / 32; ++t)
+                teams.push_back(hsb::FP4Team{hsb::persistent_jpk(h->pj), h->N, jb.c0});
+        }
+        if (!lead->bwork) {
+            const int rc = hsb::persistent_work_create(&lead->bwork);
+            if (rc != HSB_OK) return fail(rc, "%s", hsb::persistent_error());
+        }
+        hsb::StateBufs bb{};
+        hipError_t e = hsb::alloc_state(bb, Nst, Rtot);
+        if (e != hipSuccess) return hip_fail(e, "allocating batch state");
+        auto done = [&](int rc) {
+            (void)hipStreamSynchronize(s);
+            hsb::free_state_bufs(bb);
+            return rc;
+        };
+        // initial state, gamma per column, tracking (zero columns between jobs)
+        e = hsb::launch_init_seeded(bb.X, bb.Y, 0, 0, Nst, Rtot, Rtot, 0, (float)amp, s);
+        if (e == hipSuccess) e = hsb::launch_fill_gamma(bb.gamma, nullptr, 0.0f, 0, Rtot, s);
+        for (size_t q = 0; q < cj.size() && e == hipSuccess; ++q) {
+            const hsb_job &jb = jobs[cj[q]];
+            const int nc = round_up(jb.R, 32);
+            e = hsb::launch_init_seeded(bb.X + col0[q], bb.Y + col0[q], hs[jb.instance]->N, jb.R,
+                                        Nst, nc, Rtot, jb.seed, (float)amp, s);
+            if (e == hipSuccess)
+                e = hsb::launch_fill_gamma(bb.gamma + col0[q], nullptr, jb.gamma, jb.R, nc, s);
+        }
+        if (e == hipSuccess) e = hsb::launch_reset_tracking(bb, Rtot, s);
+        if (e != hipSuccess) return done(hip_fail(e, "batch set-up"));
+        hsb::PersistentRun pr{};
+        pr.X = bb.X; pr.Y = bb.Y; pr.gamma = bb.gamma;
+        pr.Npad = Nst; pr.Rpad = Rtot; pr.R = used;
+        pr.k0 = 0; pr.k1 = a->steps; pr.Ns = a->steps; pr.interval = interval;
+        pr.a0 = a->a0; pr.c0 = 0.0f; pr.dt = a->dt;
+        int rc = hsb::persistent_run_teams(lead->bwork, nkb, teams.data(), (int)teams.size(), pr,
+                                           bb, Nst, s, lead->timer);
+        if (rc != HSB_OK) return done(fail(rc, "%s", hsb::persistent_error()));
+        for (size_t q = 0; q < cj.size() && e == hipSuccess; ++q) {
+            const hsb_job &jb = jobs[cj[q]];
+            hsb::StateBufs v = bb;  // column view of the job
+            v.X += col0[q]; v.Y += col0[q]; v.best_s += col0[q]; v.best_e += col0[q];
+            v.last_e += col0[q]; v.best_step += col0[q]; v.bad += col0[q];
+            e = hsb::launch_output(v, hs[jb.instance]->N, jb.R, Rtot, a->return_best, jb.spins,
+                                   jb.energy, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+        }
+        int32_t status = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&status, bb.status, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return done(hip_fail(e, "batch output"));
+        any_bad |= status;
+        done(HSB_OK);
+        lead->last_plan = PLAN_FP4;
+    }
+
+    if (any_bad) return fail(HSB_ENUMERIC, "a replica's state became non-finite");
+    return HSB_OK;
 }

@@ -71,14 +71,19 @@ struct StateBufs {
     int32_t *status;      // [1] any replica non-finite
 };
 
-hipError_t launch_init_seeded(float *X, float *Y, int N, int R, int Npad, int Rpad, uint64_t seed,
-                              float amp, hipStream_t s);
+// rows [0, Npad) x columns [0, ncols) of a state with leading dimension ld
+hipError_t launch_init_seeded(float *X, float *Y, int N, int R, int Npad, int ncols, int ld,
+                              uint64_t seed, float amp, hipStream_t s);
 hipError_t launch_load_state(float *X, float *Y, const float *x0, const float *y0, int N, int R,
                              int Npad, int Rpad, hipStream_t s);
 hipError_t launch_make_operand(float *B, const float *X, int variant, int Npad, int Rpad,
                                hipStream_t s);
+// g[r] = gamma_rep[r] (or gamma) for r < R, 0 for R <= r < Rpad
 hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int R, int Rpad,
                              hipStream_t s);
+// allocation of the run state for Npad rows and Rpad columns (all or nothing)
+hipError_t alloc_state(StateBufs &b, int Npad, int Rpad);
+void free_state_bufs(StateBufs &b);
 hipError_t launch_reset_tracking(const StateBufs &b, int Rpad, hipStream_t s);
 hipError_t launch_step_fp32(int variant, const float *J, const float *Bin, float *Bout, float *X,
                             float *Y, const float *gamma, int Npad, int Rpad, float p, float c0,

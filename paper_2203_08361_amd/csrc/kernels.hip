@@ -15,18 +15,20 @@ namespace hsb {
 
 // ------------------------------------------------------------ state set-up
 
-__global__ void k_init_seeded(float *__restrict__ X, float *__restrict__ Y, int N, int R, int Npad,
-                              int Rpad, uint64_t seed, float amp) {
+// Columns [0, ncols) of a state with leading dimension ld: replica r < R of
+// spin i < N draws from (seed, r, i); everything else is zero.
+__global__ void k_init_seeded(float *__restrict__ X, float *__restrict__ Y, int N, int R, int ncols,
+                              int ld, uint64_t seed, float amp) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
-    if (r >= Rpad) return;
+    if (r >= ncols) return;
     float x = 0.0f, y = 0.0f;
     if (i < N && r < R) {
         x = amp * uniform_open(rng_key(seed, 0, (uint64_t)r, (uint64_t)i));
         y = amp * uniform_open(rng_key(seed, 1, (uint64_t)r, (uint64_t)i));
     }
-    X[(size_t)i * Rpad + r] = x;
-    Y[(size_t)i * Rpad + r] = y;
+    X[(size_t)i * ld + r] = x;
+    Y[(size_t)i * ld + r] = y;
 }
 
 __global__ void k_load_state(float *__restrict__ X, float *__restrict__ Y,
@@ -328,12 +330,43 @@ __global__ void k_output_energy(const double *__restrict__ best_e,
 
 // ------------------------------------------------------------ launchers
 
+void free_state_bufs(StateBufs &b) {
+    void *ptrs[] = {b.X,      b.Y,         b.B[0],      b.B[1], b.gamma, b.epart,
+                    b.best_e, b.last_e,    b.best_step, b.bad,  b.best_s, b.status};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    b = StateBufs{};
+}
+
+hipError_t alloc_state(StateBufs &b, int Npad, int Rpad) {
+    b = StateBufs{};
+    const size_t nr = (size_t)Rpad, ns = (size_t)Npad * nr;
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void **p, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, bytes);
+    };
+    alloc((void **)&b.X, ns * sizeof(float));
+    alloc((void **)&b.Y, ns * sizeof(float));
+    alloc((void **)&b.B[0], ns * sizeof(float));
+    alloc((void **)&b.B[1], ns * sizeof(float));
+    alloc((void **)&b.gamma, nr * sizeof(float));
+    alloc((void **)&b.epart, (size_t)(Npad / 32) * nr * sizeof(double));
+    alloc((void **)&b.best_e, nr * sizeof(double));
+    alloc((void **)&b.last_e, nr * sizeof(double));
+    alloc((void **)&b.best_step, nr * sizeof(int32_t));
+    alloc((void **)&b.bad, nr * sizeof(int32_t));
+    alloc((void **)&b.best_s, ns);
+    alloc((void **)&b.status, sizeof(int32_t));
+    if (e != hipSuccess) free_state_bufs(b);
+    return e;
+}
+
 static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
-hipError_t launch_init_seeded(float *X, float *Y, int N, int R, int Npad, int Rpad, uint64_t seed,
-                              float amp, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_seeded, dim3(cdiv(Rpad, 256), Npad), dim3(256), 0, s, X, Y, N, R,
-                       Npad, Rpad, seed, amp);
+hipError_t launch_init_seeded(float *X, float *Y, int N, int R, int Npad, int ncols, int ld,
+                              uint64_t seed, float amp, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_seeded, dim3(cdiv(ncols, 256), Npad), dim3(256), 0, s, X, Y, N, R,
+                       ncols, ld, seed, amp);
     return hipGetLastError();
 }
 

@@ -7,7 +7,16 @@
 
 namespace hsb {
 
-struct PersistentJ;  // FP4 J store plus the path's scratch buffers
+struct PersistentJ;     // FP4 J store of one instance plus its run scratch
+struct PersistentWork;  // scratch of one persistent run
+
+// One team (32 replicas) of a persistent launch: its instance's FP4 J
+// fragments (device), that instance's N and the c0 of eq. (16).
+struct FP4Team {
+    const void *jpk;
+    int N;
+    float c0;
+};
 
 struct PersistentRun {
     float *X, *Y;          // [Npad][Rpad] state in/out
@@ -26,5 +35,16 @@ void persistent_free(PersistentJ *pj);
 // Runs steps k0 .. k1-1 with energy samples, updating the tracking buffers of `b`.
 int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int N, hipStream_t s,
                    KernelTimer &timer);
+// The same for a batch: team t owns columns [32 t, 32 t + 32) of the state
+// (run.Rpad columns, run.R of them real) and runs the instance host_teams[t];
+// every instance has `nkb` K blocks (the same padded size).  Nrows: rows of
+// the state decoded into best spins.
+int persistent_run_teams(PersistentWork *w, int nkb, const FP4Team *host_teams, int nteams,
+                         const PersistentRun &run, StateBufs &b, int Nrows, hipStream_t s,
+                         KernelTimer &timer);
+int persistent_work_create(PersistentWork **out);
+void persistent_work_free(PersistentWork *w);
+int persistent_nkb(const PersistentJ *pj);
+const void *persistent_jpk(const PersistentJ *pj);
 
 }  // namespace hsb

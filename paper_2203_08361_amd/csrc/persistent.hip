@@ -44,9 +44,8 @@ constexpr int kMaxKB = 32;  // K blocks of 64 spins: N <= 2048
 constexpr uint32_t kNoTag = 0xFFFFFFFFu;
 constexpr uint64_t kTimeoutTicks = 400000000ull;  // 4 s of the 100 MHz wall clock
 
-struct PersistentJ {
-    int N = 0, Npad = 0, nkb = 0, nrb = 0;
-    v4i *jpk = nullptr;          // [nrb][2][nkb][64] FP4 fragments
+// Scratch of one persistent run (a single instance or a batch of teams).
+struct PersistentWork {
     uint64_t *xb = nullptr;      // [2][nchunk][Rpad] tagged sign words
     size_t xb_words = 0;
     uint32_t *snap = nullptr;    // [ns][nchunk][Rpad] sign words of sampled states
@@ -59,7 +58,14 @@ struct PersistentJ {
     uint64_t *xslot = nullptr;   // [grid] (launch epoch, XCD id) per workgroup
     size_t xslot_n = 0;
     uint32_t epoch = 0;          // launches so far
-    int waves_capacity = 0;
+    FP4Team *teams = nullptr;    // [nteams] per-team J, N and c0
+    size_t teams_n = 0;
+};
+
+struct PersistentJ {
+    int N = 0, Npad = 0, nkb = 0, nrb = 0;
+    v4i *jpk = nullptr;          // [nrb][2][nkb][64] FP4 fragments
+    PersistentWork work;         // scratch of this instance's own runs
 };
 
 namespace {
@@ -243,11 +249,11 @@ __device__ __forceinline__ bool gather_words(uint64_t (&wv)[NQ], const uint64_t 
 // the fused update of its 64 rows x 32 replicas.
 template <int NKB>
 __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
-    const v4i *__restrict__ jpk, float *__restrict__ X, float *__restrict__ Y,
+    const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, uint64_t *xb, uint32_t *__restrict__ snap,
     float *__restrict__ ep, const float *__restrict__ ptab, int32_t *__restrict__ bad,
-    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, uint32_t epoch, int N, int nkb,
-    int nrb, int Rpad, int team0, int nteams, SegArgs g, float c0, float dt, float a0dt) {
+    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, uint32_t epoch, int nkb,
+    int nrb, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
     static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
     constexpr int NQ = NKB / 4;  // K blocks expanded by each wave
     __shared__ v4i a_lds[2][NKB][64];
@@ -263,6 +269,11 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     const int tl = (kx / wpt) * 8 + xcd;  // team within this launch
     if (tl >= nteams) return;             // whole workgroup
     const int team = team0 + tl;
+    // the team's instance: its FP4 J fragments, its N and its c0 (a batch
+    // mixes instances of the same padded size in one launch)
+    const v4i *__restrict__ jpk = static_cast<const v4i *>(teams[team].jpk);
+    const int N = teams[team].N;
+    const float c0 = teams[team].c0;
     const int rb = (kx % wpt) * 4 + w;
     const int r0 = team * 32;
     const int nchunk = 2 * nrb;
@@ -526,7 +537,6 @@ int persistent_create(const float *J, int N, PersistentJ **out) {
     const size_t frags = (size_t)pj->nrb * 2 * pj->nkb * 64;
     hipError_t e = hipMalloc((void **)&dJ, np * np * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void **)&pj->jpk, frags * sizeof(v4i));
-    if (e == hipSuccess) e = hipMalloc((void **)&pj->err, sizeof(int32_t));
     if (e == hipSuccess)
         e = hipMemcpy(dJ, padded.data(), np * np * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
@@ -536,29 +546,35 @@ int persistent_create(const float *J, int N, PersistentJ **out) {
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (dJ) (void)hipFree(dJ);
-    int dev = 0, ncu = 0, nb = 0;
-    if (e == hipSuccess) e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(pj->nkb), 256, 0);
     if (e != hipSuccess) {
         persistent_free(pj);
         return perr(e == hipErrorOutOfMemory ? HSB_ENOMEM : HSB_EDEVICE, "FP4 J store: %s",
                     hipGetErrorString(e));
     }
-    pj->waves_capacity = nb * ncu * 4;
-    if (pj->waves_capacity < pj->nrb) {
-        persistent_free(pj);
-        return perr(HSB_EUNSUPPORTED, "FP4 path: %d resident waves < %d row blocks",
-                    nb * ncu * 4, pj->nrb);
-    }
     *out = pj;
     return HSB_OK;
 }
 
+int persistent_nkb(const PersistentJ *pj) { return pj->nkb; }
+const void *persistent_jpk(const PersistentJ *pj) { return pj->jpk; }
+
+int persistent_work_create(PersistentWork **out) {
+    *out = new (std::nothrow) PersistentWork;
+    return *out ? HSB_OK : perr(HSB_ENOMEM, "persistent scratch: host allocation");
+}
+
+void persistent_work_free(PersistentWork *w) {
+    if (!w) return;
+    void *ptrs[] = {w->xb, w->snap, w->ep, w->ptab, w->err, w->xslot, w->teams};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete w;
+}
+
 void persistent_free(PersistentJ *pj) {
     if (!pj) return;
-    void *ptrs[] = {pj->jpk, pj->xb, pj->snap, pj->ep, pj->ptab, pj->err, pj->xslot};
+    PersistentWork &w = pj->work;
+    void *ptrs[] = {pj->jpk, w.xb, w.snap, w.ep, w.ptab, w.err, w.xslot, w.teams};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete pj;
@@ -566,11 +582,30 @@ void persistent_free(PersistentJ *pj) {
 
 int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int N, hipStream_t s,
                    KernelTimer &timer) {
-    const int Rpad = run.Rpad, nrb = pj->nrb, nkb = pj->nkb, nchunk = 2 * nrb;
-    const int nteams_total = Rpad / 32;
+    std::vector<FP4Team> teams((size_t)run.Rpad / 32);
+    for (FP4Team &t : teams) {
+        t.jpk = pj->jpk;
+        t.N = N;
+        t.c0 = run.c0;
+    }
+    return persistent_run_teams(&pj->work, pj->nkb, teams.data(), (int)teams.size(), run, b, N, s,
+                                timer);
+}
+
+int persistent_run_teams(PersistentWork *pw, int nkb, const FP4Team *host_teams,
+                         int nteams_total, const PersistentRun &run, StateBufs &b, int Nrows,
+                         hipStream_t s, KernelTimer &timer) {
+    const int Rpad = run.Rpad, nrb = nkb, nchunk = 2 * nrb;
+    if (nteams_total * 32 > Rpad) return perr(HSB_EINVAL, "FP4 path: teams exceed the columns");
+    int dev = 0, ncu = 0, nb = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(nkb), 256, 0);
+    if (e != hipSuccess) return perr(HSB_EDEVICE, "FP4 path: %s", hipGetErrorString(e));
     // teams per launch: a multiple of 8 (one slot per XCD) whose workgroups all
     // fit on the device at once
-    const int wg_capacity = pj->waves_capacity / 4, wpt = nrb / 4;
+    const int wg_capacity = nb * ncu, wpt = nrb / 4;
     const int teams_per_launch = 8 * (wg_capacity / (8 * wpt));
     if (teams_per_launch < 8)
         return perr(HSB_EUNSUPPORTED, "FP4 path: %d resident workgroups < 8 teams of %d",
@@ -581,25 +616,31 @@ int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int 
     size_t seg_samples = ((size_t)512 << 20) / (snap_per_sample * 4);
     if (seg_samples > 4096) seg_samples = 4096;
     if (seg_samples < 1) seg_samples = 1;
-    int rc = grow(&pj->xb, &pj->xb_words, (size_t)2 * nchunk * Rpad);
-    if (!rc) rc = grow(&pj->snap, &pj->snap_words, (seg_samples + 1) * snap_per_sample);
-    if (!rc) rc = grow(&pj->ep, &pj->ep_elems, (seg_samples + 1) * (size_t)nrb * Rpad);
+    int rc = grow(&pw->xb, &pw->xb_words, (size_t)2 * nchunk * Rpad);
+    if (!rc) rc = grow(&pw->snap, &pw->snap_words, (seg_samples + 1) * snap_per_sample);
+    if (!rc) rc = grow(&pw->ep, &pw->ep_elems, (seg_samples + 1) * (size_t)nrb * Rpad);
     const long long max_seg_steps = (long long)seg_samples * interval;
     const int ptab_need = (int)((long long)(run.k1 - run.k0) < max_seg_steps
                                     ? (run.k1 - run.k0)
                                     : max_seg_steps);
-    if (!rc) rc = grow(&pj->ptab, &pj->ptab_elems, (size_t)(ptab_need > 0 ? ptab_need : 1));
-    if (!rc && pj->xslot_n < (size_t)wg_capacity + 8 * (size_t)wpt) {
-        rc = grow(&pj->xslot, &pj->xslot_n, (size_t)wg_capacity + 8 * (size_t)wpt);
+    if (!rc) rc = grow(&pw->ptab, &pw->ptab_elems, (size_t)(ptab_need > 0 ? ptab_need : 1));
+    size_t one = 0;
+    if (!rc && !pw->err) rc = grow(&pw->err, &one, 1);
+    if (!rc) rc = grow(&pw->teams, &pw->teams_n, (size_t)nteams_total);
+    if (!rc && pw->xslot_n < (size_t)wg_capacity + 8 * (size_t)wpt) {
+        rc = grow(&pw->xslot, &pw->xslot_n, (size_t)wg_capacity + 8 * (size_t)wpt);
         if (!rc) {  // epoch 0xFFFFFFFF in every slot: never a launch's epoch
-            hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((pj->xslot_n + 255) / 256)), dim3(256), 0,
-                               s, pj->xslot, pj->xslot_n);
+            hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((pw->xslot_n + 255) / 256)), dim3(256), 0,
+                               s, pw->xslot, pw->xslot_n);
             if (hipGetLastError() != hipSuccess) rc = perr(HSB_EDEVICE, "xslot fill failed");
         }
     }
     if (rc) return rc;
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, pj->err);
-    hipError_t e = hipGetLastError();
+    e = hipMemcpyAsync(pw->teams, host_teams, sizeof(FP4Team) * (size_t)nteams_total,
+                       hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, pw->err);
+    e = hipGetLastError();
     if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
     const float a0dt = run.a0 * run.dt;
     const void *kfn = pick_kernel(nkb);
@@ -622,7 +663,7 @@ int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int 
             const float ak = (run.a0 * (float)k) / (float)run.Ns;
             ptab[k - a] = run.a0 - ak;
         }
-        e = hipMemcpyAsync(pj->ptab, ptab.data(), sizeof(float) * (size_t)(e_k - a > 0 ? e_k - a : 0),
+        e = hipMemcpyAsync(pw->ptab, ptab.data(), sizeof(float) * (size_t)(e_k - a > 0 ? e_k - a : 0),
                            hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
@@ -630,20 +671,20 @@ int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int 
             int nt = nteams_total - t0 < teams_per_launch ? nteams_total - t0 : teams_per_launch;
             const size_t nxb = (size_t)2 * nchunk * Rpad;
             hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((nxb + 255) / 256)), dim3(256), 0, s,
-                               pj->xb, nxb);
+                               pw->xb, nxb);
             // block b -> team (b/8)/wpt*8 + b%8: round the team count up to 8
             const dim3 grid((unsigned)(8 * ((nt + 7) / 8) * (nrb / 4))), block(256);
-            float c0 = run.c0, dt = run.dt, a0dtv = a0dt;
-            int N_v = N, nkb_v = nkb, nrb_v = nrb, Rpad_v = Rpad, t0_v = t0, nt_v = nt;
-            uint32_t epoch = ++pj->epoch;
-            if (epoch == 0) epoch = ++pj->epoch;  // slots start zeroed: epoch 0 is never used
+            float dt = run.dt, a0dtv = a0dt;
+            int nkb_v = nkb, nrb_v = nrb, Rpad_v = Rpad, t0_v = t0, nt_v = nt;
+            uint32_t epoch = ++pw->epoch;
+            if (epoch == 0) epoch = ++pw->epoch;  // slots start zeroed: epoch 0 is never used
             const float *gam = run.gamma;
-            void *args[] = {(void *)&pj->jpk,   (void *)&run.X,    (void *)&run.Y,   (void *)&gam,
-                            (void *)&pj->xb,    (void *)&pj->snap, (void *)&pj->ep,  (void *)&pj->ptab,
-                            (void *)&b.bad,     (void *)&b.status, (void *)&pj->err, (void *)&pj->xslot,
-                            (void *)&epoch,     (void *)&N_v,      (void *)&nkb_v,   (void *)&nrb_v,
-                            (void *)&Rpad_v,    (void *)&t0_v,     (void *)&nt_v,    (void *)&g,
-                            (void *)&c0,        (void *)&dt,       (void *)&a0dtv};
+            void *args[] = {(void *)&pw->teams, (void *)&run.X,    (void *)&run.Y,   (void *)&gam,
+                            (void *)&pw->xb,    (void *)&pw->snap, (void *)&pw->ep,  (void *)&pw->ptab,
+                            (void *)&b.bad,     (void *)&b.status, (void *)&pw->err, (void *)&pw->xslot,
+                            (void *)&epoch,     (void *)&nkb_v,    (void *)&nrb_v,   (void *)&Rpad_v,
+                            (void *)&t0_v,      (void *)&nt_v,     (void *)&g,       (void *)&dt,
+                            (void *)&a0dtv};
             // every workgroup of the grid is resident at once: the grid never exceeds
             // the occupancy-derived capacity, and every wait inside the kernel is
             // bounded, so a wave that cannot make progress ends the launch cleanly
@@ -654,7 +695,7 @@ int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int 
                 return perr(HSB_EDEVICE, "FP4 persistent launch: %s", hipGetErrorString(e));
         }
         hipLaunchKernelGGL(k_fp4_best, dim3((unsigned)((run.R + 31) / 32)), dim3(256), 0, s,
-                           pj->ep, pj->snap, ns, nrb, N, run.R, Rpad, g, b.best_e, b.last_e,
+                           pw->ep, pw->snap, ns, nrb, Nrows, run.R, Rpad, g, b.best_e, b.last_e,
                            b.best_step, b.bad, b.best_s);
         e = hipGetLastError();
         if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
@@ -662,7 +703,7 @@ int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int 
         a = e_k;
     }
     int32_t herr = 0;
-    e = hipMemcpyAsync(&herr, pj->err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(&herr, pw->err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
     if (herr) return perr(HSB_EDEVICE, "FP4 persistent kernel: exchange wait timed out");

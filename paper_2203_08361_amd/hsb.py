@@ -23,7 +23,7 @@ PLAN_NAMES = {HSB_PLAN_FP32: "fp32", HSB_PLAN_FP4: "fp4", HSB_PLAN_DIGITS: "digi
 HSB_PREC_AUTO, HSB_PREC_FP32, HSB_PREC_MIXED = 0, 1, 2
 
 EXPORTED = ("hsb_create", "hsb_destroy", "hsb_last_error", "hsb_set_option", "hsb_get_option",
-            "hsb_run", "hsb_run_ex", "hsb_plan_info")
+            "hsb_run", "hsb_run_ex", "hsb_plan_info", "hsb_run_batch")
 
 _lib = None
 
@@ -48,6 +48,26 @@ class hsb_run_args(ctypes.Structure):
         ("spins", ctypes.c_void_p), ("energy", ctypes.c_void_p),
         ("best_energy", ctypes.c_void_p), ("final_energy", ctypes.c_void_p),
         ("best_step", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class hsb_job(ctypes.Structure):
+    _fields_ = [
+        ("instance", ctypes.c_int32), ("R", ctypes.c_int32),
+        ("c0", ctypes.c_float), ("gamma", ctypes.c_float),
+        ("seed", ctypes.c_uint64),
+        ("spins", ctypes.c_void_p), ("energy", ctypes.c_void_p),
+    ]
+
+
+class hsb_batch_args(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_size_t),
+        ("variant", ctypes.c_int32), ("steps", ctypes.c_int32),
+        ("a0", ctypes.c_float), ("dt", ctypes.c_float),
+        ("init_amp", ctypes.c_double),
+        ("energy_interval", ctypes.c_int32), ("return_best", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -77,6 +97,9 @@ def load_library():
     L.hsb_run_ex.argtypes = [vp, ctypes.POINTER(hsb_run_args)]
     L.hsb_plan_info.restype = i32
     L.hsb_plan_info.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    L.hsb_run_batch.restype = i32
+    L.hsb_run_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(hsb_job), i32,
+                                ctypes.POINTER(hsb_batch_args)]
     _lib = L
     return L
 
@@ -192,6 +215,41 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
     _check(rc, (HSB_ENUMERIC,) if allow_numeric else ())
     o["status"] = rc
     return o
+
+
+def hsb_run_batch(contexts, jobs, variant, steps, a0, dt, init_amp=0.1, energy_interval=100,
+                  return_best=True, stream=None, allow_numeric=False):
+    """Batch of jobs over several instances (hsb_run_batch).
+
+    contexts: list of Context; jobs: list of dicts with keys instance, R, c0,
+    gamma, seed.  Returns (list of {"spins", "energy"} device tensors, status).
+    """
+    import torch
+
+    dev = torch.device("cuda", torch.cuda.current_device())
+    hs = (ctypes.c_void_p * len(contexts))(*[c.h.value for c in contexts])
+    arr = (hsb_job * max(len(jobs), 1))()
+    outs = []
+    for k, jd in enumerate(jobs):
+        i = jd["instance"]
+        N = contexts[i].N if 0 <= i < len(contexts) else 1  # the library rejects bad indices
+        R = max(jd["R"], 1)
+        o = {"spins": torch.empty((R, N), dtype=torch.int8, device=dev),
+             "energy": torch.empty(R, dtype=torch.float64, device=dev)}
+        outs.append(o)
+        j = arr[k]
+        j.instance, j.R, j.c0, j.gamma = jd["instance"], jd["R"], jd["c0"], jd["gamma"]
+        j.seed = jd["seed"] & (2**64 - 1)
+        j.spins, j.energy = o["spins"].data_ptr(), o["energy"].data_ptr()
+    a = hsb_batch_args()
+    a.struct_size = ctypes.sizeof(hsb_batch_args)
+    a.variant, a.steps, a.a0, a.dt = variant, steps, a0, dt
+    a.init_amp, a.energy_interval, a.return_best = init_amp, energy_interval, int(return_best)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    a.stream = s.cuda_stream
+    rc = load_library().hsb_run_batch(hs, len(contexts), arr, len(jobs), ctypes.byref(a))
+    _check(rc, (HSB_ENUMERIC,) if allow_numeric else ())
+    return outs, rc
 
 
 class Context:

@@ -28,13 +28,15 @@ def test_library_exports_every_declared_symbol():
         assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
 
 
-def test_struct_layout_matches_header(tmp_path):
-    """ctypes layout of hsb_run_args equals what a C compiler makes of the header."""
-    fields = [f[0] for f in hsb.hsb_run_args._fields_]
+@pytest.mark.parametrize("struct", ["hsb_run_args", "hsb_job", "hsb_batch_args"])
+def test_struct_layout_matches_header(tmp_path, struct):
+    """ctypes layout of each argument struct equals what a C compiler makes of the header."""
+    cls = getattr(hsb, struct)
+    fields = [f[0] for f in cls._fields_]
     src = tmp_path / "layout.c"
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"hsb.h\"\nint main(void){\n"
-                   + 'printf("%zu\\n", sizeof(hsb_run_args));\n'
-                   + "".join('printf("%%zu\\n", offsetof(hsb_run_args, %s));\n' % f for f in fields)
+                   + 'printf("%%zu\\n", sizeof(%s));\n' % struct
+                   + "".join('printf("%%zu\\n", offsetof(%s, %s));\n' % (struct, f) for f in fields)
                    + "return 0;}\n")
     exe = tmp_path / "layout"
     import subprocess
@@ -42,9 +44,9 @@ def test_struct_layout_matches_header(tmp_path):
                    check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
-    assert vals[0] == ctypes.sizeof(hsb.hsb_run_args)
+    assert vals[0] == ctypes.sizeof(cls)
     for f, off in zip(fields, vals[1:]):
-        assert getattr(hsb.hsb_run_args, f).offset == off, f
+        assert getattr(cls, f).offset == off, f
 
 
 def _create_rc(J, N=None):
@@ -81,6 +83,9 @@ def test_calls_on_null_context_are_rejected():
     assert L.hsb_run(None, 0, 1.0, 0.1, 1.0, 0.0, 10, 4, 0, None, None) == hsb.HSB_EINVAL
     assert L.hsb_run_ex(None, None) == hsb.HSB_EINVAL
     assert L.hsb_set_option(None, 0, 0.1) == hsb.HSB_EINVAL
+    a = hsb.hsb_batch_args()
+    a.struct_size = ctypes.sizeof(a)
+    assert L.hsb_run_batch(None, 1, None, 0, ctypes.byref(a)) == hsb.HSB_EINVAL
     L.hsb_destroy(None)  # ignored
 
 
