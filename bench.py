@@ -14,6 +14,10 @@ Reported next to it:
     time-to-target of both plans at the same target energy;
   - the ballistic variant (bSB) on the same instance, mixed (integer-digit)
     plan against FP32;
+  - a batched workload: 256 SK instances with N uniform in [100, 2000], each
+    with 64 replicas at each of 8 heating rates (2048 jobs), 5000 steps of
+    heated dSB in one hsb_run_batch call, against per-job runs on the FP32
+    plan (timed on a sample of jobs and scaled to all of them);
   - the roofline of the dominant kernel (FP4 MFMA field + fused update),
     its launch duration measured with HIP events on the run's stream;
   - the CPU oracle timed on a bounded sample of the same workload.
@@ -80,6 +84,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bsb", action="store_true",
                     help="skip the ballistic-variant comparison of the default dSB run")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched uneven-instance workload of the default run")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched uneven-instance workload")
     ap.add_argument("--cpu-replicas", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -184,6 +192,65 @@ def main() -> int:
                  "identical_energies": same,
                  "fp32_frac_of_peak": f["roofline"]["frac"]}, tt)
 
+    def batch_workload():
+        """2048 jobs: 256 SK instances (N uniform in [100, 2000], stream 3, seed 4),
+        8 heating rates, R = 64, 5000 steps of heated dSB, c0 = 0.5/sqrt(N_i)."""
+        sizes = synth.uneven_sizes(256, 4)
+        gammas = [0.0, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1, 0.2]
+        steps_b, R_b = 5000, 64
+        log("batch: building 256 instances")
+        Js = [synth.sk_instance(int(n), 10000 + k) for k, n in enumerate(sizes)]
+        ctxs = [hsb.Context(Jk) for Jk in Js]
+        jobs = [dict(instance=k, R=R_b, c0=0.5 / math.sqrt(int(n)), gamma=g, seed=100 * k + q)
+                for k, n in enumerate(sizes) for q, g in enumerate(gammas)]
+        spin_updates = sum(int(sizes[j["instance"]]) for j in jobs) * R_b * steps_b
+        flops = sum(2.0 * int(sizes[j["instance"]]) ** 2 for j in jobs) * R_b * (steps_b + 1)
+        hsb.hsb_run_batch(ctxs, jobs, hsb.HSB_DSB, steps_b, A0, DT, energy_interval=100)
+        torch.cuda.synchronize()
+        log("batch: warmup done")
+        nt = 2
+        t0 = time.perf_counter()
+        for _ in range(nt):
+            hsb.hsb_run_batch(ctxs, jobs, hsb.HSB_DSB, steps_b, A0, DT, energy_interval=100)
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - t0) / nt
+        log(f"batch: {t_batch * 1e3:.1f} ms per batch")
+        # baseline form: each job on its own through the FP32 plan; every 32nd
+        # instance's first job is timed and scaled to the batch by its share of
+        # the per-job work (N_i^2 with the tile padding of that plan)
+        sample = list(range(0, 256, 32))
+        t_sample, w_sample = 0.0, 0.0
+        for k in sample:
+            ctxs[k].set_option("precision", "fp32")
+            jd = jobs[8 * k]
+            ctxs[k].run_ex(hsb.HSB_DSB, 200, R_b, A0, jd["c0"], DT, jd["gamma"], jd["seed"])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ctxs[k].run_ex(hsb.HSB_DSB, steps_b, R_b, A0, jd["c0"], DT, jd["gamma"], jd["seed"])
+            torch.cuda.synchronize()
+            t_sample += time.perf_counter() - t1
+            w_sample += (math.ceil(int(sizes[k]) / 64) * 64) ** 2
+        w_all = sum((math.ceil(int(sizes[j["instance"]]) / 64) * 64) ** 2 for j in jobs)
+        t_fp32 = t_sample * w_all / w_sample
+        for c in ctxs:
+            c.close()
+        return {"workload": "256 SK +-1 instances, N uniform in [100, 2000] (E[N] ~ 1050), "
+                            "8 gamma values {0, .0025, .005, .01, .02, .05, .1, .2} x R=64, "
+                            "5000 steps heated dSB, one hsb_run_batch call",
+                "jobs": len(jobs), "value": spin_updates / t_batch, "unit": "spin-updates/s",
+                "ms_per_batch": t_batch * 1e3,
+                "algorithmic_tflops": flops / t_batch / 1e12,
+                "frac_fp4_peak": flops / t_batch / 1e12 / KERNELS["fp4"][1],
+                "fp32_per_job_s_estimated": t_fp32,
+                "fp32_estimate_basis": f"{len(sample)} jobs timed on the FP32 plan "
+                                       f"({t_sample:.2f} s), scaled by padded N^2",
+                "speedup_vs_fp32_per_job": t_fp32 / t_batch}
+
+    if args.batch_only:
+        print(json.dumps({"batch": batch_workload()}), flush=True)
+        ctx.close()
+        return 0
+
     main_res = measure(variant, args.steps, args.warmup)
     plan = main_res["plan"]
     result = {
@@ -209,6 +276,8 @@ def main() -> int:
         if not args.no_fp32 and b["plan"] != "fp32":
             bsb["fp32_plan"], bsb["time_to_target"] = fp32_compare(hsb.HSB_BSB, b)
         result["bsb"] = bsb
+    if args.variant == "dsb" and not args.no_batch:
+        result["batch"] = batch_workload()
 
     if not args.no_cpu_baseline:
         import oracle
