@@ -40,7 +40,7 @@ GAMMA, DT, A0 = 0.01, 1.0, 1.0
 KERNELS = {"fp4": ("k_dsb_fp4", 10100.0, "fp4"),
            "digits": ("k_i8_field", 5000.0, "int8"),
            "fp32": ("k_step_fp32", 157.3, "fp32")}
-DTYPES = {"fp4": "fp4 x fp4 -> fp32 field (exact), fp32 state",
+DTYPES = {"fp4": "fp4 x fp4 -> fp32 field, fp32 state",
           "digits": "int8 digits -> int32 field (exactly rounded), fp32 state",
           "fp32": "fp32"}
 
@@ -150,20 +150,25 @@ def main() -> int:
         launches = int(ctx.get_option("kernel_launches"))
         ctx.set_option("timing", 0)
         # algorithmic work of the timed kernel launches: 2 N^2 R flops per field;
-        # the persistent FP4 kernel also forms the field of the final sampled state
-        fields = Ns + 1 if plan_kind == "fp4" else Ns
+        # the persistent dSB kernel also forms the field of the final sampled state
+        fields = Ns + 1 if (plan_kind == "fp4" and var == hsb.HSB_DSB) else Ns
         flops = 2.0 * N * N * R * fields
         avg_ms = kern_ms / max(launches, 1)
         achieved = flops / (kern_ms * 1e-3) / 1e12
         kname, peak, peak_dtype = KERNELS[plan_kind]
-        traffic = measured_traffic(kname, f"N{N}_R{R}") if Ns == SB_STEPS else None
+        if plan_kind == "fp4" and var == hsb.HSB_BSB:
+            kname = "k_bsb_fp4"
+        # per-launch HBM bytes: the persistent kernel's depend on the run length,
+        # a per-step kernel's do not
+        traffic = (measured_traffic(kname, f"N{N}_R{R}")
+                   if Ns == SB_STEPS or plan_kind != "fp4" else None)
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 5), "traffic": traffic,
                 "kernel": kname, "peak_dtype": peak_dtype, "avg_launch_ms": round(avg_ms, 5),
                 "launches_per_run": launches}
-        if plan_kind == "digits":
-            # int8 operations issued per algorithmic flop: one per x digit
-            roof["issued_per_algorithmic"] = 4 if var == hsb.HSB_BSB else 1
+        if var == hsb.HSB_BSB and plan_kind != "fp32":
+            # matrix-core operations issued per algorithmic flop: one per x digit
+            roof["issued_per_algorithmic"] = 4 if plan_kind == "digits" else 8
         return {"ms_per_run": ms_run, "value": N * R * Ns / (ms_run * 1e-3), "plan": plan_kind,
                 "best": torch.stack(best).cpu().numpy(), "roofline": roof}
 

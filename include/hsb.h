@@ -75,12 +75,13 @@ typedef enum {
     HSB_OPT_RETURN_BEST = 2,     /* 1 (default): return the best sampled spins and energy;
                                     0: return the final state's */
     HSB_OPT_PRECISION = 3,       /* hsb_precision; default HSB_PREC_AUTO */
-    HSB_OPT_TIMING = 4,          /* 1: bracket every launch of the dominant kernel (the
+    HSB_OPT_TIMING = 4,          /* 1: bracket the launches of the dominant kernel (the
                                     field+update kernel of the plan) with HIP events on the
-                                    run's stream; default 0 */
-    HSB_OPT_KERNEL_MS = 5,       /* read only: summed event time (ms) of those launches in
-                                    the last run with timing on (synchronises the events) */
-    HSB_OPT_KERNEL_LAUNCHES = 6, /* read only: number of those launches in that run */
+                                    run's stream, one bracket per run of consecutive
+                                    launches between two energy samples; default 0 */
+    HSB_OPT_KERNEL_MS = 5,       /* read only: summed bracketed time (ms) of the last run with
+                                    timing on (synchronises the events) */
+    HSB_OPT_KERNEL_LAUNCHES = 6, /* read only: number of launches inside those brackets */
     HSB_OPT_LAST_PLAN = 7        /* read only: plan of the last successful run, an hsb_plan */
 } hsb_option;
 

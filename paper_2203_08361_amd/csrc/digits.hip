@@ -475,6 +475,7 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
     };
     if (k1 == k0) return sample(k0);
     int cur = 0;
+    size_t nrun = 0;  // step launches since the last energy sample
     for (int k = k0; k < k1; ++k) {
         // a(t_k) = a0 k / Ns in single precision; p = a0 - a(t_k)
         const float ak = (a0 * (float)k) / (float)run.Ns;
@@ -494,10 +495,13 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
                         : launch_field<4, 1, 2, false>(p, xin, xout, b, Nst, Rpad, pk, c0, dt,
                                                        a0dt, s);
         }
-        if (e == hipSuccess) e = timer.end(s);
         if (e != hipSuccess) return derr(HSB_EDEVICE, "digit step: %s", hipGetErrorString(e));
+        ++nrun;
         cur ^= 1;
         if (is_sample(k + 1)) {
+            e = timer.end(s, nrun);
+            if (e != hipSuccess) return derr(HSB_EDEVICE, "%s", hipGetErrorString(e));
+            nrun = 0;
             rc = sample(k + 1);
             if (rc) return rc;
         }

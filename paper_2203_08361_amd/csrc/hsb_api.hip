@@ -59,6 +59,7 @@ struct hsb_ctx {
     hsb::PersistentJ *pj = nullptr;  // FP4 J store for the persistent dSB path (lazy)
     hsb::I8J *i8 = nullptr;          // integer-digit J store (lazy)
     hsb::PersistentWork *bwork = nullptr;  // scratch of batched FP4 runs led by this context
+    int32_t *d_flag = nullptr;             // start-state bound check
     std::vector<float> hJ;      // host copy kept for lazy device re-layouts
     // options
     double init_amp = 0.1;
@@ -173,6 +174,7 @@ extern "C" void hsb_destroy(hsb_ctx *h) {
     if (h->pj) hsb::persistent_free(h->pj);
     if (h->i8) hsb::i8_free(h->i8);
     if (h->bwork) hsb::persistent_work_free(h->bwork);
+    if (h->d_flag) (void)hipFree(h->d_flag);
     h->timer.release();
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -228,7 +230,7 @@ extern "C" int hsb_get_option(hsb_ctx *h, int key, double *v) {
         *v = ms;
         return HSB_OK;
     }
-    case HSB_OPT_KERNEL_LAUNCHES: *v = (double)h->timer.used; return HSB_OK;
+    case HSB_OPT_KERNEL_LAUNCHES: *v = (double)h->timer.launches; return HSB_OK;
     case HSB_OPT_LAST_PLAN: *v = h->last_plan; return HSB_OK;
     default: return fail(HSB_EINVAL, "unknown option key %d", key);
     }
@@ -248,7 +250,7 @@ enum Plan { PLAN_FP32 = HSB_PLAN_FP32, PLAN_FP4 = HSB_PLAN_FP4, PLAN_DIGITS = HS
 //          for dSB with integer J in [-127, 127] (both as accurate as FP32 or
 //          exact); FP32 otherwise.
 int choose_plan(const hsb_ctx *h, int variant, int *plan) {
-    const bool fp4_ok = variant == HSB_DSB && h->j_fp4_exact && hsb::persistent_supported(h->N);
+    const bool fp4_ok = h->j_fp4_exact && hsb::persistent_supported(h->N);
     const bool dig_ok = h->N <= hsb::i8_max_n();
     if (h->precision == HSB_PREC_FP32) {
         *plan = PLAN_FP32;
@@ -353,23 +355,24 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
         return HSB_OK;
     };
 
-    if (plan == PLAN_DIGITS) {
-        if (!h->i8) {
-            rc = hsb::i8_create(h->hJ.data(), N, &h->i8);
-            if (rc != HSB_OK) return fail(rc, "%s", hsb::i8_error());
+    if (a->variant == HSB_BSB && plan != PLAN_FP32) {
+        // the digit representations of x need |x| <= 1 in the start state (the
+        // walls of eqs. (18)-(21) keep it so afterwards)
+        if (!h->d_flag) HIP_TRY(hipMalloc((void **)&h->d_flag, sizeof(int32_t)));
+        int32_t over = 0;
+        HIP_TRY(hsb::launch_bound_check(b.X, (size_t)Npad * Rpad, h->d_flag, s));
+        HIP_TRY(hipMemcpyAsync(&over, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (over) {
+            if (h->precision == HSB_PREC_MIXED)
+                return fail(HSB_EUNSUPPORTED,
+                            "MIXED bSB needs |x| <= 1 and finite in the start state");
+            plan = PLAN_FP32;
         }
-        if (a->variant == HSB_BSB) {
-            // the x digits need |x| <= 1 in the start state (the walls keep it so)
-            bool ok = true;
-            rc = hsb::i8_start_state_ok(h->i8, b.X, (size_t)Npad * Rpad, s, &ok);
-            if (rc != HSB_OK) return fail(rc, "%s", hsb::i8_error());
-            if (!ok) {
-                if (h->precision == HSB_PREC_MIXED)
-                    return fail(HSB_EUNSUPPORTED,
-                                "MIXED bSB needs |x| <= 1 and finite in the start state");
-                plan = PLAN_FP32;
-            }
-        }
+    }
+    if (plan == PLAN_DIGITS && !h->i8) {
+        rc = hsb::i8_create(h->hJ.data(), N, &h->i8);
+        if (rc != HSB_OK) return fail(rc, "%s", hsb::i8_error());
     }
     if (plan == PLAN_DIGITS) {
         hsb::I8Run ir{};
@@ -390,7 +393,7 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
         pr.k0 = k0; pr.k1 = k1; pr.Ns = Ns; pr.interval = interval;
         pr.a0 = a0; pr.c0 = c0; pr.dt = dt;
         pr.epart = b.epart;
-        rc = hsb::persistent_run(h->pj, pr, b, N, s, h->timer);
+        rc = hsb::persistent_run(h->pj, a->variant, pr, b, N, s, h->timer);
         if (rc != HSB_OK) return fail(rc, "%s", hsb::persistent_error());
     } else {
         if (a->steps == 0) {
@@ -399,6 +402,7 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
         } else {
             HIP_TRY(hsb::launch_make_operand(b.B[0], b.X, a->variant, Npad, Rpad, s));
             int cur = 0;
+            size_t nrun = 0;  // step launches since the last energy sample
             for (int k = k0; k < k1; ++k) {
                 // a(t_k) = a0 k / Ns in single precision; p = a0 - a(t_k)
                 const float ak = (a0 * (float)k) / (float)Ns;
@@ -406,9 +410,11 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
                 HIP_TRY(h->timer.begin(s));
                 HIP_TRY(hsb::launch_step_fp32(a->variant, h->dJ, b.B[cur], b.B[cur ^ 1], b.X, b.Y,
                                               b.gamma, Npad, Rpad, p, c0, dt, a0dt, s));
-                HIP_TRY(h->timer.end(s));
+                ++nrun;
                 cur ^= 1;
                 if (is_sample(k + 1)) {
+                    HIP_TRY(h->timer.end(s, nrun));
+                    nrun = 0;
                     rc = sample(k + 1);
                     if (rc) return rc;
                 }
@@ -506,7 +512,8 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
         int plan = 0;
         const int rc = choose_plan(hs[jb.instance], a->variant, &plan);
         if (rc != HSB_OK) return rc;
-        if (plan == PLAN_FP4)
+        // bSB's digit representation of x needs |x| <= 1 at the start
+        if (plan == PLAN_FP4 && !(a->variant == HSB_BSB && amp > 1.0))
             classes[(hs[jb.instance]->N + 255) / 256 * 4].push_back(j);
         else
             singles.push_back(j);
@@ -606,8 +613,8 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
         pr.Npad = Nst; pr.Rpad = Rtot; pr.R = used;
         pr.k0 = 0; pr.k1 = a->steps; pr.Ns = a->steps; pr.interval = interval;
         pr.a0 = a->a0; pr.c0 = 0.0f; pr.dt = a->dt;
-        int rc = hsb::persistent_run_teams(lead->bwork, nkb, teams.data(), (int)teams.size(), pr,
-                                           bb, Nst, s, lead->timer);
+        int rc = hsb::persistent_run_teams(lead->bwork, a->variant, nkb, teams.data(),
+                                           (int)teams.size(), pr, bb, Nst, s, lead->timer);
         if (rc != HSB_OK) return done(fail(rc, "%s", hsb::persistent_error()));
         for (size_t q = 0; q < cj.size() && e == hipSuccess; ++q) {
             const hsb_job &jb = jobs[cj[q]];

@@ -9,17 +9,24 @@
 
 namespace hsb {
 
-// HIP-event brackets around launches of a run's dominant kernel.
+// HIP-event brackets around launches of a run's dominant kernel.  A bracket
+// may hold several back-to-back launches of that kernel (the per-step plans
+// bracket each run of consecutive steps between two energy samples), so the
+// average launch duration is the bracketed time over the launch count.
 struct KernelTimer {
     bool on = false;
-    size_t used = 0;
+    bool open = false;
+    size_t used = 0;      // closed brackets
+    size_t launches = 0;  // launches inside them
     std::vector<hipEvent_t> ev;  // pairs: begin, end
     void reset(bool enable) {
         on = enable;
+        open = false;
         used = 0;
+        launches = 0;
     }
     hipError_t begin(hipStream_t s) {
-        if (!on) return hipSuccess;
+        if (!on || open) return hipSuccess;
         if (ev.size() < 2 * (used + 1)) {
             for (int q = 0; q < 2; ++q) {
                 hipEvent_t e;
@@ -28,12 +35,16 @@ struct KernelTimer {
                 ev.push_back(e);
             }
         }
+        open = true;
         return hipEventRecord(ev[2 * used], s);
     }
-    hipError_t end(hipStream_t s) {
-        if (!on) return hipSuccess;
+    // close the open bracket, which held n launches
+    hipError_t end(hipStream_t s, size_t n = 1) {
+        if (!on || !open) return hipSuccess;
         hipError_t rc = hipEventRecord(ev[2 * used + 1], s);
         ++used;
+        launches += n;
+        open = false;
         return rc;
     }
     hipError_t total_ms(double *ms) const {
@@ -52,6 +63,8 @@ struct KernelTimer {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         ev.clear();
         used = 0;
+        launches = 0;
+        open = false;
     }
 };
 
@@ -85,6 +98,8 @@ hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int 
 hipError_t alloc_state(StateBufs &b, int Npad, int Rpad);
 void free_state_bufs(StateBufs &b);
 hipError_t launch_reset_tracking(const StateBufs &b, int Rpad, hipStream_t s);
+// *flag (device) = 1 if any of X[0 .. n) has |x| > 1 or is not finite, else 0
+hipError_t launch_bound_check(const float *X, size_t n, int32_t *flag, hipStream_t s);
 hipError_t launch_step_fp32(int variant, const float *J, const float *Bin, float *Bout, float *X,
                             float *Y, const float *gamma, int Npad, int Rpad, float p, float c0,
                             float dt, float a0dt, hipStream_t s);

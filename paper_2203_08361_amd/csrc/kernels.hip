@@ -328,6 +328,15 @@ __global__ void k_output_energy(const double *__restrict__ best_e,
     if (best_step) best_step[r] = best_step_in[r];
 }
 
+// flag[0] = 1 if any of the n values has |x| > 1 or is not finite
+__global__ void k_bound_flag(const float *__restrict__ X, size_t n, int32_t *flag) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    if (!(fabsf(X[e]) <= 1.0f)) atomicOr(flag, 1);
+}
+
+__global__ void k_clear_i32(int32_t *p) { p[0] = 0; }
+
 // ------------------------------------------------------------ launchers
 
 void free_state_bufs(StateBufs &b) {
@@ -388,6 +397,12 @@ hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int 
                              hipStream_t s) {
     hipLaunchKernelGGL(k_fill_gamma, dim3(cdiv(Rpad, 256)), dim3(256), 0, s, g, gamma_rep, gamma,
                        R, Rpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_bound_check(const float *X, size_t n, int32_t *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(1), 0, s, flag);
+    hipLaunchKernelGGL(k_bound_flag, dim3(cdiv(n, 256)), dim3(256), 0, s, X, n, flag);
     return hipGetLastError();
 }
 

@@ -33,15 +33,16 @@ const char *persistent_error();
 int persistent_create(const float *J, int N, PersistentJ **out);
 void persistent_free(PersistentJ *pj);
 // Runs steps k0 .. k1-1 with energy samples, updating the tracking buffers of `b`.
-int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int N, hipStream_t s,
-                   KernelTimer &timer);
+// variant HSB_DSB: field J sgn(x) (exact); HSB_BSB: field J x from base-8 digits of x.
+int persistent_run(PersistentJ *pj, int variant, const PersistentRun &run, StateBufs &b, int N,
+                   hipStream_t s, KernelTimer &timer);
 // The same for a batch: team t owns columns [32 t, 32 t + 32) of the state
 // (run.Rpad columns, run.R of them real) and runs the instance host_teams[t];
 // every instance has `nkb` K blocks (the same padded size).  Nrows: rows of
 // the state decoded into best spins.
-int persistent_run_teams(PersistentWork *w, int nkb, const FP4Team *host_teams, int nteams,
-                         const PersistentRun &run, StateBufs &b, int Nrows, hipStream_t s,
-                         KernelTimer &timer);
+int persistent_run_teams(PersistentWork *w, int variant, int nkb, const FP4Team *host_teams,
+                         int nteams, const PersistentRun &run, StateBufs &b, int Nrows,
+                         hipStream_t s, KernelTimer &timer);
 int persistent_work_create(PersistentWork **out);
 void persistent_work_free(PersistentWork *w);
 int persistent_nkb(const PersistentJ *pj);

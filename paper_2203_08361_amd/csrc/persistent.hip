@@ -60,6 +60,14 @@ struct PersistentWork {
     uint32_t epoch = 0;          // launches so far
     FP4Team *teams = nullptr;    // [nteams] per-team J, N and c0
     size_t teams_n = 0;
+    // bSB exchange: digit fragments [2][nkb][8][2 Rpad], chunk exponents
+    // [2][2 Rpad][nkb], step flags [nteams][nrb]
+    v4i *xd = nullptr;
+    size_t xd_n = 0;
+    uint8_t *xe = nullptr;
+    size_t xe_n = 0;
+    uint32_t *flags = nullptr;
+    size_t flags_n = 0;
 };
 
 struct PersistentJ {
@@ -425,6 +433,354 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     }
 }
 
+// --------------------------------------------------- persistent bSB (FP4 digits)
+//
+// Field (eq. (4)): f = J x.  J is held exactly as FP4, as for dSB.  x is fed
+// to the same FP4 x FP4 products as eight base-8 digits: for each 32-row
+// chunk of one replica, with E the exponent of the chunk's largest |x|
+// (max |x| <= 2^E, E clamped to [-100, 1]),
+//   Q_i = rint(x_i 2^(22-E)),  |Q_i| <= 2^22,
+//   Q_i + 0x924924 = sum_k u_ik 8^(7-k), u in [0, 7]  (balanced digits d = u - 4),
+//   x_i = sum_k d_ik 2^(E-1-3k)  up to 2^(E-23).
+// Every digit is an integer in [-4, 3], exact in E2M1, and digit k's weight
+// 2^(E-1-3k) is the operand's per-lane E8M0 block scale (lane l's scale
+// covers its 32 K values).  So f = sum_k J d_k 2^(E-1-3k) runs on the FP4
+// matrix cores with FP32 accumulation: 8 products per K block per tile.
+//
+// Exchange.  Every step each wave writes, for its two chunks and the team's
+// 32 replicas, the digit fragments already in the MFMA operand layout
+// (16 bytes per lane per digit) and the chunk exponents, waits until its
+// stores are done, then sets its step flag.  Readers poll the flags of the
+// team, invalidate their L1 (agent-scope acquire) and stage the fragments
+// through LDS in phases of 4 K blocks, double-buffered behind the products.
+// Parity buffers by step: the writer of step m+2 has read all of step m+1,
+// whose writers had finished reading step m.
+// Samples: the sign words of each sampled state go to `snap`; the energies
+// are formed after the launch (k_energy_fp4).
+
+constexpr int kXD = 8;   // base-8 digits per x
+constexpr int kPB = 4;   // K blocks per staging phase (one per wave)
+
+__device__ __forceinline__ void mfma_fp4s(v16f &acc, const v4i &j, const v4i &b, int sa, int sb) {
+    asm volatile(
+        "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, %0, %3, %4 op_sel_hi:[0,0,0] cbsz:4 blgp:4"
+        : "+v"(acc)
+        : "a"(j), "v"(b), "v"(sa), "v"(sb));
+}
+__device__ __forceinline__ void mfma_fp4s_first(v16f &acc, const v4i &j, const v4i &b, int sa,
+                                                int sb) {
+    asm volatile(
+        "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, 0, %3, %4 op_sel_hi:[0,0,0] cbsz:4 blgp:4"
+        : "=&v"(acc)
+        : "a"(j), "v"(b), "v"(sa), "v"(sb));
+}
+
+__device__ __forceinline__ uint32_t ld_flag(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Digit fragments of one tile.  Lane (h, l%32) holds 16 rows (item v: row
+// 8(v/4) + 4h + v%4 of the chunk) of replica l%32.  Returns the biased
+// exponent E + 128 of the chunk and fills frag[j][q] (j = 0..3) with the four
+// complete 16-byte fragments of digits 4h + j, after swapping halves with lane
+// l^32: dword q of digit k holds the rows of word bits 4n + 3 - q (n = 0..7),
+// low half from the lane with h = 0.
+__device__ __forceinline__ uint32_t make_digits(const float (&xs)[16], int half, v4i (&frag)[4]) {
+    float mx = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) mx = fmaxf(mx, fabsf(xs[v]));
+    mx = fmaxf(mx, __shfl_xor(mx, 32));
+    int E = (int)((__float_as_uint(mx) >> 23) & 0xFFu) - 126;  // mx < 2^E for normal mx
+    E = E < -100 ? -100 : (E > 1 ? 1 : E);
+    const float sc = __uint_as_float((uint32_t)(149 - E) << 23);  // 2^(22 - E)
+    uint32_t U[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) U[v] = (uint32_t)((int)rintf(xs[v] * sc) + 0x924924);
+    // half-word of digit k for dword q: the codes of rows v = 4n + 3 - q, n = 0..3
+    auto halfword = [&](int k, int q) {
+        const int sh = 21 - 3 * k;
+        const uint32_t sel = ((U[3 - q] >> sh) & 7u) | (((U[7 - q] >> sh) & 7u) << 8) |
+                             (((U[11 - q] >> sh) & 7u) << 16) | (((U[15 - q] >> sh) & 7u) << 24);
+        // E2M1 codes of d = u - 4: -4 -3 -2 -1 0 1 2 3
+        const uint32_t c = __builtin_amdgcn_perm(0x05040200u, 0x0A0C0D0Eu, sel);
+        const uint32_t t = c | (c >> 4);
+        return __builtin_amdgcn_perm(0u, t, 0x0C0C0200u);
+    };
+    // lane h keeps digits 4h + j: it sends the partner its half-words of those
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t lo = halfword(j, q), hi = halfword(4 + j, q);
+            const uint32_t mine = half ? hi : lo;
+            const uint32_t give = half ? lo : hi;
+            const uint32_t got = (uint32_t)__shfl_xor((int)give, 32);
+            frag[j][q] = (int)(half ? (got | (mine << 16)) : (mine | (got << 16)));
+        }
+    }
+    return (uint32_t)(E + 128);
+}
+
+template <int NKB>
+__global__ __launch_bounds__(256, 1) void k_bsb_fp4(
+    const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
+    const float *__restrict__ gamma, v4i *xd, uint8_t *xe, uint32_t *flags,
+    uint32_t *__restrict__ snap, const float *__restrict__ ptab, int32_t *__restrict__ bad,
+    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, uint32_t epoch, int nkb, int nrb,
+    int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
+    static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
+    constexpr int NPH = NKB / kPB;  // staging phases per step
+    __shared__ v4i f_lds[2][kPB][kXD][64];
+    __shared__ int wg_abort;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wpt = nrb >> 2;
+    const int xcd = blockIdx.x & 7, kx = blockIdx.x >> 3;
+    const int tl = (kx / wpt) * 8 + xcd;
+    if (tl >= nteams) return;
+    const int team = team0 + tl;
+    const v4i *__restrict__ jpk = static_cast<const v4i *>(teams[team].jpk);
+    const int N = teams[team].N;
+    const float c0 = teams[team].c0;
+    const int rb = (kx % wpt) * 4 + w;
+    const int r0 = team * 32;
+    const int nchunk = 2 * nrb;
+    const int half = lane >> 5, l32 = lane & 31;
+    const size_t cols = (size_t)2 * Rpad;  // exchange columns: team * 64 + lane
+    const int col = team * 64 + lane;
+    uint32_t *myflag = flags + (size_t)team * nrb + rb;
+    if (threadIdx.x == 0) wg_abort = 0;
+
+    const int my_xcc = xcc_id();
+    if (threadIdx.x == 0) st_tagged(xslot + blockIdx.x, ((uint64_t)epoch << 32) | (uint32_t)my_xcc);
+    bool xcd_local;
+    {
+        const int mb = 8 * (wpt * (tl >> 3) + (lane < wpt ? lane : 0)) + (tl & 7);
+        uint64_t v = ld_tagged(xslot + mb);
+        const uint64_t t0 = wall_clock64();
+        bool ok = true;
+        while (__any((uint32_t)(v >> 32) != epoch)) {
+            __builtin_amdgcn_s_sleep(1);
+            v = ld_tagged(xslot + mb);
+            if (wall_clock64() - t0 > kTimeoutTicks) {
+                ok = false;
+                break;
+            }
+        }
+        xcd_local = ok && __all((int)(uint32_t)v == my_xcc);
+    }
+
+    v4i jr0[NKB], jr1[NKB];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+        jr0[kb] = jpk[((size_t)(rb * 2 + 0) * NKB + kb) * 64 + lane];
+        jr1[kb] = jpk[((size_t)(rb * 2 + 1) * NKB + kb) * 64 + lane];
+    }
+    const int one = 127;
+
+    float xs0[16], xs1[16], ys0[16], ys1[16];
+    const int rep = r0 + l32;
+    const float gdt = gamma[rep] * dt;
+    const int rowb = rb * 64 + 4 * half;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row0 = rowb + 8 * (v >> 2) + (v & 3), row1 = row0 + 32;
+        xs0[v] = row0 < N ? X[(size_t)row0 * Rpad + rep] : 0.0f;
+        xs1[v] = row1 < N ? X[(size_t)row1 * Rpad + rep] : 0.0f;
+        ys0[v] = row0 < N ? Y[(size_t)row0 * Rpad + rep] : 0.0f;
+        ys1[v] = row1 < N ? Y[(size_t)row1 * Rpad + rep] : 0.0f;
+    }
+
+    // publish the digits of x_m: fragments of chunk 2 rb + t go to K block rb,
+    // consumer half t; then the step flag
+    auto publish = [&](int m) {
+        const int par = m & 1;
+        v4i fr[4];
+        uint32_t eb = make_digits(xs0, half, fr);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            xd[(((size_t)par * nkb + rb) * kXD + 4 * half + j) * cols + team * 64 + l32] = fr[j];
+        if (half == 0) xe[((size_t)par * cols + team * 64 + l32) * nkb + rb] = (uint8_t)eb;
+        eb = make_digits(xs1, half, fr);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            xd[(((size_t)par * nkb + rb) * kXD + 4 * half + j) * cols + team * 64 + 32 + l32] = fr[j];
+        if (half == 0) xe[((size_t)par * cols + team * 64 + 32 + l32) * nkb + rb] = (uint8_t)eb;
+        // release: the fragments are in the L2 before the flag
+        if (xcd_local)  // stores acknowledged by the L2 (the memory clobber keeps them above)
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        else
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) __hip_atomic_store(myflag, (uint32_t)m, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    };
+    // sign words of the sampled state x_m (the energy is formed afterwards)
+    auto snapshot = [&](int m) {
+        uint32_t b0 = 0, b1 = 0;
+        bool fin = true;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            b0 |= (xs0[v] >= 0.0f ? 0u : 1u) << v;
+            b1 |= (xs1[v] >= 0.0f ? 0u : 1u) << v;
+            fin = fin && isfinite(xs0[v]) && isfinite(xs1[v]) && isfinite(ys0[v]) && isfinite(ys1[v]);
+        }
+        const uint32_t got = (uint32_t)__shfl_xor((int)(half ? b0 : b1), 32);
+        const uint32_t word = half ? (got | (b1 << 16)) : (b0 | (got << 16));
+        const size_t slot = (size_t)(rb * 2 + half) * Rpad + rep;
+        snap[(size_t)seg_sample_index(g, m) * nchunk * Rpad + slot] = word;
+        if (!fin) {
+            bad[rep] = 1;
+            status[0] = 1;
+        }
+    };
+
+    if (g.seg_k0 < g.seg_k1) publish(g.seg_k0);
+    for (int m = g.seg_k0;; ++m) {
+        // the energy of a sampled state needs only its signs
+        if (seg_is_sample(g, m)) snapshot(m);
+        if (m == g.seg_k1) break;
+        const int par = m & 1;
+        const float p = ptab[m - g.seg_k0];
+        // wait for every wave of the team to have published x_m
+        {
+            const uint32_t *fp = flags + (size_t)team * nrb + (lane < nrb ? lane : 0);
+            uint32_t f = ld_flag(fp);
+            const uint64_t t0 = wall_clock64();
+            int it = 0;
+            while (__any((uint32_t)(f - (uint32_t)m) > 1u)) {
+                __builtin_amdgcn_s_sleep(1);
+                f = ld_flag(fp);
+                if ((++it & 31) == 0) {
+                    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                        wall_clock64() - t0 > kTimeoutTicks) {
+                        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        wg_abort = 1;
+                        break;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // no stale L1 lines
+        }
+        // chunk exponents of this lane's column for every K block
+        uint32_t ed[NKB / 4];
+        {
+            const uint32_t *ep4 =
+                reinterpret_cast<const uint32_t *>(xe + ((size_t)par * cols + col) * nkb);
+#pragma unroll
+            for (int q = 0; q < NKB / 4; ++q) ed[q] = ep4[q];
+        }
+        // staging: wave w loads K block kPB ph + w of phase ph
+        v4i stg[kXD];
+        auto load_stage = [&](int ph) {
+            const int kb = kPB * ph + w;
+#pragma unroll
+            for (int k = 0; k < kXD; ++k)
+                stg[k] = xd[(((size_t)par * nkb + kb) * kXD + k) * cols + col];
+        };
+        auto store_stage = [&](int buf) {
+#pragma unroll
+            for (int k = 0; k < kXD; ++k) f_lds[buf][w][k][lane] = stg[k];
+        };
+        load_stage(0);
+        store_stage(0);
+        __syncthreads();
+        if (wg_abort) break;
+        v16f acc0, acc1;
+#pragma unroll
+        for (int ph = 0; ph < NPH; ++ph) {
+            const int buf = ph & 1;
+            if (ph + 1 < NPH) load_stage(ph + 1);
+            // operand reads from LDS run kPre fragments ahead of the products
+            constexpr int kPre = 4, kFr = kPB * kXD;
+            v4i af[kPre];
+#pragma unroll
+            for (int q = 0; q < kPre; ++q) af[q] = f_lds[buf][q / kXD][q % kXD][lane];
+#pragma unroll
+            for (int fi = 0; fi < kFr; ++fi) {
+                const int kl = fi / kXD, k = fi % kXD;
+                const int kb = kPB * ph + kl;
+                const v4i a = af[fi % kPre];
+                if (fi + kPre < kFr)
+                    af[fi % kPre] = f_lds[buf][(fi + kPre) / kXD][(fi + kPre) % kXD][lane];
+                const int e = (int)((ed[kb >> 2] >> (8 * (kb & 3))) & 0xFFu);
+                const int sb = e - 2 - 3 * k;  // 127 + (E - 1 - 3k), E = e - 128
+                if (kb == 0 && k == 0) {
+                    mfma_fp4s_first(acc0, jr0[0], a, one, sb);
+                    mfma_fp4s_first(acc1, jr1[0], a, one, sb);
+                } else {
+                    mfma_fp4s(acc0, jr0[kb], a, one, sb);
+                    mfma_fp4s(acc1, jr1[kb], a, one, sb);
+                }
+            }
+            if (ph + 1 < NPH) store_stage(buf ^ 1);
+            __syncthreads();
+        }
+        mfma_drain(acc0, acc1);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            sb_update(acc0[v], p, c0, dt, a0dt, gdt, xs0[v], ys0[v]);
+            sb_update(acc1[v], p, c0, dt, a0dt, gdt, xs1[v], ys1[v]);
+        }
+        if (m + 1 < g.seg_k1) publish(m + 1);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row0 = rowb + 8 * (v >> 2) + (v & 3), row1 = row0 + 32;
+        if (row0 < N) {
+            X[(size_t)row0 * Rpad + rep] = xs0[v];
+            Y[(size_t)row0 * Rpad + rep] = ys0[v];
+        }
+        if (row1 < N) {
+            X[(size_t)row1 * Rpad + rep] = xs1[v];
+            Y[(size_t)row1 * Rpad + rep] = ys1[v];
+        }
+    }
+}
+
+// Energy partials of sampled states from their sign words (eq. (1)):
+// F = J sgn(x) on the FP4 matrix cores, then per wave sum_i s_i F_i of its 64
+// rows.  Grid (teams x row-block groups, samples), 256 threads.
+template <int NKB>
+__global__ __launch_bounds__(256) void k_energy_fp4(const FP4Team *__restrict__ teams,
+                                                    const uint32_t *__restrict__ snap,
+                                                    float *__restrict__ ep, int nrb, int Rpad,
+                                                    int team0) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wpt = nrb >> 2;
+    const int team = team0 + blockIdx.x / wpt;
+    const int rb = (blockIdx.x % wpt) * 4 + w;
+    const int j = blockIdx.y;
+    const int nchunk = 2 * nrb;
+    const int half = lane >> 5, l32 = lane & 31;
+    const int rep = team * 32 + l32;
+    const v4i *__restrict__ jpk = static_cast<const v4i *>(teams[team].jpk);
+    const uint32_t *sw = snap + (size_t)j * nchunk * Rpad;
+    v16f acc0 = {}, acc1 = {};
+#pragma unroll 4
+    for (int kb = 0; kb < NKB; ++kb) {
+        const v4i a = expand_signs(sw[(size_t)(2 * kb + half) * Rpad + rep]);
+        const v4i j0 = jpk[((size_t)(rb * 2 + 0) * NKB + kb) * 64 + lane];
+        const v4i j1 = jpk[((size_t)(rb * 2 + 1) * NKB + kb) * 64 + lane];
+        v8i a8 = {a[0], a[1], a[2], a[3], 0, 0, 0, 0};
+        v8i b0 = {j0[0], j0[1], j0[2], j0[3], 0, 0, 0, 0};
+        v8i b1 = {j1[0], j1[1], j1[2], j1[3], 0, 0, 0, 0};
+        acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(b0, a8, acc0, 4, 4, 0, 127, 0, 127);
+        acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(b1, a8, acc1, 4, 4, 0, 127, 0, 127);
+    }
+    // signs of this wave's rows: word bit of row t in chunk 2 rb + tile
+    const uint32_t w0 = sw[(size_t)(2 * rb) * Rpad + rep];
+    const uint32_t w1 = sw[(size_t)(2 * rb + 1) * Rpad + rep];
+    float part = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int t = 8 * (v >> 2) + 4 * half + (v & 3);
+        const float s0 = ((w0 >> row_word_bit(t)) & 1u) ? -1.0f : 1.0f;
+        const float s1 = ((w1 >> row_word_bit(t)) & 1u) ? -1.0f : 1.0f;
+        part += s0 * acc0[v] + s1 * acc1[v];
+    }
+    part += __shfl_xor(part, 32);
+    if (half == 0) ep[((size_t)j * nrb + rb) * Rpad + rep] = part;
+}
+
 // Energies of the segment's samples, best-sample update and its spins.
 // Grid Rpad/32, 256 threads: lane group g = threadIdx.x / 32 scans samples
 // j = g, g + 8, ... of 32 replicas; the groups' minima are merged with the
@@ -505,6 +861,50 @@ const void *pick_kernel(int nkb) {
     }
 }
 
+template <int NKB>
+const void *bsb_kernel_ptr() {
+    return reinterpret_cast<const void *>(&k_bsb_fp4<NKB>);
+}
+
+const void *pick_bsb_kernel(int nkb) {
+    switch (nkb) {
+    case 4: return bsb_kernel_ptr<4>();
+    case 8: return bsb_kernel_ptr<8>();
+    case 12: return bsb_kernel_ptr<12>();
+    case 16: return bsb_kernel_ptr<16>();
+    case 20: return bsb_kernel_ptr<20>();
+    case 24: return bsb_kernel_ptr<24>();
+    case 28: return bsb_kernel_ptr<28>();
+    default: return bsb_kernel_ptr<32>();
+    }
+}
+
+hipError_t launch_energy_fp4(int nkb, dim3 grid, const FP4Team *teams, const uint32_t *snap,
+                             float *ep, int nrb, int Rpad, int team0, hipStream_t s) {
+#define HSB_ENERGY_CASE(K)                                                                  \
+    case K:                                                                                 \
+        hipLaunchKernelGGL(k_energy_fp4<K>, grid, dim3(256), 0, s, teams, snap, ep, nrb, Rpad, \
+                           team0);                                                          \
+        break;
+    switch (nkb) {
+        HSB_ENERGY_CASE(4)
+        HSB_ENERGY_CASE(8)
+        HSB_ENERGY_CASE(12)
+        HSB_ENERGY_CASE(16)
+        HSB_ENERGY_CASE(20)
+        HSB_ENERGY_CASE(24)
+        HSB_ENERGY_CASE(28)
+        default: HSB_ENERGY_CASE(32)
+    }
+#undef HSB_ENERGY_CASE
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
 template <typename T>
 int grow(T **p, size_t *cap, size_t n) {
     if (n <= *cap) return HSB_OK;
@@ -565,7 +965,8 @@ int persistent_work_create(PersistentWork **out) {
 
 void persistent_work_free(PersistentWork *w) {
     if (!w) return;
-    void *ptrs[] = {w->xb, w->snap, w->ep, w->ptab, w->err, w->xslot, w->teams};
+    void *ptrs[] = {w->xb, w->snap, w->ep, w->ptab, w->err, w->xslot, w->teams,
+                    w->xd, w->xe, w->flags};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete w;
@@ -574,34 +975,37 @@ void persistent_work_free(PersistentWork *w) {
 void persistent_free(PersistentJ *pj) {
     if (!pj) return;
     PersistentWork &w = pj->work;
-    void *ptrs[] = {pj->jpk, w.xb, w.snap, w.ep, w.ptab, w.err, w.xslot, w.teams};
+    void *ptrs[] = {pj->jpk, w.xb, w.snap, w.ep, w.ptab, w.err, w.xslot, w.teams, w.xd, w.xe,
+                    w.flags};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete pj;
 }
 
-int persistent_run(PersistentJ *pj, const PersistentRun &run, StateBufs &b, int N, hipStream_t s,
-                   KernelTimer &timer) {
+int persistent_run(PersistentJ *pj, int variant, const PersistentRun &run, StateBufs &b, int N,
+                   hipStream_t s, KernelTimer &timer) {
     std::vector<FP4Team> teams((size_t)run.Rpad / 32);
     for (FP4Team &t : teams) {
         t.jpk = pj->jpk;
         t.N = N;
         t.c0 = run.c0;
     }
-    return persistent_run_teams(&pj->work, pj->nkb, teams.data(), (int)teams.size(), run, b, N, s,
-                                timer);
+    return persistent_run_teams(&pj->work, variant, pj->nkb, teams.data(), (int)teams.size(), run,
+                                b, N, s, timer);
 }
 
-int persistent_run_teams(PersistentWork *pw, int nkb, const FP4Team *host_teams,
+int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team *host_teams,
                          int nteams_total, const PersistentRun &run, StateBufs &b, int Nrows,
                          hipStream_t s, KernelTimer &timer) {
+    const bool bsb = variant == HSB_BSB;
     const int Rpad = run.Rpad, nrb = nkb, nchunk = 2 * nrb;
     if (nteams_total * 32 > Rpad) return perr(HSB_EINVAL, "FP4 path: teams exceed the columns");
     int dev = 0, ncu = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(nkb), 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, bsb ? pick_bsb_kernel(nkb) : pick_kernel(nkb), 256, 0);
     if (e != hipSuccess) return perr(HSB_EDEVICE, "FP4 path: %s", hipGetErrorString(e));
     // teams per launch: a multiple of 8 (one slot per XCD) whose workgroups all
     // fit on the device at once
@@ -627,6 +1031,9 @@ int persistent_run_teams(PersistentWork *pw, int nkb, const FP4Team *host_teams,
     size_t one = 0;
     if (!rc && !pw->err) rc = grow(&pw->err, &one, 1);
     if (!rc) rc = grow(&pw->teams, &pw->teams_n, (size_t)nteams_total);
+    if (!rc && bsb) rc = grow(&pw->xd, &pw->xd_n, (size_t)2 * nkb * 8 * 2 * Rpad);
+    if (!rc && bsb) rc = grow(&pw->xe, &pw->xe_n, (size_t)2 * 2 * Rpad * nkb);
+    if (!rc && bsb) rc = grow(&pw->flags, &pw->flags_n, (size_t)nteams_total * nrb);
     if (!rc && pw->xslot_n < (size_t)wg_capacity + 8 * (size_t)wpt) {
         rc = grow(&pw->xslot, &pw->xslot_n, (size_t)wg_capacity + 8 * (size_t)wpt);
         if (!rc) {  // epoch 0xFFFFFFFF in every slot: never a launch's epoch
@@ -643,7 +1050,7 @@ int persistent_run_teams(PersistentWork *pw, int nkb, const FP4Team *host_teams,
     e = hipGetLastError();
     if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
     const float a0dt = run.a0 * run.dt;
-    const void *kfn = pick_kernel(nkb);
+    const void *kfn = bsb ? pick_bsb_kernel(nkb) : pick_kernel(nkb);
     std::vector<float> ptab;
     int a = run.k0;
     for (;;) {
@@ -669,9 +1076,15 @@ int persistent_run_teams(PersistentWork *pw, int nkb, const FP4Team *host_teams,
         if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
         for (int t0 = 0; t0 < nteams_total; t0 += teams_per_launch) {
             int nt = nteams_total - t0 < teams_per_launch ? nteams_total - t0 : teams_per_launch;
-            const size_t nxb = (size_t)2 * nchunk * Rpad;
-            hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((nxb + 255) / 256)), dim3(256), 0, s,
-                               pw->xb, nxb);
+            if (bsb) {  // no wave of this launch has published yet
+                const size_t nf = (size_t)nteams_total * nrb;
+                hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s,
+                                   pw->flags, nf, kNoTag);
+            } else {
+                const size_t nxb = (size_t)2 * nchunk * Rpad;
+                hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((nxb + 255) / 256)), dim3(256), 0,
+                                   s, pw->xb, nxb);
+            }
             // block b -> team (b/8)/wpt*8 + b%8: round the team count up to 8
             const dim3 grid((unsigned)(8 * ((nt + 7) / 8) * (nrb / 4))), block(256);
             float dt = run.dt, a0dtv = a0dt;
@@ -679,12 +1092,22 @@ int persistent_run_teams(PersistentWork *pw, int nkb, const FP4Team *host_teams,
             uint32_t epoch = ++pw->epoch;
             if (epoch == 0) epoch = ++pw->epoch;  // slots start zeroed: epoch 0 is never used
             const float *gam = run.gamma;
-            void *args[] = {(void *)&pw->teams, (void *)&run.X,    (void *)&run.Y,   (void *)&gam,
-                            (void *)&pw->xb,    (void *)&pw->snap, (void *)&pw->ep,  (void *)&pw->ptab,
-                            (void *)&b.bad,     (void *)&b.status, (void *)&pw->err, (void *)&pw->xslot,
-                            (void *)&epoch,     (void *)&nkb_v,    (void *)&nrb_v,   (void *)&Rpad_v,
-                            (void *)&t0_v,      (void *)&nt_v,     (void *)&g,       (void *)&dt,
-                            (void *)&a0dtv};
+            void *args_d[] = {(void *)&pw->teams, (void *)&run.X,    (void *)&run.Y,
+                              (void *)&gam,       (void *)&pw->xb,   (void *)&pw->snap,
+                              (void *)&pw->ep,    (void *)&pw->ptab, (void *)&b.bad,
+                              (void *)&b.status,  (void *)&pw->err,  (void *)&pw->xslot,
+                              (void *)&epoch,     (void *)&nkb_v,    (void *)&nrb_v,
+                              (void *)&Rpad_v,    (void *)&t0_v,     (void *)&nt_v,
+                              (void *)&g,         (void *)&dt,       (void *)&a0dtv};
+            void *args_b[] = {(void *)&pw->teams, (void *)&run.X,     (void *)&run.Y,
+                              (void *)&gam,       (void *)&pw->xd,    (void *)&pw->xe,
+                              (void *)&pw->flags, (void *)&pw->snap,  (void *)&pw->ptab,
+                              (void *)&b.bad,     (void *)&b.status,  (void *)&pw->err,
+                              (void *)&pw->xslot, (void *)&epoch,     (void *)&nkb_v,
+                              (void *)&nrb_v,     (void *)&Rpad_v,    (void *)&t0_v,
+                              (void *)&nt_v,      (void *)&g,         (void *)&dt,
+                              (void *)&a0dtv};
+            void **args = bsb ? args_b : args_d;
             // every workgroup of the grid is resident at once: the grid never exceeds
             // the occupancy-derived capacity, and every wait inside the kernel is
             // bounded, so a wave that cannot make progress ends the launch cleanly
@@ -693,6 +1116,11 @@ int persistent_run_teams(PersistentWork *pw, int nkb, const FP4Team *host_teams,
             if (e == hipSuccess) e = timer.end(s);
             if (e != hipSuccess)
                 return perr(HSB_EDEVICE, "FP4 persistent launch: %s", hipGetErrorString(e));
+        }
+        if (bsb && ns > 0) {  // energies of the segment's samples from their sign words
+            e = launch_energy_fp4(nkb, dim3((unsigned)(nteams_total * wpt), (unsigned)ns),
+                                  pw->teams, pw->snap, pw->ep, nrb, Rpad, 0, s);
+            if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
         }
         hipLaunchKernelGGL(k_fp4_best, dim3((unsigned)((run.R + 31) / 32)), dim3(256), 0, s,
                            pw->ep, pw->snap, ns, nrb, Nrows, run.R, Rpad, g, b.best_e, b.last_e,

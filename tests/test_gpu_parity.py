@@ -221,26 +221,39 @@ def rel_err(a, b):
     return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
 
 
-@pytest.mark.parametrize("plan", ["fp32", "mixed"])
+# bSB plans: "fp32", "fp4" (mixed on +-1 couplings: FP4 J x base-8 FP4 digits of x) and
+# "digits" (mixed on +-5 couplings, not FP4-exact: int8 digits)
+BSB_PLANS = [("fp32", 1), ("mixed", 1), ("mixed", 5)]
+
+
+def bsb_case(plan, scale, N, seed):
+    J = synth.sk_instance(N, seed) * np.float32(scale)
+    expect = "fp32" if plan == "fp32" else ("fp4" if scale == 1 else "digits")
+    return J, 0.5 / np.sqrt(N) / scale, expect
+
+
+@pytest.mark.parametrize("plan,scale", BSB_PLANS)
 @pytest.mark.parametrize("steps", [1, 50])
 @pytest.mark.parametrize("gamma", [0.0, 0.01])
-def test_bsb_trajectory_within_1e5(plan, steps, gamma):
-    J = synth.sk_instance(100, 1)
-    say("bsb N=100", plan, steps, gamma)
-    g = gpu_run(J, hsb.HSB_BSB, plan, steps, 16, gamma=gamma, schedule_steps=2000)
-    assert g["last_plan"] == ("digits" if plan == "mixed" else "fp32")
-    o = oracle_run(J, oracle.BSB, oracle.FP64, steps, 16, gamma=gamma, schedule_steps=2000)
+def test_bsb_trajectory_within_1e5(plan, scale, steps, gamma):
+    J, c0, expect = bsb_case(plan, scale, 100, 1)
+    say("bsb N=100", plan, scale, steps, gamma)
+    g = gpu_run(J, hsb.HSB_BSB, plan, steps, 16, c0=c0, gamma=gamma, schedule_steps=2000)
+    assert g["last_plan"] == expect
+    o = oracle_run(J, oracle.BSB, oracle.FP64, steps, 16, c0=c0, gamma=gamma,
+                   schedule_steps=2000)
     assert rel_err(g["x"], o["x"]).max() <= 1e-5
     assert rel_err(g["y"], o["y"]).max() <= 1e-5
 
 
-@pytest.mark.parametrize("plan", ["mixed", "fp32"])
-def test_bsb_full_size_sampled_replicas(plan):
-    J = synth.sk_instance(2000, 2000)
-    say("bsb full size", plan)
-    g = gpu_run(J, hsb.HSB_BSB, plan, 50, 1024, seed=3, gamma=0.01, schedule_steps=10000)
+@pytest.mark.parametrize("plan,scale", BSB_PLANS)
+def test_bsb_full_size_sampled_replicas(plan, scale):
+    J, c0, expect = bsb_case(plan, scale, 2000, 2000)
+    say("bsb full size", plan, scale)
+    g = gpu_run(J, hsb.HSB_BSB, plan, 50, 1024, seed=3, c0=c0, gamma=0.01, schedule_steps=10000)
+    assert g["last_plan"] == expect
     for r in (0, 700, 1023):
-        o = oracle_run(J, oracle.BSB, oracle.FP64, 50, 1, seed=3, gamma=0.01, r0=r,
+        o = oracle_run(J, oracle.BSB, oracle.FP64, 50, 1, seed=3, c0=c0, gamma=0.01, r0=r,
                        schedule_steps=10000)
         assert rel_err(g["x"][r:r + 1], o["x"]).max() <= 1e-5
         assert rel_err(g["y"][r:r + 1], o["y"]).max() <= 1e-5
@@ -275,23 +288,66 @@ def test_gaussian_full_size_bsb_digits():
         assert rel_err(g["y"][r:r + 1], o["y"]).max() <= 1e-5
 
 
-def test_bsb_digits_deterministic_prefix_and_resume():
-    J = synth.sk_instance(300, 6)
+@pytest.mark.parametrize("scale", [1, 5])
+def test_bsb_mixed_deterministic_prefix_and_resume(scale):
+    J, c0, expect = bsb_case("mixed", scale, 300, 6)
     R, Ns, k = 48, 400, 150
-    say("bsb digits determinism")
-    a = gpu_run(J, hsb.HSB_BSB, "mixed", Ns, R, gamma=0.02, seed=9)
-    b = gpu_run(J, hsb.HSB_BSB, "mixed", Ns, R, gamma=0.02, seed=9)
-    d = gpu_run(J, hsb.HSB_BSB, "mixed", Ns, 17, gamma=0.02, seed=9)
+    say("bsb mixed determinism", expect)
+    a = gpu_run(J, hsb.HSB_BSB, "mixed", Ns, R, c0=c0, gamma=0.02, seed=9)
+    assert a["last_plan"] == expect
+    b = gpu_run(J, hsb.HSB_BSB, "mixed", Ns, R, c0=c0, gamma=0.02, seed=9)
+    d = gpu_run(J, hsb.HSB_BSB, "mixed", Ns, 17, c0=c0, gamma=0.02, seed=9)
     for key in ("x", "y", "spins", "energy", "best_step"):
         assert np.array_equal(a[key], b[key]), key
     assert np.array_equal(d["x"], a["x"][:17]) and np.array_equal(d["energy"], a["energy"][:17])
-    h1 = gpu_run(J, hsb.HSB_BSB, "mixed", k, R, gamma=0.02, seed=9, schedule_steps=Ns)
-    h2 = gpu_run(J, hsb.HSB_BSB, "mixed", Ns - k, R, gamma=0.02, start_step=k, schedule_steps=Ns,
-                 x0=torch.from_numpy(h1["x"]), y0=torch.from_numpy(h1["y"]))
+    h1 = gpu_run(J, hsb.HSB_BSB, "mixed", k, R, c0=c0, gamma=0.02, seed=9, schedule_steps=Ns)
+    h2 = gpu_run(J, hsb.HSB_BSB, "mixed", Ns - k, R, c0=c0, gamma=0.02, start_step=k,
+                 schedule_steps=Ns, x0=torch.from_numpy(h1["x"]), y0=torch.from_numpy(h1["y"]))
     assert np.array_equal(h2["x"], a["x"]) and np.array_equal(h2["y"], a["y"])
     # energies are eq. (1) of the returned spins, exactly
     for s_, e in zip(a["spins"], a["energy"]):
         assert oracle.energy(J, s_) == e
+
+
+@pytest.mark.parametrize("N,R,steps,interval", [(1, 3, 40, 7), (63, 33, 60, 25),
+                                                (65, 64, 50, 50), (257, 40, 50, 1),
+                                                (700, 96, 50, 20)])
+def test_bsb_fp4_ragged_shapes(N, R, steps, interval):
+    """bSB on the FP4 plan at ragged sizes: the 1e-5 bar over the first steps of a
+    2000-step schedule, and energies equal to eq. (1) of the returned spins."""
+    J = synth.sk_instance(N, N + 5)
+    c0 = 0.5 / np.sqrt(N)
+    say("bsb fp4 ragged", N, R, steps, interval)
+    g = gpu_run(J, hsb.HSB_BSB, "mixed", steps, R, seed=N, c0=c0, gamma=0.01, interval=interval,
+                schedule_steps=2000)
+    assert g["last_plan"] == "fp4"
+    o = oracle_run(J, oracle.BSB, oracle.FP64, steps, R, seed=N, c0=c0, gamma=0.01,
+                   interval=interval, schedule_steps=2000)
+    assert rel_err(g["x"], o["x"]).max() <= 1e-5 and rel_err(g["y"], o["y"]).max() <= 1e-5
+    for s_, e in zip(g["spins"], g["energy"]):
+        assert oracle.energy(J, s_) == e
+
+
+def test_dsb_real_j_digits_and_host_api():
+    """dSB on Gaussian couplings with the digit plan (four-digit J): the early
+    trajectory within the 1e-5 bar of FP64; the host-buffer entry point returns
+    the same spins and energies as the device one."""
+    J = synth.gaussian_instance(300, 8)
+    say("dsb real J digits")
+    g = gpu_run(J, hsb.HSB_DSB, "mixed", 50, 16, c0=0.5, gamma=0.01, schedule_steps=1000)
+    assert g["last_plan"] == "digits"
+    o = oracle_run(J, oracle.DSB, oracle.FP64, 50, 16, c0=0.5, gamma=0.01, schedule_steps=1000)
+    assert rel_err(g["x"], o["x"]).max() <= 1e-5 and rel_err(g["y"], o["y"]).max() <= 1e-5
+    with hsb.Context(J, precision="mixed", init_amp=0.1) as ctx:
+        spins, energy, rc = ctx.run(hsb.HSB_DSB, 1.0, 0.5, 1.0, 0.01, 200, 16, 3)
+        dev = ctx.run_ex(hsb.HSB_DSB, 200, 16, 1.0, 0.5, 1.0, 0.01, 3)
+        torch.cuda.synchronize()
+    assert rc == hsb.HSB_OK
+    assert np.array_equal(spins, dev["spins"].cpu().numpy())
+    assert np.array_equal(energy, dev["energy"].cpu().numpy())
+    for s_, e in zip(spins, energy):
+        ref = oracle.energy(J, s_)
+        assert abs(e - ref) <= 1e-12 * abs(ref)
 
 
 def test_bsb_digits_need_bounded_start_state():
