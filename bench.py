@@ -79,7 +79,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1, help="untimed runs")
     ap.add_argument("--sb-steps", type=int, default=SB_STEPS)
     ap.add_argument("--variant", choices=["dsb", "bsb"], default="dsb")
-    ap.add_argument("--plan", choices=["mixed", "fp32", "auto"], default="mixed")
+    ap.add_argument("--plan", choices=["mixed", "fp32", "auto", "digits"], default="mixed")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-plan comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bsb", action="store_true",

@@ -89,16 +89,19 @@ typedef enum {
     HSB_PREC_AUTO = 0,  /* the FP4 plan where MIXED takes it; the digit plan for bSB and
                            for dSB with integer J in [-127, 127]; FP32 otherwise */
     HSB_PREC_FP32 = 1,  /* plain FP32 field products (the baseline form) */
-    HSB_PREC_MIXED = 2  /* dSB with J exact in FP4 (entries in {0, +-0.5, +-1, +-1.5, +-2,
-                           +-3, +-4, +-6}) and N <= 2048: FP4 operands, FP32 accumulation
-                           (exact); otherwise, N <= 16384: the integer-digit plan */
+    HSB_PREC_MIXED = 2, /* J exact in FP4 (entries in {0, +-0.5, +-1, +-1.5, +-2, +-3, +-4,
+                           +-6}) and N <= 2048: the FP4 plan (dSB exact; bSB from base-8
+                           digits of x); otherwise, N <= 16384: the integer-digit plan */
+    HSB_PREC_DIGITS = 3 /* the integer-digit plan (N <= 16384) whatever J */
 } hsb_precision;
 
 /*
  * Execution plans (HSB_OPT_LAST_PLAN).  The field of eqs. (4)/(5) is
  *   HSB_PLAN_FP32    FP32 matrix-core products, one launch per step;
- *   HSB_PLAN_FP4     dSB only: FP4 x FP4 products, every step in one
- *                    persistent launch; exact;
+ *   HSB_PLAN_FP4     FP4 x FP4 products, every step in one persistent launch.
+ *                    dSB: exact.  bSB: x as eight base-8 digits in [-4, 3] per
+ *                    32-row chunk, weighted by the operand's block scales
+ *                    (x to 2^-23 of the chunk's largest |x|), FP32 sums;
  *   HSB_PLAN_DIGITS  int8 products of digits, one launch per step:
  *                    x = rint(x 2^30) 2^-30 as four base-256 digits (exact for
  *                    |x| >= 2^-6), sgn(x) as one digit, J as one digit when every
@@ -106,8 +109,9 @@ typedef enum {
  *                    exactly rounded FP32 value of sum_j J_ij x_j) or as four
  *                    digits of a per-row power-of-two scaled J (real J: relative
  *                    error about 2^-31 per entry).  bSB on this plan needs
- *                    |x| <= 1 in the start state (eqs. (18)-(21) keep it so):
- *                    otherwise MIXED returns HSB_EUNSUPPORTED and AUTO runs FP32.
+ *                    |x| <= 1 in the start state (eqs. (18)-(21) keep it so), as
+ *                    does bSB on HSB_PLAN_FP4: otherwise MIXED and DIGITS return
+ *                    HSB_EUNSUPPORTED and AUTO runs FP32.
  */
 typedef enum { HSB_PLAN_FP32 = 0, HSB_PLAN_FP4 = 1, HSB_PLAN_DIGITS = 2 } hsb_plan;
 

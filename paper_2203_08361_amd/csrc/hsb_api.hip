@@ -198,8 +198,9 @@ extern "C" int hsb_set_option(hsb_ctx *h, int key, double v) {
         h->return_best = (int)v;
         return HSB_OK;
     case HSB_OPT_PRECISION:
-        if (!(v == HSB_PREC_AUTO || v == HSB_PREC_FP32 || v == HSB_PREC_MIXED))
-            return fail(HSB_EINVAL, "PRECISION must be AUTO (0), FP32 (1) or MIXED (2)");
+        if (!(v == HSB_PREC_AUTO || v == HSB_PREC_FP32 || v == HSB_PREC_MIXED ||
+              v == HSB_PREC_DIGITS))
+            return fail(HSB_EINVAL, "PRECISION must be AUTO (0), FP32 (1), MIXED (2) or DIGITS (3)");
         h->precision = (int)v;
         return HSB_OK;
     case HSB_OPT_TIMING:
@@ -254,6 +255,9 @@ int choose_plan(const hsb_ctx *h, int variant, int *plan) {
     const bool dig_ok = h->N <= hsb::i8_max_n();
     if (h->precision == HSB_PREC_FP32) {
         *plan = PLAN_FP32;
+    } else if (h->precision == HSB_PREC_DIGITS) {
+        if (!dig_ok) return fail(HSB_EUNSUPPORTED, "DIGITS precision needs N <= %d", hsb::i8_max_n());
+        *plan = PLAN_DIGITS;
     } else if (h->precision == HSB_PREC_MIXED) {
         if (fp4_ok)
             *plan = PLAN_FP4;
@@ -364,9 +368,10 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
         HIP_TRY(hipMemcpyAsync(&over, h->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (over) {
-            if (h->precision == HSB_PREC_MIXED)
+            if (h->precision != HSB_PREC_AUTO)
                 return fail(HSB_EUNSUPPORTED,
-                            "MIXED bSB needs |x| <= 1 and finite in the start state");
+                            "bSB on the FP4 or digit plan needs |x| <= 1 and finite in the "
+                            "start state");
             plan = PLAN_FP32;
         }
     }

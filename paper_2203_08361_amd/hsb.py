@@ -20,7 +20,7 @@ HSB_OPT_INIT_AMP, HSB_OPT_ENERGY_INTERVAL, HSB_OPT_RETURN_BEST, HSB_OPT_PRECISIO
 HSB_OPT_TIMING, HSB_OPT_KERNEL_MS, HSB_OPT_KERNEL_LAUNCHES, HSB_OPT_LAST_PLAN = 4, 5, 6, 7
 HSB_PLAN_FP32, HSB_PLAN_FP4, HSB_PLAN_DIGITS = 0, 1, 2
 PLAN_NAMES = {HSB_PLAN_FP32: "fp32", HSB_PLAN_FP4: "fp4", HSB_PLAN_DIGITS: "digits"}
-HSB_PREC_AUTO, HSB_PREC_FP32, HSB_PREC_MIXED = 0, 1, 2
+HSB_PREC_AUTO, HSB_PREC_FP32, HSB_PREC_MIXED, HSB_PREC_DIGITS = 0, 1, 2, 3
 
 EXPORTED = ("hsb_create", "hsb_destroy", "hsb_last_error", "hsb_set_option", "hsb_get_option",
             "hsb_run", "hsb_run_ex", "hsb_plan_info", "hsb_run_batch")
@@ -267,7 +267,8 @@ class Context:
              "return_best": HSB_OPT_RETURN_BEST, "precision": HSB_OPT_PRECISION,
              "timing": HSB_OPT_TIMING, "kernel_ms": HSB_OPT_KERNEL_MS,
              "kernel_launches": HSB_OPT_KERNEL_LAUNCHES, "last_plan": HSB_OPT_LAST_PLAN}
-    _PREC = {"auto": HSB_PREC_AUTO, "fp32": HSB_PREC_FP32, "mixed": HSB_PREC_MIXED}
+    _PREC = {"auto": HSB_PREC_AUTO, "fp32": HSB_PREC_FP32, "mixed": HSB_PREC_MIXED,
+             "digits": HSB_PREC_DIGITS}
 
     def set_option(self, key, value):
         if isinstance(value, str):

@@ -222,13 +222,13 @@ def rel_err(a, b):
 
 
 # bSB plans: "fp32", "fp4" (mixed on +-1 couplings: FP4 J x base-8 FP4 digits of x) and
-# "digits" (mixed on +-5 couplings, not FP4-exact: int8 digits)
-BSB_PLANS = [("fp32", 1), ("mixed", 1), ("mixed", 5)]
+# "digits" (mixed on +-5 couplings, not FP4-exact, or forced: int8 digits)
+BSB_PLANS = [("fp32", 1), ("mixed", 1), ("mixed", 5), ("digits", 1)]
 
 
 def bsb_case(plan, scale, N, seed):
     J = synth.sk_instance(N, seed) * np.float32(scale)
-    expect = "fp32" if plan == "fp32" else ("fp4" if scale == 1 else "digits")
+    expect = {"fp32": "fp32", "digits": "digits"}.get(plan, "fp4" if scale == 1 else "digits")
     return J, 0.5 / np.sqrt(N) / scale, expect
 
 
