@@ -14,6 +14,9 @@ Reported next to it:
     time-to-target of both plans at the same target energy;
   - the ballistic variant (bSB) on the same instance, mixed (integer-digit)
     plan against FP32;
+  - Gaussian couplings J_ij ~ N(0, 1)/sqrt(N) at N = 2000, R = 1024, 10^4
+    steps of heated bSB (c0 = 0.5): mixed (four-digit split J) plan against
+    FP32, with the FP64 energies checked against the oracle's eq. (1);
   - a batched workload: 256 SK instances with N uniform in [100, 2000], each
     with 64 replicas at each of 8 heating rates (2048 jobs), 5000 steps of
     heated dSB in one hsb_run_batch call, against per-job runs on the FP32
@@ -88,6 +91,8 @@ def main() -> int:
                     help="skip the batched uneven-instance workload of the default run")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched uneven-instance workload")
+    ap.add_argument("--no-gaussian", action="store_true",
+                    help="skip the Gaussian-coupling workload of the default run")
     ap.add_argument("--cpu-replicas", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -251,6 +256,37 @@ def main() -> int:
                                        f"({t_sample:.2f} s), scaled by padded N^2",
                 "speedup_vs_fp32_per_job": t_fp32 / t_batch}
 
+    def gaussian_workload():
+        """Gaussian couplings (N = 2000, seed 3), R = 1024, 10^4 steps of heated bSB,
+        gamma = 0.01, c0 = 0.5 (c1 / (sigma_J sqrt(N)) with sigma_J = 1/sqrt(N))."""
+        import oracle
+
+        Jg = synth.gaussian_instance(N, 3)
+        cg = hsb.Context(Jg, precision=args.plan, init_amp=0.1, energy_interval=100)
+        out = {}
+        for prec in (args.plan, "fp32"):
+            cg.set_option("precision", prec)
+            cg.run_ex(hsb.HSB_BSB, 200, R, A0, 0.5, DT, GAMMA, 100, schedule_steps=Ns)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = cg.run_ex(hsb.HSB_BSB, Ns, R, A0, 0.5, DT, GAMMA, 1)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            out[prec] = (ms, cg.last_plan(), o)
+        ms_m, plan_m, o_m = out[args.plan]
+        spins = o_m["spins"].cpu().numpy()
+        energy = o_m["energy"].cpu().numpy()
+        rel = [abs(energy[r] - oracle.energy(Jg, spins[r])) / abs(oracle.energy(Jg, spins[r]))
+               for r in range(0, R, 64)]
+        cg.close()
+        return {"workload": f"Gaussian J ~ N(0,1)/sqrt(N), N={N}, R={R}, {Ns} steps heated bsb "
+                            f"gamma={GAMMA}, c0=0.5",
+                "plan": plan_m, "value": N * R * Ns / (ms_m * 1e-3), "ms_per_run": ms_m,
+                "fp32_ms_per_run": out["fp32"][0], "speedup_vs_fp32": out["fp32"][0] / ms_m,
+                "fp64_energy_rel_err_max": max(rel),
+                "fp64_energy_check": f"eq. (1) of the returned spins of {len(rel)} replicas "
+                                     f"(every 64th) recomputed by the FP64 oracle"}
+
     if args.batch_only:
         print(json.dumps({"batch": batch_workload()}), flush=True)
         ctx.close()
@@ -281,6 +317,8 @@ def main() -> int:
         if not args.no_fp32 and b["plan"] != "fp32":
             bsb["fp32_plan"], bsb["time_to_target"] = fp32_compare(hsb.HSB_BSB, b)
         result["bsb"] = bsb
+    if args.variant == "dsb" and not args.no_gaussian:
+        result["gaussian"] = gaussian_workload()
     if args.variant == "dsb" and not args.no_batch:
         result["batch"] = batch_workload()
 
