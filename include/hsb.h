@@ -218,9 +218,10 @@ int hsb_plan_info(hsb_ctx *h, int variant, int *precision);
  * Job j gives exactly what hsb_run_ex on its instance gives with the same
  * variant, steps, R, a0, c0, dt, gamma and seed (and the batch's amplitude,
  * interval and return mode), under the plan its instance's precision option
- * selects; dSB jobs whose J is exact in FP4 with N <= 2048 run together, one
- * persistent launch per padded size for all their instances, so a batch of
- * small instances fills the device.  Other jobs run one after another.
+ * selects.  Jobs on the FP4 plan (J exact in FP4 with N <= 2048; for bSB also
+ * initial amplitude <= 1) run together, one persistent launch sequence per
+ * padded size for all their instances, so a batch of small instances fills
+ * the device.  Other jobs run one after another.
  * Outputs are device pointers owned by the caller: jobs[j].spins [R][N] int8
  * and jobs[j].energy [R] double.  Validation failures return HSB_EINVAL before
  * any device work; HSB_ENUMERIC if any replica of any job became non-finite.

@@ -40,9 +40,6 @@ struct I8Run {
     float a0, c0, dt;
 };
 
-// Whether every x of the state X ([n] FP32) satisfies |x| <= 1 (synchronises s).
-int i8_start_state_ok(I8J *p, const float *X, size_t n, hipStream_t s, bool *ok);
-
 // Run steps k0..k1-1 of the digit plan on the state in `b` (X, Y in
 // [Nst][Rpad]); samples energies at the sample points (as the FP32 plan).
 // `fp32J` is the FP32 J store ([Nst][Nst]) used for FP64 energies of real J.

@@ -45,7 +45,6 @@ struct I8J {
     size_t xd_bytes = 0;
     int8_t *sd = nullptr;        // [Npad/16][Rpad][16] sign digits of sampled states
     size_t sd_bytes = 0;
-    int32_t *flag = nullptr;     // start-state bound check
 };
 
 namespace {
@@ -115,16 +114,6 @@ __global__ __launch_bounds__(64) void k_i8_digits(const float *__restrict__ X,
             v4i rec = {(int)w[b][0], (int)w[b][1], (int)w[b][2], (int)w[b][3]};
             reinterpret_cast<v4i *>(xd)[s * set + ((size_t)b * nkb + kb) * Rpad + r] = rec;
         }
-}
-
-__global__ void k_i8_clear_flag(int32_t *flag) { *flag = 0; }
-
-// 1 in *flag if any |x| > 1 or x is not finite (the digit plan's premise).
-__global__ void k_i8_bound(const float *__restrict__ X, size_t n, int32_t *flag) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const float x = X[e];
-    if (!(fabsf(x) <= 1.0f)) atomicOr(flag, 1);
 }
 
 // One time step (ENERGY = false) or the energy partials of the current state
@@ -395,7 +384,6 @@ int i8_create(const float *hJ, int N, I8J **out) {
     }
     hipError_t e = hipMalloc((void **)&p->jd, rec * 16);
     if (e == hipSuccess) e = hipMalloc((void **)&p->rowscale, sizeof(double) * Np);
-    if (e == hipSuccess) e = hipMalloc((void **)&p->flag, sizeof(int32_t));
     if (e == hipSuccess) e = hipMemcpy(p->jd, jd.data(), rec * 16, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(p->rowscale, rs.data(), sizeof(double) * Np, hipMemcpyHostToDevice);
@@ -410,26 +398,10 @@ int i8_create(const float *hJ, int N, I8J **out) {
 
 void i8_free(I8J *p) {
     if (!p) return;
-    void *ptrs[] = {p->jd, p->rowscale, p->xd, p->sd, p->flag};
+    void *ptrs[] = {p->jd, p->rowscale, p->xd, p->sd};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
-}
-
-int i8_start_state_ok(I8J *p, const float *X, size_t n, hipStream_t s, bool *ok) {
-    hipLaunchKernelGGL(k_i8_clear_flag, dim3(1), dim3(1), 0, s, p->flag);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_i8_bound, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n,
-                           p->flag);
-        e = hipGetLastError();
-    }
-    int32_t f = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&f, p->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return derr(HSB_EDEVICE, "start-state check: %s", hipGetErrorString(e));
-    *ok = f == 0;
-    return HSB_OK;
 }
 
 int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream_t s,
