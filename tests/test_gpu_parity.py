@@ -93,6 +93,18 @@ def test_dsb_ragged_shapes_bit_exact(plan, N, R, steps, interval):
     assert_bit_exact(g, o)
 
 
+@pytest.mark.parametrize("N", [700, 1100, 1500, 1800])
+def test_dsb_fp4_every_padded_size_bit_exact(N):
+    """Padded sizes of 12, 20, 24 and 28 K blocks of 64 spins on the FP4 plan;
+    samples every 25 steps, so that runs of unsampled steps lie between them."""
+    J = synth.sk_instance(N, N + 11)
+    say("dsb fp4 padded size", N)
+    g = gpu_run(J, hsb.HSB_DSB, "mixed", 60, 40, seed=N, gamma=0.02, interval=25)
+    assert g["plan"] == "mixed"
+    o = oracle_run(J, oracle.DSB, oracle.FP32, 60, 40, seed=N, gamma=0.02, interval=25)
+    assert_bit_exact(g, o)
+
+
 @pytest.mark.parametrize("plan", ["fp32", "mixed"])
 def test_dsb_zero_steps_and_final_mode(plan):
     J = synth.sk_instance(50, 2)
