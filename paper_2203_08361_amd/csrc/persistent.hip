@@ -249,6 +249,21 @@ __device__ __forceinline__ bool gather_words(uint64_t (&wv)[NQ], const uint64_t 
     }
 }
 
+// sb_update (the same operations and roundings) with the last FMA written
+// so that y' lands in the register of y: the compiler would otherwise
+// accumulate into the register of y~~ and copy every y back each step.
+__device__ __forceinline__ void sb_update_tied(float f, float p, float c0, float dt, float a0dt,
+                                               float gdt, float &x, float &y) {
+    const float c0f = c0 * f;
+    const float u = __fmaf_rn(-p, x, c0f);
+    const float yt = __fmaf_rn(u, dt, y);
+    const float xt = __fmaf_rn(a0dt, yt, x);
+    const bool wall = fabsf(xt) > 1.0f;
+    x = __builtin_amdgcn_fmed3f(xt, -1.0f, 1.0f);
+    const float ytt = wall ? 0.0f : yt;
+    asm("v_fma_f32 %0, %1, %0, %2" : "+v"(y) : "v"(gdt), "v"(ytt));  // y' = (gamma dt) y + y~~
+}
+
 // One workgroup = 4 waves = 4 consecutive row blocks of one team, so the four
 // waves need the same +-1 operand (the team's signs).  Each step every wave
 // gathers and expands a quarter of the K blocks into LDS (ping-pong by step
@@ -320,7 +335,9 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     const int one = 127;  // E8M0 block scale 2^0
 
     // item v of tile rt: replica r0 + l%32, row 64 rb + 32 rt + 8(v/4) + 4(l/32) + v%4
-    float xs0[16], xs1[16], ys0[16], ys1[16];
+    // (vectors rather than arrays: the register allocator then keeps them in
+    // place across the step loop instead of copying them every step)
+    v16f xs0, xs1, ys0, ys1;
     const int rep = r0 + l32;
     const float gdt = gamma[rep] * dt;
     const int rowb = rb * 64 + 4 * half;
@@ -339,11 +356,12 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     // Lane l holds 16 rows of each tile for replica l%32: its bits form half a
     // word, and lanes l, l+32 swap the halves they do not store.
     auto publish = [&](int m) {
+        // b = (b << 1) | sign bit, highest item first: one operation per item
         uint32_t b0 = 0, b1 = 0;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            b0 |= (__float_as_uint(xs0[v]) >> 31) << v;
-            b1 |= (__float_as_uint(xs1[v]) >> 31) << v;
+        for (int v = 15; v >= 0; --v) {
+            b0 = __builtin_amdgcn_alignbit(b0, __float_as_uint(xs0[v]), 31);
+            b1 = __builtin_amdgcn_alignbit(b1, __float_as_uint(xs1[v]), 31);
         }
         const uint32_t got = (uint32_t)__shfl_xor((int)(half ? b0 : b1), 32);
         const uint32_t word = half ? (got | (b1 << 16)) : (b0 | (got << 16));
@@ -413,8 +431,13 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
         if (m == g.seg_k1) break;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            sb_update(acc0[v], p, c0, dt, a0dt, gdt, xs0[v], ys0[v]);
-            sb_update(acc1[v], p, c0, dt, a0dt, gdt, xs1[v], ys1[v]);
+            float x0 = xs0[v], y0 = ys0[v], x1 = xs1[v], y1 = ys1[v];
+            sb_update_tied(acc0[v], p, c0, dt, a0dt, gdt, x0, y0);
+            sb_update_tied(acc1[v], p, c0, dt, a0dt, gdt, x1, y1);
+            xs0[v] = x0;
+            ys0[v] = y0;
+            xs1[v] = x1;
+            ys1[v] = y1;
         }
         publish(m + 1);
     }
@@ -477,6 +500,20 @@ __device__ __forceinline__ void mfma_fp4s_first(v16f &acc, const v4i &j, const v
 
 __device__ __forceinline__ uint32_t ld_flag(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// A 16-byte fragment as two device-scope 8-byte loads: they bypass the L1,
+// so a reader that shares the writer's L2 needs no acquire invalidation (an
+// agent-scope invalidation is costly when every wave issues it each step).
+__device__ __forceinline__ v4i ld_frag(const v4i *p) {
+    const uint64_t *q = reinterpret_cast<const uint64_t *>(p);
+    const uint64_t lo = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t hi = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v4i r;
+    r[0] = (int)(uint32_t)lo;
+    r[1] = (int)(uint32_t)(lo >> 32);
+    r[2] = (int)(uint32_t)hi;
+    r[3] = (int)(uint32_t)(hi >> 32);
+    return r;
 }
 
 // Digit fragments of one tile.  Lane (h, l%32) holds 16 rows (item v: row
@@ -606,12 +643,17 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
             xd[(((size_t)par * nkb + rb) * kXD + 4 * half + j) * cols + team * 64 + 32 + l32] = fr[j];
         if (half == 0) xe[((size_t)par * cols + team * 64 + 32 + l32) * nkb + rb] = (uint8_t)eb;
         // release: the fragments are in the L2 before the flag
-        if (xcd_local)  // stores acknowledged by the L2 (the memory clobber keeps them above)
+        if (xcd_local) {
+            // stores acknowledged by the shared L2 (the memory clobber keeps them
+            // above); the flag only has to reach that L2 too
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        else
+            if (lane == 0) __hip_atomic_store(myflag, (uint32_t)m, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0) __hip_atomic_store(myflag, (uint32_t)m, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0) __hip_atomic_store(myflag, (uint32_t)m, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        }
     };
     // sign words of the sampled state x_m (the energy is formed afterwards)
     auto snapshot = [&](int m) {
@@ -658,15 +700,17 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
                     }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // no stale L1 lines
+            // readers on another L2: invalidate for the data written there
+            if (!xcd_local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        // chunk exponents of this lane's column for every K block
+        // chunk exponents of this lane's column for every K block (device-scope
+        // loads: no stale L1 lines)
         uint32_t ed[NKB / 4];
         {
             const uint32_t *ep4 =
                 reinterpret_cast<const uint32_t *>(xe + ((size_t)par * cols + col) * nkb);
 #pragma unroll
-            for (int q = 0; q < NKB / 4; ++q) ed[q] = ep4[q];
+            for (int q = 0; q < NKB / 4; ++q) ed[q] = ld_flag(ep4 + q);
         }
         // staging: wave w loads K block kPB ph + w of phase ph
         v4i stg[kXD];
@@ -674,7 +718,7 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
             const int kb = kPB * ph + w;
 #pragma unroll
             for (int k = 0; k < kXD; ++k)
-                stg[k] = xd[(((size_t)par * nkb + kb) * kXD + k) * cols + col];
+                stg[k] = ld_frag(xd + (((size_t)par * nkb + kb) * kXD + k) * cols + col);
         };
         auto store_stage = [&](int buf) {
 #pragma unroll
