@@ -519,41 +519,58 @@ __device__ __forceinline__ v4i ld_frag(const v4i *p) {
 // Digit fragments of one tile.  Lane (h, l%32) holds 16 rows (item v: row
 // 8(v/4) + 4h + v%4 of the chunk) of replica l%32.  Returns the biased
 // exponent E + 128 of the chunk and fills frag[j][q] (j = 0..3) with the four
-// complete 16-byte fragments of digits 4h + j, after swapping halves with lane
-// l^32: dword q of digit k holds the rows of word bits 4n + 3 - q (n = 0..7),
-// low half from the lane with h = 0.
+// complete 16-byte fragments of digits 4h + j: dword q of digit k holds the
+// rows of word bits 4n + 3 - q (n = 0..7), the low half from the lane with
+// h = 0, the high half from its partner l^32.
+//   Per item, the eight octal digits of U are spread to one byte each (two
+// words: digits 7,5,3,1 and 6,4,2,0) and mapped to E2M1 codes by a byte
+// table lookup.  Per q, the codes of the four items 3-q, 7-q, 11-q, 15-q
+// are merged nibble-wise and regrouped by byte permutes into dwords holding
+// the half-words of two digits; one cross-half swap per pair of dwords gives
+// each lane its own and its partner's half-words of the digits it keeps.
 __device__ __forceinline__ uint32_t make_digits(const float (&xs)[16], int half, v4i (&frag)[4]) {
     float mx = 0.0f;
 #pragma unroll
     for (int v = 0; v < 16; ++v) mx = fmaxf(mx, fabsf(xs[v]));
-    mx = fmaxf(mx, __shfl_xor(mx, 32));
+    {
+        const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(mx), __float_as_uint(mx),
+                                                        false, false);
+        mx = fmaxf(mx, __uint_as_float(half ? s[0] : s[1]));  // the partner's maximum
+    }
     int E = (int)((__float_as_uint(mx) >> 23) & 0xFFu) - 126;  // mx < 2^E for normal mx
     E = E < -100 ? -100 : (E > 1 ? 1 : E);
     const float sc = __uint_as_float((uint32_t)(149 - E) << 23);  // 2^(22 - E)
-    uint32_t U[16];
+    // E2M1 codes of d = u - 4 for u = 0..7 (bytes of the lookup table):
+    // -4 -3 -2 -1 0 1 2 3
+    constexpr uint32_t kLutHi = 0x05040200u, kLutLo = 0x0A0C0D0Eu;
+    uint32_t cl[16], ch[16];  // codes of digits 7,5,3,1 / 6,4,2,0, one per byte
 #pragma unroll
-    for (int v = 0; v < 16; ++v) U[v] = (uint32_t)((int)rintf(xs[v] * sc) + 0x924924);
-    // half-word of digit k for dword q: the codes of rows v = 4n + 3 - q, n = 0..3
-    auto halfword = [&](int k, int q) {
-        const int sh = 21 - 3 * k;
-        const uint32_t sel = ((U[3 - q] >> sh) & 7u) | (((U[7 - q] >> sh) & 7u) << 8) |
-                             (((U[11 - q] >> sh) & 7u) << 16) | (((U[15 - q] >> sh) & 7u) << 24);
-        // E2M1 codes of d = u - 4: -4 -3 -2 -1 0 1 2 3
-        const uint32_t c = __builtin_amdgcn_perm(0x05040200u, 0x0A0C0D0Eu, sel);
-        const uint32_t t = c | (c >> 4);
-        return __builtin_amdgcn_perm(0u, t, 0x0C0C0200u);
-    };
-    // lane h keeps digits 4h + j: it sends the partner its half-words of those
+    for (int v = 0; v < 16; ++v) {
+        const uint32_t U = (uint32_t)((int)rintf(xs[v] * sc) + 0x924924);
+        // octal digit i (bits 3i..3i+2) to bits 0-2 (i even) or 3-5 (i odd) of byte i/2
+        const uint32_t w1 = (U & 0xFFFu) | ((U & 0xFFF000u) << 4);
+        const uint32_t w2 = (w1 & 0x003F003Fu) | ((w1 & 0x0FC00FC0u) << 2);
+        cl[v] = __builtin_amdgcn_perm(kLutHi, kLutLo, w2 & 0x07070707u);
+        ch[v] = __builtin_amdgcn_perm(kLutHi, kLutLo, (w2 >> 3) & 0x07070707u);
+    }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t lo = halfword(j, q), hi = halfword(4 + j, q);
-            const uint32_t mine = half ? hi : lo;
-            const uint32_t give = half ? lo : hi;
-            const uint32_t got = (uint32_t)__shfl_xor((int)give, 32);
-            frag[j][q] = (int)(half ? (got | (mine << 16)) : (mine | (got << 16)));
-        }
+    for (int q = 0; q < 4; ++q) {
+        const int a = 3 - q, b = 7 - q, c = 11 - q, d = 15 - q;  // nibbles n = 0..3
+        const uint32_t abl = cl[a] | (cl[b] << 4), cdl = cl[c] | (cl[d] << 4);
+        const uint32_t abh = ch[a] | (ch[b] << 4), cdh = ch[c] | (ch[d] << 4);
+        // half-words of digits (7, 5), (3, 1), (6, 4), (2, 0)
+        const uint32_t p75 = __builtin_amdgcn_perm(cdl, abl, 0x05010400u);
+        const uint32_t p31 = __builtin_amdgcn_perm(cdl, abl, 0x07030602u);
+        const uint32_t p64 = __builtin_amdgcn_perm(cdh, abh, 0x05010400u);
+        const uint32_t p20 = __builtin_amdgcn_perm(cdh, abh, 0x07030602u);
+        // lanes h = 0 keep digits 0-3, lanes h = 1 digits 4-7; after the swap
+        // [0] holds the low-half lane's dword and [1] the high-half lane's
+        const auto sa = __builtin_amdgcn_permlane32_swap(p31, p75, false, false);
+        const auto sb = __builtin_amdgcn_permlane32_swap(p20, p64, false, false);
+        frag[0][q] = (int)__builtin_amdgcn_perm(sb[1], sb[0], 0x07060302u);  // digit 0 / 4
+        frag[1][q] = (int)__builtin_amdgcn_perm(sa[1], sa[0], 0x07060302u);  // digit 1 / 5
+        frag[2][q] = (int)__builtin_amdgcn_perm(sb[1], sb[0], 0x05040100u);  // digit 2 / 6
+        frag[3][q] = (int)__builtin_amdgcn_perm(sa[1], sa[0], 0x05040100u);  // digit 3 / 7
     }
     return (uint32_t)(E + 128);
 }
