@@ -501,19 +501,18 @@ __device__ __forceinline__ void mfma_fp4s_first(v16f &acc, const v4i &j, const v
 __device__ __forceinline__ uint32_t ld_flag(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// A 16-byte fragment as two device-scope 8-byte loads: they bypass the L1,
-// so a reader that shares the writer's L2 needs no acquire invalidation (an
-// agent-scope invalidation is costly when every wave issues it each step).
-__device__ __forceinline__ v4i ld_frag(const v4i *p) {
-    const uint64_t *q = reinterpret_cast<const uint64_t *>(p);
-    const uint64_t lo = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t hi = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    v4i r;
-    r[0] = (int)(uint32_t)lo;
-    r[1] = (int)(uint32_t)(lo >> 32);
-    r[2] = (int)(uint32_t)hi;
-    r[3] = (int)(uint32_t)(hi >> 32);
-    return r;
+// Direct load of 16 bytes per lane from global memory (wave-uniform base
+// plus the lane's 32-bit byte offset) into LDS at lds_base + 16 lane
+// (wave-uniform), device scope (the L1 is bypassed).  Written as assembly so
+// that the compiler does not track it: it would otherwise make reads of the
+// other staging buffers wait for it.  The caller waits for it (vmcnt) and
+// synchronises the workgroup before any wave reads the bytes; the compiler's
+// own vmcnt waits only get stricter from the extra loads in flight.
+__device__ __forceinline__ void lds_load16(const void *base, uint32_t lane_off, uint32_t lds_base) {
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1 sc1"
+                 :
+                 : "v"(lane_off), "s"(base), "s"(lds_base)
+                 : "memory", "m0");
 }
 
 // Digit fragments of one tile.  Lane (h, l%32) holds 16 rows (item v: row
@@ -584,9 +583,13 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
     static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
     constexpr int NPH = NKB / kPB;  // staging phases per step
-    __shared__ v4i f_lds[2][kPB][kXD][64];
+    // three staging buffers (phase ph uses buffer ph % 3): separate arrays, so
+    // that the compiler sees that reading one does not wait for the direct
+    // loads into the others
+    __shared__ v4i f_b0[kPB][kXD][64], f_b1[kPB][kXD][64], f_b2[kPB][kXD][64];
     __shared__ int wg_abort;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wu = __builtin_amdgcn_readfirstlane(w);  // the same, known to be wave-uniform
     const int wpt = nrb >> 2;
     const int xcd = blockIdx.x & 7, kx = blockIdx.x >> 3;
     const int tl = (kx / wpt) * 8 + xcd;
@@ -728,40 +731,64 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
                 reinterpret_cast<const uint32_t *>(xe + ((size_t)par * cols + col) * nkb);
 #pragma unroll
             for (int q = 0; q < NKB / 4; ++q) ed[q] = ld_flag(ep4 + q);
+            // consumed here, before the direct loads below are in flight: a
+            // later compiler wait for them would also wait for those loads
+#pragma unroll
+            for (int q = 0; q < NKB / 4; ++q) asm volatile("" : "+v"(ed[q]));
         }
-        // staging: wave w loads K block kPB ph + w of phase ph
-        v4i stg[kXD];
+        // staging: wave w loads the fragments of K block kPB ph + w of phase ph
+        // straight into LDS (device scope: no stale L1 lines), two phases
+        // ahead of the products.  Every access names its buffer directly (one
+        // branch per buffer, resolved when the phase loop is unrolled), so the
+        // compiler can tell the buffers apart and does not make the reads of
+        // one wait for the loads into another.
+        // fragment (kb, k) of this step: row (par nkb + kb) kXD + k of xd, the
+        // lane's column col (uniform row base, per-lane byte offset 16 col)
+        auto dma_into = [&](v4i(&dst)[kPB][kXD][64], int ph) {
+            const int kb = kPB * ph + wu;
+#pragma unroll
+            for (int k = 0; k < kXD; ++k) {
+                const v4i *row = xd + (((size_t)par * nkb + kb) * kXD + k) * cols;
+                lds_load16(row, (uint32_t)col * 16u,
+                           (uint32_t)(uintptr_t)(__attribute__((address_space(3))) void *)&dst[wu][k][0]);
+            }
+        };
         auto load_stage = [&](int ph) {
-            const int kb = kPB * ph + w;
-#pragma unroll
-            for (int k = 0; k < kXD; ++k)
-                stg[k] = ld_frag(xd + (((size_t)par * nkb + kb) * kXD + k) * cols + col);
+            if (ph % 3 == 0) dma_into(f_b0, ph);
+            else if (ph % 3 == 1) dma_into(f_b1, ph);
+            else dma_into(f_b2, ph);
         };
-        auto store_stage = [&](int buf) {
-#pragma unroll
-            for (int k = 0; k < kXD; ++k) f_lds[buf][w][k][lane] = stg[k];
+        // this wave's loads of phase ph are in LDS when at most the kXD loads of
+        // phase ph+1 are outstanding; the barrier then covers all waves'.  (A
+        // bare barrier: __syncthreads would also wait for the loads in flight.)
+        auto wait_stage = [&](int ph) {
+            if (ph + 1 < NPH)
+                asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+            else
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __builtin_amdgcn_s_barrier();
         };
+        static_assert(kXD == 8, "the wait above counts kXD loads per phase");
         load_stage(0);
-        store_stage(0);
-        __syncthreads();
+        if (NPH > 1) load_stage(1);
+        asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)" ::: "memory");
+        if (NPH == 1) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();  // also publishes wg_abort
         if (wg_abort) break;
         v16f acc0, acc1;
-#pragma unroll
-        for (int ph = 0; ph < NPH; ++ph) {
-            const int buf = ph & 1;
-            if (ph + 1 < NPH) load_stage(ph + 1);
+        // the products of phase ph, operands from its buffer
+        auto products = [&](const v4i(&src)[kPB][kXD][64], int ph) {
             // operand reads from LDS run kPre fragments ahead of the products
             constexpr int kPre = 4, kFr = kPB * kXD;
             v4i af[kPre];
 #pragma unroll
-            for (int q = 0; q < kPre; ++q) af[q] = f_lds[buf][q / kXD][q % kXD][lane];
+            for (int q = 0; q < kPre; ++q) af[q] = src[q / kXD][q % kXD][lane];
 #pragma unroll
             for (int fi = 0; fi < kFr; ++fi) {
                 const int kl = fi / kXD, k = fi % kXD;
                 const int kb = kPB * ph + kl;
                 const v4i a = af[fi % kPre];
-                if (fi + kPre < kFr)
-                    af[fi % kPre] = f_lds[buf][(fi + kPre) / kXD][(fi + kPre) % kXD][lane];
+                if (fi + kPre < kFr) af[fi % kPre] = src[(fi + kPre) / kXD][(fi + kPre) % kXD][lane];
                 const int e = (int)((ed[kb >> 2] >> (8 * (kb & 3))) & 0xFFu);
                 const int sb = e - 2 - 3 * k;  // 127 + (E - 1 - 3k), E = e - 128
                 if (kb == 0 && k == 0) {
@@ -772,8 +799,14 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
                     mfma_fp4s(acc1, jr1[kb], a, one, sb);
                 }
             }
-            if (ph + 1 < NPH) store_stage(buf ^ 1);
-            __syncthreads();
+        };
+#pragma unroll
+        for (int ph = 0; ph < NPH; ++ph) {
+            if (ph + 2 < NPH) load_stage(ph + 2);
+            if (ph % 3 == 0) products(f_b0, ph);
+            else if (ph % 3 == 1) products(f_b1, ph);
+            else products(f_b2, ph);
+            if (ph + 1 < NPH) wait_stage(ph + 1);
         }
         mfma_drain(acc0, acc1);
 #pragma unroll
