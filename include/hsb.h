@@ -82,7 +82,12 @@ typedef enum {
     HSB_OPT_KERNEL_MS = 5,       /* read only: summed bracketed time (ms) of the last run with
                                     timing on (synchronises the events) */
     HSB_OPT_KERNEL_LAUNCHES = 6, /* read only: number of launches inside those brackets */
-    HSB_OPT_LAST_PLAN = 7        /* read only: plan of the last successful run, an hsb_plan */
+    HSB_OPT_LAST_PLAN = 7,       /* read only: plan of the last successful run, an hsb_plan */
+    HSB_OPT_LOCAL_EXCHANGE = 8   /* FP4 plan: 1 (default): a team of workgroups that share
+                                    one XCD exchanges its per-step data through that XCD's L2
+                                    (workgroup-scope stores, no cache invalidation); 0: always
+                                    device scope (slower; results are the same).  Batches use
+                                    the option of their first context. */
 } hsb_option;
 
 typedef enum {

@@ -68,6 +68,7 @@ struct hsb_ctx {
     int precision = HSB_PREC_AUTO;
     int timing = 0;
     int last_plan = -1;
+    int local_exchange = 1;
     hsb::KernelTimer timer;
     // workspace
     int Rpad_cap = 0;
@@ -207,6 +208,10 @@ extern "C" int hsb_set_option(hsb_ctx *h, int key, double v) {
         if (!(v == 0.0 || v == 1.0)) return fail(HSB_EINVAL, "TIMING must be 0 or 1");
         h->timing = (int)v;
         return HSB_OK;
+    case HSB_OPT_LOCAL_EXCHANGE:
+        if (!(v == 0.0 || v == 1.0)) return fail(HSB_EINVAL, "LOCAL_EXCHANGE must be 0 or 1");
+        h->local_exchange = (int)v;
+        return HSB_OK;
     case HSB_OPT_KERNEL_MS:
     case HSB_OPT_KERNEL_LAUNCHES:
     case HSB_OPT_LAST_PLAN:
@@ -233,6 +238,7 @@ extern "C" int hsb_get_option(hsb_ctx *h, int key, double *v) {
     }
     case HSB_OPT_KERNEL_LAUNCHES: *v = (double)h->timer.launches; return HSB_OK;
     case HSB_OPT_LAST_PLAN: *v = h->last_plan; return HSB_OK;
+    case HSB_OPT_LOCAL_EXCHANGE: *v = h->local_exchange; return HSB_OK;
     default: return fail(HSB_EINVAL, "unknown option key %d", key);
     }
 }
@@ -398,6 +404,7 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
         pr.k0 = k0; pr.k1 = k1; pr.Ns = Ns; pr.interval = interval;
         pr.a0 = a0; pr.c0 = c0; pr.dt = dt;
         pr.epart = b.epart;
+        pr.local_exchange = h->local_exchange;
         rc = hsb::persistent_run(h->pj, a->variant, pr, b, N, s, h->timer);
         if (rc != HSB_OK) return fail(rc, "%s", hsb::persistent_error());
     } else {
@@ -618,6 +625,7 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
         pr.Npad = Nst; pr.Rpad = Rtot; pr.R = used;
         pr.k0 = 0; pr.k1 = a->steps; pr.Ns = a->steps; pr.interval = interval;
         pr.a0 = a->a0; pr.c0 = 0.0f; pr.dt = a->dt;
+        pr.local_exchange = hs[0]->local_exchange;
         int rc = hsb::persistent_run_teams(lead->bwork, a->variant, nkb, teams.data(),
                                            (int)teams.size(), pr, bb, Nst, s, lead->timer);
         if (rc != HSB_OK) return done(fail(rc, "%s", hsb::persistent_error()));

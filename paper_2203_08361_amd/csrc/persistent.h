@@ -25,6 +25,7 @@ struct PersistentRun {
     int k0, k1, Ns, interval;
     float a0, c0, dt;
     double *epart;         // unused by this path (its own partials are kept per sample)
+    int local_exchange = 1;  // 0: device-scope exchange even for XCD-local teams
 };
 
 bool persistent_supported(int N);

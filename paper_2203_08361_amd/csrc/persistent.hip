@@ -275,8 +275,8 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, uint64_t *xb, uint32_t *__restrict__ snap,
     float *__restrict__ ep, const float *__restrict__ ptab, int32_t *__restrict__ bad,
-    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, uint32_t epoch, int nkb,
-    int nrb, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
+    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, uint32_t epoch, int local_ok,
+    int nkb, int nrb, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
     static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
     constexpr int NQ = NKB / 4;  // K blocks expanded by each wave
     __shared__ v4i a_lds[2][NKB][64];
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
                 break;
             }
         }
-        xcd_local = ok && __all((int)(uint32_t)v == my_xcc);
+        xcd_local = local_ok && ok && __all((int)(uint32_t)v == my_xcc);
     }
 
     v4i jr0[NKB], jr1[NKB];
@@ -579,8 +579,8 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, v4i *xd, uint8_t *xe, uint32_t *flags,
     uint32_t *__restrict__ snap, const float *__restrict__ ptab, int32_t *__restrict__ bad,
-    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, uint32_t epoch, int nkb, int nrb,
-    int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
+    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, uint32_t epoch, int local_ok,
+    int nkb, int nrb, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
     static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
     constexpr int NPH = NKB / kPB;  // staging phases per step
     // three staging buffers (phase ph uses buffer ph % 3): separate arrays, so
@@ -623,7 +623,7 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
                 break;
             }
         }
-        xcd_local = ok && __all((int)(uint32_t)v == my_xcc);
+        xcd_local = local_ok && ok && __all((int)(uint32_t)v == my_xcc);
     }
 
     v4i jr0[NKB], jr1[NKB];
@@ -1185,22 +1185,24 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
             int nkb_v = nkb, nrb_v = nrb, Rpad_v = Rpad, t0_v = t0, nt_v = nt;
             uint32_t epoch = ++pw->epoch;
             if (epoch == 0) epoch = ++pw->epoch;  // slots start zeroed: epoch 0 is never used
+            int local_ok = run.local_exchange ? 1 : 0;
             const float *gam = run.gamma;
             void *args_d[] = {(void *)&pw->teams, (void *)&run.X,    (void *)&run.Y,
                               (void *)&gam,       (void *)&pw->xb,   (void *)&pw->snap,
                               (void *)&pw->ep,    (void *)&pw->ptab, (void *)&b.bad,
                               (void *)&b.status,  (void *)&pw->err,  (void *)&pw->xslot,
-                              (void *)&epoch,     (void *)&nkb_v,    (void *)&nrb_v,
-                              (void *)&Rpad_v,    (void *)&t0_v,     (void *)&nt_v,
-                              (void *)&g,         (void *)&dt,       (void *)&a0dtv};
+                              (void *)&epoch,     (void *)&local_ok, (void *)&nkb_v,
+                              (void *)&nrb_v,     (void *)&Rpad_v,   (void *)&t0_v,
+                              (void *)&nt_v,      (void *)&g,        (void *)&dt,
+                              (void *)&a0dtv};
             void *args_b[] = {(void *)&pw->teams, (void *)&run.X,     (void *)&run.Y,
                               (void *)&gam,       (void *)&pw->xd,    (void *)&pw->xe,
                               (void *)&pw->flags, (void *)&pw->snap,  (void *)&pw->ptab,
                               (void *)&b.bad,     (void *)&b.status,  (void *)&pw->err,
-                              (void *)&pw->xslot, (void *)&epoch,     (void *)&nkb_v,
-                              (void *)&nrb_v,     (void *)&Rpad_v,    (void *)&t0_v,
-                              (void *)&nt_v,      (void *)&g,         (void *)&dt,
-                              (void *)&a0dtv};
+                              (void *)&pw->xslot, (void *)&epoch,     (void *)&local_ok,
+                              (void *)&nkb_v,     (void *)&nrb_v,     (void *)&Rpad_v,
+                              (void *)&t0_v,      (void *)&nt_v,      (void *)&g,
+                              (void *)&dt,        (void *)&a0dtv};
             void **args = bsb ? args_b : args_d;
             // every workgroup of the grid is resident at once: the grid never exceeds
             // the occupancy-derived capacity, and every wait inside the kernel is

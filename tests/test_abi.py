@@ -49,6 +49,26 @@ def test_struct_layout_matches_header(tmp_path, struct):
         assert getattr(cls, f).offset == off, f
 
 
+def test_constants_match_header(tmp_path):
+    """Every HSB_* enumerator and return code of the header has the binding's value."""
+    text = open(os.path.join(ROOT, "include", "hsb.h")).read()
+    names = sorted(set(re.findall(r"\b(HSB_(?:OK|E[A-Z]+|OPT_[A-Z_]+|PREC_[A-Z0-9_]+|PLAN_[A-Z0-9]+|"
+                                  r"DSB|BSB))\b", text)))
+    names = [n for n in names if hasattr(hsb, n)]
+    assert len(names) >= 20
+    src = tmp_path / "consts.c"
+    src.write_text("#include <stdio.h>\n#include \"hsb.h\"\nint main(void){\n"
+                   + "".join('printf("%%d\\n", (int)%s);\n' % n for n in names) + "return 0;}\n")
+    exe = tmp_path / "consts"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    for n, v in zip(names, vals):
+        assert getattr(hsb, n) == v, n
+
+
 def _create_rc(J, N=None):
     L = hsb.load_library()
     J = np.ascontiguousarray(J, dtype=np.float32)

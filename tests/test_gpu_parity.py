@@ -105,6 +105,33 @@ def test_dsb_fp4_every_padded_size_bit_exact(N):
     assert_bit_exact(g, o)
 
 
+@pytest.mark.parametrize("variant", ["dsb", "bsb"])
+def test_fp4_device_scope_exchange_gives_the_same_run(variant):
+    """LOCAL_EXCHANGE = 0 sends every team's per-step data through device-scope
+    stores and loads (with acquire/release fences for bSB), the path used when
+    a team's workgroups do not share an XCD; the run must not change."""
+    var = hsb.HSB_DSB if variant == "dsb" else hsb.HSB_BSB
+    J = synth.sk_instance(700, 17)
+    say("fp4 device-scope exchange", variant)
+    outs = []
+    for local in (1, 0):
+        with hsb.Context(J, precision="mixed", init_amp=0.1, energy_interval=25) as ctx:
+            assert ctx.get_option("local_exchange") == 1
+            ctx.set_option("local_exchange", local)
+            assert ctx.get_option("local_exchange") == local
+            out = ctx.run_ex(var, 80, 40, 1.0, 0.5 / np.sqrt(700), 1.0, 0.02, 9, want_state=True)
+            torch.cuda.synchronize()
+            assert ctx.last_plan() == "fp4"
+            outs.append({k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()})
+            with pytest.raises(hsb.HSBError):
+                ctx.set_option("local_exchange", 2)
+    for k in ("x", "y", "spins", "energy", "best_energy", "final_energy", "best_step"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+    if variant == "dsb":
+        o = oracle_run(J, oracle.DSB, oracle.FP32, 80, 40, seed=9, gamma=0.02, interval=25)
+        assert_bit_exact(outs[1], o)
+
+
 @pytest.mark.parametrize("plan", ["fp32", "mixed"])
 def test_dsb_zero_steps_and_final_mode(plan):
     J = synth.sk_instance(50, 2)
