@@ -36,6 +36,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 namespace hsb {
@@ -484,19 +485,30 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
 constexpr int kXD = 8;   // base-8 digits per x
 constexpr int kPB = 4;   // K blocks per staging phase (one per wave)
 
+// The same product with the B operand's block scale taken from byte BYTE of
+// sb (four digits' scales packed in one register; op_sel / op_sel_hi bit 1
+// give the byte index's low and high bit).
+#define HSB_MFMA_FP4S(SEL, SRC_C, CONSTR)                                                    \
+    asm volatile("v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, " SRC_C ", %3, %4 " SEL      \
+                 " cbsz:4 blgp:4"                                                            \
+                 : CONSTR(acc)                                                               \
+                 : "a"(j), "v"(b), "v"(sa), "v"(sb))
+template <int BYTE>
 __device__ __forceinline__ void mfma_fp4s(v16f &acc, const v4i &j, const v4i &b, int sa, int sb) {
-    asm volatile(
-        "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, %0, %3, %4 op_sel_hi:[0,0,0] cbsz:4 blgp:4"
-        : "+v"(acc)
-        : "a"(j), "v"(b), "v"(sa), "v"(sb));
+    if constexpr (BYTE == 0) HSB_MFMA_FP4S("op_sel_hi:[0,0,0]", "%0", "+v");
+    else if constexpr (BYTE == 1) HSB_MFMA_FP4S("op_sel:[0,1,0] op_sel_hi:[0,0,0]", "%0", "+v");
+    else if constexpr (BYTE == 2) HSB_MFMA_FP4S("op_sel_hi:[0,1,0]", "%0", "+v");
+    else HSB_MFMA_FP4S("op_sel:[0,1,0] op_sel_hi:[0,1,0]", "%0", "+v");
 }
+template <int BYTE>
 __device__ __forceinline__ void mfma_fp4s_first(v16f &acc, const v4i &j, const v4i &b, int sa,
                                                 int sb) {
-    asm volatile(
-        "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, 0, %3, %4 op_sel_hi:[0,0,0] cbsz:4 blgp:4"
-        : "=&v"(acc)
-        : "a"(j), "v"(b), "v"(sa), "v"(sb));
+    if constexpr (BYTE == 0) HSB_MFMA_FP4S("op_sel_hi:[0,0,0]", "0", "=&v");
+    else if constexpr (BYTE == 1) HSB_MFMA_FP4S("op_sel:[0,1,0] op_sel_hi:[0,0,0]", "0", "=&v");
+    else if constexpr (BYTE == 2) HSB_MFMA_FP4S("op_sel_hi:[0,1,0]", "0", "=&v");
+    else HSB_MFMA_FP4S("op_sel:[0,1,0] op_sel_hi:[0,1,0]", "0", "=&v");
 }
+#undef HSB_MFMA_FP4S
 
 __device__ __forceinline__ uint32_t ld_flag(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -598,7 +610,7 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     const v4i *__restrict__ jpk = static_cast<const v4i *>(teams[team].jpk);
     const int N = teams[team].N;
     const float c0 = teams[team].c0;
-    const int rb = (kx % wpt) * 4 + w;
+    const int rb = (kx % wpt) * 4 + wu;  // uniform: its addresses stay in scalar registers
     const int r0 = team * 32;
     const int nchunk = 2 * nrb;
     const int half = lane >> 5, l32 = lane & 31;
@@ -783,20 +795,37 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
             v4i af[kPre];
 #pragma unroll
             for (int q = 0; q < kPre; ++q) af[q] = src[q / kXD][q % kXD][lane];
+            // scale of digit k of K block kb: 127 + (E - 1 - 3k) = e - 2 - 3k (E = e - 128),
+            // bytes k = 0..3 in sbp[0] and 4..7 in sbp[1]: the exponent byte of kb
+            // copied to all four bytes, less 2 + 3k per byte (e >= 28: no borrows)
+            int sbp[2];
 #pragma unroll
             for (int fi = 0; fi < kFr; ++fi) {
                 const int kl = fi / kXD, k = fi % kXD;
                 const int kb = kPB * ph + kl;
                 const v4i a = af[fi % kPre];
                 if (fi + kPre < kFr) af[fi % kPre] = src[(fi + kPre) / kXD][(fi + kPre) % kXD][lane];
-                const int e = (int)((ed[kb >> 2] >> (8 * (kb & 3))) & 0xFFu);
-                const int sb = e - 2 - 3 * k;  // 127 + (E - 1 - 3k), E = e - 128
-                if (kb == 0 && k == 0) {
-                    mfma_fp4s_first(acc0, jr0[0], a, one, sb);
-                    mfma_fp4s_first(acc1, jr1[0], a, one, sb);
-                } else {
-                    mfma_fp4s(acc0, jr0[kb], a, one, sb);
-                    mfma_fp4s(acc1, jr1[kb], a, one, sb);
+                if (k == 0) {
+                    const uint32_t rep = __builtin_amdgcn_perm(0u, ed[kb >> 2], 0x01010101u * (kb & 3));
+                    sbp[0] = (int)(rep - 0x0B080502u);
+                    sbp[1] = (int)(rep - 0x1714110Eu);
+                }
+                const int sb = sbp[k >> 2];
+                auto pair = [&](auto byte) {
+                    constexpr int B = decltype(byte)::value;
+                    if (kb == 0 && k == 0) {
+                        mfma_fp4s_first<B>(acc0, jr0[0], a, one, sb);
+                        mfma_fp4s_first<B>(acc1, jr1[0], a, one, sb);
+                    } else {
+                        mfma_fp4s<B>(acc0, jr0[kb], a, one, sb);
+                        mfma_fp4s<B>(acc1, jr1[kb], a, one, sb);
+                    }
+                };
+                switch (k & 3) {
+                case 0: pair(std::integral_constant<int, 0>{}); break;
+                case 1: pair(std::integral_constant<int, 1>{}); break;
+                case 2: pair(std::integral_constant<int, 2>{}); break;
+                default: pair(std::integral_constant<int, 3>{}); break;
                 }
             }
         };
