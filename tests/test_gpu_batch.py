@@ -55,8 +55,9 @@ def test_batch_uneven_instances_bit_exact():
 
 
 def test_batch_matches_single_runs_outside_fp4():
-    """A Gaussian instance (not FP4-exact) and the bSB variant run job by job;
-    the batch must return what hsb_run_ex returns for each job."""
+    """Jobs of a Gaussian instance (not FP4-exact: run job by job) and, for bSB,
+    jobs of an FP4-exact instance (one FP4 class): the batch must return what
+    hsb_run_ex returns for each job."""
     Js = [synth.sk_instance(120, 3), synth.gaussian_instance(90, 4)]
     ctxs = [hsb.Context(J) for J in Js]
     jobs = [dict(instance=0, R=24, c0=0.05, gamma=0.01, seed=5),
