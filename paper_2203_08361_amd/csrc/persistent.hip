@@ -8,9 +8,9 @@
 //
 // Work decomposition.  Replicas never interact, so a "team" of waves owns a
 // tile of 32 replicas for the whole run, and inside the team wave `rb` owns
-// spin rows [64 rb, 64 rb + 64).  Each wave keeps, for the whole launch,
-//   - its 64 rows of J as FP4 MFMA operands in registers (64 x Npad x 4 bit),
-//   - x and y of its 64 x 32 (row, replica) block in registers.
+// spin rows [32 rb, 32 rb + 32).  Each wave keeps, for the whole launch,
+//   - its 32 rows of J as FP4 MFMA operands in registers (32 x Npad x 4 bit),
+//   - x and y of its 32 x 32 (row, replica) block in registers.
 // One step (Methods, eqs. (16)-(22)) is
 //   1. F^T = S^T J  with S = sgn(x(t_k)) of all Npad rows of the team's 32
 //      replicas, on v_mfma_scale_f32_32x32x64_f8f6f4 (FP4 x FP4, unit scales);
@@ -51,7 +51,7 @@ struct PersistentWork {
     size_t xb_words = 0;
     uint32_t *snap = nullptr;    // [ns][nchunk][Rpad] sign words of sampled states
     size_t snap_words = 0;
-    float *ep = nullptr;         // [ns][nrb][Rpad] energy partials
+    float *ep = nullptr;         // [ns][nparts][Rpad] energy partials (per row block)
     size_t ep_elems = 0;
     float *ptab = nullptr;       // p_k = a0 - a(t_k) of the steps of one segment
     size_t ptab_elems = 0;
@@ -132,6 +132,9 @@ __device__ __forceinline__ void mfma_fp4(v16f &acc, const v4i &j, const v4i &b, 
 // 21 wait states: more than an XDL write needs before a VALU read of its vdst.
 __device__ __forceinline__ void mfma_drain(v16f &acc0, v16f &acc1) {
     asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 4" : "+v"(acc0), "+v"(acc1));
+}
+__device__ __forceinline__ void mfma_drain(v16f &acc) {
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 4" : "+v"(acc));
 }
 
 // FP4 encoding of the values exact in E2M1.
@@ -265,19 +268,25 @@ __device__ __forceinline__ void sb_update_tied(float f, float p, float c0, float
     asm("v_fma_f32 %0, %1, %0, %2" : "+v"(y) : "v"(gdt), "v"(ytt));  // y' = (gamma dt) y + y~~
 }
 
-// One workgroup = 4 waves = 4 consecutive row blocks of one team, so the four
-// waves need the same +-1 operand (the team's signs).  Each step every wave
-// gathers and expands a quarter of the K blocks into LDS (ping-pong by step
-// parity), one workgroup barrier publishes them, and each wave then runs its
-// MFMAs with its J rows from registers and the operand from LDS, followed by
-// the fused update of its 64 rows x 32 replicas.
+// One workgroup = 4 waves = 4 consecutive 32-row blocks of one team, so the
+// four waves need the same +-1 operand (the team's signs).  Each step every
+// wave gathers and expands a quarter of the K blocks into LDS (ping-pong by
+// step parity), one workgroup barrier publishes them, and each wave then runs
+// its MFMAs with its J rows from registers and the operand from LDS, followed
+// by the fused update of its 32 rows x 32 replicas.
+// Two workgroups share a CU (two waves per SIMD): a wave's step is a serial
+// chain (products, update, exchange round trip), and the other wave on the
+// SIMD -- of another team, which is out of step with it -- fills the matrix
+// core while this one waits for its team's signs.  That is why a wave holds
+// 32 rows rather than 64: 32 rows of J take 128 of the 256 registers two waves
+// per SIMD leave each.
 template <int NKB>
-__global__ __launch_bounds__(256, 1) void k_dsb_fp4(
+__global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, uint64_t *xb, uint32_t *__restrict__ snap,
     float *__restrict__ ep, const float *__restrict__ ptab, int32_t *__restrict__ bad,
     int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, uint32_t epoch, int local_ok,
-    int nkb, int nrb, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
+    int nkb, int nchunk, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
     static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
     constexpr int NQ = NKB / 4;  // K blocks expanded by each wave
     __shared__ v4i a_lds[2][NKB][64];
@@ -288,7 +297,7 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     // words they exchange every step stay in that XCD's L2: team t uses the
     // blocks b = 8 (wpt (t / 8) + k) + t % 8, k = 0 .. wpt-1.  (Correctness does
     // not depend on the placement; only the exchange latency does.)
-    const int wpt = nrb >> 2;  // workgroups per team
+    const int wpt = nchunk >> 2;  // workgroups per team
     const int xcd = blockIdx.x & 7, kx = blockIdx.x >> 3;
     const int tl = (kx / wpt) * 8 + xcd;  // team within this launch
     if (tl >= nteams) return;             // whole workgroup
@@ -298,9 +307,8 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
     const v4i *__restrict__ jpk = static_cast<const v4i *>(teams[team].jpk);
     const int N = teams[team].N;
     const float c0 = teams[team].c0;
-    const int rb = (kx % wpt) * 4 + w;
+    const int rb = (kx % wpt) * 4 + w;  // 32-row block = chunk
     const int r0 = team * 32;
-    const int nchunk = 2 * nrb;
     const int half = lane >> 5, l32 = lane & 31;
     if (threadIdx.x == 0) wg_abort = 0;
 
@@ -327,53 +335,47 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
         xcd_local = local_ok && ok && __all((int)(uint32_t)v == my_xcc);
     }
 
-    v4i jr0[NKB], jr1[NKB];
+    v4i jr[NKB];
 #pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) {
-        jr0[kb] = jpk[((size_t)(rb * 2 + 0) * NKB + kb) * 64 + lane];
-        jr1[kb] = jpk[((size_t)(rb * 2 + 1) * NKB + kb) * 64 + lane];
-    }
+    for (int kb = 0; kb < NKB; ++kb) jr[kb] = jpk[((size_t)rb * NKB + kb) * 64 + lane];
     const int one = 127;  // E8M0 block scale 2^0
 
-    // item v of tile rt: replica r0 + l%32, row 64 rb + 32 rt + 8(v/4) + 4(l/32) + v%4
-    // (vectors rather than arrays: the register allocator then keeps them in
-    // place across the step loop instead of copying them every step)
-    v16f xs0, xs1, ys0, ys1;
+    // item v: replica r0 + l%32, row 32 rb + 8(v/4) + 4(l/32) + v%4 (vectors
+    // rather than arrays: the register allocator then keeps them in place
+    // across the step loop instead of copying them every step)
+    v16f xs, ys;
     const int rep = r0 + l32;
     const float gdt = gamma[rep] * dt;
-    const int rowb = rb * 64 + 4 * half;
+    const int rowb = rb * 32 + 4 * half;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-        const int row0 = rowb + 8 * (v >> 2) + (v & 3), row1 = row0 + 32;
+        const int row = rowb + 8 * (v >> 2) + (v & 3);
         // + 0.0f turns a caller's -0.0 into +0.0, so that the sign bit of x is its
         // sgn (sgn(0) = +1); the update never produces -0.0 from a non-negative zero
-        xs0[v] = row0 < N ? X[(size_t)row0 * Rpad + rep] + 0.0f : 0.0f;
-        xs1[v] = row1 < N ? X[(size_t)row1 * Rpad + rep] + 0.0f : 0.0f;
-        ys0[v] = row0 < N ? Y[(size_t)row0 * Rpad + rep] : 0.0f;
-        ys1[v] = row1 < N ? Y[(size_t)row1 * Rpad + rep] : 0.0f;
+        xs[v] = row < N ? X[(size_t)row * Rpad + rep] + 0.0f : 0.0f;
+        ys[v] = row < N ? Y[(size_t)row * Rpad + rep] : 0.0f;
     }
 
-    // publish the sign words of the state x_m (tag m); snapshot at samples.
-    // Lane l holds 16 rows of each tile for replica l%32: its bits form half a
-    // word, and lanes l, l+32 swap the halves they do not store.
+    // publish the sign word of the state x_m (tag m); snapshot at samples.
+    // Lane l holds 16 rows of the block for replica l%32, lane l+32 the other
+    // 16: the lower half of the wave stores the merged word.
     auto publish = [&](int m) {
         // b = (b << 1) | sign bit, highest item first: one operation per item
-        uint32_t b0 = 0, b1 = 0;
+        uint32_t b = 0;
 #pragma unroll
-        for (int v = 15; v >= 0; --v) {
-            b0 = __builtin_amdgcn_alignbit(b0, __float_as_uint(xs0[v]), 31);
-            b1 = __builtin_amdgcn_alignbit(b1, __float_as_uint(xs1[v]), 31);
+        for (int v = 15; v >= 0; --v) b = __builtin_amdgcn_alignbit(b, __float_as_uint(xs[v]), 31);
+        const uint32_t got = (uint32_t)__shfl_xor((int)b, 32);
+        if (half == 0) {
+            const uint32_t word = b | (got << 16);
+            const size_t slot = (size_t)rb * Rpad + rep;
+            const uint64_t tagged = ((uint64_t)(uint32_t)m << 32) | word;
+            if (xcd_local)
+                st_tagged_xcd(xb + (size_t)(m & 1) * nchunk * Rpad + slot, tagged);
+            else
+                st_tagged(xb + (size_t)(m & 1) * nchunk * Rpad + slot, tagged);
+            if (seg_is_sample(g, m))
+                snap[(size_t)seg_sample_index(g, m) * nchunk * Rpad + slot] = word;
         }
-        const uint32_t got = (uint32_t)__shfl_xor((int)(half ? b0 : b1), 32);
-        const uint32_t word = half ? (got | (b1 << 16)) : (b0 | (got << 16));
-        const size_t slot = (size_t)(rb * 2 + half) * Rpad + rep;
-        const uint64_t tagged = ((uint64_t)(uint32_t)m << 32) | word;
-        if (xcd_local)
-            st_tagged_xcd(xb + (size_t)(m & 1) * nchunk * Rpad + slot, tagged);
-        else
-            st_tagged(xb + (size_t)(m & 1) * nchunk * Rpad + slot, tagged);
-        if (seg_is_sample(g, m))
-            snap[(size_t)seg_sample_index(g, m) * nchunk * Rpad + slot] = word;
     };
 
     publish(g.seg_k0);
@@ -392,7 +394,7 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
         }
         __syncthreads();
         if (wg_abort) break;
-        v16f acc0, acc1;
+        v16f acc;
         // operand reads from LDS run kPre K blocks ahead of the products
         constexpr int kPre = 4;
         v4i af[kPre];
@@ -402,28 +404,24 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
         for (int kb = 0; kb < NKB; ++kb) {
             const v4i a = af[kb % kPre];
             if (kb + kPre < NKB) af[kb % kPre] = a_lds[buf][kb + kPre][lane];
-            if (kb == 0) {
-                mfma_fp4_first(acc0, jr0[0], a, one);
-                mfma_fp4_first(acc1, jr1[0], a, one);
-            } else {
-                mfma_fp4(acc0, jr0[kb], a, one);
-                mfma_fp4(acc1, jr1[kb], a, one);
-            }
+            if (kb == 0)
+                mfma_fp4_first(acc, jr[0], a, one);
+            else
+                mfma_fp4(acc, jr[kb], a, one);
         }
-        mfma_drain(acc0, acc1);
+        mfma_drain(acc);
         if (seg_is_sample(g, m)) {
-            // eq. (1) partial over this wave's 64 rows of s_i f_i (exact integers/halves)
+            // eq. (1) partial over this wave's 32 rows of s_i f_i (exact integers/halves)
             const int j = seg_sample_index(g, m);
             float part = 0.0f;
             bool fin = true;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                part += sgnf(xs0[v]) * acc0[v] + sgnf(xs1[v]) * acc1[v];
-                fin = fin && isfinite(xs0[v]) && isfinite(xs1[v]) && isfinite(ys0[v]) &&
-                      isfinite(ys1[v]);
+                part += sgnf(xs[v]) * acc[v];
+                fin = fin && isfinite(xs[v]) && isfinite(ys[v]);
             }
             part += __shfl_xor(part, 32);
-            if (half == 0) ep[((size_t)j * nrb + rb) * Rpad + rep] = part;
+            if (half == 0) ep[((size_t)j * nchunk + rb) * Rpad + rep] = part;
             if (!fin) {
                 bad[rep] = 1;
                 status[0] = 1;
@@ -432,27 +430,20 @@ __global__ __launch_bounds__(256, 1) void k_dsb_fp4(
         if (m == g.seg_k1) break;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            float x0 = xs0[v], y0 = ys0[v], x1 = xs1[v], y1 = ys1[v];
-            sb_update_tied(acc0[v], p, c0, dt, a0dt, gdt, x0, y0);
-            sb_update_tied(acc1[v], p, c0, dt, a0dt, gdt, x1, y1);
-            xs0[v] = x0;
-            ys0[v] = y0;
-            xs1[v] = x1;
-            ys1[v] = y1;
+            float x = xs[v], y = ys[v];
+            sb_update_tied(acc[v], p, c0, dt, a0dt, gdt, x, y);
+            xs[v] = x;
+            ys[v] = y;
         }
         publish(m + 1);
     }
     // write the state back
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-        const int row0 = rowb + 8 * (v >> 2) + (v & 3), row1 = row0 + 32;
-        if (row0 < N) {
-            X[(size_t)row0 * Rpad + rep] = xs0[v];
-            Y[(size_t)row0 * Rpad + rep] = ys0[v];
-        }
-        if (row1 < N) {
-            X[(size_t)row1 * Rpad + rep] = xs1[v];
-            Y[(size_t)row1 * Rpad + rep] = ys1[v];
+        const int row = rowb + 8 * (v >> 2) + (v & 3);
+        if (row < N) {
+            X[(size_t)row * Rpad + rep] = xs[v];
+            Y[(size_t)row * Rpad + rep] = ys[v];
         }
     }
 }
@@ -908,23 +899,24 @@ __global__ __launch_bounds__(256) void k_energy_fp4(const FP4Team *__restrict__ 
 // Grid Rpad/32, 256 threads: lane group g = threadIdx.x / 32 scans samples
 // j = g, g + 8, ... of 32 replicas; the groups' minima are merged with the
 // earliest sample winning ties, then the winning sample's sign words are
-// decoded into best_s.  Every partial is a multiple of 1/2 below 2^23 in
-// magnitude, so the FP64 totals are exact in any order.
+// decoded into best_s.  A sample's energy is -1/2 times the sum of its nparts
+// partials (one per row block of the kernel that formed them).  Every partial
+// is a multiple of 1/2 below 2^23 in magnitude, so the FP64 totals are exact
+// in any order.
 __global__ __launch_bounds__(256) void k_fp4_best(
-    const float *__restrict__ ep, const uint32_t *__restrict__ snap, int ns, int nrb, int N, int R,
-    int Rpad, SegArgs g, double *__restrict__ best_e, double *__restrict__ last_e,
+    const float *__restrict__ ep, const uint32_t *__restrict__ snap, int ns, int nparts, int nchunk,
+    int N, int R, int Rpad, SegArgs g, double *__restrict__ best_e, double *__restrict__ last_e,
     int32_t *__restrict__ best_step, const int32_t *__restrict__ bad, int8_t *__restrict__ best_s) {
     __shared__ double s_e[8][32];
     __shared__ int s_j[8][32];
     const int rl = threadIdx.x & 31, grp = threadIdx.x >> 5;
     const int r = blockIdx.x * 32 + rl;
-    const int nchunk = 2 * nrb;
     double emin = __builtin_huge_val();
     int jmin = -1;
     if (r < R) {
         for (int j = grp; j < ns; j += 8) {
             double e = 0.0;
-            for (int b = 0; b < nrb; ++b) e += (double)ep[((size_t)j * nrb + b) * Rpad + r];
+            for (int b = 0; b < nparts; ++b) e += (double)ep[((size_t)j * nparts + b) * Rpad + r];
             e = -0.5 * e;
             if (j == ns - 1) last_e[r] = bad[r] ? __builtin_nan("") : e;
             if (e < emin) {
@@ -1131,8 +1123,10 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
             &nb, bsb ? pick_bsb_kernel(nkb) : pick_kernel(nkb), 256, 0);
     if (e != hipSuccess) return perr(HSB_EDEVICE, "FP4 path: %s", hipGetErrorString(e));
     // teams per launch: a multiple of 8 (one slot per XCD) whose workgroups all
-    // fit on the device at once
-    const int wg_capacity = nb * ncu, wpt = nrb / 4;
+    // fit on the device at once.  Waves hold 64 rows (bSB) or 32 rows (dSB);
+    // so do the energy partials
+    const int nparts = bsb ? nrb : nchunk;
+    const int wg_capacity = nb * ncu, wpt = nparts / 4;
     const int teams_per_launch = 8 * (wg_capacity / (8 * wpt));
     if (teams_per_launch < 8)
         return perr(HSB_EUNSUPPORTED, "FP4 path: %d resident workgroups < 8 teams of %d",
@@ -1145,7 +1139,7 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     if (seg_samples < 1) seg_samples = 1;
     int rc = grow(&pw->xb, &pw->xb_words, (size_t)2 * nchunk * Rpad);
     if (!rc) rc = grow(&pw->snap, &pw->snap_words, (seg_samples + 1) * snap_per_sample);
-    if (!rc) rc = grow(&pw->ep, &pw->ep_elems, (seg_samples + 1) * (size_t)nrb * Rpad);
+    if (!rc) rc = grow(&pw->ep, &pw->ep_elems, (seg_samples + 1) * (size_t)nparts * Rpad);
     const long long max_seg_steps = (long long)seg_samples * interval;
     const int ptab_need = (int)((long long)(run.k1 - run.k0) < max_seg_steps
                                     ? (run.k1 - run.k0)
@@ -1209,9 +1203,9 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
                                    s, pw->xb, nxb);
             }
             // block b -> team (b/8)/wpt*8 + b%8: round the team count up to 8
-            const dim3 grid((unsigned)(8 * ((nt + 7) / 8) * (nrb / 4))), block(256);
+            const dim3 grid((unsigned)(8 * ((nt + 7) / 8) * wpt)), block(256);
             float dt = run.dt, a0dtv = a0dt;
-            int nkb_v = nkb, nrb_v = nrb, Rpad_v = Rpad, t0_v = t0, nt_v = nt;
+            int nkb_v = nkb, nrb_v = nrb, nchunk_v = nchunk, Rpad_v = Rpad, t0_v = t0, nt_v = nt;
             uint32_t epoch = ++pw->epoch;
             if (epoch == 0) epoch = ++pw->epoch;  // slots start zeroed: epoch 0 is never used
             int local_ok = run.local_exchange ? 1 : 0;
@@ -1221,7 +1215,7 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
                               (void *)&pw->ep,    (void *)&pw->ptab, (void *)&b.bad,
                               (void *)&b.status,  (void *)&pw->err,  (void *)&pw->xslot,
                               (void *)&epoch,     (void *)&local_ok, (void *)&nkb_v,
-                              (void *)&nrb_v,     (void *)&Rpad_v,   (void *)&t0_v,
+                              (void *)&nchunk_v,  (void *)&Rpad_v,   (void *)&t0_v,
                               (void *)&nt_v,      (void *)&g,        (void *)&dt,
                               (void *)&a0dtv};
             void *args_b[] = {(void *)&pw->teams, (void *)&run.X,     (void *)&run.Y,
@@ -1248,7 +1242,7 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
             if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
         }
         hipLaunchKernelGGL(k_fp4_best, dim3((unsigned)((run.R + 31) / 32)), dim3(256), 0, s,
-                           pw->ep, pw->snap, ns, nrb, Nrows, run.R, Rpad, g, b.best_e, b.last_e,
+                           pw->ep, pw->snap, ns, nparts, nchunk, Nrows, run.R, Rpad, g, b.best_e, b.last_e,
                            b.best_step, b.bad, b.best_s);
         e = hipGetLastError();
         if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
