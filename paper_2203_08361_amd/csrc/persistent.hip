@@ -170,6 +170,18 @@ __device__ __forceinline__ v4i expand_signs(uint32_t w) {
     return a;
 }
 
+// The same expansion at one operation per dword: v_and_or_b32 computes
+// (a & b) | c, but its encoding takes no literal, so the two constants come in
+// registers (the mask in a scalar one, the +1.0 pattern in a vector one).
+__device__ __forceinline__ v4i expand_signs_fast(uint32_t w, uint32_t mask, uint32_t ones) {
+    v4i a;
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a[0]) : "v"(w), "s"(mask), "v"(ones));
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a[1]) : "v"(w << 1), "s"(mask), "v"(ones));
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a[2]) : "v"(w << 2), "s"(mask), "v"(ones));
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a[3]) : "v"(w << 3), "s"(mask), "v"(ones));
+    return a;
+}
+
 // J fragment for (row block rb, row tile rt, K block kb, lane): lane l holds
 // row 64 rb + 32 rt + l%32 and the 32 spins of chunk 2 kb + l/32, in the order
 // of the packing convention.
@@ -388,13 +400,19 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         uint64_t wv[NQ];
         if (gather_words<NQ>(wv, src, (size_t)8 * Rpad, NQ, (uint32_t)m, err)) {
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) a_lds[buf][w + 4 * q][lane] = expand_signs((uint32_t)wv[q]);
+            for (int q = 0; q < NQ; ++q)
+                a_lds[buf][w + 4 * q][lane] = expand_signs_fast((uint32_t)wv[q], 0x88888888u, 0x22222222u);
         } else {
             wg_abort = 1;
         }
         __syncthreads();
         if (wg_abort) break;
         v16f acc;
+        // The products run at the lowest issue priority and the rest of the
+        // step at a raised one: while the other wave on this SIMD is in its
+        // products, this wave's update, publish and expansion -- the part of
+        // its chain that its team waits for -- issue first.
+        __builtin_amdgcn_s_setprio(0);
         // operand reads from LDS run kPre K blocks ahead of the products
         constexpr int kPre = 4;
         v4i af[kPre];
@@ -410,6 +428,7 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
                 mfma_fp4(acc, jr[kb], a, one);
         }
         mfma_drain(acc);
+        __builtin_amdgcn_s_setprio(3);
         if (seg_is_sample(g, m)) {
             // eq. (1) partial over this wave's 32 rows of s_i f_i (exact integers/halves)
             const int j = seg_sample_index(g, m);
