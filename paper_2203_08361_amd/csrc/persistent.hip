@@ -116,7 +116,10 @@ __device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((3 <<
 // (the compiler would otherwise copy them to VGPRs before every use).
 // Hazards: exactly overlapping srcC/vdst chains are interlocked by the
 // hardware; the first product of a step uses an inline zero for srcC; VALU
-// reads of the results wait behind mfma_drain().
+// reads of the results wait behind mfma_drain().  A VGPR source written by a
+// vector instruction needs two wait states before an MFMA reads it, and the
+// compiler does not insert them around inline assembly: the B operands here
+// come from LDS loads and the scale is loop-invariant, so none arise.
 __device__ __forceinline__ void mfma_fp4_first(v16f &acc, const v4i &j, const v4i &b, int one) {
     asm volatile(
         "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, 0, %3, %3 op_sel_hi:[0,0,0] cbsz:4 blgp:4"
@@ -129,6 +132,7 @@ __device__ __forceinline__ void mfma_fp4(v16f &acc, const v4i &j, const v4i &b, 
         : "+v"(acc)
         : "a"(j), "v"(b), "v"(one));
 }
+
 // 21 wait states: more than an XDL write needs before a VALU read of its vdst.
 __device__ __forceinline__ void mfma_drain(v16f &acc0, v16f &acc1) {
     asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 4" : "+v"(acc0), "+v"(acc1));
@@ -414,7 +418,7 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         // its chain that its team waits for -- issue first.
         __builtin_amdgcn_s_setprio(0);
         // operand reads from LDS run kPre K blocks ahead of the products
-        constexpr int kPre = 4;
+        constexpr int kPre = 2;
         v4i af[kPre];
 #pragma unroll
         for (int q = 0; q < kPre; ++q) af[q] = a_lds[buf][q][lane];
@@ -497,27 +501,31 @@ constexpr int kPB = 4;   // K blocks per staging phase (one per wave)
 
 // The same product with the B operand's block scale taken from byte BYTE of
 // sb (four digits' scales packed in one register; op_sel / op_sel_hi bit 1
-// give the byte index's low and high bit).
-#define HSB_MFMA_FP4S(SEL, SRC_C, CONSTR)                                                    \
-    asm volatile("v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, " SRC_C ", %3, %4 " SEL      \
+// give the byte index's low and high bit).  FRESH: sb was just computed by a
+// vector instruction (two wait states first, as for mfma_fp4).
+#define HSB_MFMA_FP4S(PRE, SEL, SRC_C, CONSTR)                                               \
+    asm volatile(PRE "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, " SRC_C ", %3, %4 " SEL  \
                  " cbsz:4 blgp:4"                                                            \
                  : CONSTR(acc)                                                               \
                  : "a"(j), "v"(b), "v"(sa), "v"(sb))
-template <int BYTE>
+#define HSB_MFMA_FP4S_BYTE(PRE, SRC_C, CONSTR)                                                \
+    if constexpr (BYTE == 0) HSB_MFMA_FP4S(PRE, "op_sel_hi:[0,0,0]", SRC_C, CONSTR);          \
+    else if constexpr (BYTE == 1)                                                            \
+        HSB_MFMA_FP4S(PRE, "op_sel:[0,1,0] op_sel_hi:[0,0,0]", SRC_C, CONSTR);                \
+    else if constexpr (BYTE == 2) HSB_MFMA_FP4S(PRE, "op_sel_hi:[0,1,0]", SRC_C, CONSTR);     \
+    else HSB_MFMA_FP4S(PRE, "op_sel:[0,1,0] op_sel_hi:[0,1,0]", SRC_C, CONSTR)
+template <int BYTE, bool FRESH>
 __device__ __forceinline__ void mfma_fp4s(v16f &acc, const v4i &j, const v4i &b, int sa, int sb) {
-    if constexpr (BYTE == 0) HSB_MFMA_FP4S("op_sel_hi:[0,0,0]", "%0", "+v");
-    else if constexpr (BYTE == 1) HSB_MFMA_FP4S("op_sel:[0,1,0] op_sel_hi:[0,0,0]", "%0", "+v");
-    else if constexpr (BYTE == 2) HSB_MFMA_FP4S("op_sel_hi:[0,1,0]", "%0", "+v");
-    else HSB_MFMA_FP4S("op_sel:[0,1,0] op_sel_hi:[0,1,0]", "%0", "+v");
+    if constexpr (FRESH) { HSB_MFMA_FP4S_BYTE("s_nop 1\n\t", "%0", "+v"); }
+    else { HSB_MFMA_FP4S_BYTE("", "%0", "+v"); }
 }
-template <int BYTE>
+template <int BYTE, bool FRESH>
 __device__ __forceinline__ void mfma_fp4s_first(v16f &acc, const v4i &j, const v4i &b, int sa,
                                                 int sb) {
-    if constexpr (BYTE == 0) HSB_MFMA_FP4S("op_sel_hi:[0,0,0]", "0", "=&v");
-    else if constexpr (BYTE == 1) HSB_MFMA_FP4S("op_sel:[0,1,0] op_sel_hi:[0,0,0]", "0", "=&v");
-    else if constexpr (BYTE == 2) HSB_MFMA_FP4S("op_sel_hi:[0,1,0]", "0", "=&v");
-    else HSB_MFMA_FP4S("op_sel:[0,1,0] op_sel_hi:[0,1,0]", "0", "=&v");
+    if constexpr (FRESH) { HSB_MFMA_FP4S_BYTE("s_nop 1\n\t", "0", "=&v"); }
+    else { HSB_MFMA_FP4S_BYTE("", "0", "=&v"); }
 }
+#undef HSB_MFMA_FP4S_BYTE
 #undef HSB_MFMA_FP4S
 
 __device__ __forceinline__ uint32_t ld_flag(const uint32_t *p) {
@@ -823,12 +831,17 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
                 const int sb = sbp[k >> 2];
                 auto pair = [&](auto byte) {
                     constexpr int B = decltype(byte)::value;
+                    // sb is new at k = 0 and k = 4 (computed by vector
+                    // instructions just before): wait states before its first use
                     if (kb == 0 && k == 0) {
-                        mfma_fp4s_first<B>(acc0, jr0[0], a, one, sb);
-                        mfma_fp4s_first<B>(acc1, jr1[0], a, one, sb);
+                        mfma_fp4s_first<B, true>(acc0, jr0[0], a, one, sb);
+                        mfma_fp4s_first<B, false>(acc1, jr1[0], a, one, sb);
+                    } else if ((k & 3) == 0) {
+                        mfma_fp4s<B, true>(acc0, jr0[kb], a, one, sb);
+                        mfma_fp4s<B, false>(acc1, jr1[kb], a, one, sb);
                     } else {
-                        mfma_fp4s<B>(acc0, jr0[kb], a, one, sb);
-                        mfma_fp4s<B>(acc1, jr1[kb], a, one, sb);
+                        mfma_fp4s<B, false>(acc0, jr0[kb], a, one, sb);
+                        mfma_fp4s<B, false>(acc1, jr1[kb], a, one, sb);
                     }
                 };
                 switch (k & 3) {

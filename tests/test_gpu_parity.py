@@ -367,6 +367,30 @@ def test_bsb_fp4_ragged_shapes(N, R, steps, interval):
         assert oracle.energy(J, s_) == e
 
 
+@pytest.mark.parametrize("steps", [1, 20])
+def test_bsb_fp4_chunk_scales_differ(steps):
+    """bSB on the FP4 plan from a start state whose 32-row chunks differ in
+    magnitude by factors of 2 up to 2^7, so that the digits' block scales change
+    from every K block to the next (in the usual start states they are nearly
+    all equal): a product that used another block's scale would miss the 1e-5
+    bar.  Also the bar on y."""
+    N, R = 512, 64
+    J = synth.sk_instance(N, 31)
+    c0 = 0.5 / np.sqrt(N)
+    x0, y0 = oracle.init_state(9, R, N, amp=0.9)
+    scale = (2.0 ** -((np.arange(N) // 32) % 8)).astype(np.float32)
+    x0 = (x0 * scale).astype(np.float32)
+    y0 = (y0 * scale * np.float32(0.1)).astype(np.float32)
+    say("bsb fp4 chunk scales", steps)
+    g = gpu_run(J, hsb.HSB_BSB, "mixed", steps, R, c0=c0, gamma=0.01, schedule_steps=2000,
+                x0=torch.from_numpy(x0), y0=torch.from_numpy(y0))
+    assert g["last_plan"] == "fp4"
+    o = oracle_run(J, oracle.BSB, oracle.FP64, steps, R, c0=c0, gamma=0.01, schedule_steps=2000,
+                   x0=x0, y0=y0)
+    assert rel_err(g["x"], o["x"]).max() <= 1e-5
+    assert rel_err(g["y"], o["y"]).max() <= 1e-5
+
+
 def test_dsb_real_j_digits_and_host_api():
     """dSB on Gaussian couplings with the digit plan (four-digit J): the early
     trajectory within the 1e-5 bar of FP64; the host-buffer entry point returns
