@@ -435,9 +435,12 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
     }
     HIP_TRY(hsb::launch_output(b, N, R, Rpad, h->return_best, a->spins, a->energy, a->x_out,
                                a->y_out, a->best_energy, a->final_energy, a->best_step, s));
+    // status: bit 0 a non-finite state, bit 1 an exchange wait of the
+    // persistent kernels that timed out
     int32_t status = 0;
     HIP_TRY(hipMemcpyAsync(&status, b.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (status & 2) return fail(HSB_EDEVICE, "FP4 persistent kernel: exchange wait timed out");
     h->last_plan = plan;
     if (status) return fail(HSB_ENUMERIC, "a replica's state became non-finite");
     return HSB_OK;
@@ -642,6 +645,8 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
             e = hipMemcpyAsync(&status, bb.status, sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return done(hip_fail(e, "batch output"));
+        if (status & 2)
+            return done(fail(HSB_EDEVICE, "FP4 persistent kernel: exchange wait timed out"));
         any_bad |= status;
         done(HSB_OK);
         lead->last_plan = PLAN_FP4;

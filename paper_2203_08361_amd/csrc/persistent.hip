@@ -53,6 +53,8 @@ struct PersistentWork {
     size_t snap_words = 0;
     float *ep = nullptr;         // [ns][nparts][Rpad] energy partials (per row block)
     size_t ep_elems = 0;
+    double *es = nullptr;        // [ns][Rpad] sample energies
+    size_t es_elems = 0;
     float *ptab = nullptr;       // p_k = a0 - a(t_k) of the steps of one segment
     size_t ptab_elems = 0;
     int32_t *err = nullptr;      // [1] timeout flag
@@ -408,6 +410,7 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
                 a_lds[buf][w + 4 * q][lane] = expand_signs_fast((uint32_t)wv[q], 0x88888888u, 0x22222222u);
         } else {
             wg_abort = 1;
+            __hip_atomic_fetch_or(status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
         if (wg_abort) break;
@@ -447,7 +450,7 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
             if (half == 0) ep[((size_t)j * nchunk + rb) * Rpad + rep] = part;
             if (!fin) {
                 bad[rep] = 1;
-                status[0] = 1;
+                __hip_atomic_fetch_or(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         if (m == g.seg_k1) break;
@@ -721,7 +724,7 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
         snap[(size_t)seg_sample_index(g, m) * nchunk * Rpad + slot] = word;
         if (!fin) {
             bad[rep] = 1;
-            status[0] = 1;
+            __hip_atomic_fetch_or(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     };
 
@@ -745,6 +748,8 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
                     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
                         wall_clock64() - t0 > kTimeoutTicks) {
                         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_fetch_or(status, 2, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
                         wg_abort = 1;
                         break;
                     }
@@ -927,16 +932,27 @@ __global__ __launch_bounds__(256) void k_energy_fp4(const FP4Team *__restrict__ 
     if (half == 0) ep[((size_t)j * nrb + rb) * Rpad + rep] = part;
 }
 
-// Energies of the segment's samples, best-sample update and its spins.
-// Grid Rpad/32, 256 threads: lane group g = threadIdx.x / 32 scans samples
-// j = g, g + 8, ... of 32 replicas; the groups' minima are merged with the
-// earliest sample winning ties, then the winning sample's sign words are
-// decoded into best_s.  A sample's energy is -1/2 times the sum of its nparts
+// Energy of sample j of replica r (eq. (1)): -1/2 times the sum of its nparts
 // partials (one per row block of the kernel that formed them).  Every partial
 // is a multiple of 1/2 below 2^23 in magnitude, so the FP64 totals are exact
-// in any order.
+// in any order.  Grid (Rpad/256, samples), one thread per (replica, sample).
+__global__ __launch_bounds__(256) void k_fp4_energies(const float *__restrict__ ep,
+                                                      double *__restrict__ es, int nparts,
+                                                      int Rpad) {
+    const int r = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    if (r >= Rpad) return;
+    const float *p = ep + (size_t)j * nparts * Rpad + r;
+    double e = 0.0;
+    for (int b = 0; b < nparts; ++b) e += (double)p[(size_t)b * Rpad];
+    es[(size_t)j * Rpad + r] = -0.5 * e;
+}
+
+// Best-sample update of the segment's samples and its spins.  Grid Rpad/32,
+// 256 threads: lane group g = threadIdx.x / 32 scans samples j = g, g + 8, ...
+// of 32 replicas; the groups' minima are merged with the earliest sample
+// winning ties, then the winning sample's sign words are decoded into best_s.
 __global__ __launch_bounds__(256) void k_fp4_best(
-    const float *__restrict__ ep, const uint32_t *__restrict__ snap, int ns, int nparts, int nchunk,
+    const double *__restrict__ es, const uint32_t *__restrict__ snap, int ns, int nchunk,
     int N, int R, int Rpad, SegArgs g, double *__restrict__ best_e, double *__restrict__ last_e,
     int32_t *__restrict__ best_step, const int32_t *__restrict__ bad, int8_t *__restrict__ best_s) {
     __shared__ double s_e[8][32];
@@ -947,9 +963,7 @@ __global__ __launch_bounds__(256) void k_fp4_best(
     int jmin = -1;
     if (r < R) {
         for (int j = grp; j < ns; j += 8) {
-            double e = 0.0;
-            for (int b = 0; b < nparts; ++b) e += (double)ep[((size_t)j * nparts + b) * Rpad + r];
-            e = -0.5 * e;
+            const double e = es[(size_t)j * Rpad + r];
             if (j == ns - 1) last_e[r] = bad[r] ? __builtin_nan("") : e;
             if (e < emin) {
                 emin = e;
@@ -1047,6 +1061,16 @@ hipError_t launch_energy_fp4(int nkb, dim3 grid, const FP4Team *teams, const uin
     return hipGetLastError();
 }
 
+// p_k = a0 - a(t_k) with a(t_k) = a0 k / Ns, for k = k0 .. k0 + n - 1: the
+// same single-precision operations, in the same order and rounding, as the
+// host's table of the other plans.
+__global__ void k_fill_ptab(float *ptab, int k0, int n, float a0, float Ns_f) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float ak = __fdiv_rn(__fmul_rn(a0, (float)(k0 + i)), Ns_f);
+    ptab[i] = __fsub_rn(a0, ak);
+}
+
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) p[e] = v;
@@ -1112,7 +1136,7 @@ int persistent_work_create(PersistentWork **out) {
 
 void persistent_work_free(PersistentWork *w) {
     if (!w) return;
-    void *ptrs[] = {w->xb, w->snap, w->ep, w->ptab, w->err, w->xslot, w->teams,
+    void *ptrs[] = {w->xb, w->snap, w->ep, w->es, w->ptab, w->err, w->xslot, w->teams,
                     w->xd, w->xe, w->flags};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1122,8 +1146,8 @@ void persistent_work_free(PersistentWork *w) {
 void persistent_free(PersistentJ *pj) {
     if (!pj) return;
     PersistentWork &w = pj->work;
-    void *ptrs[] = {pj->jpk, w.xb, w.snap, w.ep, w.ptab, w.err, w.xslot, w.teams, w.xd, w.xe,
-                    w.flags};
+    void *ptrs[] = {pj->jpk, w.xb, w.snap, w.ep, w.es, w.ptab, w.err, w.xslot, w.teams, w.xd,
+                    w.xe, w.flags};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete pj;
@@ -1172,6 +1196,7 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     int rc = grow(&pw->xb, &pw->xb_words, (size_t)2 * nchunk * Rpad);
     if (!rc) rc = grow(&pw->snap, &pw->snap_words, (seg_samples + 1) * snap_per_sample);
     if (!rc) rc = grow(&pw->ep, &pw->ep_elems, (seg_samples + 1) * (size_t)nparts * Rpad);
+    if (!rc) rc = grow(&pw->es, &pw->es_elems, (seg_samples + 1) * (size_t)Rpad);
     const long long max_seg_steps = (long long)seg_samples * interval;
     const int ptab_need = (int)((long long)(run.k1 - run.k0) < max_seg_steps
                                     ? (run.k1 - run.k0)
@@ -1200,7 +1225,6 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
     const float a0dt = run.a0 * run.dt;
     const void *kfn = bsb ? pick_bsb_kernel(nkb) : pick_kernel(nkb);
-    std::vector<float> ptab;
     int a = run.k0;
     for (;;) {
         // segment [a, e]: at most seg_samples multiples of interval in (a, e]
@@ -1213,16 +1237,12 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
         g.interval = interval;
         g.nmult = e_k / interval - a / interval;
         const int ns = g.nmult + ((e_k == run.k1 && (e_k % interval != 0 || e_k == a)) ? 1 : 0);
-        ptab.resize((size_t)(e_k - a > 0 ? e_k - a : 1));
-        for (int k = a; k < e_k; ++k) {
-            // a(t_k) = a0 k / Ns in single precision; p = a0 - a(t_k)
-            const float ak = (run.a0 * (float)k) / (float)run.Ns;
-            ptab[k - a] = run.a0 - ak;
+        if (e_k > a) {  // p_k of the segment's steps, on the device (no host round trip)
+            hipLaunchKernelGGL(k_fill_ptab, dim3((unsigned)((e_k - a + 255) / 256)), dim3(256), 0,
+                               s, pw->ptab, a, e_k - a, run.a0, (float)run.Ns);
+            e = hipGetLastError();
+            if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
         }
-        e = hipMemcpyAsync(pw->ptab, ptab.data(), sizeof(float) * (size_t)(e_k - a > 0 ? e_k - a : 0),
-                           hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
         for (int t0 = 0; t0 < nteams_total; t0 += teams_per_launch) {
             int nt = nteams_total - t0 < teams_per_launch ? nteams_total - t0 : teams_per_launch;
             if (bsb) {  // no wave of this launch has published yet
@@ -1273,19 +1293,19 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
                                   pw->teams, pw->snap, pw->ep, nrb, Rpad, 0, s);
             if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
         }
+        if (ns > 0)
+            hipLaunchKernelGGL(k_fp4_energies, dim3((unsigned)((Rpad + 255) / 256), (unsigned)ns),
+                               dim3(256), 0, s, pw->ep, pw->es, nparts, Rpad);
         hipLaunchKernelGGL(k_fp4_best, dim3((unsigned)((run.R + 31) / 32)), dim3(256), 0, s,
-                           pw->ep, pw->snap, ns, nparts, nchunk, Nrows, run.R, Rpad, g, b.best_e, b.last_e,
+                           pw->es, pw->snap, ns, nchunk, Nrows, run.R, Rpad, g, b.best_e, b.last_e,
                            b.best_step, b.bad, b.best_s);
         e = hipGetLastError();
         if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
         if (e_k >= run.k1) break;
         a = e_k;
     }
-    int32_t herr = 0;
-    e = hipMemcpyAsync(&herr, pw->err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
-    if (herr) return perr(HSB_EDEVICE, "FP4 persistent kernel: exchange wait timed out");
+    // an exchange wait that timed out sets bit 1 of the run's status word,
+    // which the caller reads with the rest of the status after its output
     return HSB_OK;
 }
 
