@@ -83,11 +83,23 @@ typedef enum {
                                     timing on (synchronises the events) */
     HSB_OPT_KERNEL_LAUNCHES = 6, /* read only: number of launches inside those brackets */
     HSB_OPT_LAST_PLAN = 7,       /* read only: plan of the last successful run, an hsb_plan */
-    HSB_OPT_LOCAL_EXCHANGE = 8   /* FP4 plan: 1 (default): a team of workgroups that share
+    HSB_OPT_LOCAL_EXCHANGE = 8,  /* FP4 plan: 1 (default): a team of workgroups that share
                                     one XCD exchanges its per-step data through that XCD's L2
                                     (workgroup-scope stores, no cache invalidation); 0: always
                                     device scope (slower; results are the same).  Batches use
                                     the option of their first context. */
+    HSB_OPT_GRAPH = 9,           /* 1 (default): hsb_run_ex / hsb_run of dSB on the FP4 plan
+                                    keep a HIP graph of the last repeated run.  The first call
+                                    with given arguments, options and buffers runs as usual;
+                                    the next identical call captures its queued work into a
+                                    graph (on a stream of the context, ordered after and
+                                    before the caller's stream by events) and launches it;
+                                    later identical calls launch the graph again.  Results
+                                    are those of the eager run.  Any other call on the
+                                    context, or one that reallocates a buffer the graph uses,
+                                    drops the graph.  Not used while timing is on or while
+                                    the caller's stream is being captured.  0: always eager */
+    HSB_OPT_GRAPH_LAUNCHES = 10  /* read only: runs of this context served by a graph launch */
 } hsb_option;
 
 typedef enum {

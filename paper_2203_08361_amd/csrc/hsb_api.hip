@@ -69,9 +69,24 @@ struct hsb_ctx {
     int timing = 0;
     int last_plan = -1;
     int local_exchange = 1;
+    int graph = 1;
     hsb::KernelTimer timer;
+    // graph of the last repeated run (HSB_OPT_GRAPH): the key of that run, whether
+    // it ran once eagerly, the instantiated graph, its stream and the events that
+    // order it after and before the caller's stream
+    std::vector<uint64_t> gkey;
+    bool gseen = false;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev_in = nullptr, gev_out = nullptr;
+    uint64_t glaunches = 0;
+    // the run's seed: pinned host slot written by every call, device copy read by
+    // the initialiser (a graph launch then takes the seed of its call)
+    uint64_t *h_seed = nullptr;
+    uint64_t *d_seed = nullptr;
     // workspace
     int Rpad_cap = 0;
+    uint64_t state_gen = 0;  // raised when the state buffers are reallocated
     hsb::StateBufs b{};
     int8_t *d_spins = nullptr;  // hsb_run staging
     double *d_energy = nullptr;
@@ -89,6 +104,7 @@ void free_state(hsb_ctx *h) {
 int ensure_state(hsb_ctx *h, int Rpad) {
     if (Rpad <= h->Rpad_cap) return HSB_OK;
     free_state(h);
+    ++h->state_gen;
     hipError_t e = hsb::alloc_state(h->b, h->Npad, Rpad);
     if (e != hipSuccess) return hip_fail(e, "allocating run state");
     h->Rpad_cap = Rpad;
@@ -96,6 +112,13 @@ int ensure_state(hsb_ctx *h, int Rpad) {
 }
 
 bool finite_f(float v) { return std::isfinite(v); }
+
+void graph_drop(hsb_ctx *h) {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    h->gseen = false;
+    h->gkey.clear();
+}
 
 }  // namespace
 
@@ -176,6 +199,12 @@ extern "C" void hsb_destroy(hsb_ctx *h) {
     if (h->i8) hsb::i8_free(h->i8);
     if (h->bwork) hsb::persistent_work_free(h->bwork);
     if (h->d_flag) (void)hipFree(h->d_flag);
+    graph_drop(h);
+    if (h->gev_in) (void)hipEventDestroy(h->gev_in);
+    if (h->gev_out) (void)hipEventDestroy(h->gev_out);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
+    if (h->h_seed) (void)hipHostFree(h->h_seed);
+    if (h->d_seed) (void)hipFree(h->d_seed);
     h->timer.release();
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -212,9 +241,15 @@ extern "C" int hsb_set_option(hsb_ctx *h, int key, double v) {
         if (!(v == 0.0 || v == 1.0)) return fail(HSB_EINVAL, "LOCAL_EXCHANGE must be 0 or 1");
         h->local_exchange = (int)v;
         return HSB_OK;
+    case HSB_OPT_GRAPH:
+        if (!(v == 0.0 || v == 1.0)) return fail(HSB_EINVAL, "GRAPH must be 0 or 1");
+        h->graph = (int)v;
+        if (!h->graph) graph_drop(h);
+        return HSB_OK;
     case HSB_OPT_KERNEL_MS:
     case HSB_OPT_KERNEL_LAUNCHES:
     case HSB_OPT_LAST_PLAN:
+    case HSB_OPT_GRAPH_LAUNCHES:
         return fail(HSB_EINVAL, "option %d is read only", key);
     default:
         return fail(HSB_EINVAL, "unknown option key %d", key);
@@ -239,6 +274,8 @@ extern "C" int hsb_get_option(hsb_ctx *h, int key, double *v) {
     case HSB_OPT_KERNEL_LAUNCHES: *v = (double)h->timer.launches; return HSB_OK;
     case HSB_OPT_LAST_PLAN: *v = h->last_plan; return HSB_OK;
     case HSB_OPT_LOCAL_EXCHANGE: *v = h->local_exchange; return HSB_OK;
+    case HSB_OPT_GRAPH: *v = h->graph; return HSB_OK;
+    case HSB_OPT_GRAPH_LAUNCHES: *v = (double)h->glaunches; return HSB_OK;
     default: return fail(HSB_EINVAL, "unknown option key %d", key);
     }
 }
@@ -294,45 +331,16 @@ extern "C" int hsb_plan_info(hsb_ctx *h, int variant, int *precision) {
     return rc;
 }
 
-extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
-    g_err[0] = 0;
-    if (!h || !a) return fail(HSB_EINVAL, "hsb_run_ex: NULL argument");
-    if (a->struct_size != sizeof(hsb_run_args))
-        return fail(HSB_EINVAL, "hsb_run_ex: struct_size %zu != %zu", a->struct_size,
-                    sizeof(hsb_run_args));
-    if (a->variant != HSB_BSB && a->variant != HSB_DSB)
-        return fail(HSB_EINVAL, "variant must be HSB_BSB (0) or HSB_DSB (1)");
-    if (a->steps < 0) return fail(HSB_EINVAL, "steps must be >= 0");
-    if (a->R < 1 || a->R > (1 << 22)) return fail(HSB_EINVAL, "R must be in [1, 4194304]");
-    if (a->start_step < 0) return fail(HSB_EINVAL, "start_step must be >= 0");
-    if ((long long)a->start_step + a->steps > 2147483647LL)
-        return fail(HSB_EINVAL, "start_step + steps overflows");
+namespace {
+
+// Queue the device work of one run on s: state set-up, the plan's steps and
+// the output.  Returns without waiting for it, except where the bSB digit
+// plans check the start state.
+int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
     const int Ns = a->schedule_steps > 0 ? a->schedule_steps : a->start_step + a->steps;
-    if (a->schedule_steps < 0 || Ns < a->start_step + a->steps)
-        return fail(HSB_EINVAL, "schedule_steps must be 0 or >= start_step + steps");
-    if (!(std::isfinite(a->a0) && std::isfinite(a->c0) && std::isfinite(a->dt) &&
-          std::isfinite(a->gamma)))
-        return fail(HSB_EINVAL, "a0, c0, dt and gamma must be finite");
-    if (!(a->dt > 0.0f)) return fail(HSB_EINVAL, "dt must be > 0");
-    if (!(a->gamma >= 0.0f)) return fail(HSB_EINVAL, "gamma must be >= 0");
-    if (!a->spins || !a->energy) return fail(HSB_EINVAL, "spins and energy are required");
-    if ((a->x0 == nullptr) != (a->y0 == nullptr))
-        return fail(HSB_EINVAL, "x0 and y0 must be given together");
-    int plan = 0;
-    int rc = choose_plan(h, a->variant, &plan);
-    if (rc != HSB_OK) return rc;
-    HIP_TRY(hipSetDevice(h->device));
-    hipStream_t s = (hipStream_t)a->stream;
     const int N = h->N, Npad = h->Npad, R = a->R;
     const int Rpad = round_up(R, hsb::kTile);
-    if (a->gamma_rep) {
-        std::vector<float> g(R);
-        HIP_TRY(hipMemcpyAsync(g.data(), a->gamma_rep, sizeof(float) * R, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        for (int r = 0; r < R; ++r)
-            if (!(std::isfinite(g[r]) && g[r] >= 0.0f))
-                return fail(HSB_EINVAL, "gamma_rep[%d] = %g must be finite and >= 0", r, g[r]);
-    }
+    int rc = HSB_OK;
     rc = ensure_state(h, Rpad);
     if (rc != HSB_OK) return rc;
     hsb::StateBufs &b = h->b;
@@ -342,8 +350,10 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
     // state set-up (eq. (16)-(22) start from x(t_0), y(t_0))
     if (a->x0)
         HIP_TRY(hsb::launch_load_state(b.X, b.Y, a->x0, a->y0, N, R, Npad, Rpad, s));
-    else
-        HIP_TRY(hsb::launch_init_seeded(b.X, b.Y, N, R, Npad, Rpad, Rpad, a->seed, amp, s));
+    else {
+        HIP_TRY(hipMemcpyAsync(h->d_seed, h->h_seed, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hsb::launch_init_seeded(b.X, b.Y, N, R, Npad, Rpad, Rpad, 0, amp, s, h->d_seed));
+    }
     HIP_TRY(hsb::launch_fill_gamma(b.gamma, a->gamma_rep, a->gamma, R, Rpad, s));
     HIP_TRY(hsb::launch_reset_tracking(b, Rpad, s));
 
@@ -437,8 +447,148 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
                                a->y_out, a->best_energy, a->final_energy, a->best_step, s));
     // status: bit 0 a non-finite state, bit 1 an exchange wait of the
     // persistent kernels that timed out
+    return HSB_OK;
+}
+
+// Everything the device work queued by enqueue_run depends on: the arguments,
+// the options, the plan, and the buffers it uses (by address and generation).
+std::vector<uint64_t> run_key(const hsb_ctx *h, const hsb_run_args *a, int plan) {
+    auto fb = [](float v) {
+        uint32_t u;
+        std::memcpy(&u, &v, sizeof u);
+        return (uint64_t)u;
+    };
+    auto pb = [](const void *q) { return (uint64_t)(uintptr_t)q; };
+    uint64_t amp;
+    std::memcpy(&amp, &h->init_amp, sizeof amp);
+    // (not the seed: the queued work reads it from the context's pinned slot)
+    return {(uint64_t)a->variant, (uint64_t)a->steps, (uint64_t)a->R, (uint64_t)a->start_step,
+            (uint64_t)a->schedule_steps, fb(a->a0), fb(a->c0), fb(a->dt), fb(a->gamma),
+            pb(a->gamma_rep), pb(a->x0), pb(a->y0), pb(a->x_out), pb(a->y_out), pb(a->spins),
+            pb(a->energy), pb(a->best_energy), pb(a->final_energy), pb(a->best_step), amp,
+            (uint64_t)h->interval, (uint64_t)h->return_best, (uint64_t)h->local_exchange,
+            (uint64_t)plan, pb(h->b.X), (uint64_t)h->Rpad_cap, h->state_gen, pb(h->pj),
+            h->pj ? hsb::persistent_gen(h->pj) : 0};
+}
+
+// Launch the cached graph on the context's stream, ordered after the work
+// already queued on s and before whatever s gets next.
+int graph_launch(hsb_ctx *h, hipStream_t s) {
+    HIP_TRY(hipEventRecord(h->gev_in, s));
+    HIP_TRY(hipStreamWaitEvent(h->gstream, h->gev_in, 0));
+    HIP_TRY(hipGraphLaunch(h->gexec, h->gstream));
+    HIP_TRY(hipEventRecord(h->gev_out, h->gstream));
+    HIP_TRY(hipStreamWaitEvent(s, h->gev_out, 0));
+    ++h->glaunches;
+    return HSB_OK;
+}
+
+// A run through the graph cache: the first call with a key runs eagerly
+// (allocating what the run needs); the next call with the same key captures
+// the same queued work on the context's stream into a graph and launches it;
+// later calls with that key launch the graph again.  Any other key, or a
+// buffer reallocated in between (a new generation), drops the graph.
+int run_graph(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
+    const std::vector<uint64_t> key = run_key(h, a, plan);
+    if (h->gexec && key == h->gkey) return graph_launch(h, s);
+    if (h->gseen && key == h->gkey) {
+        if (!h->gstream) {
+            HIP_TRY(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&h->gev_in, hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&h->gev_out, hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventRecord(h->gev_in, s));
+        HIP_TRY(hipStreamWaitEvent(h->gstream, h->gev_in, 0));
+        HIP_TRY(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_run(h, a, plan, h->gstream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->gstream, &g);
+        if (rc == HSB_OK && e != hipSuccess) rc = hip_fail(e, "capturing the run");
+        // the captured work must be that of the key: nothing reallocated
+        if (rc == HSB_OK && run_key(h, a, plan) != key)
+            rc = fail(HSB_EDEVICE, "run buffers changed while capturing");
+        if (rc == HSB_OK) {
+            const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+            if (ei != hipSuccess) {
+                h->gexec = nullptr;
+                rc = hip_fail(ei, "instantiating the run graph");
+            }
+        }
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != HSB_OK) {
+            graph_drop(h);
+            return rc;
+        }
+        return graph_launch(h, s);
+    }
+    graph_drop(h);
+    const int rc = enqueue_run(h, a, plan, s);
+    if (rc != HSB_OK) return rc;
+    h->gkey = run_key(h, a, plan);  // after the run: the buffers it grew are part of it
+    h->gseen = true;
+    return HSB_OK;
+}
+
+}  // namespace
+
+extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
+    g_err[0] = 0;
+    if (!h || !a) return fail(HSB_EINVAL, "hsb_run_ex: NULL argument");
+    if (a->struct_size != sizeof(hsb_run_args))
+        return fail(HSB_EINVAL, "hsb_run_ex: struct_size %zu != %zu", a->struct_size,
+                    sizeof(hsb_run_args));
+    if (a->variant != HSB_BSB && a->variant != HSB_DSB)
+        return fail(HSB_EINVAL, "variant must be HSB_BSB (0) or HSB_DSB (1)");
+    if (a->steps < 0) return fail(HSB_EINVAL, "steps must be >= 0");
+    if (a->R < 1 || a->R > (1 << 22)) return fail(HSB_EINVAL, "R must be in [1, 4194304]");
+    if (a->start_step < 0) return fail(HSB_EINVAL, "start_step must be >= 0");
+    if ((long long)a->start_step + a->steps > 2147483647LL)
+        return fail(HSB_EINVAL, "start_step + steps overflows");
+    const int Ns = a->schedule_steps > 0 ? a->schedule_steps : a->start_step + a->steps;
+    if (a->schedule_steps < 0 || Ns < a->start_step + a->steps)
+        return fail(HSB_EINVAL, "schedule_steps must be 0 or >= start_step + steps");
+    if (!(std::isfinite(a->a0) && std::isfinite(a->c0) && std::isfinite(a->dt) &&
+          std::isfinite(a->gamma)))
+        return fail(HSB_EINVAL, "a0, c0, dt and gamma must be finite");
+    if (!(a->dt > 0.0f)) return fail(HSB_EINVAL, "dt must be > 0");
+    if (!(a->gamma >= 0.0f)) return fail(HSB_EINVAL, "gamma must be >= 0");
+    if (!a->spins || !a->energy) return fail(HSB_EINVAL, "spins and energy are required");
+    if ((a->x0 == nullptr) != (a->y0 == nullptr))
+        return fail(HSB_EINVAL, "x0 and y0 must be given together");
+    int plan = 0;
+    int rc = choose_plan(h, a->variant, &plan);
+    if (rc != HSB_OK) return rc;
+    HIP_TRY(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)a->stream;
+    const int R = a->R;
+    if (!h->d_seed) {
+        HIP_TRY(hipMalloc((void **)&h->d_seed, sizeof(uint64_t)));
+        HIP_TRY(hipHostMalloc((void **)&h->h_seed, sizeof(uint64_t), hipHostMallocDefault));
+    }
+    // no queued work of an earlier call reads the slot any more: every call
+    // ends by synchronising its stream
+    *h->h_seed = a->seed;
+    if (a->gamma_rep) {
+        std::vector<float> g(R);
+        HIP_TRY(hipMemcpyAsync(g.data(), a->gamma_rep, sizeof(float) * R, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int r = 0; r < R; ++r)
+            if (!(std::isfinite(g[r]) && g[r] >= 0.0f))
+                return fail(HSB_EINVAL, "gamma_rep[%d] = %g must be finite and >= 0", r, g[r]);
+    }
+    // graphs for the persistent dSB runs (their queued work is free of host
+    // round trips once the run's buffers exist), unless the caller is
+    // capturing the stream itself
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cap));
+    const bool graphable = h->graph && plan == PLAN_FP4 && a->variant == HSB_DSB && !h->timing &&
+                           cap == hipStreamCaptureStatusNone;
+    rc = graphable ? run_graph(h, a, plan, s) : enqueue_run(h, a, plan, s);
+    if (rc != HSB_OK) return rc;
+    // status: bit 0 a non-finite state, bit 1 an exchange wait of the
+    // persistent kernels that timed out
     int32_t status = 0;
-    HIP_TRY(hipMemcpyAsync(&status, b.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&status, h->b.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (status & 2) return fail(HSB_EDEVICE, "FP4 persistent kernel: exchange wait timed out");
     h->last_plan = plan;

@@ -84,9 +84,11 @@ struct StateBufs {
     int32_t *status;      // [1] any replica non-finite
 };
 
-// rows [0, Npad) x columns [0, ncols) of a state with leading dimension ld
+// rows [0, Npad) x columns [0, ncols) of a state with leading dimension ld; the
+// seed is `seed`, or *seed_p (device memory, read when the kernel runs) if given
 hipError_t launch_init_seeded(float *X, float *Y, int N, int R, int Npad, int ncols, int ld,
-                              uint64_t seed, float amp, hipStream_t s);
+                              uint64_t seed, float amp, hipStream_t s,
+                              const uint64_t *seed_p = nullptr);
 hipError_t launch_load_state(float *X, float *Y, const float *x0, const float *y0, int N, int R,
                              int Npad, int Rpad, hipStream_t s);
 hipError_t launch_make_operand(float *B, const float *X, int variant, int Npad, int Rpad,

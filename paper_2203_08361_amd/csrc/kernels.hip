@@ -18,10 +18,12 @@ namespace hsb {
 // Columns [0, ncols) of a state with leading dimension ld: replica r < R of
 // spin i < N draws from (seed, r, i); everything else is zero.
 __global__ void k_init_seeded(float *__restrict__ X, float *__restrict__ Y, int N, int R, int ncols,
-                              int ld, uint64_t seed, float amp) {
+                              int ld, uint64_t seed_v, const uint64_t *__restrict__ seed_p,
+                              float amp) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     if (r >= ncols) return;
+    const uint64_t seed = seed_p ? seed_p[0] : seed_v;
     float x = 0.0f, y = 0.0f;
     if (i < N && r < R) {
         x = amp * uniform_open(rng_key(seed, 0, (uint64_t)r, (uint64_t)i));
@@ -373,9 +375,9 @@ hipError_t alloc_state(StateBufs &b, int Npad, int Rpad) {
 static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
 hipError_t launch_init_seeded(float *X, float *Y, int N, int R, int Npad, int ncols, int ld,
-                              uint64_t seed, float amp, hipStream_t s) {
+                              uint64_t seed, float amp, hipStream_t s, const uint64_t *seed_p) {
     hipLaunchKernelGGL(k_init_seeded, dim3(cdiv(ncols, 256), Npad), dim3(256), 0, s, X, Y, N, R,
-                       ncols, ld, seed, amp);
+                       ncols, ld, seed, seed_p, amp);
     return hipGetLastError();
 }
 

@@ -48,5 +48,8 @@ int persistent_work_create(PersistentWork **out);
 void persistent_work_free(PersistentWork *w);
 int persistent_nkb(const PersistentJ *pj);
 const void *persistent_jpk(const PersistentJ *pj);
+// Raised whenever a scratch buffer of the instance's own runs is reallocated or its
+// team table re-uploaded: device work queued before depends on the old state.
+uint64_t persistent_gen(const PersistentJ *pj);
 
 }  // namespace hsb

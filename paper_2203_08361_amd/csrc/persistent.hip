@@ -60,7 +60,10 @@ struct PersistentWork {
     int32_t *err = nullptr;      // [1] timeout flag
     uint64_t *xslot = nullptr;   // [grid] (launch epoch, XCD id) per workgroup
     size_t xslot_n = 0;
-    uint32_t epoch = 0;          // launches so far
+    uint32_t *epoch = nullptr;   // [1] launch epoch, advanced on the device before each launch
+    size_t epoch_n = 0;
+    std::vector<FP4Team> teams_up;  // the team table last uploaded to `teams`
+    uint64_t gen = 0;            // raised when a buffer is reallocated or the table re-uploaded
     FP4Team *teams = nullptr;    // [nteams] per-team J, N and c0
     size_t teams_n = 0;
     // bSB exchange: digit fragments [2][nkb][8][2 Rpad], chunk exponents
@@ -303,7 +306,8 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, uint64_t *xb, uint32_t *__restrict__ snap,
     float *__restrict__ ep, const float *__restrict__ ptab, int32_t *__restrict__ bad,
-    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, uint32_t epoch, int local_ok,
+    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, const uint32_t *epoch_p,
+    int local_ok,
     int nkb, int nchunk, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
     static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
     constexpr int NQ = NKB / 4;  // K blocks expanded by each wave
@@ -335,6 +339,9 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     // publish with XCD-scoped stores (readers always load at device scope, and
     // the step tags reject any stale word whatever the placement).
     const int my_xcc = xcc_id();
+    // this launch's epoch (advanced on the stream before the launch, so that a
+    // replayed launch differs from the previous one too)
+    const uint32_t epoch = __hip_atomic_load(epoch_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (threadIdx.x == 0) st_tagged(xslot + blockIdx.x, ((uint64_t)epoch << 32) | (uint32_t)my_xcc);
     bool xcd_local;
     {
@@ -612,7 +619,8 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, v4i *xd, uint8_t *xe, uint32_t *flags,
     uint32_t *__restrict__ snap, const float *__restrict__ ptab, int32_t *__restrict__ bad,
-    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, uint32_t epoch, int local_ok,
+    int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, const uint32_t *epoch_p,
+    int local_ok,
     int nkb, int nrb, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
     static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
     constexpr int NPH = NKB / kPB;  // staging phases per step
@@ -641,6 +649,9 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     if (threadIdx.x == 0) wg_abort = 0;
 
     const int my_xcc = xcc_id();
+    // this launch's epoch (advanced on the stream before the launch, so that a
+    // replayed launch differs from the previous one too)
+    const uint32_t epoch = __hip_atomic_load(epoch_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (threadIdx.x == 0) st_tagged(xslot + blockIdx.x, ((uint64_t)epoch << 32) | (uint32_t)my_xcc);
     bool xcd_local;
     {
@@ -1071,6 +1082,13 @@ __global__ void k_fill_ptab(float *ptab, int k0, int n, float a0, float Ns_f) {
     ptab[i] = __fsub_rn(a0, ak);
 }
 
+// Next launch epoch: never 0xFFFFFFFF, the value the slots are filled with.
+__global__ void k_next_epoch(uint32_t *epoch) {
+    uint32_t e = epoch[0] + 1u;
+    if (e == 0xFFFFFFFFu) e = 1u;
+    epoch[0] = e;
+}
+
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) p[e] = v;
@@ -1127,6 +1145,7 @@ int persistent_create(const float *J, int N, PersistentJ **out) {
 }
 
 int persistent_nkb(const PersistentJ *pj) { return pj->nkb; }
+uint64_t persistent_gen(const PersistentJ *pj) { return pj->work.gen; }
 const void *persistent_jpk(const PersistentJ *pj) { return pj->jpk; }
 
 int persistent_work_create(PersistentWork **out) {
@@ -1136,7 +1155,7 @@ int persistent_work_create(PersistentWork **out) {
 
 void persistent_work_free(PersistentWork *w) {
     if (!w) return;
-    void *ptrs[] = {w->xb, w->snap, w->ep, w->es, w->ptab, w->err, w->xslot, w->teams,
+    void *ptrs[] = {w->xb, w->snap, w->ep, w->es, w->ptab, w->err, w->xslot, w->epoch, w->teams,
                     w->xd, w->xe, w->flags};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1146,8 +1165,8 @@ void persistent_work_free(PersistentWork *w) {
 void persistent_free(PersistentJ *pj) {
     if (!pj) return;
     PersistentWork &w = pj->work;
-    void *ptrs[] = {pj->jpk, w.xb, w.snap, w.ep, w.es, w.ptab, w.err, w.xslot, w.teams, w.xd,
-                    w.xe, w.flags};
+    void *ptrs[] = {pj->jpk, w.xb, w.snap, w.ep, w.es, w.ptab, w.err, w.xslot, w.epoch, w.teams,
+                    w.xd, w.xe, w.flags};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete pj;
@@ -1193,6 +1212,8 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     size_t seg_samples = ((size_t)512 << 20) / (snap_per_sample * 4);
     if (seg_samples > 4096) seg_samples = 4096;
     if (seg_samples < 1) seg_samples = 1;
+    const void *const before[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->ptab, pw->err, pw->teams,
+                                  pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
     int rc = grow(&pw->xb, &pw->xb_words, (size_t)2 * nchunk * Rpad);
     if (!rc) rc = grow(&pw->snap, &pw->snap_words, (seg_samples + 1) * snap_per_sample);
     if (!rc) rc = grow(&pw->ep, &pw->ep_elems, (seg_samples + 1) * (size_t)nparts * Rpad);
@@ -1204,10 +1225,21 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     if (!rc) rc = grow(&pw->ptab, &pw->ptab_elems, (size_t)(ptab_need > 0 ? ptab_need : 1));
     size_t one = 0;
     if (!rc && !pw->err) rc = grow(&pw->err, &one, 1);
-    if (!rc) rc = grow(&pw->teams, &pw->teams_n, (size_t)nteams_total);
+    if (!rc) {
+        const FP4Team *before = pw->teams;
+        rc = grow(&pw->teams, &pw->teams_n, (size_t)nteams_total);
+        if (pw->teams != before) pw->teams_up.clear();  // a new buffer holds no table yet
+    }
     if (!rc && bsb) rc = grow(&pw->xd, &pw->xd_n, (size_t)2 * nkb * 8 * 2 * Rpad);
     if (!rc && bsb) rc = grow(&pw->xe, &pw->xe_n, (size_t)2 * 2 * Rpad * nkb);
     if (!rc && bsb) rc = grow(&pw->flags, &pw->flags_n, (size_t)nteams_total * nrb);
+    if (!rc && !pw->epoch) {
+        rc = grow(&pw->epoch, &pw->epoch_n, 1);
+        if (!rc) {
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, pw->epoch, (size_t)1, 0u);
+            if (hipGetLastError() != hipSuccess) rc = perr(HSB_EDEVICE, "epoch fill failed");
+        }
+    }
     if (!rc && pw->xslot_n < (size_t)wg_capacity + 8 * (size_t)wpt) {
         rc = grow(&pw->xslot, &pw->xslot_n, (size_t)wg_capacity + 8 * (size_t)wpt);
         if (!rc) {  // epoch 0xFFFFFFFF in every slot: never a launch's epoch
@@ -1217,9 +1249,22 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
         }
     }
     if (rc) return rc;
-    e = hipMemcpyAsync(pw->teams, host_teams, sizeof(FP4Team) * (size_t)nteams_total,
-                       hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
+    {
+        const void *const after[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->ptab, pw->err, pw->teams,
+                                     pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
+        if (std::memcmp(before, after, sizeof(before)) != 0) ++pw->gen;
+    }
+    // the team table, uploaded only when it differs from the last upload (a
+    // repeated run then queues no host-to-device copy)
+    if (pw->teams_up.size() != (size_t)nteams_total ||
+        std::memcmp(pw->teams_up.data(), host_teams, sizeof(FP4Team) * (size_t)nteams_total) != 0) {
+        e = hipMemcpyAsync(pw->teams, host_teams, sizeof(FP4Team) * (size_t)nteams_total,
+                           hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // host_teams may go away after return
+        if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
+        pw->teams_up.assign(host_teams, host_teams + nteams_total);
+        ++pw->gen;
+    }
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, pw->err);
     e = hipGetLastError();
     if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
@@ -1258,15 +1303,14 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
             const dim3 grid((unsigned)(8 * ((nt + 7) / 8) * wpt)), block(256);
             float dt = run.dt, a0dtv = a0dt;
             int nkb_v = nkb, nrb_v = nrb, nchunk_v = nchunk, Rpad_v = Rpad, t0_v = t0, nt_v = nt;
-            uint32_t epoch = ++pw->epoch;
-            if (epoch == 0) epoch = ++pw->epoch;  // slots start zeroed: epoch 0 is never used
+            hipLaunchKernelGGL(k_next_epoch, dim3(1), dim3(1), 0, s, pw->epoch);
             int local_ok = run.local_exchange ? 1 : 0;
             const float *gam = run.gamma;
             void *args_d[] = {(void *)&pw->teams, (void *)&run.X,    (void *)&run.Y,
                               (void *)&gam,       (void *)&pw->xb,   (void *)&pw->snap,
                               (void *)&pw->ep,    (void *)&pw->ptab, (void *)&b.bad,
                               (void *)&b.status,  (void *)&pw->err,  (void *)&pw->xslot,
-                              (void *)&epoch,     (void *)&local_ok, (void *)&nkb_v,
+                              (void *)&pw->epoch, (void *)&local_ok, (void *)&nkb_v,
                               (void *)&nchunk_v,  (void *)&Rpad_v,   (void *)&t0_v,
                               (void *)&nt_v,      (void *)&g,        (void *)&dt,
                               (void *)&a0dtv};
@@ -1274,7 +1318,7 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
                               (void *)&gam,       (void *)&pw->xd,    (void *)&pw->xe,
                               (void *)&pw->flags, (void *)&pw->snap,  (void *)&pw->ptab,
                               (void *)&b.bad,     (void *)&b.status,  (void *)&pw->err,
-                              (void *)&pw->xslot, (void *)&epoch,     (void *)&local_ok,
+                              (void *)&pw->xslot, (void *)&pw->epoch, (void *)&local_ok,
                               (void *)&nkb_v,     (void *)&nrb_v,     (void *)&Rpad_v,
                               (void *)&t0_v,      (void *)&nt_v,      (void *)&g,
                               (void *)&dt,        (void *)&a0dtv};

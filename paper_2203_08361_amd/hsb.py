@@ -19,6 +19,8 @@ HSB_OK, HSB_EINVAL, HSB_ENOMEM, HSB_EDEVICE, HSB_ENUMERIC, HSB_EUNSUPPORTED = 0,
 HSB_OPT_INIT_AMP, HSB_OPT_ENERGY_INTERVAL, HSB_OPT_RETURN_BEST, HSB_OPT_PRECISION = 0, 1, 2, 3
 HSB_OPT_TIMING, HSB_OPT_KERNEL_MS, HSB_OPT_KERNEL_LAUNCHES, HSB_OPT_LAST_PLAN = 4, 5, 6, 7
 HSB_OPT_LOCAL_EXCHANGE = 8
+HSB_OPT_GRAPH = 9
+HSB_OPT_GRAPH_LAUNCHES = 10
 HSB_PLAN_FP32, HSB_PLAN_FP4, HSB_PLAN_DIGITS = 0, 1, 2
 PLAN_NAMES = {HSB_PLAN_FP32: "fp32", HSB_PLAN_FP4: "fp4", HSB_PLAN_DIGITS: "digits"}
 HSB_PREC_AUTO, HSB_PREC_FP32, HSB_PREC_MIXED, HSB_PREC_DIGITS = 0, 1, 2, 3
@@ -268,7 +270,8 @@ class Context:
              "return_best": HSB_OPT_RETURN_BEST, "precision": HSB_OPT_PRECISION,
              "timing": HSB_OPT_TIMING, "kernel_ms": HSB_OPT_KERNEL_MS,
              "kernel_launches": HSB_OPT_KERNEL_LAUNCHES, "last_plan": HSB_OPT_LAST_PLAN,
-             "local_exchange": HSB_OPT_LOCAL_EXCHANGE}
+             "local_exchange": HSB_OPT_LOCAL_EXCHANGE, "graph": HSB_OPT_GRAPH,
+             "graph_launches": HSB_OPT_GRAPH_LAUNCHES}
     _PREC = {"auto": HSB_PREC_AUTO, "fp32": HSB_PREC_FP32, "mixed": HSB_PREC_MIXED,
              "digits": HSB_PREC_DIGITS}
 
