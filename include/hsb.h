@@ -88,8 +88,9 @@ typedef enum {
                                     (workgroup-scope stores, no cache invalidation); 0: always
                                     device scope (slower; results are the same).  Batches use
                                     the option of their first context. */
-    HSB_OPT_GRAPH = 9,           /* 1 (default): hsb_run_ex / hsb_run of dSB on the FP4 plan
-                                    keep a HIP graph of the last repeated run.  The first call
+    HSB_OPT_GRAPH = 9,           /* 1 (default): hsb_run_ex / hsb_run on the FP4 plan (dSB;
+                                    bSB from a seeded start state with INIT_AMP <= 1) keep a
+                                    HIP graph of the last repeated run.  The first call
                                     with given arguments, options and buffers runs as usual;
                                     the next identical call captures its queued work into a
                                     graph (on a stream of the context, ordered after and

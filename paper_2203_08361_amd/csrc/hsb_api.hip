@@ -375,9 +375,10 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
         return HSB_OK;
     };
 
-    if (a->variant == HSB_BSB && plan != PLAN_FP32) {
+    if (a->variant == HSB_BSB && plan != PLAN_FP32 && (a->x0 || h->init_amp > 1.0)) {
         // the digit representations of x need |x| <= 1 in the start state (the
-        // walls of eqs. (18)-(21) keep it so afterwards)
+        // walls of eqs. (18)-(21) keep it so afterwards).  A seeded state with
+        // amplitude <= 1 has it by construction: amp v with v in (-1, 1).
         if (!h->d_flag) HIP_TRY(hipMalloc((void **)&h->d_flag, sizeof(int32_t)));
         int32_t over = 0;
         HIP_TRY(hsb::launch_bound_check(b.X, (size_t)Npad * Rpad, h->d_flag, s));
@@ -516,8 +517,10 @@ int run_graph(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
         }
         if (g) (void)hipGraphDestroy(g);
         if (rc != HSB_OK) {
+            // nothing of a failed capture ran: queue the run eagerly instead
             graph_drop(h);
-            return rc;
+            (void)hipGetLastError();
+            return enqueue_run(h, a, plan, s);
         }
         return graph_launch(h, s);
     }
@@ -576,13 +579,14 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
             if (!(std::isfinite(g[r]) && g[r] >= 0.0f))
                 return fail(HSB_EINVAL, "gamma_rep[%d] = %g must be finite and >= 0", r, g[r]);
     }
-    // graphs for the persistent dSB runs (their queued work is free of host
-    // round trips once the run's buffers exist), unless the caller is
-    // capturing the stream itself
+    // graphs for the persistent FP4 runs (their queued work is free of host
+    // round trips once the run's buffers exist; for bSB, when no start-state
+    // check is needed), unless the caller is capturing the stream itself
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(s, &cap));
-    const bool graphable = h->graph && plan == PLAN_FP4 && a->variant == HSB_DSB && !h->timing &&
-                           cap == hipStreamCaptureStatusNone;
+    const bool graphable = h->graph && plan == PLAN_FP4 && !h->timing &&
+                           cap == hipStreamCaptureStatusNone &&
+                           (a->variant == HSB_DSB || (!a->x0 && h->init_amp <= 1.0));
     rc = graphable ? run_graph(h, a, plan, s) : enqueue_run(h, a, plan, s);
     if (rc != HSB_OK) return rc;
     // status: bit 0 a non-finite state, bit 1 an exchange wait of the

@@ -123,3 +123,27 @@ def test_graph_other_seed_and_dropped_by_other_runs():
         assert np.array_equal(fin["x"], ref5["x"])  # same trajectory, other readout
         ctx.set_option("graph", 0)
         assert ctx.get_option("graph") == 0
+
+
+def test_bsb_graph_launches_equal_eager_run():
+    """bSB on the FP4 plan from a seeded state (INIT_AMP <= 1: no start-state
+    check, so the run is graph-launched too)."""
+    N, R = 300, 64
+    J = synth.sk_instance(N, 15)
+    c0 = 0.5 / np.sqrt(N)
+    say("bsb graph launches", N, R)
+
+    def bsb(ctx, o, seed):
+        ctx.run_ex(hsb.HSB_BSB, 120, R, 1.0, c0, 1.0, 0.01, seed=seed, want_state=True, out=o)
+        torch.cuda.synchronize()
+        return {k: o[k].cpu().numpy().copy() for k in KEYS}
+
+    with hsb.Context(J, precision="mixed", energy_interval=40, graph=0) as ctx:
+        ref = bsb(ctx, outputs(R, N), 3)
+        assert ctx.last_plan() == "fp4"
+    with hsb.Context(J, precision="mixed", energy_interval=40) as ctx:
+        o = outputs(R, N)
+        for i in range(4):
+            scramble(o)
+            assert_same(bsb(ctx, o, 3), ref, f"bsb call {i}")
+        assert ctx.get_option("graph_launches") == 3
