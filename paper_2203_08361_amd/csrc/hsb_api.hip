@@ -59,6 +59,10 @@ struct hsb_ctx {
     hsb::PersistentJ *pj = nullptr;  // FP4 J store for the persistent dSB path (lazy)
     hsb::I8J *i8 = nullptr;          // integer-digit J store (lazy)
     hsb::PersistentWork *bwork = nullptr;  // scratch of batched FP4 runs led by this context
+    hsb::StateBufs bstate{};               // state of batch classes led by this context
+    size_t bstate_ns = 0, bstate_nr = 0;   // its capacity: elements, columns
+    hsb::BatchJob *bjobs = nullptr;        // device job table of a batch class
+    size_t bjobs_cap = 0;
     int32_t *d_flag = nullptr;             // start-state bound check
     std::vector<float> hJ;      // host copy kept for lazy device re-layouts
     // options
@@ -198,6 +202,8 @@ extern "C" void hsb_destroy(hsb_ctx *h) {
     if (h->pj) hsb::persistent_free(h->pj);
     if (h->i8) hsb::i8_free(h->i8);
     if (h->bwork) hsb::persistent_work_free(h->bwork);
+    hsb::free_state_bufs(h->bstate);
+    if (h->bjobs) (void)hipFree(h->bjobs);
     if (h->d_flag) (void)hipFree(h->d_flag);
     graph_drop(h);
     if (h->gev_in) (void)hipEventDestroy(h->gev_in);
@@ -730,6 +736,29 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
     // FP4 jobs: one persistent launch sequence per padded size; the lead
     // context's timer (TIMING on) records those launches
     lead->timer.reset(lead->timing != 0);
+    // The classes' state: kept by the lead context and grown only when a class
+    // needs more elements or columns than it holds (the FP4 plan uses neither
+    // the FP32 operand nor its energy buffers).  Class c uses Nst Rtot elements
+    // with leading dimension Rtot.
+    {
+        size_t need_ns = 0, need_nr = 0;
+        for (auto &cls : classes) {
+            size_t cols = 0;
+            for (int j : cls.second) cols += (size_t)round_up(jobs[j].R, 32);
+            const size_t rtot = (size_t)round_up((int)cols, hsb::kTile);
+            need_ns = std::max(need_ns, (size_t)cls.first * 64 * rtot);
+            need_nr = std::max(need_nr, rtot);
+        }
+        if (need_ns > lead->bstate_ns || need_nr > lead->bstate_nr) {
+            hsb::free_state_bufs(lead->bstate);
+            lead->bstate_ns = lead->bstate_nr = 0;
+            const int rows = (int)((need_ns + need_nr - 1) / need_nr);
+            hipError_t ea = hsb::alloc_state(lead->bstate, rows, (int)need_nr, false);
+            if (ea != hipSuccess) return hip_fail(ea, "allocating batch state");
+            lead->bstate_ns = (size_t)rows * need_nr;
+            lead->bstate_nr = need_nr;
+        }
+    }
     for (auto &cls : classes) {
         const int nkb = cls.first, Nst = nkb * 64;
         const std::vector<int> &cj = cls.second;
@@ -756,25 +785,33 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
             const int rc = hsb::persistent_work_create(&lead->bwork);
             if (rc != HSB_OK) return fail(rc, "%s", hsb::persistent_error());
         }
-        hsb::StateBufs bb{};
-        hipError_t e = hsb::alloc_state(bb, Nst, Rtot);
-        if (e != hipSuccess) return hip_fail(e, "allocating batch state");
+        hsb::StateBufs &bb = lead->bstate;  // sized for every class above
+        // the class's job table (device copy read by the set-up and output kernels)
+        std::vector<hsb::BatchJob> bj(cj.size());
+        int Nmax = 0;
+        for (size_t q = 0; q < cj.size(); ++q) {
+            const hsb_job &jb = jobs[cj[q]];
+            bj[q] = hsb::BatchJob{col0[q], jb.R, hs[jb.instance]->N, jb.gamma, jb.seed, jb.spins,
+                                  jb.energy};
+            if (bj[q].N > Nmax) Nmax = bj[q].N;
+        }
+        if (bj.size() > lead->bjobs_cap) {
+            if (lead->bjobs) (void)hipFree(lead->bjobs);
+            lead->bjobs = nullptr;
+            lead->bjobs_cap = 0;
+            HIP_TRY(hipMalloc((void **)&lead->bjobs, sizeof(hsb::BatchJob) * bj.size()));
+            lead->bjobs_cap = bj.size();
+        }
         auto done = [&](int rc) {
-            (void)hipStreamSynchronize(s);
-            hsb::free_state_bufs(bb);
+            (void)hipStreamSynchronize(s);  // also keeps bj alive until its copy is done
             return rc;
         };
-        // initial state, gamma per column, tracking (zero columns between jobs)
-        e = hsb::launch_init_seeded(bb.X, bb.Y, 0, 0, Nst, Rtot, Rtot, 0, (float)amp, s);
-        if (e == hipSuccess) e = hsb::launch_fill_gamma(bb.gamma, nullptr, 0.0f, 0, Rtot, s);
-        for (size_t q = 0; q < cj.size() && e == hipSuccess; ++q) {
-            const hsb_job &jb = jobs[cj[q]];
-            const int nc = round_up(jb.R, 32);
-            e = hsb::launch_init_seeded(bb.X + col0[q], bb.Y + col0[q], hs[jb.instance]->N, jb.R,
-                                        Nst, nc, Rtot, jb.seed, (float)amp, s);
-            if (e == hipSuccess)
-                e = hsb::launch_fill_gamma(bb.gamma + col0[q], nullptr, jb.gamma, jb.R, nc, s);
-        }
+        hipError_t e = hipMemcpyAsync(lead->bjobs, bj.data(), sizeof(hsb::BatchJob) * bj.size(),
+                                      hipMemcpyHostToDevice, s);
+        // initial state and gamma per column (zero columns between jobs), tracking
+        if (e == hipSuccess)
+            e = hsb::launch_init_batch(bb.X, bb.Y, bb.gamma, lead->bjobs, (int)bj.size(), Nst, Rtot,
+                                       (float)amp, s);
         if (e == hipSuccess) e = hsb::launch_reset_tracking(bb, Rtot, s);
         if (e != hipSuccess) return done(hip_fail(e, "batch set-up"));
         hsb::PersistentRun pr{};
@@ -786,14 +823,7 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
         int rc = hsb::persistent_run_teams(lead->bwork, a->variant, nkb, teams.data(),
                                            (int)teams.size(), pr, bb, Nst, s, lead->timer);
         if (rc != HSB_OK) return done(fail(rc, "%s", hsb::persistent_error()));
-        for (size_t q = 0; q < cj.size() && e == hipSuccess; ++q) {
-            const hsb_job &jb = jobs[cj[q]];
-            hsb::StateBufs v = bb;  // column view of the job
-            v.X += col0[q]; v.Y += col0[q]; v.best_s += col0[q]; v.best_e += col0[q];
-            v.last_e += col0[q]; v.best_step += col0[q]; v.bad += col0[q];
-            e = hsb::launch_output(v, hs[jb.instance]->N, jb.R, Rtot, a->return_best, jb.spins,
-                                   jb.energy, nullptr, nullptr, nullptr, nullptr, nullptr, s);
-        }
+        e = hsb::launch_output_batch(bb, lead->bjobs, (int)bj.size(), Nmax, Rtot, a->return_best, s);
         int32_t status = 0;
         if (e == hipSuccess)
             e = hipMemcpyAsync(&status, bb.status, sizeof(int32_t), hipMemcpyDeviceToHost, s);

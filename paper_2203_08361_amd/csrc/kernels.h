@@ -96,8 +96,28 @@ hipError_t launch_make_operand(float *B, const float *X, int variant, int Npad, 
 // g[r] = gamma_rep[r] (or gamma) for r < R, 0 for R <= r < Rpad
 hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int R, int Rpad,
                              hipStream_t s);
-// allocation of the run state for Npad rows and Rpad columns (all or nothing)
-hipError_t alloc_state(StateBufs &b, int Npad, int Rpad);
+// allocation of the run state for Npad rows and Rpad columns (all or nothing);
+// without the FP32 plan's operand and energy buffers (B, epart) if !fp32_plan
+hipError_t alloc_state(StateBufs &b, int Npad, int Rpad, bool fp32_plan = true);
+
+// One job of a batch class: its columns [col0, col0 + R) of the class state
+// (then up to the next job's col0: zero padding), its instance size N, seed,
+// gamma and output buffers.
+struct BatchJob {
+    int col0, R, N;
+    float gamma;
+    uint64_t seed;
+    int8_t *spins;   // [R][N]
+    double *energy;  // [R]
+};
+// Seeded initial state and gamma of every job of a class in one launch:
+// column r belongs to the job with the largest col0 <= r (jobs sorted by
+// col0); columns past a job's R and rows past its N are zero.
+hipError_t launch_init_batch(float *X, float *Y, float *gamma, const BatchJob *jobs, int njobs,
+                             int Npad, int Rtot, float amp, hipStream_t s);
+// Spins and energies of every job of a class (as launch_output per job)
+hipError_t launch_output_batch(const StateBufs &b, const BatchJob *jobs, int njobs, int Nmax,
+                               int Rtot, int return_best, hipStream_t s);
 void free_state_bufs(StateBufs &b);
 hipError_t launch_reset_tracking(const StateBufs &b, int Rpad, hipStream_t s);
 // *flag (device) = 1 if any of X[0 .. n) has |x| > 1 or is not finite, else 0

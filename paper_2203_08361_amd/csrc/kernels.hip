@@ -339,6 +339,63 @@ __global__ void k_bound_flag(const float *__restrict__ X, size_t n, int32_t *fla
 
 __global__ void k_clear_i32(int32_t *p) { p[0] = 0; }
 
+// job of column r: the last job with col0 <= r (jobs sorted by col0)
+__device__ __forceinline__ int batch_job_of(const BatchJob *jobs, int njobs, int r) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].col0 <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_init_batch(float *__restrict__ X, float *__restrict__ Y, float *__restrict__ gamma,
+                             const BatchJob *__restrict__ jobs, int njobs, int Rtot, float amp) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (r >= Rtot) return;
+    const BatchJob jb = jobs[batch_job_of(jobs, njobs, r)];
+    const int rep = r - jb.col0;
+    const bool col_ok = rep >= 0 && rep < jb.R;
+    float x = 0.0f, y = 0.0f;
+    if (col_ok && i < jb.N) {
+        x = amp * uniform_open(rng_key(jb.seed, 0, (uint64_t)rep, (uint64_t)i));
+        y = amp * uniform_open(rng_key(jb.seed, 1, (uint64_t)rep, (uint64_t)i));
+    }
+    X[(size_t)i * Rtot + r] = x;
+    Y[(size_t)i * Rtot + r] = y;
+    if (i == 0) gamma[r] = col_ok ? jb.gamma : 0.0f;
+}
+
+__global__ void k_output_batch_spins(const float *__restrict__ X, const int8_t *__restrict__ best_s,
+                                     const int32_t *__restrict__ best_step,
+                                     const BatchJob *__restrict__ jobs, int njobs, int Rtot,
+                                     int return_best) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int r = blockIdx.y; r < Rtot; r += gridDim.y) {
+        const BatchJob jb = jobs[batch_job_of(jobs, njobs, r)];
+        const int rep = r - jb.col0;
+        if (rep < 0 || rep >= jb.R || i >= jb.N) continue;
+        const size_t src = (size_t)i * Rtot + r;
+        jb.spins[(size_t)rep * jb.N + i] =
+            (return_best && best_step[r] >= 0) ? best_s[src] : (X[src] >= 0.0f ? 1 : -1);
+    }
+}
+
+__global__ void k_output_batch_energy(const double *__restrict__ best_e,
+                                      const double *__restrict__ last_e,
+                                      const int32_t *__restrict__ bad,
+                                      const BatchJob *__restrict__ jobs, int njobs, int Rtot,
+                                      int return_best) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= Rtot) return;
+    const BatchJob jb = jobs[batch_job_of(jobs, njobs, r)];
+    const int rep = r - jb.col0;
+    if (rep < 0 || rep >= jb.R) return;
+    jb.energy[rep] = bad[r] ? __builtin_nan("") : (return_best ? best_e[r] : last_e[r]);
+}
+
 // ------------------------------------------------------------ launchers
 
 void free_state_bufs(StateBufs &b) {
@@ -349,7 +406,7 @@ void free_state_bufs(StateBufs &b) {
     b = StateBufs{};
 }
 
-hipError_t alloc_state(StateBufs &b, int Npad, int Rpad) {
+hipError_t alloc_state(StateBufs &b, int Npad, int Rpad, bool fp32_plan) {
     b = StateBufs{};
     const size_t nr = (size_t)Rpad, ns = (size_t)Npad * nr;
     hipError_t e = hipSuccess;
@@ -358,10 +415,12 @@ hipError_t alloc_state(StateBufs &b, int Npad, int Rpad) {
     };
     alloc((void **)&b.X, ns * sizeof(float));
     alloc((void **)&b.Y, ns * sizeof(float));
-    alloc((void **)&b.B[0], ns * sizeof(float));
-    alloc((void **)&b.B[1], ns * sizeof(float));
+    if (fp32_plan) {
+        alloc((void **)&b.B[0], ns * sizeof(float));
+        alloc((void **)&b.B[1], ns * sizeof(float));
+    }
     alloc((void **)&b.gamma, nr * sizeof(float));
-    alloc((void **)&b.epart, (size_t)(Npad / 32) * nr * sizeof(double));
+    if (fp32_plan) alloc((void **)&b.epart, (size_t)(Npad / 32) * nr * sizeof(double));
     alloc((void **)&b.best_e, nr * sizeof(double));
     alloc((void **)&b.last_e, nr * sizeof(double));
     alloc((void **)&b.best_step, nr * sizeof(int32_t));
@@ -378,6 +437,23 @@ hipError_t launch_init_seeded(float *X, float *Y, int N, int R, int Npad, int nc
                               uint64_t seed, float amp, hipStream_t s, const uint64_t *seed_p) {
     hipLaunchKernelGGL(k_init_seeded, dim3(cdiv(ncols, 256), Npad), dim3(256), 0, s, X, Y, N, R,
                        ncols, ld, seed, seed_p, amp);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_batch(float *X, float *Y, float *gamma, const BatchJob *jobs, int njobs,
+                             int Npad, int Rtot, float amp, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_batch, dim3(cdiv(Rtot, 256), Npad), dim3(256), 0, s, X, Y, gamma,
+                       jobs, njobs, Rtot, amp);
+    return hipGetLastError();
+}
+
+hipError_t launch_output_batch(const StateBufs &b, const BatchJob *jobs, int njobs, int Nmax,
+                               int Rtot, int return_best, hipStream_t s) {
+    hipLaunchKernelGGL(k_output_batch_spins, dim3(cdiv(Nmax, 256), Rtot < 32768 ? Rtot : 32768),
+                       dim3(256), 0, s, b.X, b.best_s, b.best_step, jobs, njobs, Rtot,
+                       return_best);
+    hipLaunchKernelGGL(k_output_batch_energy, dim3(cdiv(Rtot, 256)), dim3(256), 0, s, b.best_e,
+                       b.last_e, b.bad, jobs, njobs, Rtot, return_best);
     return hipGetLastError();
 }
 
