@@ -204,6 +204,11 @@ typedef struct {
     double *final_energy;   /* optional [R] energy of the final state */
     int32_t *best_step;     /* optional [R] step count of the best sample */
     void *stream;           /* hipStream_t; NULL = the null stream */
+    double *trace_energy;   /* optional [n_samples][R]: eq. (1) of sgn(x) at every sample
+                               point of the call, in step order (hsb_num_samples) */
+    double *trace_tinst;    /* optional [n_samples][R]: the instantaneous temperature
+                               T_inst = (1/N) sum_i y_i^2 of eq. (9) at the same points,
+                               summed in FP64 */
 } hsb_run_args;
 
 /*
@@ -213,8 +218,20 @@ typedef struct {
  * stream to report HSB_ENUMERIC.  Sample points are step counts m with
  * start_step < m <= start_step + steps and m % energy_interval == 0, plus the
  * state after the last step of the call (and the initial state when steps = 0).
+ * The traces, if given, receive the energy and T_inst of every sample point;
+ * the entries of a replica that became non-finite are unspecified.
  */
 int hsb_run_ex(hsb_ctx *h, const hsb_run_args *args);
+
+/*
+ * hsb_num_samples -- number of sample points of a call of hsb_run_ex with this
+ * start_step and steps under the context's HSB_OPT_ENERGY_INTERVAL I: the
+ * multiples of I in (start_step, start_step + steps], plus the last state if
+ * it is not one of them (the initial state when steps = 0).  This is the
+ * leading dimension of trace_energy and trace_tinst; row j is the j-th sample
+ * point in step order.  start_step, steps >= 0, else HSB_EINVAL.
+ */
+int hsb_num_samples(hsb_ctx *h, int start_step, int steps, int *n);
 
 /*
  * hsb_plan_info -- the precision plan AUTO (or the forced option) would use

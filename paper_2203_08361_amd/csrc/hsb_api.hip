@@ -286,6 +286,15 @@ extern "C" int hsb_get_option(hsb_ctx *h, int key, double *v) {
     }
 }
 
+extern "C" int hsb_num_samples(hsb_ctx *h, int start_step, int steps, int *n) {
+    if (!h || !n) return fail(HSB_EINVAL, "hsb_num_samples: NULL argument");
+    if (start_step < 0 || steps < 0 || (long long)start_step + steps > INT32_MAX)
+        return fail(HSB_EINVAL, "hsb_num_samples: start_step and steps must be >= 0");
+    const int I = h->interval, k1 = start_step + steps;
+    *n = k1 / I - start_step / I + ((k1 % I != 0 || steps == 0) ? 1 : 0);
+    return HSB_OK;
+}
+
 namespace {
 
 // Execution plans (hsb_plan); the precision reported for both mixed plans is
@@ -363,6 +372,10 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
     HIP_TRY(hsb::launch_fill_gamma(b.gamma, a->gamma_rep, a->gamma, R, Rpad, s));
     HIP_TRY(hsb::launch_reset_tracking(b, Rpad, s));
 
+    b.trace_e = a->trace_energy;
+    b.trace_t = a->trace_tinst;
+    b.trace_k0 = a->start_step;
+    b.trace_interval = interval;
     h->timer.reset(h->timing != 0);
     const float a0 = a->a0, c0 = a->c0, dt = a->dt;
     const float a0dt = a0 * dt;
@@ -472,7 +485,8 @@ std::vector<uint64_t> run_key(const hsb_ctx *h, const hsb_run_args *a, int plan)
     return {(uint64_t)a->variant, (uint64_t)a->steps, (uint64_t)a->R, (uint64_t)a->start_step,
             (uint64_t)a->schedule_steps, fb(a->a0), fb(a->c0), fb(a->dt), fb(a->gamma),
             pb(a->gamma_rep), pb(a->x0), pb(a->y0), pb(a->x_out), pb(a->y_out), pb(a->spins),
-            pb(a->energy), pb(a->best_energy), pb(a->final_energy), pb(a->best_step), amp,
+            pb(a->energy), pb(a->best_energy), pb(a->final_energy), pb(a->best_step),
+            pb(a->trace_energy), pb(a->trace_tinst), amp,
             (uint64_t)h->interval, (uint64_t)h->return_best, (uint64_t)h->local_exchange,
             (uint64_t)plan, pb(h->b.X), (uint64_t)h->Rpad_cap, h->state_gen, pb(h->pj),
             h->pj ? hsb::persistent_gen(h->pj) : 0};

@@ -82,7 +82,17 @@ struct StateBufs {
     int32_t *bad;         // [Rpad] non-finite flag per replica
     int8_t *best_s;       // [Npad][Rpad]
     int32_t *status;      // [1] any replica non-finite
+    // optional per-call traces, [n_samples][R] (caller memory, not owned):
+    // energy and T_inst of every sample point of the run steps trace_k0 ..
+    double *trace_e = nullptr, *trace_t = nullptr;
+    int trace_k0 = 0, trace_interval = 1;
 };
+
+// Row of the trace that receives the sample at step m of a call starting at
+// step k0: the multiples of the interval in (k0, m) come before it.
+inline int trace_row(int m, int k0, int interval) {
+    return m / interval - k0 / interval - ((m > k0 && m % interval == 0) ? 1 : 0);
+}
 
 // rows [0, Npad) x columns [0, ncols) of a state with leading dimension ld; the
 // seed is `seed`, or *seed_p (device memory, read when the kernel runs) if given

@@ -249,6 +249,8 @@ __global__ __launch_bounds__(256) void k_energy_f64(const float *__restrict__ J,
 // in a fixed order, non-finite detection, strict-improvement best update
 // (ties keep the earliest sample) with a copy of the spins.  A workgroup of
 // 1024 threads owns 64 replicas (lane = replica); its 16 waves split the rows.
+// With traces, row `trow` of trace_e / trace_t ([.][R]) receives the energy
+// and T_inst = (1/N) sum_i y_i^2 (eq. (9); FP64 sums in a fixed order).
 __global__ __launch_bounds__(1024) void k_best(const double *__restrict__ epart, int nblk,
                                                const float *__restrict__ X,
                                                const float *__restrict__ Y, int N, int R,
@@ -257,23 +259,32 @@ __global__ __launch_bounds__(1024) void k_best(const double *__restrict__ epart,
                                                int32_t *__restrict__ best_step,
                                                int32_t *__restrict__ bad,
                                                int8_t *__restrict__ best_s,
-                                               int32_t *__restrict__ status, int step) {
+                                               int32_t *__restrict__ status, int step,
+                                               double *__restrict__ trace_e,
+                                               double *__restrict__ trace_t, int trow) {
     __shared__ int s_bad[16][64];
+    __shared__ double s_t[16][64];
     __shared__ int s_take[64];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = blockIdx.x * 64 + l;
     int nf = 0;
+    double t = 0.0;
     if (r < R)
         for (int i = w; i < N; i += 16) {
             const float x = X[(size_t)i * Rpad + r], y = Y[(size_t)i * Rpad + r];
             nf |= !(isfinite(x) && isfinite(y));
+            t += (double)y * (double)y;
         }
     s_bad[w][l] = nf;
+    s_t[w][l] = t;
     __syncthreads();
     if (w == 0) {
         int take = 0;
         if (r < R) {
-            for (int q = 1; q < 16; ++q) nf |= s_bad[q][l];
+            for (int q = 1; q < 16; ++q) {
+                nf |= s_bad[q][l];
+                t += s_t[q][l];
+            }
             double e = 0.0;
             for (int b = 0; b < nblk; ++b) e += epart[(size_t)b * Rpad + r];
             e = -0.5 * e;
@@ -283,6 +294,8 @@ __global__ __launch_bounds__(1024) void k_best(const double *__restrict__ epart,
                 e = __builtin_nan("");
             }
             last_e[r] = e;
+            if (trace_e) trace_e[(size_t)trow * R + r] = e;
+            if (trace_t) trace_t[(size_t)trow * R + r] = t / N;
             if (e < best_e[r]) {
                 best_e[r] = e;
                 best_step[r] = step;
@@ -520,7 +533,9 @@ hipError_t launch_energy_f64(const float *J, const float *X, double *epart, int 
 hipError_t launch_best(const StateBufs &b, int nblk, int N, int R, int Rpad, int step,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_best, dim3(cdiv(R, 64)), dim3(1024), 0, s, b.epart, nblk, b.X, b.Y, N, R,
-                       Rpad, b.best_e, b.last_e, b.best_step, b.bad, b.best_s, b.status, step);
+                       Rpad, b.best_e, b.last_e, b.best_step, b.bad, b.best_s, b.status, step,
+                       b.trace_e, b.trace_t,
+                       (b.trace_e || b.trace_t) ? trace_row(step, b.trace_k0, b.trace_interval) : 0);
     return hipGetLastError();
 }
 

@@ -55,6 +55,8 @@ struct PersistentWork {
     size_t ep_elems = 0;
     double *es = nullptr;        // [ns][Rpad] sample energies
     size_t es_elems = 0;
+    double *tp = nullptr;        // [ns][nparts][Rpad] partial sums of y^2 (traces only)
+    size_t tp_elems = 0;
     float *ptab = nullptr;       // p_k = a0 - a(t_k) of the steps of one segment
     size_t ptab_elems = 0;
     int32_t *err = nullptr;      // [1] timeout flag
@@ -305,7 +307,8 @@ template <int NKB>
 __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, uint64_t *xb, uint32_t *__restrict__ snap,
-    float *__restrict__ ep, const float *__restrict__ ptab, int32_t *__restrict__ bad,
+    float *__restrict__ ep, double *__restrict__ tp, const float *__restrict__ ptab,
+    int32_t *__restrict__ bad,
     int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, const uint32_t *epoch_p,
     int local_ok,
     int nkb, int nchunk, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
@@ -455,6 +458,13 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
             }
             part += __shfl_xor(part, 32);
             if (half == 0) ep[((size_t)j * nchunk + rb) * Rpad + rep] = part;
+            if (tp) {  // sum of y_i^2 over the same rows (eq. (9)), exact squares
+                double t = 0.0;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) t += (double)ys[v] * (double)ys[v];
+                t += __shfl_xor(t, 32);
+                if (half == 0) tp[((size_t)j * nchunk + rb) * Rpad + rep] = t;
+            }
             if (!fin) {
                 bad[rep] = 1;
                 __hip_atomic_fetch_or(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -618,7 +628,8 @@ template <int NKB>
 __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, v4i *xd, uint8_t *xe, uint32_t *flags,
-    uint32_t *__restrict__ snap, const float *__restrict__ ptab, int32_t *__restrict__ bad,
+    uint32_t *__restrict__ snap, double *__restrict__ tp, const float *__restrict__ ptab,
+    int32_t *__restrict__ bad,
     int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, const uint32_t *epoch_p,
     int local_ok,
     int nkb, int nrb, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
@@ -733,6 +744,14 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
         const uint32_t word = half ? (got | (b1 << 16)) : (b0 | (got << 16));
         const size_t slot = (size_t)(rb * 2 + half) * Rpad + rep;
         snap[(size_t)seg_sample_index(g, m) * nchunk * Rpad + slot] = word;
+        if (tp) {  // sum of y_i^2 over the wave's 64 rows (eq. (9)), exact squares
+            double t = 0.0;
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                t += (double)ys0[v] * (double)ys0[v] + (double)ys1[v] * (double)ys1[v];
+            t += __shfl_xor(t, 32);
+            if (half == 0) tp[((size_t)seg_sample_index(g, m) * nrb + rb) * Rpad + rep] = t;
+        }
         if (!fin) {
             bad[rep] = 1;
             __hip_atomic_fetch_or(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -958,6 +977,27 @@ __global__ __launch_bounds__(256) void k_fp4_energies(const float *__restrict__ 
     es[(size_t)j * Rpad + r] = -0.5 * e;
 }
 
+// Traces of the segment's samples: row row0 + j of trace_e / trace_t ([.][R])
+// receives sample j's energy and T_inst = (1/N) sum_i y_i^2 (eq. (9)), the
+// latter from the nparts FP64 partial sums, added in a fixed order.  Grid
+// (R/256, samples), one thread per (replica, sample).
+__global__ __launch_bounds__(256) void k_fp4_trace(const double *__restrict__ es,
+                                                   const double *__restrict__ tp, int nparts,
+                                                   int N, int R, int Rpad, int row0,
+                                                   double *__restrict__ trace_e,
+                                                   double *__restrict__ trace_t) {
+    const int r = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    if (r >= R) return;
+    const size_t o = (size_t)(row0 + j) * R + r;
+    if (trace_e) trace_e[o] = es[(size_t)j * Rpad + r];
+    if (trace_t) {
+        const double *q = tp + (size_t)j * nparts * Rpad + r;
+        double t = 0.0;
+        for (int b = 0; b < nparts; ++b) t += q[(size_t)b * Rpad];
+        trace_t[o] = t / N;
+    }
+}
+
 // Best-sample update of the segment's samples and its spins.  Grid Rpad/32,
 // 256 threads: lane group g = threadIdx.x / 32 scans samples j = g, g + 8, ...
 // of 32 replicas; the groups' minima are merged with the earliest sample
@@ -1155,8 +1195,8 @@ int persistent_work_create(PersistentWork **out) {
 
 void persistent_work_free(PersistentWork *w) {
     if (!w) return;
-    void *ptrs[] = {w->xb, w->snap, w->ep, w->es, w->ptab, w->err, w->xslot, w->epoch, w->teams,
-                    w->xd, w->xe, w->flags};
+    void *ptrs[] = {w->xb, w->snap, w->ep, w->es, w->tp, w->ptab, w->err, w->xslot, w->epoch,
+                    w->teams, w->xd, w->xe, w->flags};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete w;
@@ -1165,8 +1205,8 @@ void persistent_work_free(PersistentWork *w) {
 void persistent_free(PersistentJ *pj) {
     if (!pj) return;
     PersistentWork &w = pj->work;
-    void *ptrs[] = {pj->jpk, w.xb, w.snap, w.ep, w.es, w.ptab, w.err, w.xslot, w.epoch, w.teams,
-                    w.xd, w.xe, w.flags};
+    void *ptrs[] = {pj->jpk, w.xb, w.snap, w.ep, w.es, w.tp, w.ptab, w.err, w.xslot, w.epoch,
+                    w.teams, w.xd, w.xe, w.flags};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete pj;
@@ -1212,12 +1252,18 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     size_t seg_samples = ((size_t)512 << 20) / (snap_per_sample * 4);
     if (seg_samples > 4096) seg_samples = 4096;
     if (seg_samples < 1) seg_samples = 1;
-    const void *const before[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->ptab, pw->err, pw->teams,
-                                  pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
+    const bool traces = b.trace_e || b.trace_t;
+    const void *const before[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->tp, pw->ptab, pw->err,
+                                  pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
     int rc = grow(&pw->xb, &pw->xb_words, (size_t)2 * nchunk * Rpad);
     if (!rc) rc = grow(&pw->snap, &pw->snap_words, (seg_samples + 1) * snap_per_sample);
     if (!rc) rc = grow(&pw->ep, &pw->ep_elems, (seg_samples + 1) * (size_t)nparts * Rpad);
     if (!rc) rc = grow(&pw->es, &pw->es_elems, (seg_samples + 1) * (size_t)Rpad);
+    if (!rc && traces) {  // partials of at most the run's own samples per segment
+        const size_t run_samples = (size_t)(run.k1 / interval - run.k0 / interval) + 1;
+        const size_t tps = run_samples < seg_samples + 1 ? run_samples : seg_samples + 1;
+        rc = grow(&pw->tp, &pw->tp_elems, tps * (size_t)nparts * Rpad);
+    }
     const long long max_seg_steps = (long long)seg_samples * interval;
     const int ptab_need = (int)((long long)(run.k1 - run.k0) < max_seg_steps
                                     ? (run.k1 - run.k0)
@@ -1250,8 +1296,8 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     }
     if (rc) return rc;
     {
-        const void *const after[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->ptab, pw->err, pw->teams,
-                                     pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
+        const void *const after[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->tp, pw->ptab, pw->err,
+                                     pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
         if (std::memcmp(before, after, sizeof(before)) != 0) ++pw->gen;
     }
     // the team table, uploaded only when it differs from the last upload (a
@@ -1306,9 +1352,11 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
             hipLaunchKernelGGL(k_next_epoch, dim3(1), dim3(1), 0, s, pw->epoch);
             int local_ok = run.local_exchange ? 1 : 0;
             const float *gam = run.gamma;
+            double *tpv = traces ? pw->tp : nullptr;
             void *args_d[] = {(void *)&pw->teams, (void *)&run.X,    (void *)&run.Y,
                               (void *)&gam,       (void *)&pw->xb,   (void *)&pw->snap,
-                              (void *)&pw->ep,    (void *)&pw->ptab, (void *)&b.bad,
+                              (void *)&pw->ep,    (void *)&tpv,      (void *)&pw->ptab,
+                              (void *)&b.bad,
                               (void *)&b.status,  (void *)&pw->err,  (void *)&pw->xslot,
                               (void *)&pw->epoch, (void *)&local_ok, (void *)&nkb_v,
                               (void *)&nchunk_v,  (void *)&Rpad_v,   (void *)&t0_v,
@@ -1316,7 +1364,8 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
                               (void *)&a0dtv};
             void *args_b[] = {(void *)&pw->teams, (void *)&run.X,     (void *)&run.Y,
                               (void *)&gam,       (void *)&pw->xd,    (void *)&pw->xe,
-                              (void *)&pw->flags, (void *)&pw->snap,  (void *)&pw->ptab,
+                              (void *)&pw->flags, (void *)&pw->snap,  (void *)&tpv,
+                              (void *)&pw->ptab,
                               (void *)&b.bad,     (void *)&b.status,  (void *)&pw->err,
                               (void *)&pw->xslot, (void *)&pw->epoch, (void *)&local_ok,
                               (void *)&nkb_v,     (void *)&nrb_v,     (void *)&Rpad_v,
@@ -1343,6 +1392,10 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
         hipLaunchKernelGGL(k_fp4_best, dim3((unsigned)((run.R + 31) / 32)), dim3(256), 0, s,
                            pw->es, pw->snap, ns, nchunk, Nrows, run.R, Rpad, g, b.best_e, b.last_e,
                            b.best_step, b.bad, b.best_s);
+        if (traces && ns > 0)  // rows of the segment's samples: after those of (k0, a]
+            hipLaunchKernelGGL(k_fp4_trace, dim3((unsigned)((run.R + 255) / 256), (unsigned)ns),
+                               dim3(256), 0, s, pw->es, pw->tp, nparts, Nrows, run.R, Rpad,
+                               a / interval - run.k0 / interval, b.trace_e, b.trace_t);
         e = hipGetLastError();
         if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
         if (e_k >= run.k1) break;

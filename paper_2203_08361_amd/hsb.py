@@ -26,7 +26,7 @@ PLAN_NAMES = {HSB_PLAN_FP32: "fp32", HSB_PLAN_FP4: "fp4", HSB_PLAN_DIGITS: "digi
 HSB_PREC_AUTO, HSB_PREC_FP32, HSB_PREC_MIXED, HSB_PREC_DIGITS = 0, 1, 2, 3
 
 EXPORTED = ("hsb_create", "hsb_destroy", "hsb_last_error", "hsb_set_option", "hsb_get_option",
-            "hsb_run", "hsb_run_ex", "hsb_plan_info", "hsb_run_batch")
+            "hsb_run", "hsb_run_ex", "hsb_plan_info", "hsb_run_batch", "hsb_num_samples")
 
 _lib = None
 
@@ -52,6 +52,7 @@ class hsb_run_args(ctypes.Structure):
         ("best_energy", ctypes.c_void_p), ("final_energy", ctypes.c_void_p),
         ("best_step", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
+        ("trace_energy", ctypes.c_void_p), ("trace_tinst", ctypes.c_void_p),
     ]
 
 
@@ -100,6 +101,8 @@ def load_library():
     L.hsb_run_ex.argtypes = [vp, ctypes.POINTER(hsb_run_args)]
     L.hsb_plan_info.restype = i32
     L.hsb_plan_info.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    L.hsb_num_samples.restype = i32
+    L.hsb_num_samples.argtypes = [vp, i32, i32, ctypes.POINTER(i32)]
     L.hsb_run_batch.restype = i32
     L.hsb_run_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(hsb_job), i32,
                                 ctypes.POINTER(hsb_batch_args)]
@@ -164,14 +167,22 @@ def _ctx_n(h) -> int:
     return _sizes[h.value]
 
 
+def hsb_num_samples(h, start_step: int, steps: int) -> int:
+    n = ctypes.c_int()
+    _check(load_library().hsb_num_samples(h, start_step, steps, ctypes.byref(n)))
+    return n.value
+
+
 def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=None, x0=None,
                y0=None, start_step=0, schedule_steps=0, want_state=False, stream=None,
-               allow_numeric=False, out=None):
+               allow_numeric=False, out=None, traces=False):
     """Device run through hsb_run_ex.  Tensors are torch CUDA tensors.
 
     Returns a dict of device tensors: spins [R][N] int8, energy/best_energy/
-    final_energy [R] float64, best_step [R] int32, and x/y [R][N] float32 when
-    want_state.  `out` may pass preallocated tensors under the same keys.
+    final_energy [R] float64, best_step [R] int32, x/y [R][N] float32 when
+    want_state, and trace_energy/trace_tinst [n_samples][R] float64 (energy
+    and T_inst of eq. (9) at every sample point) when traces.  `out` may pass
+    preallocated tensors under the same keys.
     """
     import torch
 
@@ -185,6 +196,12 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
     if want_state:
         o.setdefault("x", torch.empty((R, N), dtype=torch.float32, device=dev))
         o.setdefault("y", torch.empty((R, N), dtype=torch.float32, device=dev))
+    if traces:
+        ns = hsb_num_samples(h, start_step, steps)
+        for k in ("trace_energy", "trace_tinst"):
+            o.setdefault(k, torch.empty((ns, R), dtype=torch.float64, device=dev))
+            if tuple(o[k].shape) != (ns, R) or o[k].dtype != torch.float64:
+                raise ValueError(f"{k} must be a float64 tensor of shape {(ns, R)}")
     a = hsb_run_args()
     a.struct_size = ctypes.sizeof(hsb_run_args)
     a.variant, a.steps, a.R = variant, steps, R
@@ -212,6 +229,9 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
     a.best_energy = o["best_energy"].data_ptr()
     a.final_energy = o["final_energy"].data_ptr()
     a.best_step = o["best_step"].data_ptr()
+    if traces:
+        a.trace_energy = o["trace_energy"].data_ptr()
+        a.trace_tinst = o["trace_tinst"].data_ptr()
     s = stream if stream is not None else torch.cuda.current_stream()
     a.stream = s.cuda_stream
     rc = load_library().hsb_run_ex(h, ctypes.byref(a))
@@ -292,6 +312,9 @@ class Context:
 
     def run(self, variant, a0, c0, dt, gamma, steps, R, seed, allow_numeric=False):
         return hsb_run(self.h, variant, a0, c0, dt, gamma, steps, R, seed, allow_numeric)
+
+    def num_samples(self, start_step, steps):
+        return hsb_num_samples(self.h, start_step, steps)
 
     def run_ex(self, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, **kw):
         return hsb_run_ex(self.h, variant, steps, R, a0, c0, dt, gamma, seed, **kw)

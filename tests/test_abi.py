@@ -106,6 +106,9 @@ def test_calls_on_null_context_are_rejected():
     a = hsb.hsb_batch_args()
     a.struct_size = ctypes.sizeof(a)
     assert L.hsb_run_batch(None, 1, None, 0, ctypes.byref(a)) == hsb.HSB_EINVAL
+    n = ctypes.c_int(-7)
+    assert L.hsb_num_samples(None, 0, 10, ctypes.byref(n)) == hsb.HSB_EINVAL
+    assert n.value == -7
     L.hsb_destroy(None)  # ignored
 
 
