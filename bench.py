@@ -93,6 +93,10 @@ def main() -> int:
                     help="run only the batched uneven-instance workload")
     ap.add_argument("--no-gaussian", action="store_true",
                     help="skip the Gaussian-coupling workload of the default run")
+    ap.add_argument("--no-evaluation", action="store_true",
+                    help="skip the 700-spin evaluation of the four SB forms")
+    ap.add_argument("--evaluation-only", action="store_true",
+                    help="run only the 700-spin evaluation of the four SB forms")
     ap.add_argument("--cpu-replicas", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -301,8 +305,37 @@ def main() -> int:
                 "fp64_energy_check": f"eq. (1) of the returned spins of {len(rel)} replicas "
                                      f"(every 64th) recomputed by the FP64 oracle"}
 
+    def evaluation_workload():
+        # the 700-spin comparison of the Results: 100 instances, the energy at
+        # the last step, the four forms at the paper's parameters over a range
+        # of N_s; one hsb_run_batch call per (form, N_s)
+        from paper_2203_08361_amd import evaluate as ev
+
+        n_inst, n_spins, trials, grid = 100, 700, 1024, (200, 500, 1000, 2000)
+        Js = [synth.sk_instance(n_spins, 700 + i) for i in range(n_inst)]
+        log(f"evaluation: {n_inst} SK instances N={n_spins}, {trials} trials, N_s {grid}")
+        with ev.GpuRunner(Js) as run:
+            res = ev.evaluate(Js, run, ev.PRESETS, grid, R=trials, seed=1, final_only=True)
+        best = res["best_Ns"]
+        ratio = (best["HbSB"]["median_S"] / best["dSB"]["median_S"]
+                 if math.isfinite(best["dSB"]["median_S"]) and best["dSB"]["median_S"] > 0
+                 else None)
+        return {"workload": f"{n_inst} seeded SK +-1 instances N={n_spins}, {trials} trials per "
+                            f"instance, forms bSB/dSB/HbSB/HdSB at the paper's parameters, "
+                            f"N_s in {list(grid)}, energy at the last step; one "
+                            f"hsb_run_batch call per (form, N_s)",
+                "seconds": res["seconds"], "spin_updates_per_s": res["spin_updates_per_s"],
+                "reference": "per instance, the best energy any trial reached",
+                "median_S": {f"{r['form']}@{r['Ns']}": r["median_S"] for r in res["rows"]},
+                "mean_P": {f"{r['form']}@{r['Ns']}": r["mean_P"] for r in res["rows"]},
+                "best_Ns": best, "best_median_S_HbSB_over_dSB": ratio}
+
     if args.batch_only:
         print(json.dumps({"batch": batch_workload()}), flush=True)
+        ctx.close()
+        return 0
+    if args.evaluation_only:
+        print(json.dumps({"evaluation": evaluation_workload()}), flush=True)
         ctx.close()
         return 0
 
@@ -336,6 +369,8 @@ def main() -> int:
         result["gaussian"] = gaussian_workload()
     if args.variant == "dsb" and not args.no_batch:
         result["batch"] = batch_workload()
+    if args.variant == "dsb" and not args.no_evaluation:
+        result["evaluation"] = evaluation_workload()
 
     if not args.no_cpu_baseline:
         import oracle

@@ -35,7 +35,10 @@ def wilson_interval(k: int, n: int, z: float = 1.959963984540054):
     den = 1 + z * z / n
     c = (p + z * z / (2 * n)) / den
     h = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / den
-    return (max(0.0, c - h), min(1.0, c + h))
+    # the ends are exactly 0 at k = 0 and 1 at k = n (c - h, c + h round near them)
+    lo = 0.0 if k == 0 else max(0.0, c - h)
+    hi = 1.0 if k == n else min(1.0, c + h)
+    return (lo, hi)
 
 
 def step_to_solution(P: float, Ns: int) -> float:
@@ -44,7 +47,9 @@ def step_to_solution(P: float, Ns: int) -> float:
         return math.inf
     if P >= 0.99:
         return float(Ns)
-    return Ns * math.log(0.01) / math.log(1.0 - P)
+    q = 1.0 - P
+    # a P below the rounding of 1 - P: log1p keeps S finite (and very large)
+    return Ns * math.log(0.01) / (math.log(q) if q < 1.0 else math.log1p(-P))
 
 
 def newcombe_interval(k1: int, n1: int, k2: int, n2: int, z: float = 1.959963984540054):

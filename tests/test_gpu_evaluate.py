@@ -1,0 +1,128 @@
+"""Evaluation harness on the GPU (marked `gpu`): the same evaluation with its
+trials run by hsb_run_batch and by the oracle.
+
+  - dSB and HdSB: the trajectories are bitwise the oracle's FP32 mirror, so
+    the whole evaluation (reference energies, every P, S, C, median) is equal.
+  - bSB and HbSB: per instance and N_s, Welch's 95% interval of the difference
+    of the mean best energies (GPU minus FP64 oracle) contains 0.
+  - time_evolution: T_inst and C at every step equal the oracle's traces
+    (dSB exactly, T_inst to FP64 summation order).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2203_08361_amd import evaluate as ev  # noqa: E402
+from paper_2203_08361_amd import hsb, metrics  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    hsb.load_library()
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+class OracleRunner:
+    def __init__(self, Js, precision):
+        self.Js = Js
+        self.precision = precision
+
+    def __call__(self, p, Ns, R, seeds, c0s, interval, amp):
+        variant = oracle.BSB if p.variant == hsb.HSB_BSB else oracle.DSB
+        return np.stack([oracle.run(J, variant, 1.0, np.float32(c0s[i]), p.dt, p.gamma, Ns, R,
+                                    seed=seeds[i], amp=amp, interval=interval,
+                                    precision=self.precision)["best_e"]
+                         for i, J in enumerate(self.Js)])
+
+
+def strip(res):
+    return {k: v for k, v in res.items() if k not in ("seconds", "spin_updates_per_s")}
+
+
+@pytest.mark.parametrize("final_only", [False, True])
+def test_dsb_forms_equal_the_oracle_evaluation(final_only):
+    Js = [synth.sk_instance(N, 50 + N) for N in (64, 100, 150, 257)]
+    forms = [ev.preset("dSB"), ev.preset("HdSB")]
+    say("evaluation dSB forms", final_only)
+    with ev.GpuRunner(Js) as run:
+        g = ev.evaluate(Js, run, forms, (60, 150), R=24, seed=4, interval=50,
+                        final_only=final_only)
+    o = ev.evaluate(Js, OracleRunner(Js, oracle.FP32), forms, (60, 150), R=24, seed=4,
+                    interval=50, final_only=final_only)
+    assert strip(g) == strip(o)
+    assert g["spin_updates_per_s"] > 0
+
+
+def test_bsb_forms_agree_with_the_fp64_oracle_in_distribution():
+    Js = [synth.sk_instance(N, 60 + N) for N in (100, 200)]
+    forms = [ev.preset("bSB"), ev.preset("HbSB")]
+    R, Ns = 128, (100, 300)
+    say("evaluation bSB forms")
+    energies = {}
+
+    def recording(runner, tag):
+        def call(p, ns, r, seeds, c0s, interval, amp):
+            E = runner(p, ns, r, seeds, c0s, interval, amp)
+            energies[tag, p.name, ns] = E
+            return E
+        return call
+
+    with ev.GpuRunner(Js) as run:
+        ev.evaluate(Js, recording(run, "gpu"), forms, Ns, R=R, seed=5)
+    ev.evaluate(Js, recording(OracleRunner(Js, oracle.FP64), "orc"), forms, Ns, R=R, seed=5)
+    for p in forms:
+        for ns in Ns:
+            for i in range(len(Js)):
+                a, b = energies["gpu", p.name, ns][i], energies["orc", p.name, ns][i]
+                lo, hi = metrics.welch_interval(a, b)
+                say(f"{p.name} Ns={ns} instance {i}: mean {a.mean():.3f} vs {b.mean():.3f}, "
+                    f"difference in [{lo:.3f}, {hi:.3f}]")
+                assert lo <= 0.0 <= hi
+
+
+@pytest.mark.parametrize("form", ["dSB", "HdSB"])
+def test_time_evolution_equals_oracle_traces(form):
+    N, Ns, R = 100, 200, 3
+    J = synth.sk_instance(N, 77)
+    p = ev.preset(form)
+    say("time evolution", form)
+    g = ev.time_evolution(J, p, Ns, R=R, seed=9)
+    assert g["T_inst"].shape == g["C"].shape == (Ns + 1, R)
+    c0 = np.float32(ev.c0_for(J, p.c1))
+    o0 = oracle.run(J, oracle.DSB, 1.0, c0, p.dt, p.gamma, 0, R, seed=9, amp=1.0, interval=1,
+                    precision=oracle.FP32, traces=True)
+    o = oracle.run(J, oracle.DSB, 1.0, c0, p.dt, p.gamma, Ns, R, seed=9, amp=1.0, interval=1,
+                   precision=oracle.FP32, traces=True)
+    E = np.concatenate([o0["trace_e"], o["trace_e"]])
+    T = np.concatenate([o0["trace_tinst"], o["trace_tinst"]])
+    assert np.array_equal(g["energy"], E)
+    assert np.array_equal(g["C"], metrics.cut_from_energy(E, J))
+    np.testing.assert_allclose(g["T_inst"], T, rtol=1e-13, atol=0)
+
+
+def test_time_evolution_of_the_heated_ballistic_form():
+    """HbSB (gamma = 0.5) against bSB on a 2000-spin SK instance, 10^4 steps:
+    the heating keeps T_inst far above bSB's at the end of the run (the
+    time-evolution figure of the Results); both traces are finite."""
+    N, Ns = 2000, 10000
+    J = synth.sk_instance(N, 2000)
+    say("time evolution HbSB vs bSB", N, Ns)
+    h = ev.time_evolution(J, ev.preset("HbSB"), Ns, R=8, seed=3)
+    b = ev.time_evolution(J, ev.preset("bSB"), Ns, R=8, seed=3)
+    for t in (h, b):
+        assert np.all(np.isfinite(t["T_inst"])) and np.all(np.isfinite(t["C"]))
+    end_h = np.median(h["T_inst"][-1000:])
+    end_b = np.median(b["T_inst"][-1000:])
+    say(f"median T_inst over the last 1000 steps: HbSB {end_h:.3e}, bSB {end_b:.3e}")
+    assert end_h > 10 * end_b

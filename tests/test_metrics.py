@@ -5,6 +5,7 @@ Newcombe's hybrid score interval is pinned to the published worked examples
 scipy's own Welch test and to its coverage on samples of equal means.
 """
 import json
+import math
 import os
 
 import numpy as np
@@ -53,3 +54,16 @@ def test_welch_coverage_with_equal_means():
         lo, hi = metrics.welch_interval(a, b)
         hits += lo <= 0.0 <= hi
     assert 0.93 <= hits / trials <= 0.97
+
+
+def test_wilson_ends_and_step_to_solution_of_tiny_P():
+    for n in (1, 4, 24, 128, 1024, 10**4):
+        assert metrics.wilson_interval(0, n)[0] == 0.0
+        assert metrics.wilson_interval(n, n)[1] == 1.0
+        if n > 1:
+            lo, hi = metrics.wilson_interval(1, n)
+            assert 0.0 < lo < 1.0 / n < hi
+    # eq. (15) stays finite and decreasing for P far below the rounding of 1 - P
+    S = [metrics.step_to_solution(P, 100) for P in (1e-3, 1e-12, 1e-17, 1e-300)]
+    assert all(math.isfinite(x) for x in S) and S == sorted(S)
+    assert S[2] == pytest.approx(100 * math.log(100) / 1e-17, rel=1e-12)
