@@ -323,12 +323,31 @@ def main() -> int:
         return {"workload": f"{n_inst} seeded SK +-1 instances N={n_spins}, {trials} trials per "
                             f"instance, forms bSB/dSB/HbSB/HdSB at the paper's parameters, "
                             f"N_s in {list(grid)}, energy at the last step; one "
-                            f"hsb_run_batch call per (form, N_s)",
+                            f"hsb_run_batch call per (variant, dt, N_s)",
                 "seconds": res["seconds"], "spin_updates_per_s": res["spin_updates_per_s"],
                 "reference": "per instance, the best energy any trial reached",
                 "median_S": {f"{r['form']}@{r['Ns']}": r["median_S"] for r in res["rows"]},
                 "mean_P": {f"{r['form']}@{r['Ns']}": r["mean_P"] for r in res["rows"]},
-                "best_Ns": best, "best_median_S_HbSB_over_dSB": ratio}
+                "best_Ns": best, "best_median_S_HbSB_over_dSB": ratio,
+                "sweep": sweep_workload(Js[:20])}
+
+    def sweep_workload(Js):
+        # the parameter search of the Results on the first 20 of those
+        # instances: a 4 x 4 x 4 (dt, c1, gamma) grid per heated form, the
+        # points sharing dt in one hsb_run_batch call
+        from paper_2203_08361_amd import evaluate as ev
+
+        out = {}
+        with ev.GpuRunner(Js) as run:
+            for form, gammas in (("HdSB", (0.0, 0.03, 0.06, 0.12)), ("HbSB", (0.0, 0.25, 0.5, 0.75))):
+                log(f"sweep: {form}, {len(Js)} instances")
+                r = ev.sweep(Js, run, ev.preset(form).variant, 1000, (0.9, 1.0, 1.1, 1.25),
+                             (0.5, 0.6, 0.7, 0.8), gammas, R=256, seed=2, final_only=True)
+                out[form] = {"best": r["best"], "criterion": r["criterion"],
+                             "seconds": r["seconds"], "spin_updates_per_s": r["spin_updates_per_s"],
+                             "grid": "dt {0.9, 1.0, 1.1, 1.25} x c1 {0.5, 0.6, 0.7, 0.8} x "
+                                     f"gamma {list(gammas)}, 256 trials, N_s = 1000"}
+        return out
 
     if args.batch_only:
         print(json.dumps({"batch": batch_workload()}), flush=True)

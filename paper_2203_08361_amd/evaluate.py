@@ -22,11 +22,15 @@ Protocols (Results):
   - 700-spin set: the energy is evaluated at the last step only
     (final_only=True).
 
-The trials run on the GPU through hsb_run_batch (one call per form and N_s
-over all instances); `time_evolution` gives per-step T_inst (eq. (9)) and C
-traces of single runs, through the traces of hsb_run_ex.  A runner is any
-callable with GpuRunner's call signature, so other executions of the same
-trials can be evaluated by the same code.
+`sweep` is the parameter search of the Results: a grid of (dt, c1, gamma)
+ranked by median S, or by the average cut where no trial reaches E*.
+
+The trials run on the GPU through hsb_run_batch (one call per N_s and per
+group of forms sharing variant and dt, over all instances); `time_evolution`
+gives per-step T_inst (eq. (9)) and C traces of single runs, through the
+traces of hsb_run_ex.  A runner is any callable with GpuRunner's call
+signature, so other executions of the same trials can be evaluated by the
+same code.
 """
 from __future__ import annotations
 
@@ -90,8 +94,9 @@ def trial_seed(seed: int, form: int, Ns: int, instance: int) -> int:
 
 
 class GpuRunner:
-    """Runs trials on the GPU: one hsb_run_batch call per (form, N_s) over all
-    instances, one job of R trials per instance."""
+    """Runs trials on the GPU: one hsb_run_batch call per (form, N_s), or per
+    group of forms that share variant and dt, over all instances; one job of
+    R trials per (form, instance)."""
 
     def __init__(self, Js, precision: str = "mixed"):
         import torch
@@ -102,12 +107,22 @@ class GpuRunner:
 
     def __call__(self, p: Preset, Ns: int, R: int, seeds, c0s, interval: int,
                  amp: float = AMP) -> np.ndarray:
-        jobs = [{"instance": i, "R": R, "c0": c0s[i], "gamma": p.gamma, "seed": seeds[i]}
-                for i in range(len(self.ctxs))]
-        outs, _ = hsb.hsb_run_batch(self.ctxs, jobs, p.variant, Ns, A0, p.dt, init_amp=amp,
-                                    energy_interval=interval, return_best=True)
+        return self.run_group([p], Ns, R, [seeds], [c0s], interval, amp)[0]
+
+    def run_group(self, presets, Ns: int, R: int, seeds, c0s, interval: int,
+                  amp: float = AMP) -> np.ndarray:
+        """Several forms that share the variant and dt (c1 and gamma are per
+        job) in one batch call: [len(presets)][instances][R] energies."""
+        if len({(p.variant, p.dt) for p in presets}) != 1:
+            raise ValueError("a group shares its variant and dt")
+        n = len(self.ctxs)
+        jobs = [{"instance": i, "R": R, "c0": c0s[k][i], "gamma": p.gamma, "seed": seeds[k][i]}
+                for k, p in enumerate(presets) for i in range(n)]
+        outs, _ = hsb.hsb_run_batch(self.ctxs, jobs, presets[0].variant, Ns, A0, presets[0].dt,
+                                    init_amp=amp, energy_interval=interval, return_best=True)
         self._torch.cuda.synchronize()
-        return np.stack([o["energy"].cpu().numpy() for o in outs])
+        E = np.stack([o["energy"].cpu().numpy() for o in outs])
+        return E.reshape(len(presets), n, R)
 
     def close(self):
         for c in self.ctxs:
@@ -139,21 +154,40 @@ def evaluate(Js, runner, presets=PRESETS, Ns_list=(200, 500, 1000, 2000), R: int
              seed: int = 1, interval: int = 100, final_only: bool = False, reference=None,
              amp: float = AMP) -> dict:
     """Trials of every form in `presets` at every N_s of Ns_list on every
-    instance of Js, and their statistics (see the module docstring)."""
+    instance of Js, and their statistics (see the module docstring).  A runner
+    with a `run_group` method runs the forms that share variant and dt
+    together (the trials, and so the results, are the same)."""
     Js = [np.asarray(J) for J in Js]
     n = len(Js)
+    presets = list(presets)
+    if len({p.name for p in presets}) != len(presets):
+        raise ValueError("form names must differ")
+    c0s = [[c0_for(J, p.c1) for J in Js] for p in presets]
+    groups = {}
+    for fi, p in enumerate(presets):
+        key = (p.variant, p.dt) if hasattr(runner, "run_group") else fi
+        groups.setdefault(key, []).append(fi)
     energies = {}
     t0 = time.perf_counter()
-    for fi, p in enumerate(presets):
-        c0s = [c0_for(J, p.c1) for J in Js]
+    for members in groups.values():
         for Ns in Ns_list:
-            seeds = [trial_seed(seed, fi, Ns, i) for i in range(n)]
-            E = np.asarray(runner(p, Ns, R, seeds, c0s, Ns if final_only else interval, amp),
-                           dtype=np.float64)
-            if E.shape != (n, R):
-                raise ValueError(f"runner returned shape {E.shape}, expected {(n, R)}")
-            energies[p.name, Ns] = E
+            seeds = [[trial_seed(seed, fi, Ns, i) for i in range(n)] for fi in members]
+            iv = Ns if final_only else interval
+            if len(members) > 1:
+                E = np.asarray(runner.run_group([presets[fi] for fi in members], Ns, R, seeds,
+                                                [c0s[fi] for fi in members], iv, amp),
+                               dtype=np.float64)
+            else:
+                fi = members[0]
+                E = np.asarray(runner(presets[fi], Ns, R, seeds[0], c0s[fi], iv, amp),
+                               dtype=np.float64)[None]
+            if E.shape != (len(members), n, R):
+                raise ValueError(f"runner returned shape {E.shape[1:]}, expected {(n, R)}")
+            for k, fi in enumerate(members):
+                energies[presets[fi].name, Ns] = E[k]
     seconds = time.perf_counter() - t0
+    # rows in the order of the forms, then of N_s
+    energies = {(p.name, Ns): energies[p.name, Ns] for p in presets for Ns in Ns_list}
     if reference is None:
         ref = np.min(np.stack([E.min(axis=1) for E in energies.values()]), axis=0)
     else:
@@ -177,6 +211,29 @@ def evaluate(Js, runner, presets=PRESETS, Ns_list=(200, 500, 1000, 2000), R: int
             "trials": R, "protocol": "final" if final_only else f"best of every {interval}",
             "rows": rows, "best_Ns": best, "seconds": seconds,
             "spin_updates_per_s": updates / seconds if seconds > 0 else None}
+
+
+def sweep(Js, runner, variant: int, Ns: int, dts, c1s, gammas, R: int = 256, seed: int = 1,
+          interval: int = 100, final_only: bool = False, reference=None,
+          amp: float = AMP) -> dict:
+    """Parameter search of the Results: every (dt, c1, gamma) of the grid is
+    a form, evaluated at N_s steps on every instance against one common
+    reference; the forms are ranked by median S (smallest first) and, where S
+    is infinite for all (P = 0, as the paper found for bSB), by the average
+    cut value (largest first)."""
+    grid = [Preset(f"dt={dt:g},c1={c1:g},gamma={g:g}", variant, float(dt), float(c1), float(g))
+            for dt in dts for c1 in c1s for g in gammas]
+    res = evaluate(Js, runner, grid, (Ns,), R, seed, interval, final_only, reference, amp)
+    rows = sorted(res["rows"], key=lambda r: (r["median_S"], -r["mean_C"]))
+    by_name = {p.name: p for p in grid}
+    ranked = [{"dt": by_name[r["form"]].dt, "c1": by_name[r["form"]].c1,
+               "gamma": by_name[r["form"]].gamma, "median_S": r["median_S"],
+               "mean_P": r["mean_P"], "mean_C": r["mean_C"]} for r in rows]
+    criterion = "median S" if math.isfinite(ranked[0]["median_S"]) else "mean C (P = 0)"
+    return {"best": ranked[0], "criterion": criterion, "ranked": ranked, "Ns": Ns,
+            "points": len(grid), "seconds": res["seconds"],
+            "spin_updates_per_s": res["spin_updates_per_s"],
+            "reference_energy": res["reference_energy"]}
 
 
 def time_evolution(J, p: Preset, Ns: int, R: int = 1, seed: int = 1, amp: float = AMP,
@@ -212,6 +269,12 @@ def _parse(argv):
     ap.add_argument("--forms", default=",".join(p.name for p in PRESETS))
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--instance-seed", type=int, default=700)
+    ap.add_argument("--sweep", default=None, metavar="FORM",
+                    help="instead of the comparison: search (dt, c1, gamma) for FORM's "
+                         "variant at the first N_s over --dts, --c1s, --gammas")
+    ap.add_argument("--dts", default="0.9,1.0,1.1,1.25")
+    ap.add_argument("--c1s", default="0.5,0.6,0.7,0.8")
+    ap.add_argument("--gammas", default="0,0.03,0.06,0.12")
     ap.add_argument("--out", default=None, help="write the full result as JSON here")
     return ap.parse_args(argv)
 
@@ -230,6 +293,17 @@ def main(argv=None) -> int:
         N = a.N or 2000
         Js = [synth.sk_instance(N, 2000)]
         final_only = False
+    if a.sweep:
+        floats = lambda t: [float(v) for v in t.split(",")]  # noqa: E731
+        with GpuRunner(Js) as run:
+            res = sweep(Js, run, preset(a.sweep).variant, Ns_list[0], floats(a.dts),
+                        floats(a.c1s), floats(a.gammas), a.trials, a.seed, 100, final_only)
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(res, f)
+        print(json.dumps({k: res[k] for k in ("best", "criterion", "Ns", "points", "seconds",
+                                              "spin_updates_per_s")}))
+        return 0
     with GpuRunner(Js) as run:
         res = evaluate(Js, run, forms, Ns_list, a.trials, a.seed, 100, final_only)
     if a.out:

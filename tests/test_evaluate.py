@@ -132,3 +132,72 @@ def test_oracle_trials_reach_brute_force_ground_states():
             # eq. (14) against eq. (13) on a ground state: the maximum cut
             max_cut = oracle.cut(Js[i], bf[i][1])
             assert q["C_max"] <= max_cut and (k == 0 or q["C_max"] == max_cut)
+
+
+class GroupingOracleRunner(OracleRunner):
+    """The oracle runner with the grouped call (forms sharing variant and dt)."""
+
+    def __init__(self, Js):
+        super().__init__(Js)
+        self.groups = []
+
+    def run_group(self, presets, Ns, R, seeds, c0s, interval, amp):
+        assert len({(p.variant, p.dt) for p in presets}) == 1
+        self.groups.append(([p.name for p in presets], Ns))
+        return np.stack([self(p, Ns, R, seeds[k], c0s[k], interval, amp)
+                         for k, p in enumerate(presets)])
+
+
+def test_grouped_forms_give_the_same_evaluation():
+    """dSB and HdSB share variant and dt: a grouped runner runs them in one
+    call, with the same seeds, rows and statistics as one call per form."""
+    Js = [synth.sk_instance(12, 70 + i) for i in range(2)]
+    plain = ev.evaluate(Js, OracleRunner(Js), ev.PRESETS, (20, 40), R=8, seed=6)
+    grouped_runner = GroupingOracleRunner(Js)
+    grouped = ev.evaluate(Js, grouped_runner, ev.PRESETS, (20, 40), R=8, seed=6)
+    assert grouped_runner.groups == [(["dSB", "HdSB"], 20), (["dSB", "HdSB"], 40)]
+    assert [(r["form"], r["Ns"]) for r in grouped["rows"]] == \
+        [(p.name, ns) for p in ev.PRESETS for ns in (20, 40)]
+    strip = lambda r: {k: v for k, v in r.items() if k not in ("seconds", "spin_updates_per_s")}  # noqa: E731
+    assert strip(grouped) == strip(plain)
+
+
+def test_sweep_ranks_by_median_S_then_by_average_cut():
+    """A grid of 2 x 2 x 2 points with trial energies chosen per point: the
+    ranking follows median S, and with no trial at the reference (P = 0
+    everywhere) the average cut value; points sharing dt run in one call."""
+    J = synth.ferromagnet(4)  # E in {-6, 0, 2}
+    calls = []
+
+    def energies(p):
+        hits = {(1.0, 0.5, 0.0): 1, (1.0, 0.5, 0.1): 3, (1.0, 0.7, 0.0): 0,
+                (1.0, 0.7, 0.1): 2, (1.2, 0.5, 0.0): 4, (1.2, 0.5, 0.1): 0,
+                (1.2, 0.7, 0.0): 1, (1.2, 0.7, 0.1): 0}[p.dt, p.c1, p.gamma]
+        zeros = {(1.0, 0.7, 0.0): 3, (1.2, 0.5, 0.1): 1}.get((p.dt, p.c1, p.gamma), 0)
+        rest = 8 - hits - zeros
+        return np.array([[-6.0] * hits + [0.0] * zeros + [2.0] * rest])
+
+    class Runner:
+        def __call__(self, p, Ns, R, seeds, c0s, interval, amp):
+            calls.append([p.name])
+            return energies(p)
+
+        def run_group(self, presets, Ns, R, seeds, c0s, interval, amp):
+            calls.append([p.name for p in presets])
+            return np.stack([energies(p) for p in presets])
+
+    res = ev.sweep([J], Runner(), hsb.HSB_DSB, 50, (1.0, 1.2), (0.5, 0.7), (0.0, 0.1), R=8)
+    assert len(calls) == 2 and sorted(len(c) for c in calls) == [4, 4]
+    assert res["points"] == 8 and res["criterion"] == "median S"
+    assert (res["best"]["dt"], res["best"]["c1"], res["best"]["gamma"]) == (1.2, 0.5, 0.0)
+    assert res["best"]["median_S"] == pytest.approx(50 * math.log(0.01) / math.log(0.5))
+    order = [(q["dt"], q["c1"], q["gamma"]) for q in res["ranked"]]
+    assert order[:3] == [(1.2, 0.5, 0.0), (1.0, 0.5, 0.1), (1.0, 0.7, 0.1)]
+    # among the P = 0 points, the larger average cut first (more E = 0 trials)
+    assert order[5:] == [(1.0, 0.7, 0.0), (1.2, 0.5, 0.1), (1.2, 0.7, 0.1)]
+    # no trial at the reference: ranked by average cut alone
+    low = ev.sweep([J], Runner(), hsb.HSB_DSB, 50, (1.0, 1.2), (0.5, 0.7), (0.0, 0.1), R=8,
+                   reference=[-100.0])
+    assert low["criterion"] == "mean C (P = 0)"
+    means = [q["mean_C"] for q in low["ranked"]]
+    assert means == sorted(means, reverse=True)

@@ -126,3 +126,30 @@ def test_time_evolution_of_the_heated_ballistic_form():
     end_b = np.median(b["T_inst"][-1000:])
     say(f"median T_inst over the last 1000 steps: HbSB {end_h:.3e}, bSB {end_b:.3e}")
     assert end_h > 10 * end_b
+
+
+def test_dsb_sweep_equals_the_oracle_sweep():
+    """(dt, c1, gamma) search for dSB: 8 points in two grouped batch calls on
+    the GPU, one oracle run per point and instance; the same ranking."""
+    Js = [synth.sk_instance(N, 80 + N) for N in (64, 100, 130)]
+    say("dsb sweep")
+    grid = ((1.0, 1.1), (0.5, 0.7), (0.0, 0.06))
+    with ev.GpuRunner(Js) as run:
+        g = ev.sweep(Js, run, hsb.HSB_DSB, 80, *grid, R=16, seed=8)
+    o = ev.sweep(Js, OracleRunner(Js, oracle.FP32), hsb.HSB_DSB, 80, *grid, R=16, seed=8)
+    assert g["ranked"] == o["ranked"] and g["best"] == o["best"]
+    assert g["reference_energy"] == o["reference_energy"]
+
+
+def test_grouped_bsb_forms_equal_single_calls():
+    """Forms sharing variant and dt in one batch call give exactly the trials
+    of one call per form (bSB on the FP4 plan)."""
+    Js = [synth.sk_instance(N, 90 + N) for N in (100, 300)]
+    forms = [ev.Preset(f"g{g}", hsb.HSB_BSB, 1.1, c1, g) for c1 in (0.6, 0.9) for g in (0.0, 0.5)]
+    say("grouped bsb forms")
+    with ev.GpuRunner(Js) as run:
+        seeds = [[11 * k + i for i in range(2)] for k in range(4)]
+        c0s = [[ev.c0_for(J, p.c1) for J in Js] for p in forms]
+        grouped = run.run_group(forms, 150, 40, seeds, c0s, 50)
+        single = np.stack([run(p, 150, 40, seeds[k], c0s[k], 50) for k, p in enumerate(forms)])
+    assert np.array_equal(grouped, single)
