@@ -43,15 +43,17 @@ class _Params(ctypes.Structure):
                 ("variant", ctypes.c_int32), ("interval", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("return_best", ctypes.c_int32),
                 ("start_step", ctypes.c_int32), ("schedule_steps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("thermostat", ctypes.c_int32),
                 ("a0", ctypes.c_double), ("c0", ctypes.c_double), ("dt", ctypes.c_double),
-                ("gamma", ctypes.c_double), ("gamma_rep", ctypes.c_void_p)]
+                ("gamma", ctypes.c_double), ("gamma_rep", ctypes.c_void_p),
+                ("nh_inv_mass", ctypes.c_double), ("nh_temperature", ctypes.c_double),
+                ("xi0", ctypes.c_void_p)]
 
 
 class _Outputs(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("x", "y", "spins", "energy", "best_e", "final_e", "best_step", "trace_e",
-                 "trace_tinst")]
+                 "trace_tinst", "xi")]
 
 
 def lib():
@@ -177,8 +179,12 @@ def num_samples(steps: int, interval: int) -> int:
 def run(J, variant: int, a0: float, c0: float, dt: float, gamma, steps: int, R: int,
         seed: int = 0, amp: float = 0.1, interval: int = 100, precision: int = FP64,
         return_best: bool = True, x0=None, y0=None, r0: int = 0, traces: bool = False,
-        start_step: int = 0, schedule_steps: int = 0):
+        start_step: int = 0, schedule_steps: int = 0, nose_hoover=None, xi0=None):
     """Run R replicas (replica ids r0 .. r0+R-1) for `steps` steps.
+
+    nose_hoover=(inv_mass, T) replaces the constant heating rate gamma by the
+    thermostat variable xi of eqs. (6)-(8) (rate -xi; xi starts at -gamma or
+    at xi0 [R]); the result then has "xi", its value after the last step.
 
     start_step/schedule_steps resume a run: steps k = start_step .. start_step+steps-1
     of a pump schedule a(t_k) = a0 k / schedule_steps (0 means start_step + steps).
@@ -199,6 +205,13 @@ def run(J, variant: int, a0: float, c0: float, dt: float, gamma, steps: int, R: 
     P.interval, P.precision, P.return_best = interval, precision, int(bool(return_best))
     P.start_step, P.schedule_steps = start_step, schedule_steps
     P.a0, P.c0, P.dt = a0, c0, dt
+    xi_arr = None
+    if nose_hoover is not None:
+        P.thermostat = 1
+        P.nh_inv_mass, P.nh_temperature = float(nose_hoover[0]), float(nose_hoover[1])
+        if xi0 is not None:
+            xi_arr = np.ascontiguousarray(xi0, dtype=np.float64).reshape(R)
+            P.xi0 = xi_arr.ctypes.data
     g_arr = None
     if np.ndim(gamma) == 0:
         P.gamma = float(gamma)
@@ -219,9 +232,11 @@ def run(J, variant: int, a0: float, c0: float, dt: float, gamma, steps: int, R: 
     if traces:
         out["trace_e"] = np.empty((ns, R))
         out["trace_tinst"] = np.empty((ns, R))
+    if nose_hoover is not None:
+        out["xi"] = np.empty(R)
     O = _Outputs()
     for name in ("x", "y", "spins", "energy", "best_e", "final_e", "best_step", "trace_e",
-                 "trace_tinst"):
+                 "trace_tinst", "xi"):
         setattr(O, name, out[name].ctypes.data if name in out else None)
     rc = lib().orc_run(ctypes.byref(P), _p(J), _p(x0), _p(y0), ctypes.byref(O))
     if rc == -1:

@@ -28,6 +28,12 @@
  *     trials: evaluation every 100 steps, best value output); interval = Ns
  *     evaluates the last step only (Results, 700-spin instances).
  *   - instantaneous temperature T_inst = (1/N) sum_i y_i^2 ... eq. (9)
+ *   - the Nose-Hoover thermostat that heated SB is derived from (eqs. (6)-(8)):
+ *     the heating rate of eq. (22) is -xi, a variable of each run, with
+ *       xi(t_k+1) = xi(t_k) + (dt / M) (sum_i y_i(t_k)^2 - N T)
+ *     (explicit Euler on eq. (8), with the state at t_k as in eq. (22)); xi
+ *     starts at -gamma (or a given value).  1/M = 0 keeps xi = -gamma, which
+ *     is heated SB itself.
  *   - exhaustive ground state for small N (brute force over 2^N states).
  *
  * Readings where the paper is silent (each is listed in the design notes):
@@ -209,9 +215,11 @@ typedef struct {
     int32_t return_best;
     int32_t start_step;                 /* k0: first step index (resumed runs); 0 normally */
     int32_t schedule_steps;             /* Ns of a(t_k) = a0 k / Ns; 0 means start_step + steps */
-    int32_t reserved;
+    int32_t thermostat;                 /* 0: heating at rate gamma; 1: Nose-Hoover xi */
     double a0, c0, dt, gamma;
     const double *gamma_rep;            /* optional per-replica gamma [R] */
+    double nh_inv_mass, nh_temperature; /* 1/M >= 0 and T of eq. (8) (thermostat 1) */
+    const double *xi0;                  /* optional [R] initial xi (default -gamma) */
 } orc_params;
 
 typedef struct {
@@ -223,6 +231,7 @@ typedef struct {
     int32_t *best_step;     /* [R] step count of the best sample (optional) */
     double *trace_e;        /* [n_samples][R] energy at each sample (optional) */
     double *trace_tinst;    /* [n_samples][R] T_inst at each sample (optional) */
+    double *xi;             /* [R] xi after the last step (thermostat 1, optional) */
 } orc_outputs;
 
 /* Sample points of a run over steps k0 .. k1-1: step counts m in (k0, k1]
@@ -247,6 +256,8 @@ int orc_run(const orc_params *P, const double *J, const float *x0, const float *
     const int k0 = P->start_step, k1 = P->start_step + P->steps;
     const int Ns = P->schedule_steps > 0 ? P->schedule_steps : k1;
     if (N < 1 || R < 1 || P->steps < 0 || k0 < 0 || P->interval < 1 || Ns < k1) return -1;
+    if (P->thermostat != 0 && P->thermostat != 1) return -1;
+    if (P->thermostat == 1 && !(P->nh_inv_mass >= 0.0 && P->nh_temperature >= 0.0)) return -1;
 
     int rc = 0;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -267,6 +278,7 @@ int orc_run(const orc_params *P, const double *J, const float *x0, const float *
         }
         double best = INFINITY, last = NAN;
         int best_m = -1, sample = 0;
+        double xi = P->xi0 ? P->xi0[r] : -gamma; /* Nose-Hoover variable (thermostat 1) */
         for (int m = k0; m <= k1; ++m) {
             /* state after m steps is in (xd,yd) or (xf,yf) */
             if (is_sample(m, k0, k1, P->interval)) {
@@ -290,6 +302,16 @@ int orc_run(const orc_params *P, const double *J, const float *x0, const float *
                 last = e;
             }
             if (m == k1) break;
+            /* heating rate of this step: gamma, or -xi(t_k) under the thermostat,
+             * whose xi(t_k+1) integrates sum_i y_i(t_k)^2 (eq. (8)) */
+            double rate = gamma, sum_y2 = 0.0;
+            if (P->thermostat == 1) {
+                rate = -xi;
+                for (int i = 0; i < N; ++i) {
+                    double yi = P->precision == 1 ? (double)yf[i] : yd[i];
+                    sum_y2 += yi * yi;
+                }
+            }
             if (P->precision == 1) {
                 /* a(t_k) as a float: (a0*k)/Ns; p = a0 - a(t_k) */
                 float a0f = (float)P->a0;
@@ -297,11 +319,16 @@ int orc_run(const orc_params *P, const double *J, const float *x0, const float *
                 float p = a0f - ak;
                 for (int i = 0; i < N; ++i) xd[i] = xf[i];
                 orc_field(N, J, xd, P->variant, f);
-                orc_update32(N, f, p, a0f, (float)P->c0, (float)P->dt, (float)gamma, xf, yf);
+                orc_update32(N, f, p, a0f, (float)P->c0, (float)P->dt, (float)rate, xf, yf);
             } else {
                 double p = P->a0 - P->a0 * (double)m / (double)Ns;
                 orc_field(N, J, xd, P->variant, f);
-                orc_update64(N, f, p, P->a0, P->c0, P->dt, gamma, xd, yd);
+                orc_update64(N, f, p, P->a0, P->c0, P->dt, rate, xd, yd);
+            }
+            if (P->thermostat == 1) {
+                /* dt as the step used it: a float in the FP32 mirror */
+                const double dt = P->precision == 1 ? (double)(float)P->dt : P->dt;
+                xi = xi + dt * P->nh_inv_mass * (sum_y2 - (double)N * P->nh_temperature);
             }
         }
         (void)sample;
@@ -315,6 +342,7 @@ int orc_run(const orc_params *P, const double *J, const float *x0, const float *
         if (O->best_e) O->best_e[r] = best;
         if (O->final_e) O->final_e[r] = last;
         if (O->best_step) O->best_step[r] = best_m;
+        if (O->xi) O->xi[r] = xi;
         if (O->spins) memcpy(O->spins + (size_t)r * N, P->return_best ? best_s : s, (size_t)N);
         if (O->energy) O->energy[r] = P->return_best ? best : last;
         if (!isfinite(last)) {

@@ -8,7 +8,10 @@ What fixes each part independently of the oracle's code:
     unheated, wall-free step;
   - invariants: |x| <= 1 after every step, a wall hit leaves y' = gamma dt y;
   - exact global-flip and gauge symmetry of whole trajectories;
-  - brute-force ground states bound (and are reached by) the sampled energies.
+  - brute-force ground states bound (and are reached by) the sampled energies;
+  - the Nose-Hoover thermostat (eqs. (6)-(8)): heated SB at infinite mass, an
+    independent loop of its recursion for free particles, and the change of
+    xi over a run against the T_inst traces of the states before each step.
 """
 import json
 import os
@@ -202,3 +205,69 @@ def test_step_to_solution_eq15():
     assert oracle.step_to_solution(0.0, 1000) == np.inf
     assert oracle.step_to_solution(0.5, 1000) == pytest.approx(6643.856189774724, rel=1e-12)
     assert oracle.step_to_solution(0.995, 1000) == 1000.0
+
+
+# ---------------------------------------------------------------- eqs. (6)-(8)
+
+@pytest.mark.parametrize("precision", [oracle.FP64, oracle.FP32])
+@pytest.mark.parametrize("variant", [oracle.BSB, oracle.DSB])
+def test_nose_hoover_with_infinite_mass_is_heated_sb(precision, variant):
+    """1/M = 0 keeps xi at its start value -gamma: the heated SB of eqs.
+    (10)-(11) is the thermostat with a constant xi, bit for bit."""
+    J = synth.sk_instance(40, 5)
+    kw = dict(seed=3, amp=0.5, interval=25, precision=precision, traces=True)
+    heated = oracle.run(J, variant, 1.0, 0.08, 0.9, 0.07, 300, 6, **kw)
+    nh = oracle.run(J, variant, 1.0, 0.08, 0.9, 0.07, 300, 6, nose_hoover=(0.0, 0.4), **kw)
+    for k in ("x", "y", "best_e", "final_e", "best_step", "trace_e", "trace_tinst"):
+        assert np.array_equal(heated[k], nh[k]), k
+    assert np.all(nh["xi"] == -0.07)
+
+
+def test_nose_hoover_free_particles_follow_the_recursion():
+    """J = 0 and a0 = 0: x stays put and eqs. (7)-(8) leave
+    y(t_k+1) = y(t_k) - xi(t_k) y(t_k) dt,
+    xi(t_k+1) = xi(t_k) + (dt/M) (sum_i y_i(t_k)^2 - N T),
+    computed here by an independent loop.  Started below the temperature T,
+    xi turns negative and T_inst rises (the heating described after eq. (9))."""
+    N, R, K, dt, inv_m, T = 5, 3, 40, 0.5, 0.2, 0.3
+    J = np.zeros((N, N))
+    rng = np.random.default_rng(1)
+    x0 = rng.uniform(-0.5, 0.5, (R, N))
+    y0 = rng.uniform(-0.2, 0.2, (R, N))  # T_inst(0) <= 0.04 < T
+    xi0 = np.array([0.0, 0.1, -0.05])
+    o = oracle.run(J, oracle.BSB, 0.0, 0.3, dt, 0.0, K, R, x0=x0, y0=y0, nose_hoover=(inv_m, T),
+                   xi0=xi0, precision=oracle.FP64)
+    y = y0.astype(np.float32).astype(np.float64)
+    xi = xi0.copy()
+    xis = [xi.copy()]
+    for _ in range(K):
+        s = (y * y).sum(axis=1)
+        y = y - xi[:, None] * y * dt
+        xi = xi + dt * inv_m * (s - N * T)
+        xis.append(xi.copy())
+    np.testing.assert_allclose(o["y"], y, rtol=1e-12)
+    np.testing.assert_allclose(o["xi"], xi, rtol=1e-12, atol=1e-15)
+    assert np.array_equal(o["x"], x0.astype(np.float32).astype(np.float64))
+    assert np.all(np.array(xis)[1] < xi0) and np.all(np.array(xis)[5] < 0)
+    # while T_inst < T the thermostat heats: T_inst after 6 steps is larger
+    early = oracle.run(J, oracle.BSB, 0.0, 0.3, dt, 0.0, 6, R, x0=x0, y0=y0,
+                       nose_hoover=(inv_m, T), xi0=xi0, precision=oracle.FP64)
+    t0 = (y0.astype(np.float32).astype(np.float64) ** 2).mean(axis=1)
+    assert np.all((early["y"] ** 2).mean(axis=1) > t0)
+
+
+@pytest.mark.parametrize("variant", [oracle.BSB, oracle.DSB])
+def test_nose_hoover_xi_integrates_the_states_before_each_step(variant):
+    """Summed over K steps, eq. (8) gives xi(t_K) - xi(t_0) = (dt/M) sum over
+    k = 0 .. K-1 of (N T_inst(t_k) - N T): the T_inst traces of the states
+    after 0 .. K-1 steps (not 1 .. K) account for the change of xi."""
+    N, R, K, dt, inv_m, T = 60, 4, 120, 0.8, 0.01, 0.05
+    J = synth.sk_instance(N, 9)
+    kw = dict(seed=4, amp=0.6, precision=oracle.FP64, nose_hoover=(inv_m, T))
+    first = oracle.run(J, variant, 1.0, 0.1, dt, 0.02, 0, R, interval=1, traces=True, **kw)
+    o = oracle.run(J, variant, 1.0, 0.1, dt, 0.02, K, R, interval=1, traces=True, **kw)
+    tinst = np.concatenate([first["trace_tinst"], o["trace_tinst"]])  # states 0 .. K
+    want = -0.02 + dt * inv_m * (N * tinst[:K] - N * T).sum(axis=0)
+    np.testing.assert_allclose(o["xi"], want, rtol=1e-10)
+    wrong = -0.02 + dt * inv_m * (N * tinst[1:] - N * T).sum(axis=0)
+    assert not np.allclose(o["xi"], wrong, rtol=1e-6)
