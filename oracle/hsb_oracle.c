@@ -32,8 +32,8 @@
  *     the heating rate of eq. (22) is -xi, a variable of each run, with
  *       xi(t_k+1) = xi(t_k) + (dt / M) (sum_i y_i(t_k)^2 - N T)
  *     (explicit Euler on eq. (8), with the state at t_k as in eq. (22)); xi
- *     starts at -gamma (or a given value).  1/M = 0 keeps xi = -gamma, which
- *     is heated SB itself.
+ *     starts at -gamma (or a given value; gamma rounded to float in the FP32
+ *     mirror).  1/M = 0 keeps xi = -gamma, which is heated SB itself.
  *   - exhaustive ground state for small N (brute force over 2^N states).
  *
  * Readings where the paper is silent (each is listed in the design notes):
@@ -278,7 +278,9 @@ int orc_run(const orc_params *P, const double *J, const float *x0, const float *
         }
         double best = INFINITY, last = NAN;
         int best_m = -1, sample = 0;
-        double xi = P->xi0 ? P->xi0[r] : -gamma; /* Nose-Hoover variable (thermostat 1) */
+        /* Nose-Hoover variable (thermostat 1); the FP32 mirror holds gamma as a
+         * float, as its heated step does */
+        double xi = P->xi0 ? P->xi0[r] : -(P->precision == 1 ? (double)(float)gamma : gamma);
         for (int m = k0; m <= k1; ++m) {
             /* state after m steps is in (xd,yd) or (xf,yf) */
             if (is_sample(m, k0, k1, P->interval)) {
