@@ -93,6 +93,10 @@ def main() -> int:
                     help="run only the batched uneven-instance workload")
     ap.add_argument("--no-gaussian", action="store_true",
                     help="skip the Gaussian-coupling workload of the default run")
+    ap.add_argument("--no-thermostat", action="store_true",
+                    help="skip the Nose-Hoover thermostat run of the default run")
+    ap.add_argument("--thermostat-only", action="store_true",
+                    help="run only the Nose-Hoover thermostat comparison")
     ap.add_argument("--no-evaluation", action="store_true",
                     help="skip the 700-spin evaluation of the four SB forms")
     ap.add_argument("--evaluation-only", action="store_true",
@@ -305,6 +309,33 @@ def main() -> int:
                 "fp64_energy_check": f"eq. (1) of the returned spins of {len(rel)} replicas "
                                      f"(every 64th) recomputed by the FP64 oracle"}
 
+    def thermostat_workload():
+        """The Nose-Hoover thermostat (eqs. (6)-(8)) on the bench instance: dSB,
+        R = 1024, 10^4 steps on the integer-digit plan (the thermostat's per-step
+        sum over all spins runs on the per-step plans), against the heated run
+        on the same plan."""
+        cd = hsb.Context(J, precision="digits", init_amp=0.1, energy_interval=100)
+        # large mass (the paper's observation: xi kept negative, its rate small):
+        # xi falls by at most N T / M per step, so it stays above -0.015 and
+        # |xi| dt < 1 (a smaller M lets wall-pinned spins' y grow without bound)
+        nh = (1e-8, 0.02)
+        out = {}
+        for name, kw in (("heated", {}), ("nose_hoover", {"nose_hoover": nh})):
+            cd.run_ex(hsb.HSB_DSB, 200, R, A0, c0, DT, GAMMA, 100, schedule_steps=Ns, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = cd.run_ex(hsb.HSB_DSB, Ns, R, A0, c0, DT, GAMMA, 1, **kw)
+            torch.cuda.synchronize()
+            out[name] = (1e3 * (time.perf_counter() - t0), cd.last_plan(), o)
+        xi = out["nose_hoover"][2]["xi"].cpu().numpy()
+        cd.close()
+        ms_h, ms_n = out["heated"][0], out["nose_hoover"][0]
+        return {"workload": f"SK +-1 N={N}, R={R}, {Ns} steps dSB, Nose-Hoover 1/M={nh[0]}, "
+                            f"T={nh[1]}, xi from -{GAMMA}",
+                "plan": out["nose_hoover"][1], "value": N * R * Ns / (ms_n * 1e-3),
+                "ms_per_run": ms_n, "heated_ms_per_run": ms_h, "overhead": ms_n / ms_h - 1.0,
+                "xi_final_range": [float(xi.min()), float(xi.max())]}
+
     def evaluation_workload():
         # the 700-spin comparison of the Results: 100 instances, the energy at
         # the last step, the four forms at the paper's parameters over a range
@@ -353,6 +384,10 @@ def main() -> int:
         print(json.dumps({"batch": batch_workload()}), flush=True)
         ctx.close()
         return 0
+    if args.thermostat_only:
+        print(json.dumps({"thermostat": thermostat_workload()}), flush=True)
+        ctx.close()
+        return 0
     if args.evaluation_only:
         print(json.dumps({"evaluation": evaluation_workload()}), flush=True)
         ctx.close()
@@ -388,6 +423,8 @@ def main() -> int:
         result["gaussian"] = gaussian_workload()
     if args.variant == "dsb" and not args.no_batch:
         result["batch"] = batch_workload()
+    if args.variant == "dsb" and not args.no_thermostat:
+        result["thermostat"] = thermostat_workload()
     if args.variant == "dsb" and not args.no_evaluation:
         result["evaluation"] = evaluation_workload()
 

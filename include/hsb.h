@@ -191,7 +191,8 @@ typedef struct {
     int32_t R;              /* replicas, >= 1 */
     int32_t start_step;     /* first step index k0 of this call, >= 0 (resume) */
     int32_t schedule_steps; /* Ns defining a(t_k) = a0 k / Ns; 0 means start_step + steps */
-    int32_t reserved0;
+    int32_t thermostat;     /* hsb_thermostat: HSB_THERMO_HEAT (0, the zero fill) or
+                               HSB_THERMO_NOSE_HOOVER */
     float a0, c0, dt, gamma;
     uint64_t seed;
     const float *gamma_rep; /* optional [R] per-replica gamma (overrides gamma) */
@@ -209,7 +210,31 @@ typedef struct {
     double *trace_tinst;    /* optional [n_samples][R]: the instantaneous temperature
                                T_inst = (1/N) sum_i y_i^2 of eq. (9) at the same points,
                                summed in FP64 */
+    /* HSB_THERMO_NOSE_HOOVER only (must be 0 / NULL otherwise): */
+    double nh_inv_mass;     /* 1/M >= 0 of eq. (8), finite; 0 keeps xi constant */
+    double nh_temperature;  /* T >= 0 of eq. (8), finite */
+    const double *xi0;      /* optional [R] xi at start_step; default -gamma (per replica) */
+    double *xi_out;         /* optional [R] xi after the last step (to resume) */
 } hsb_run_args;
+
+/*
+ * hsb_thermostat -- what drives the heating term of eq. (22).
+ *
+ *   HSB_THERMO_HEAT         the constant rate gamma (per replica with gamma_rep):
+ *                           heated SB, eqs. (10)-(11) and (16)-(22).
+ *   HSB_THERMO_NOSE_HOOVER  the Nose-Hoover thermostat that heated SB comes from,
+ *                           eqs. (6)-(8): every replica carries xi (FP64); step k
+ *                           heats at the rate -xi(t_k) (rounded to float, in
+ *                           eq. (22)'s place) and then
+ *                             xi(t_k+1) = xi(t_k) + (dt/M)(sum_i y_i(t_k)^2 - N T),
+ *                           explicit Euler on eq. (8) with the state before the
+ *                           step.  xi starts at -gamma, so 1/M = 0 is exactly
+ *                           heated SB.  The thermostat needs the sum over all
+ *                           spins every step, which the persistent FP4 plan does
+ *                           not form: where AUTO or MIXED would take that plan,
+ *                           the integer-digit plan runs instead.
+ */
+typedef enum { HSB_THERMO_HEAT = 0, HSB_THERMO_NOSE_HOOVER = 1 } hsb_thermostat;
 
 /*
  * hsb_run_ex -- hsb_run with device buffers, a caller stream, per-replica gamma,

@@ -38,6 +38,7 @@ struct I8Run {
     int R;
     int k0, k1, Ns, interval;
     float a0, c0, dt;
+    const NHState *nh = nullptr;  // Nose-Hoover thermostat: rate -xi(t_k) per step
 };
 
 // Run steps k0..k1-1 of the digit plan on the state in `b` (X, Y in

@@ -454,6 +454,10 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
         const float pk = a0 - ak;
         const int8_t *xin = p->xd + cur * set;
         int8_t *xout = p->xd + (cur ^ 1) * set;
+        if (run.nh) {  // this step's heating rate -xi(t_k) from the state before it
+            e = launch_nh_step(*run.nh, b.Y, b.gamma, run.N, run.R, Rpad, s);
+            if (e != hipSuccess) return derr(HSB_EDEVICE, "thermostat: %s", hipGetErrorString(e));
+        }
         e = timer.begin(s);
         if (e == hipSuccess) {
             if (p->njd == 1)

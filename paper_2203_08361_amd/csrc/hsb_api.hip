@@ -64,6 +64,8 @@ struct hsb_ctx {
     hsb::BatchJob *bjobs = nullptr;        // device job table of a batch class
     size_t bjobs_cap = 0;
     int32_t *d_flag = nullptr;             // start-state bound check
+    hsb::NHState nh{};                     // thermostat of the current run
+    int nh_cap = 0;                        // its capacity in columns
     std::vector<float> hJ;      // host copy kept for lazy device re-layouts
     // options
     double init_amp = 0.1;
@@ -205,6 +207,8 @@ extern "C" void hsb_destroy(hsb_ctx *h) {
     hsb::free_state_bufs(h->bstate);
     if (h->bjobs) (void)hipFree(h->bjobs);
     if (h->d_flag) (void)hipFree(h->d_flag);
+    if (h->nh.xi) (void)hipFree(h->nh.xi);
+    if (h->nh.part) (void)hipFree(h->nh.part);
     graph_drop(h);
     if (h->gev_in) (void)hipEventDestroy(h->gev_in);
     if (h->gev_out) (void)hipEventDestroy(h->gev_out);
@@ -371,6 +375,22 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
     }
     HIP_TRY(hsb::launch_fill_gamma(b.gamma, a->gamma_rep, a->gamma, R, Rpad, s));
     HIP_TRY(hsb::launch_reset_tracking(b, Rpad, s));
+    const bool nh = a->thermostat == HSB_THERMO_NOSE_HOOVER;
+    if (nh) {
+        if (h->nh_cap < Rpad) {
+            if (h->nh.xi) (void)hipFree(h->nh.xi);
+            if (h->nh.part) (void)hipFree(h->nh.part);
+            h->nh.xi = h->nh.part = nullptr;
+            h->nh_cap = 0;
+            HIP_TRY(hipMalloc((void **)&h->nh.xi, sizeof(double) * Rpad));
+            HIP_TRY(hipMalloc((void **)&h->nh.part, sizeof(double) * hsb::kNHGroups * Rpad));
+            h->nh_cap = Rpad;
+        }
+        // dt as the step kernels use it: a float
+        h->nh.c = (double)a->dt * a->nh_inv_mass;
+        h->nh.NT = (double)N * a->nh_temperature;
+        HIP_TRY(hsb::launch_nh_init(h->nh, a->xi0, b.gamma, R, s));
+    }
 
     b.trace_e = a->trace_energy;
     b.trace_t = a->trace_tinst;
@@ -421,6 +441,7 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
         ir.N = N; ir.Nst = Npad; ir.Rpad = Rpad; ir.R = R;
         ir.k0 = k0; ir.k1 = k1; ir.Ns = Ns; ir.interval = interval;
         ir.a0 = a0; ir.c0 = c0; ir.dt = dt;
+        ir.nh = nh ? &h->nh : nullptr;
         rc = hsb::i8_run(h->i8, ir, b, h->dJ, s, h->timer);
         if (rc != HSB_OK) return fail(rc, "%s", hsb::i8_error());
     } else if (plan == PLAN_FP4) {
@@ -449,6 +470,8 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
                 // a(t_k) = a0 k / Ns in single precision; p = a0 - a(t_k)
                 const float ak = (a0 * (float)k) / (float)Ns;
                 const float p = a0 - ak;
+                if (nh)  // this step's heating rate -xi(t_k) from the state before it
+                    HIP_TRY(hsb::launch_nh_step(h->nh, b.Y, b.gamma, N, R, Rpad, s));
                 HIP_TRY(h->timer.begin(s));
                 HIP_TRY(hsb::launch_step_fp32(a->variant, h->dJ, b.B[cur], b.B[cur ^ 1], b.X, b.Y,
                                               b.gamma, Npad, Rpad, p, c0, dt, a0dt, s));
@@ -465,6 +488,7 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
     }
     HIP_TRY(hsb::launch_output(b, N, R, Rpad, h->return_best, a->spins, a->energy, a->x_out,
                                a->y_out, a->best_energy, a->final_energy, a->best_step, s));
+    if (nh && a->xi_out) HIP_TRY(hsb::launch_copy_f64(a->xi_out, h->nh.xi, R, s));
     // status: bit 0 a non-finite state, bit 1 an exchange wait of the
     // persistent kernels that timed out
     return HSB_OK;
@@ -479,6 +503,11 @@ std::vector<uint64_t> run_key(const hsb_ctx *h, const hsb_run_args *a, int plan)
         return (uint64_t)u;
     };
     auto pb = [](const void *q) { return (uint64_t)(uintptr_t)q; };
+    auto db = [](double v) {
+        uint64_t u;
+        std::memcpy(&u, &v, sizeof u);
+        return u;
+    };
     uint64_t amp;
     std::memcpy(&amp, &h->init_amp, sizeof amp);
     // (not the seed: the queued work reads it from the context's pinned slot)
@@ -486,7 +515,8 @@ std::vector<uint64_t> run_key(const hsb_ctx *h, const hsb_run_args *a, int plan)
             (uint64_t)a->schedule_steps, fb(a->a0), fb(a->c0), fb(a->dt), fb(a->gamma),
             pb(a->gamma_rep), pb(a->x0), pb(a->y0), pb(a->x_out), pb(a->y_out), pb(a->spins),
             pb(a->energy), pb(a->best_energy), pb(a->final_energy), pb(a->best_step),
-            pb(a->trace_energy), pb(a->trace_tinst), amp,
+            pb(a->trace_energy), pb(a->trace_tinst), (uint64_t)a->thermostat, db(a->nh_inv_mass),
+            db(a->nh_temperature), pb(a->xi0), pb(a->xi_out), amp,
             (uint64_t)h->interval, (uint64_t)h->return_best, (uint64_t)h->local_exchange,
             (uint64_t)plan, pb(h->b.X), (uint64_t)h->Rpad_cap, h->state_gen, pb(h->pj),
             h->pj ? hsb::persistent_gen(h->pj) : 0};
@@ -578,9 +608,21 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
     if (!a->spins || !a->energy) return fail(HSB_EINVAL, "spins and energy are required");
     if ((a->x0 == nullptr) != (a->y0 == nullptr))
         return fail(HSB_EINVAL, "x0 and y0 must be given together");
+    if (a->thermostat != HSB_THERMO_HEAT && a->thermostat != HSB_THERMO_NOSE_HOOVER)
+        return fail(HSB_EINVAL, "thermostat must be HSB_THERMO_HEAT (0) or HSB_THERMO_NOSE_HOOVER (1)");
+    if (a->thermostat == HSB_THERMO_NOSE_HOOVER) {
+        if (!(std::isfinite(a->nh_inv_mass) && a->nh_inv_mass >= 0.0 &&
+              std::isfinite(a->nh_temperature) && a->nh_temperature >= 0.0))
+            return fail(HSB_EINVAL, "nh_inv_mass and nh_temperature must be finite and >= 0");
+    } else if (a->nh_inv_mass != 0.0 || a->nh_temperature != 0.0 || a->xi0 || a->xi_out) {
+        return fail(HSB_EINVAL, "nh_inv_mass, nh_temperature, xi0 and xi_out need "
+                                "HSB_THERMO_NOSE_HOOVER");
+    }
     int plan = 0;
     int rc = choose_plan(h, a->variant, &plan);
     if (rc != HSB_OK) return rc;
+    if (a->thermostat == HSB_THERMO_NOSE_HOOVER && plan == PLAN_FP4)
+        plan = h->N <= hsb::i8_max_n() ? PLAN_DIGITS : PLAN_FP32;
     HIP_TRY(hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)a->stream;
     const int R = a->R;

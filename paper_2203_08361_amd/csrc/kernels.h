@@ -106,6 +106,21 @@ hipError_t launch_make_operand(float *B, const float *X, int variant, int Npad, 
 // g[r] = gamma_rep[r] (or gamma) for r < R, 0 for R <= r < Rpad
 hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int R, int Rpad,
                              hipStream_t s);
+// Nose-Hoover thermostat of a run (eqs. (6)-(8)): xi [>= R] in FP64 and the
+// partial sums of y^2 [kNHGroups][Rpad]; c = dt / M and NT = N T.
+constexpr int kNHGroups = 16;
+struct NHState {
+    double *xi = nullptr, *part = nullptr;
+    double c = 0.0, NT = 0.0;
+};
+// xi = xi0 (device [R]) if given, else -gamma[r]
+hipError_t launch_nh_init(const NHState &nh, const double *xi0, const float *gamma, int R,
+                          hipStream_t s);
+// before step k: gamma[r] = fl32(-xi(t_k)); xi(t_k+1) = xi(t_k) + c (sum_i y_i(t_k)^2 - NT)
+// over rows [0, N) of Y [.][Rpad]
+hipError_t launch_nh_step(const NHState &nh, const float *Y, float *gamma, int N, int R, int Rpad,
+                          hipStream_t s);
+hipError_t launch_copy_f64(double *dst, const double *src, int n, hipStream_t s);
 // allocation of the run state for Npad rows and Rpad columns (all or nothing);
 // without the FP32 plan's operand and energy buffers (B, epart) if !fp32_plan
 hipError_t alloc_state(StateBufs &b, int Npad, int Rpad, bool fp32_plan = true);

@@ -58,6 +58,53 @@ __global__ void k_fill_gamma(float *__restrict__ g, const float *__restrict__ ga
     g[r] = r < R ? (gamma_rep ? gamma_rep[r] : gamma) : 0.0f;
 }
 
+// Nose-Hoover thermostat (eqs. (6)-(8)): xi per replica, in FP64.  The
+// heating rate of step k is -xi(t_k) rounded to float, written into the
+// per-replica gamma array that the step kernels read; then
+//   xi(t_k+1) = xi(t_k) + c (sum_i y_i(t_k)^2 - N T),  c = dt / M,
+// with the sum of the state before the step (explicit Euler on eq. (8)).
+// Start value: xi0[r], or -gamma_r (so that 1/M = 0 is heated SB itself).
+__global__ void k_nh_init(double *__restrict__ xi, const double *__restrict__ xi0,
+                          const float *__restrict__ g, int R) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R) xi[r] = xi0 ? xi0[r] : -(double)g[r];
+}
+
+// Partial sums of y^2 of row group blockIdx.y (rows [y rows_per, ...)) for 64
+// replicas: 4 waves split the group's rows, combined in a fixed order.
+__global__ __launch_bounds__(256) void k_nh_partial(const float *__restrict__ Y, int N, int Rpad,
+                                                    int rows_per, double *__restrict__ part) {
+    __shared__ double s_p[4][64];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = blockIdx.x * 64 + l;
+    const int i0 = blockIdx.y * rows_per;
+    const int i1 = i0 + rows_per < N ? i0 + rows_per : N;
+    double t = 0.0;
+    for (int i = i0 + w; i < i1; i += 4) {
+        const double y = Y[(size_t)i * Rpad + r];
+        t += y * y;
+    }
+    s_p[w][l] = t;
+    __syncthreads();
+    if (w == 0) part[(size_t)blockIdx.y * Rpad + r] = ((s_p[0][l] + s_p[1][l]) + s_p[2][l]) + s_p[3][l];
+}
+
+__global__ void k_nh_update(const double *__restrict__ part, int groups, int R, int Rpad,
+                            double *__restrict__ xi, float *__restrict__ g, double c, double NT) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double S = 0.0;
+    for (int q = 0; q < groups; ++q) S += part[(size_t)q * Rpad + r];
+    const double x = xi[r];
+    g[r] = (float)(-x);
+    xi[r] = x + c * (S - NT);
+}
+
+__global__ void k_copy_f64(double *__restrict__ dst, const double *__restrict__ src, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 __global__ void k_reset_tracking(double *best_e, double *last_e, int32_t *best_step, int32_t *bad,
                                  int32_t *status, int Rpad) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -488,6 +535,27 @@ hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int 
                              hipStream_t s) {
     hipLaunchKernelGGL(k_fill_gamma, dim3(cdiv(Rpad, 256)), dim3(256), 0, s, g, gamma_rep, gamma,
                        R, Rpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_nh_init(const NHState &nh, const double *xi0, const float *gamma, int R,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_nh_init, dim3(cdiv(R, 256)), dim3(256), 0, s, nh.xi, xi0, gamma, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_nh_step(const NHState &nh, const float *Y, float *gamma, int N, int R, int Rpad,
+                          hipStream_t s) {
+    const int rows_per = (N + kNHGroups - 1) / kNHGroups;
+    hipLaunchKernelGGL(k_nh_partial, dim3(cdiv(Rpad, 64), kNHGroups), dim3(256), 0, s, Y, N, Rpad,
+                       rows_per, nh.part);
+    hipLaunchKernelGGL(k_nh_update, dim3(cdiv(R, 256)), dim3(256), 0, s, nh.part, kNHGroups, R,
+                       Rpad, nh.xi, gamma, nh.c, nh.NT);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(double *dst, const double *src, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_f64, dim3(cdiv(n, 256)), dim3(256), 0, s, dst, src, n);
     return hipGetLastError();
 }
 

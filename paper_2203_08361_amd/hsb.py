@@ -24,6 +24,7 @@ HSB_OPT_GRAPH_LAUNCHES = 10
 HSB_PLAN_FP32, HSB_PLAN_FP4, HSB_PLAN_DIGITS = 0, 1, 2
 PLAN_NAMES = {HSB_PLAN_FP32: "fp32", HSB_PLAN_FP4: "fp4", HSB_PLAN_DIGITS: "digits"}
 HSB_PREC_AUTO, HSB_PREC_FP32, HSB_PREC_MIXED, HSB_PREC_DIGITS = 0, 1, 2, 3
+HSB_THERMO_HEAT, HSB_THERMO_NOSE_HOOVER = 0, 1
 
 EXPORTED = ("hsb_create", "hsb_destroy", "hsb_last_error", "hsb_set_option", "hsb_get_option",
             "hsb_run", "hsb_run_ex", "hsb_plan_info", "hsb_run_batch", "hsb_num_samples")
@@ -42,7 +43,7 @@ class hsb_run_args(ctypes.Structure):
         ("struct_size", ctypes.c_size_t),
         ("variant", ctypes.c_int32), ("steps", ctypes.c_int32), ("R", ctypes.c_int32),
         ("start_step", ctypes.c_int32), ("schedule_steps", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("thermostat", ctypes.c_int32),
         ("a0", ctypes.c_float), ("c0", ctypes.c_float), ("dt", ctypes.c_float),
         ("gamma", ctypes.c_float),
         ("seed", ctypes.c_uint64),
@@ -53,6 +54,8 @@ class hsb_run_args(ctypes.Structure):
         ("best_step", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
         ("trace_energy", ctypes.c_void_p), ("trace_tinst", ctypes.c_void_p),
+        ("nh_inv_mass", ctypes.c_double), ("nh_temperature", ctypes.c_double),
+        ("xi0", ctypes.c_void_p), ("xi_out", ctypes.c_void_p),
     ]
 
 
@@ -175,7 +178,7 @@ def hsb_num_samples(h, start_step: int, steps: int) -> int:
 
 def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=None, x0=None,
                y0=None, start_step=0, schedule_steps=0, want_state=False, stream=None,
-               allow_numeric=False, out=None, traces=False):
+               allow_numeric=False, out=None, traces=False, nose_hoover=None, xi0=None):
     """Device run through hsb_run_ex.  Tensors are torch CUDA tensors.
 
     Returns a dict of device tensors: spins [R][N] int8, energy/best_energy/
@@ -183,6 +186,10 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
     want_state, and trace_energy/trace_tinst [n_samples][R] float64 (energy
     and T_inst of eq. (9) at every sample point) when traces.  `out` may pass
     preallocated tensors under the same keys.
+
+    nose_hoover=(inv_mass, T) runs the thermostat of eqs. (6)-(8) in place of
+    the constant heating rate (xi starts at -gamma, or at xi0 [R] float64);
+    the result then has xi [R] float64, its value after the last step.
     """
     import torch
 
@@ -220,6 +227,14 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
         return t.data_ptr()
 
     a.gamma_rep = dptr(gamma_rep, torch.float32, (R,))
+    if nose_hoover is not None:
+        a.thermostat = HSB_THERMO_NOSE_HOOVER
+        a.nh_inv_mass, a.nh_temperature = float(nose_hoover[0]), float(nose_hoover[1])
+        o.setdefault("xi", torch.empty(R, dtype=torch.float64, device=dev))
+        a.xi_out = o["xi"].data_ptr()
+        a.xi0 = dptr(xi0, torch.float64, (R,))
+    elif xi0 is not None:
+        raise ValueError("xi0 needs nose_hoover")
     a.x0 = dptr(x0, torch.float32, (R, N))
     a.y0 = dptr(y0, torch.float32, (R, N))
     a.x_out = o["x"].data_ptr() if want_state else None

@@ -1,0 +1,173 @@
+"""Nose-Hoover thermostat (eqs. (6)-(8)) through hsb_run_ex (marked `gpu`).
+
+Bars:
+  - dSB: the state is bitwise the oracle's FP32 mirror on the FP32 and the
+    integer-digit plans.  xi is summed in another order than the oracle's
+    (FP64 partial sums of y^2), so it agrees to 1e-12 relative; the rate the
+    step uses, xi rounded to float, is then the same except in the rare case
+    of a rounding boundary between the two values, which these seeded runs
+    do not meet.
+  - bSB (start amplitude 0.1, as in the other bSB bars): the 1e-5 bar on x
+    and y after 1 and 50 steps against the FP64 oracle, and xi to 1e-6
+    relative.
+  - 1/M = 0 is heated SB bitwise; a run split into two calls (xi_out fed back
+    as xi0) equals one call; where MIXED would take the FP4 plan the digit
+    plan runs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2203_08361_amd import hsb  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    hsb.load_library()
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+# 1/M, T: xi moves from -gamma = -0.02 to between 0.01 and 0.16 (the
+# thermostat cools) and the runs stay finite; at 1/M = 2e-3 xi and y diverge
+NH = (1e-4, 0.05)
+
+
+GAMMA = float(np.float32(0.02))  # exact in float: both sides start xi at -GAMMA
+
+
+def gpu(J, variant, plan, steps, R, gamma=GAMMA, nose_hoover=NH, seed=1, amp=0.3, **kw):
+    N = J.shape[0]
+    with hsb.Context(J, precision=plan, init_amp=amp, energy_interval=50) as ctx:
+        out = ctx.run_ex(variant, steps, R, 1.0, 0.5 / np.sqrt(N), 1.0, gamma, seed,
+                         want_state=True, nose_hoover=nose_hoover, **kw)
+        torch.cuda.synchronize()
+        res = {k: v.cpu().numpy() for k, v in out.items() if hasattr(v, "cpu")}
+        res["plan"] = ctx.last_plan()
+    return res
+
+
+def orc(J, variant, precision, steps, R, gamma=GAMMA, nose_hoover=NH, seed=1, amp=0.3, **kw):
+    N = J.shape[0]
+    return oracle.run(J, variant, 1.0, np.float32(0.5 / np.sqrt(N)), 1.0, gamma, steps, R,
+                      seed=seed, amp=amp, interval=50, precision=precision,
+                      nose_hoover=nose_hoover, **kw)
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b, axis=-1) / np.linalg.norm(b, axis=-1)
+
+
+@pytest.mark.parametrize("plan,expect", [("fp32", "fp32"), ("digits", "digits"),
+                                         ("mixed", "digits")])
+@pytest.mark.parametrize("N,R,steps", [(100, 16, 400), (257, 33, 300)])
+def test_dsb_thermostat_equals_mirror(plan, expect, N, R, steps):
+    J = synth.sk_instance(N, 100 + N)
+    say("dsb thermostat", plan, N, R, steps)
+    g = gpu(J, hsb.HSB_DSB, plan, steps, R)
+    assert g["plan"] == expect
+    o = orc(J, oracle.DSB, oracle.FP32, steps, R)
+    assert np.array_equal(g["x"].astype(np.float64), o["x"])
+    assert np.array_equal(g["y"].astype(np.float64), o["y"])
+    assert np.array_equal(g["best_energy"], o["best_e"])
+    assert np.array_equal(g["final_energy"], o["final_e"])
+    np.testing.assert_allclose(g["xi"], o["xi"], rtol=1e-12, atol=0)
+    # the thermostat moved xi away from its start value -gamma
+    assert np.all(np.abs(o["xi"] + GAMMA) > 1e-3)
+
+
+@pytest.mark.parametrize("plan", ["fp32", "digits"])
+def test_infinite_mass_is_heated_sb(plan):
+    J = synth.sk_instance(150, 7)
+    say("thermostat at infinite mass", plan)
+    heated = gpu(J, hsb.HSB_DSB, plan, 300, 20, gamma=0.05, nose_hoover=None)
+    nh = gpu(J, hsb.HSB_DSB, plan, 300, 20, gamma=0.05, nose_hoover=(0.0, 0.3))
+    for k in ("x", "y", "spins", "best_energy", "final_energy", "best_step"):
+        assert np.array_equal(heated[k], nh[k]), k
+    assert np.all(nh["xi"] == -np.float64(np.float32(0.05)))
+
+
+@pytest.mark.parametrize("plan", ["fp32", "digits"])
+def test_split_run_equals_one_run(plan):
+    J = synth.sk_instance(200, 8)
+    say("thermostat resume", plan)
+    one = gpu(J, hsb.HSB_DSB, plan, 240, 24)
+    a = gpu(J, hsb.HSB_DSB, plan, 110, 24, schedule_steps=240)
+    dev = torch.device("cuda", 0)
+    b = gpu(J, hsb.HSB_DSB, plan, 130, 24, start_step=110, schedule_steps=240,
+            x0=torch.from_numpy(a["x"]).to(dev), y0=torch.from_numpy(a["y"]).to(dev),
+            xi0=torch.from_numpy(a["xi"]).to(dev))
+    for k in ("x", "y", "xi"):
+        assert np.array_equal(b[k], one[k]), k
+
+
+@pytest.mark.parametrize("plan,N,seed,R,Ns", [("fp32", 100, 1, 16, 2000),
+                                              ("digits", 100, 1, 16, 2000),
+                                              ("digits", 300, 9, 24, 1000)])
+@pytest.mark.parametrize("steps", [1, 50])
+def test_bsb_thermostat_within_bar(plan, N, seed, R, Ns, steps):
+    """The configuration of the heated bSB bar (N = 100, Ns = 2000) on both
+    plans, and a 300-spin instance with a faster pump on the digit plan.  The
+    FP32 plan's FP32-summed field is 3.5e-5 away there after 50 steps: the
+    rounding the R10 reading allows for, amplified by the faster pump."""
+    J = synth.sk_instance(N, seed)
+    say("bsb thermostat", plan, N, steps)
+    g = gpu(J, hsb.HSB_BSB, plan, steps, R, schedule_steps=Ns, amp=0.1)
+    o = orc(J, oracle.BSB, oracle.FP64, steps, R, schedule_steps=Ns, amp=0.1)
+    assert rel_err(g["x"], o["x"]).max() <= 1e-5
+    assert rel_err(g["y"], o["y"]).max() <= 1e-5
+    np.testing.assert_allclose(g["xi"], o["xi"], rtol=1e-6, atol=0)
+
+
+def test_given_start_xi_and_per_replica_gamma():
+    N, R = 120, 12
+    J = synth.sk_instance(N, 10)
+    say("thermostat xi0 and gamma_rep")
+    dev = torch.device("cuda", 0)
+    xi0 = np.linspace(-0.1, 0.05, R)
+    grep = np.linspace(0.0, 0.06, R).astype(np.float32)
+    g = gpu(J, hsb.HSB_DSB, "fp32", 200, R, xi0=torch.from_numpy(xi0).to(dev),
+            gamma_rep=torch.from_numpy(grep).to(dev))
+    o = orc(J, oracle.DSB, oracle.FP32, 200, R, xi0=xi0)
+    assert np.array_equal(g["x"].astype(np.float64), o["x"])
+    np.testing.assert_allclose(g["xi"], o["xi"], rtol=1e-12, atol=0)
+    # without xi0 the start value is -gamma_rep
+    g2 = gpu(J, hsb.HSB_DSB, "fp32", 0, R, gamma_rep=torch.from_numpy(grep).to(dev))
+    assert np.array_equal(g2["xi"], -grep.astype(np.float64))
+
+
+def test_thermostat_argument_errors():
+    J = synth.sk_instance(50, 11)
+    with hsb.Context(J) as ctx:
+        for bad in [(-1e-3, 0.1), (1e-3, -0.1), (float("inf"), 0.1), (1e-3, float("nan"))]:
+            with pytest.raises(hsb.HSBError) as e:
+                ctx.run_ex(hsb.HSB_DSB, 10, 4, 1.0, 0.1, 1.0, 0.0, 1, nose_hoover=bad)
+            assert e.value.code == hsb.HSB_EINVAL
+        L = hsb.load_library()
+        import ctypes
+        dev = torch.device("cuda", 0)
+        spins = torch.empty((4, 50), dtype=torch.int8, device=dev)
+        energy = torch.empty(4, dtype=torch.float64, device=dev)
+        a = hsb.hsb_run_args()
+        a.struct_size = ctypes.sizeof(a)
+        a.variant, a.steps, a.R, a.a0, a.c0, a.dt = hsb.HSB_DSB, 10, 4, 1.0, 0.1, 1.0
+        a.spins, a.energy = spins.data_ptr(), energy.data_ptr()
+        a.thermostat = 2
+        assert L.hsb_run_ex(ctx.h, ctypes.byref(a)) == hsb.HSB_EINVAL
+        a.thermostat = hsb.HSB_THERMO_HEAT
+        a.nh_inv_mass = 1e-3  # thermostat fields without the thermostat
+        assert L.hsb_run_ex(ctx.h, ctypes.byref(a)) == hsb.HSB_EINVAL
+        a.nh_inv_mass = 0.0
+        assert L.hsb_run_ex(ctx.h, ctypes.byref(a)) == hsb.HSB_OK
