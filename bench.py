@@ -362,6 +362,29 @@ def main() -> int:
                 "best_Ns": best, "best_median_S_HbSB_over_dSB": ratio,
                 "sweep": sweep_workload(Js[:20])}
 
+    def k2000_workload():
+        # the K2000 comparison of the Results on the synthetic 2000-spin
+        # instance: the four forms at the paper's parameters, N_s from 10^3 to
+        # 10^4, the best of every 100 steps per trial, E* the pooled best
+        from paper_2203_08361_amd import evaluate as ev
+
+        trials, grid = 2048, (1000, 2000, 5000, 10000)
+        log(f"k2000: one SK instance N={N}, {trials} trials, N_s {grid}")
+        with ev.GpuRunner([J]) as run:
+            res = ev.evaluate([J], run, ev.PRESETS, grid, R=trials, seed=3, interval=100)
+        rows = {f"{r['form']}@{r['Ns']}": {k: r["instances"][0][k]
+                                           for k in ("P", "S", "C_mean", "C_max")}
+                for r in res["rows"]}
+        best = res["best_Ns"]
+        d = best["dSB"]["median_S"]
+        red = {f: (1.0 - best[f]["median_S"] / d) if math.isfinite(d) and d > 0 else None
+               for f in ("HbSB", "HdSB")}
+        return {"workload": f"SK +-1 N={N} (the bench instance), {trials} trials per form and "
+                            f"N_s, N_s in {list(grid)}, best of every 100 steps",
+                "seconds": res["seconds"], "spin_updates_per_s": res["spin_updates_per_s"],
+                "reference_cut": res["reference_cut"][0], "per_form_and_Ns": rows,
+                "best_Ns": best, "S_reduction_vs_dSB": red}
+
     def sweep_workload(Js):
         # the parameter search of the Results on the first 20 of those
         # instances: a 4 x 4 x 4 (dt, c1, gamma) grid per heated form, the
@@ -389,7 +412,8 @@ def main() -> int:
         ctx.close()
         return 0
     if args.evaluation_only:
-        print(json.dumps({"evaluation": evaluation_workload()}), flush=True)
+        print(json.dumps({"evaluation": evaluation_workload(), "k2000": k2000_workload()}),
+              flush=True)
         ctx.close()
         return 0
 
@@ -427,6 +451,7 @@ def main() -> int:
         result["thermostat"] = thermostat_workload()
     if args.variant == "dsb" and not args.no_evaluation:
         result["evaluation"] = evaluation_workload()
+        result["k2000"] = k2000_workload()
 
     if not args.no_cpu_baseline:
         import oracle
