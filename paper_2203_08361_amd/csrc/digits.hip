@@ -118,12 +118,12 @@ __global__ __launch_bounds__(64) void k_i8_digits(const float *__restrict__ X,
 
 // One time step (ENERGY = false) or the energy partials of the current state
 // (ENERGY = true, sign digits, one-digit J).  Grid (Npad / 256, Rpad / 32).
-template <int NJD, int NXD, int KC, bool ENERGY>
+template <int NJD, int NXD, int KC, bool ENERGY, bool NH>
 __global__ __launch_bounds__(256) void k_i8_field(
     const v4i *__restrict__ jd, const double *__restrict__ rowscale, const v4i *__restrict__ xin,
     int8_t *__restrict__ xout, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gam, double *__restrict__ epart, int Nst, int Npad, int Rpad,
-    float p, float c0, float dt, float a0dt) {
+    float p, float c0, float dt, float a0dt, NHFused nhf) {
     constexpr int NW = (NJD + NXD - 1) < 4 ? (NJD + NXD - 1) : 4;  // accumulated weights
     constexpr int KB = 2 * KC;                                       // K blocks per stage
     constexpr int BTOT = NXD * KB * 32;                              // B records per stage
@@ -145,6 +145,29 @@ __global__ __launch_bounds__(256) void k_i8_field(
     const int i0 = sb * 256 + w * 64, r0 = rb * 32;
     const int nkb = Npad / 16;
     const int S = Npad / (32 * KC);  // stages (even: Npad is a multiple of 256)
+    // thermostat: xi(t_k) of this lane's replica, formed before the products so
+    // that its loads overlap them
+    double xi_k = 0.0;
+    if constexpr (NH) {
+        const int rr = r0 + l32;
+        xi_k = nhf.xi_in[rr];
+        if (!nhf.first) {
+            // partials added in the order q = 0, 1, ...; loaded 8 at a time so
+            // that the loads overlap
+            const double *pp = nhf.part_in + rr;
+            double Ssum = 0.0;
+            int q = 0;
+            for (; q + 8 <= nhf.nparts; q += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = pp[(size_t)(q + u) * Rpad];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) Ssum += v[u];
+            }
+            for (; q < nhf.nparts; ++q) Ssum += pp[(size_t)q * Rpad];
+            xi_k = xi_k + nhf.c * (Ssum - nhf.NT);
+        }
+    }
 
     v16i acc[2][NW];
 #pragma unroll
@@ -248,7 +271,13 @@ __global__ __launch_bounds__(256) void k_i8_field(
     // every load of the tile's state is issued before the first store, so the
     // 64 loads per lane overlap instead of each waiting behind a store
     if (i0 >= Nst) return;  // Nst is a multiple of 64: a wave's rows are wholly in or out
-    const float gdt = gam[r] * dt;
+    float gdt;
+    if constexpr (NH) {
+        gdt = (float)(-xi_k) * dt;  // the rate -xi(t_k) in eq. (22)'s place
+        if (i0 == 0 && h == 0) nhf.xi_out[r] = xi_k;
+    } else {
+        gdt = gam[r] * dt;
+    }
     float xs[2][16], ys[2][16];
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt)
@@ -258,6 +287,15 @@ __global__ __launch_bounds__(256) void k_i8_field(
             xs[tt][v] = X[idx];
             ys[tt][v] = Y[idx];
         }
+    if constexpr (NH) {  // sum of y_i(t_k)^2 over this wave's 64 rows (exact squares)
+        double t2 = 0.0;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) t2 += (double)ys[tt][v] * (double)ys[tt][v];
+        t2 += __shfl_xor(t2, 32);
+        if (h == 0) nhf.part_out[(size_t)(i0 / 64) * Rpad + r] = t2;
+    }
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt) {
         const int ib = i0 + tt * 32;
@@ -331,13 +369,14 @@ void split4_host(long long q, int d[4]) {
     d[0] = (int)q;
 }
 
-template <int NJD, int NXD, int KC, bool ENERGY>
+template <int NJD, int NXD, int KC, bool ENERGY, bool NH = false>
 hipError_t launch_field(const I8J *p, const int8_t *xin, int8_t *xout, StateBufs &b, int Nst,
-                        int Rpad, float pk, float c0, float dt, float a0dt, hipStream_t s) {
+                        int Rpad, float pk, float c0, float dt, float a0dt, hipStream_t s,
+                        const NHFused &nhf = NHFused{}) {
     const dim3 grid(p->Npad / 256, Rpad / 32);
-    hipLaunchKernelGGL((k_i8_field<NJD, NXD, KC, ENERGY>), grid, dim3(256), 0, s, p->jd,
+    hipLaunchKernelGGL((k_i8_field<NJD, NXD, KC, ENERGY, NH>), grid, dim3(256), 0, s, p->jd,
                        p->rowscale, reinterpret_cast<const v4i *>(xin), xout, b.X, b.Y, b.gamma,
-                       b.epart, Nst, p->Npad, Rpad, pk, c0, dt, a0dt);
+                       b.epart, Nst, p->Npad, Rpad, pk, c0, dt, a0dt, nhf);
     return hipGetLastError();
 }
 
@@ -446,6 +485,7 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
         return HSB_OK;
     };
     if (k1 == k0) return sample(k0);
+    const int nh_parts = Nst / 64;  // 64-row partials of the thermostat's sum
     int cur = 0;
     size_t nrun = 0;  // step launches since the last energy sample
     for (int k = k0; k < k1; ++k) {
@@ -454,12 +494,30 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
         const float pk = a0 - ak;
         const int8_t *xin = p->xd + cur * set;
         int8_t *xout = p->xd + (cur ^ 1) * set;
-        if (run.nh) {  // this step's heating rate -xi(t_k) from the state before it
-            e = launch_nh_step(*run.nh, b.Y, b.gamma, run.N, run.R, Rpad, s);
-            if (e != hipSuccess) return derr(HSB_EDEVICE, "thermostat: %s", hipGetErrorString(e));
-        }
         e = timer.begin(s);
-        if (e == hipSuccess) {
+        if (e == hipSuccess && run.nh) {
+            // the thermostat fused into the step: slots alternate with the step
+            const int j = k - k0;
+            NHFused f;
+            f.xi_in = run.nh->xi + (size_t)(j & 1) * Rpad;
+            f.xi_out = run.nh->xi + (size_t)((j + 1) & 1) * Rpad;
+            f.part_out = run.nh->part + (size_t)(j & 1) * nh_parts * Rpad;
+            f.part_in = run.nh->part + (size_t)((j + 1) & 1) * nh_parts * Rpad;
+            f.nparts = nh_parts;
+            f.first = j == 0;
+            f.c = run.nh->c;
+            f.NT = run.nh->NT;
+            if (p->njd == 1)
+                e = bsb ? launch_field<1, 4, 4, false, true>(p, xin, xout, b, Nst, Rpad, pk, c0,
+                                                             dt, a0dt, s, f)
+                        : launch_field<1, 1, 4, false, true>(p, xin, xout, b, Nst, Rpad, pk, c0,
+                                                             dt, a0dt, s, f);
+            else
+                e = bsb ? launch_field<4, 4, 2, false, true>(p, xin, xout, b, Nst, Rpad, pk, c0,
+                                                             dt, a0dt, s, f)
+                        : launch_field<4, 1, 2, false, true>(p, xin, xout, b, Nst, Rpad, pk, c0,
+                                                             dt, a0dt, s, f);
+        } else if (e == hipSuccess) {
             if (p->njd == 1)
                 e = bsb ? launch_field<1, 4, 4, false>(p, xin, xout, b, Nst, Rpad, pk, c0, dt,
                                                        a0dt, s)
@@ -481,6 +539,13 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
             rc = sample(k + 1);
             if (rc) return rc;
         }
+    }
+    if (run.nh) {  // xi after the last step, from its slot and partials, into slot 0
+        const int steps = k1 - k0;
+        e = launch_nh_final(run.nh->xi + (size_t)(steps & 1) * Rpad,
+                            run.nh->part + (size_t)((steps - 1) & 1) * nh_parts * Rpad, nh_parts,
+                            run.R, Rpad, run.nh->xi, run.nh->c, run.nh->NT, s);
+        if (e != hipSuccess) return derr(HSB_EDEVICE, "thermostat: %s", hipGetErrorString(e));
     }
     return HSB_OK;
 }

@@ -378,12 +378,15 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
     const bool nh = a->thermostat == HSB_THERMO_NOSE_HOOVER;
     if (nh) {
         if (h->nh_cap < Rpad) {
+            // xi: two slots; partials: the per-step plan's groups, or two sets
+            // of 64-row partials for the digit plan's fused steps
+            const size_t parts = std::max<size_t>(hsb::kNHGroups, 2 * (size_t)(Npad / 64));
             if (h->nh.xi) (void)hipFree(h->nh.xi);
             if (h->nh.part) (void)hipFree(h->nh.part);
             h->nh.xi = h->nh.part = nullptr;
             h->nh_cap = 0;
-            HIP_TRY(hipMalloc((void **)&h->nh.xi, sizeof(double) * Rpad));
-            HIP_TRY(hipMalloc((void **)&h->nh.part, sizeof(double) * hsb::kNHGroups * Rpad));
+            HIP_TRY(hipMalloc((void **)&h->nh.xi, sizeof(double) * 2 * Rpad));
+            HIP_TRY(hipMalloc((void **)&h->nh.part, sizeof(double) * parts * Rpad));
             h->nh_cap = Rpad;
         }
         // dt as the step kernels use it: a float

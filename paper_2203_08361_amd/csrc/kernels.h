@@ -106,13 +106,32 @@ hipError_t launch_make_operand(float *B, const float *X, int variant, int Npad, 
 // g[r] = gamma_rep[r] (or gamma) for r < R, 0 for R <= r < Rpad
 hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int R, int Rpad,
                              hipStream_t s);
-// Nose-Hoover thermostat of a run (eqs. (6)-(8)): xi [>= R] in FP64 and the
-// partial sums of y^2 [kNHGroups][Rpad]; c = dt / M and NT = N T.
+// Nose-Hoover thermostat of a run (eqs. (6)-(8)): xi in FP64 [2][Rpad] (slot 0
+// holds the start and the final value), partial sums of y^2 [at least
+// max(kNHGroups, 2 Npad/64)][Rpad]; c = dt / M and NT = N T.
 constexpr int kNHGroups = 16;
 struct NHState {
     double *xi = nullptr, *part = nullptr;
     double c = 0.0, NT = 0.0;
 };
+// One thermostat step fused into a step kernel (integer-digit plan): the
+// kernel forms xi(t_k) = xi_in + c (sum of part_in's nparts 64-row partials -
+// NT), or takes xi_in as it is on the first step, heats at the rate -xi(t_k),
+// stores xi(t_k) in xi_out (row block 0) and the 64-row partials of
+// sum_i y_i(t_k)^2 of the state it reads in part_out.  Consecutive steps swap
+// the slots, so no launch reads what it writes.
+struct NHFused {
+    const double *xi_in = nullptr;
+    double *xi_out = nullptr;
+    const double *part_in = nullptr;
+    double *part_out = nullptr;
+    int nparts = 0, first = 1;
+    double c = 0.0, NT = 0.0;
+};
+// xi_dst[r] = xi_in[r] + c (sum of part_in's nparts partials - NT): the value
+// after the last fused step
+hipError_t launch_nh_final(const double *xi_in, const double *part_in, int nparts, int R,
+                           int Rpad, double *xi_dst, double c, double NT, hipStream_t s);
 // xi = xi0 (device [R]) if given, else -gamma[r]
 hipError_t launch_nh_init(const NHState &nh, const double *xi0, const float *gamma, int R,
                           hipStream_t s);

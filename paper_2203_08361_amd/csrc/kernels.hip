@@ -100,6 +100,16 @@ __global__ void k_nh_update(const double *__restrict__ part, int groups, int R, 
     xi[r] = x + c * (S - NT);
 }
 
+__global__ void k_nh_final(const double *__restrict__ xi_in, const double *__restrict__ part_in,
+                           int nparts, int R, int Rpad, double *__restrict__ xi_dst, double c,
+                           double NT) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double S = 0.0;
+    for (int q = 0; q < nparts; ++q) S += part_in[(size_t)q * Rpad + r];
+    xi_dst[r] = xi_in[r] + c * (S - NT);
+}
+
 __global__ void k_copy_f64(double *__restrict__ dst, const double *__restrict__ src, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
@@ -551,6 +561,13 @@ hipError_t launch_nh_step(const NHState &nh, const float *Y, float *gamma, int N
                        rows_per, nh.part);
     hipLaunchKernelGGL(k_nh_update, dim3(cdiv(R, 256)), dim3(256), 0, s, nh.part, kNHGroups, R,
                        Rpad, nh.xi, gamma, nh.c, nh.NT);
+    return hipGetLastError();
+}
+
+hipError_t launch_nh_final(const double *xi_in, const double *part_in, int nparts, int R,
+                           int Rpad, double *xi_dst, double c, double NT, hipStream_t s) {
+    hipLaunchKernelGGL(k_nh_final, dim3(cdiv(R, 256)), dim3(256), 0, s, xi_in, part_in, nparts,
+                       R, Rpad, xi_dst, c, NT);
     return hipGetLastError();
 }
 

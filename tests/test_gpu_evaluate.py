@@ -153,3 +153,25 @@ def test_grouped_bsb_forms_equal_single_calls():
         grouped = run.run_group(forms, 150, 40, seeds, c0s, 50)
         single = np.stack([run(p, 150, 40, seeds[k], c0s[k], 50) for k, p in enumerate(forms)])
     assert np.array_equal(grouped, single)
+
+
+def test_command_line(tmp_path, capsys):
+    """python -m paper_2203_08361_amd.evaluate: the comparison and the sweep on
+    a small instance set, with the full result written as JSON."""
+    import json
+
+    say("evaluate command line")
+    out = tmp_path / "eval.json"
+    assert ev.main(["--set", "sk700", "--instances", "3", "--N", "96", "--trials", "32",
+                    "--Ns", "50,100", "--forms", "dSB,HdSB", "--out", str(out)]) == 0
+    summary = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    full = json.loads(out.read_text())
+    assert summary["instances"] == 3 and summary["N"] == 96
+    assert set(summary["median_S"]) == {"dSB@50", "dSB@100", "HdSB@50", "HdSB@100"}
+    assert len(full["rows"]) == 4 and len(full["reference_energy"]) == 3
+    assert ev.main(["--set", "sk700", "--instances", "2", "--N", "64", "--trials", "16",
+                    "--Ns", "60", "--sweep", "HdSB", "--dts", "1.0,1.1", "--c1s", "0.6",
+                    "--gammas", "0,0.06"]) == 0
+    sw = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert sw["points"] == 4 and sw["Ns"] == 60
+    assert sw["best"]["dt"] in (1.0, 1.1) and sw["best"]["gamma"] in (0.0, 0.06)
