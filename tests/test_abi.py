@@ -119,3 +119,13 @@ def test_valid_J_without_gpu_is_a_device_error():
         pytest.skip("a GPU is present")
     rc, h, err = _create_rc(np.array([[0, 1], [1, 0]]))
     assert rc == hsb.HSB_EDEVICE and not h.value
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without libhsb.so the binding raises; there is no other execution path."""
+    monkeypatch.setattr(hsb, "LIB_PATH", str(tmp_path / "absent" / "libhsb.so"))
+    monkeypatch.setattr(hsb, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        hsb.load_library()
+    with pytest.raises(RuntimeError, match="not built"):
+        hsb.Context(np.zeros((4, 4), dtype=np.float32))
