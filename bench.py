@@ -345,7 +345,7 @@ def main() -> int:
         n_inst, n_spins, trials, grid = 100, 700, 1024, (200, 500, 1000, 2000)
         Js = [synth.sk_instance(n_spins, 700 + i) for i in range(n_inst)]
         log(f"evaluation: {n_inst} SK instances N={n_spins}, {trials} trials, N_s {grid}")
-        with ev.GpuRunner(Js) as run:
+        with ev.DeviceRunner(Js) as run:
             res = ev.evaluate(Js, run, ev.PRESETS, grid, R=trials, seed=1, final_only=True)
         best = res["best_Ns"]
         ratio = (best["HbSB"]["median_S"] / best["dSB"]["median_S"]
@@ -370,7 +370,7 @@ def main() -> int:
 
         trials, grid = 2048, (1000, 2000, 5000, 10000)
         log(f"k2000: one SK instance N={N}, {trials} trials, N_s {grid}")
-        with ev.GpuRunner([J]) as run:
+        with ev.DeviceRunner([J]) as run:
             res = ev.evaluate([J], run, ev.PRESETS, grid, R=trials, seed=3, interval=100)
         rows = {f"{r['form']}@{r['Ns']}": {k: r["instances"][0][k]
                                            for k in ("P", "S", "C_mean", "C_max")}
@@ -392,7 +392,7 @@ def main() -> int:
         from paper_2203_08361_amd import evaluate as ev
 
         out = {}
-        with ev.GpuRunner(Js) as run:
+        with ev.DeviceRunner(Js) as run:
             for form, gammas in (("HdSB", (0.0, 0.03, 0.06, 0.12)), ("HbSB", (0.0, 0.25, 0.5, 0.75))):
                 log(f"sweep: {form}, {len(Js)} instances")
                 r = ev.sweep(Js, run, ev.preset(form).variant, 1000, (0.9, 1.0, 1.1, 1.25),

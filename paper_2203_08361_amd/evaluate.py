@@ -28,7 +28,7 @@ ranked by median S, or by the average cut where no trial reaches E*.
 The trials run on the GPU through hsb_run_batch (one call per N_s and per
 group of forms sharing variant and dt, over all instances); `time_evolution`
 gives per-step T_inst (eq. (9)) and C traces of single runs, through the
-traces of hsb_run_ex.  A runner is any callable with GpuRunner's call
+traces of hsb_run_ex.  A runner is any callable with DeviceRunner's call
 signature, so other executions of the same trials can be evaluated by the
 same code.
 """
@@ -93,7 +93,7 @@ def trial_seed(seed: int, form: int, Ns: int, instance: int) -> int:
     return (seed * 1000003 + form * 7919 + Ns * 104729 + instance * 15485863) % (1 << 64)
 
 
-class GpuRunner:
+class DeviceRunner:
     """Runs trials on the GPU: one hsb_run_batch call per (form, N_s), or per
     group of forms that share variant and dt, over all instances; one job of
     R trials per (form, instance)."""
@@ -295,7 +295,7 @@ def main(argv=None) -> int:
         final_only = False
     if a.sweep:
         floats = lambda t: [float(v) for v in t.split(",")]  # noqa: E731
-        with GpuRunner(Js) as run:
+        with DeviceRunner(Js) as run:
             res = sweep(Js, run, preset(a.sweep).variant, Ns_list[0], floats(a.dts),
                         floats(a.c1s), floats(a.gammas), a.trials, a.seed, 100, final_only)
         if a.out:
@@ -304,7 +304,7 @@ def main(argv=None) -> int:
         print(json.dumps({k: res[k] for k in ("best", "criterion", "Ns", "points", "seconds",
                                               "spin_updates_per_s")}))
         return 0
-    with GpuRunner(Js) as run:
+    with DeviceRunner(Js) as run:
         res = evaluate(Js, run, forms, Ns_list, a.trials, a.seed, 100, final_only)
     if a.out:
         with open(a.out, "w") as f:

@@ -55,7 +55,7 @@ def test_dsb_forms_equal_the_oracle_evaluation(final_only):
     Js = [synth.sk_instance(N, 50 + N) for N in (64, 100, 150, 257)]
     forms = [ev.preset("dSB"), ev.preset("HdSB")]
     say("evaluation dSB forms", final_only)
-    with ev.GpuRunner(Js) as run:
+    with ev.DeviceRunner(Js) as run:
         g = ev.evaluate(Js, run, forms, (60, 150), R=24, seed=4, interval=50,
                         final_only=final_only)
     o = ev.evaluate(Js, OracleRunner(Js, oracle.FP32), forms, (60, 150), R=24, seed=4,
@@ -78,7 +78,7 @@ def test_bsb_forms_agree_with_the_fp64_oracle_in_distribution():
             return E
         return call
 
-    with ev.GpuRunner(Js) as run:
+    with ev.DeviceRunner(Js) as run:
         ev.evaluate(Js, recording(run, "gpu"), forms, Ns, R=R, seed=5)
     ev.evaluate(Js, recording(OracleRunner(Js, oracle.FP64), "orc"), forms, Ns, R=R, seed=5)
     for p in forms:
@@ -134,7 +134,7 @@ def test_dsb_sweep_equals_the_oracle_sweep():
     Js = [synth.sk_instance(N, 80 + N) for N in (64, 100, 130)]
     say("dsb sweep")
     grid = ((1.0, 1.1), (0.5, 0.7), (0.0, 0.06))
-    with ev.GpuRunner(Js) as run:
+    with ev.DeviceRunner(Js) as run:
         g = ev.sweep(Js, run, hsb.HSB_DSB, 80, *grid, R=16, seed=8)
     o = ev.sweep(Js, OracleRunner(Js, oracle.FP32), hsb.HSB_DSB, 80, *grid, R=16, seed=8)
     assert g["ranked"] == o["ranked"] and g["best"] == o["best"]
@@ -147,7 +147,7 @@ def test_grouped_bsb_forms_equal_single_calls():
     Js = [synth.sk_instance(N, 90 + N) for N in (100, 300)]
     forms = [ev.Preset(f"g{g}", hsb.HSB_BSB, 1.1, c1, g) for c1 in (0.6, 0.9) for g in (0.0, 0.5)]
     say("grouped bsb forms")
-    with ev.GpuRunner(Js) as run:
+    with ev.DeviceRunner(Js) as run:
         seeds = [[11 * k + i for i in range(2)] for k in range(4)]
         c0s = [[ev.c0_for(J, p.c1) for J in Js] for p in forms]
         grouped = run.run_group(forms, 150, 40, seeds, c0s, 50)
