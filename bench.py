@@ -102,7 +102,7 @@ def main() -> int:
     ap.add_argument("--evaluation-only", action="store_true",
                     help="run only the 700-spin evaluation of the four SB forms")
     ap.add_argument("--cpu-replicas", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=700)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain FP32 copy of MIB MiB (read once, written once) three "
                          "times: the reference dispatch for scaling HBM byte counters")
