@@ -171,3 +171,27 @@ def test_thermostat_argument_errors():
         assert L.hsb_run_ex(ctx.h, ctypes.byref(a)) == hsb.HSB_EINVAL
         a.nh_inv_mass = 0.0
         assert L.hsb_run_ex(ctx.h, ctypes.byref(a)) == hsb.HSB_OK
+
+
+def test_bench_configuration_sampled_replicas():
+    """The thermostat at the size the bench times (dSB, N = 2000, R = 1024,
+    digit plan, 1/M = 1e-8, T = 0.02): the first 2000 steps of the 10^4-step
+    schedule, replicas 0, 511 and 1023 against the FP32 mirror."""
+    N, R, steps, Ns = 2000, 1024, 2000, 10000
+    J = synth.sk_instance(N, 2000)
+    c0 = 0.5 / np.sqrt(N)
+    say("thermostat at the bench size", N, R, steps)
+    with hsb.Context(J, precision="mixed", init_amp=0.1, energy_interval=100) as ctx:
+        g = ctx.run_ex(hsb.HSB_DSB, steps, R, 1.0, c0, 1.0, GAMMA, 1, want_state=True,
+                       schedule_steps=Ns, nose_hoover=(1e-8, 0.02))
+        torch.cuda.synchronize()
+        assert ctx.last_plan() == "digits"
+        g = {k: v.cpu().numpy() for k, v in g.items() if hasattr(v, "cpu")}
+    for r in (0, 511, 1023):
+        o = oracle.run(J, oracle.DSB, 1.0, np.float32(c0), 1.0, GAMMA, steps, 1, seed=1, amp=0.1,
+                       interval=100, precision=oracle.FP32, r0=r, schedule_steps=Ns,
+                       nose_hoover=(1e-8, 0.02))
+        assert np.array_equal(g["x"][r:r + 1].astype(np.float64), o["x"]), r
+        assert np.array_equal(g["y"][r:r + 1].astype(np.float64), o["y"]), r
+        assert np.array_equal(g["best_energy"][r:r + 1], o["best_e"]), r
+        np.testing.assert_allclose(g["xi"][r:r + 1], o["xi"], rtol=1e-12, atol=0)
