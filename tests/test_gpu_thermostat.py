@@ -195,3 +195,16 @@ def test_bench_configuration_sampled_replicas():
         assert np.array_equal(g["y"][r:r + 1].astype(np.float64), o["y"]), r
         assert np.array_equal(g["best_energy"][r:r + 1], o["best_e"]), r
         np.testing.assert_allclose(g["xi"][r:r + 1], o["xi"], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("plan", ["fp32", "digits"])
+def test_thermostat_with_traces(plan):
+    """Traces of a thermostat run: energy rows equal the mirror's, T_inst rows
+    agree to FP64 summation order."""
+    N, R, steps = 130, 20, 240
+    J = synth.sk_instance(N, 12)
+    say("thermostat traces", plan)
+    g = gpu(J, hsb.HSB_DSB, plan, steps, R, traces=True)
+    o = orc(J, oracle.DSB, oracle.FP32, steps, R, traces=True)
+    assert np.array_equal(g["trace_energy"], o["trace_e"])
+    np.testing.assert_allclose(g["trace_tinst"], o["trace_tinst"], rtol=1e-13, atol=0)
