@@ -117,9 +117,9 @@ __global__ __launch_bounds__(64) void k_i8_digits(const float *__restrict__ X,
 }
 
 // One time step (ENERGY = false) or the energy partials of the current state
-// (ENERGY = true, sign digits, one-digit J).  Grid (Npad / 256, Rpad / 32).
-template <int NJD, int NXD, int KC, bool ENERGY, bool NH>
-__global__ __launch_bounds__(256) void k_i8_field(
+// (ENERGY = true, sign digits, one-digit J).  Grid (Npad / (128 NT), Rpad / 32).
+template <int NJD, int NXD, int KC, bool ENERGY, bool NH, int NT>
+__global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_field(
     const v4i *__restrict__ jd, const double *__restrict__ rowscale, const v4i *__restrict__ xin,
     int8_t *__restrict__ xout, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gam, double *__restrict__ epart, int Nst, int Npad, int Rpad,
@@ -142,7 +142,8 @@ __global__ __launch_bounds__(256) void k_i8_field(
     const int L = blockIdx.x + gx * blockIdx.y;
     const int tile = (T & 7) == 0 ? (L & 7) * (T >> 3) + (L >> 3) : L;
     const int sb = tile % gx, rb = tile / gx;
-    const int i0 = sb * 256 + w * 64, r0 = rb * 32;
+    // NT 32-row tiles per wave: 64 rows (one wave per SIMD) or 32 rows (two)
+    const int i0 = sb * (128 * NT) + w * (32 * NT), r0 = rb * 32;
     const int nkb = Npad / 16;
     const int S = Npad / (32 * KC);  // stages (even: Npad is a multiple of 256)
     // thermostat: xi(t_k) of this lane's replica, formed before the products so
@@ -169,18 +170,18 @@ __global__ __launch_bounds__(256) void k_i8_field(
         }
     }
 
-    v16i acc[2][NW];
+    v16i acc[NT][NW];
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
         for (int q = 0; q < NW; ++q) acc[tt][q] = v16i{};
 
-    v4i a0r[2][NJD][KC], a1r[2][NJD][KC];
+    v4i a0r[NT][NJD][KC], a1r[NT][NJD][KC];
     v4i breg[BPT];
 
-    auto loadA = [&](int s, v4i(&dst)[2][NJD][KC]) {
+    auto loadA = [&](int s, v4i(&dst)[NT][NJD][KC]) {
 #pragma unroll
-        for (int tt = 0; tt < 2; ++tt)
+        for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
             for (int a = 0; a < NJD; ++a)
 #pragma unroll
@@ -208,14 +209,14 @@ __global__ __launch_bounds__(256) void k_i8_field(
             }
         }
     };
-    auto compute = [&](int buf, const v4i(&A)[2][NJD][KC]) {
+    auto compute = [&](int buf, const v4i(&A)[NT][NJD][KC]) {
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
             v4i bf[NXD];
 #pragma unroll
             for (int b = 0; b < NXD; ++b) bf[b] = bs[buf][b][2 * c + h][l32];
 #pragma unroll
-            for (int tt = 0; tt < 2; ++tt)
+            for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
                 for (int a = 0; a < NJD; ++a)
 #pragma unroll
@@ -249,11 +250,12 @@ __global__ __launch_bounds__(256) void k_i8_field(
     }
 
     const int r = r0 + l32;
+    static_assert(NT == 2 || (!ENERGY && !NH), "energy and thermostat partials are per 64 rows");
     if (ENERGY) {
         // eq. (1): partial sum_i s_i f_i over this wave's 64 spins, exact in int32
         int part = 0;
 #pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
+        for (int tt = 0; tt < NT; ++tt) {
             const int ib = i0 + tt * 32;
             if (ib >= Nst) continue;
 #pragma unroll
@@ -278,9 +280,9 @@ __global__ __launch_bounds__(256) void k_i8_field(
     } else {
         gdt = gam[r] * dt;
     }
-    float xs[2][16], ys[2][16];
+    float xs[NT][16], ys[NT][16];
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const size_t idx = (size_t)(i0 + tt * 32 + 8 * (v >> 2) + 4 * h + (v & 3)) * Rpad + r;
@@ -290,14 +292,14 @@ __global__ __launch_bounds__(256) void k_i8_field(
     if constexpr (NH) {  // sum of y_i(t_k)^2 over this wave's 64 rows (exact squares)
         double t2 = 0.0;
 #pragma unroll
-        for (int tt = 0; tt < 2; ++tt)
+        for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
             for (int v = 0; v < 16; ++v) t2 += (double)ys[tt][v] * (double)ys[tt][v];
         t2 += __shfl_xor(t2, 32);
         if (h == 0) nhf.part_out[(size_t)(i0 / 64) * Rpad + r] = t2;
     }
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
+    for (int tt = 0; tt < NT; ++tt) {
         const int ib = i0 + tt * 32;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -332,7 +334,7 @@ __global__ __launch_bounds__(256) void k_i8_field(
         }
     }
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const size_t idx = (size_t)(i0 + tt * 32 + 8 * (v >> 2) + 4 * h + (v & 3)) * Rpad + r;
@@ -373,8 +375,10 @@ template <int NJD, int NXD, int KC, bool ENERGY, bool NH = false>
 hipError_t launch_field(const I8J *p, const int8_t *xin, int8_t *xout, StateBufs &b, int Nst,
                         int Rpad, float pk, float c0, float dt, float a0dt, hipStream_t s,
                         const NHFused &nhf = NHFused{}) {
-    const dim3 grid(p->Npad / 256, Rpad / 32);
-    hipLaunchKernelGGL((k_i8_field<NJD, NXD, KC, ENERGY, NH>), grid, dim3(256), 0, s, p->jd,
+    // four-digit J steps take 32-row waves (two per SIMD); the rest 64-row waves
+    constexpr int NT = (NJD == 4 && !ENERGY && !NH) ? 1 : 2;
+    const dim3 grid(p->Npad / (128 * NT), Rpad / 32);
+    hipLaunchKernelGGL((k_i8_field<NJD, NXD, KC, ENERGY, NH, NT>), grid, dim3(256), 0, s, p->jd,
                        p->rowscale, reinterpret_cast<const v4i *>(xin), xout, b.X, b.Y, b.gamma,
                        b.epart, Nst, p->Npad, Rpad, pk, c0, dt, a0dt, nhf);
     return hipGetLastError();
