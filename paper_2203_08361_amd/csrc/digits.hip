@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_field(
     }
 
     const int r = r0 + l32;
-    static_assert(NT == 2 || (!ENERGY && !NH), "energy and thermostat partials are per 64 rows");
+    static_assert(NT == 2 || !ENERGY, "energy partials are per 64 rows");
     if (ENERGY) {
         // eq. (1): partial sum_i s_i f_i over this wave's 64 spins, exact in int32
         int part = 0;
@@ -289,14 +289,14 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_field(
             xs[tt][v] = X[idx];
             ys[tt][v] = Y[idx];
         }
-    if constexpr (NH) {  // sum of y_i(t_k)^2 over this wave's 64 rows (exact squares)
+    if constexpr (NH) {  // sum of y_i(t_k)^2 over this wave's rows (exact squares)
         double t2 = 0.0;
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
             for (int v = 0; v < 16; ++v) t2 += (double)ys[tt][v] * (double)ys[tt][v];
         t2 += __shfl_xor(t2, 32);
-        if (h == 0) nhf.part_out[(size_t)(i0 / 64) * Rpad + r] = t2;
+        if (h == 0) nhf.part_out[(size_t)(i0 / (32 * NT)) * Rpad + r] = t2;
     }
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) {
@@ -371,12 +371,19 @@ void split4_host(long long q, int d[4]) {
     d[0] = (int)q;
 }
 
+// 32-row tiles per wave of a step kernel: one (32-row waves, two per SIMD)
+// for four-digit J and for sign digits, measured faster there; two for
+// one-digit J with x digits, where the halved operand reuse cost as much as
+// the second wave gained; two for the energy partials
+constexpr int tiles_per_wave(int njd, int nxd, bool energy) {
+    return energy ? 2 : ((njd == 4 || nxd == 1) ? 1 : 2);
+}
+
 template <int NJD, int NXD, int KC, bool ENERGY, bool NH = false>
 hipError_t launch_field(const I8J *p, const int8_t *xin, int8_t *xout, StateBufs &b, int Nst,
                         int Rpad, float pk, float c0, float dt, float a0dt, hipStream_t s,
                         const NHFused &nhf = NHFused{}) {
-    // four-digit J steps take 32-row waves (two per SIMD); the rest 64-row waves
-    constexpr int NT = (NJD == 4 && !ENERGY && !NH) ? 1 : 2;
+    constexpr int NT = tiles_per_wave(NJD, NXD, ENERGY);
     const dim3 grid(p->Npad / (128 * NT), Rpad / 32);
     hipLaunchKernelGGL((k_i8_field<NJD, NXD, KC, ENERGY, NH, NT>), grid, dim3(256), 0, s, p->jd,
                        p->rowscale, reinterpret_cast<const v4i *>(xin), xout, b.X, b.Y, b.gamma,
@@ -489,7 +496,8 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
         return HSB_OK;
     };
     if (k1 == k0) return sample(k0);
-    const int nh_parts = Nst / 64;  // 64-row partials of the thermostat's sum
+    // per-wave partials of the thermostat's sum (32 or 64 rows)
+    const int nh_parts = Nst / (32 * tiles_per_wave(p->njd, bsb ? 4 : 1, false));
     int cur = 0;
     size_t nrun = 0;  // step launches since the last energy sample
     for (int k = k0; k < k1; ++k) {

@@ -379,8 +379,8 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
     if (nh) {
         if (h->nh_cap < Rpad) {
             // xi: two slots; partials: the per-step plan's groups, or two sets
-            // of 64-row partials for the digit plan's fused steps
-            const size_t parts = std::max<size_t>(hsb::kNHGroups, 2 * (size_t)(Npad / 64));
+            // of per-wave (32- or 64-row) partials for the digit plan's fused steps
+            const size_t parts = std::max<size_t>(hsb::kNHGroups, 2 * (size_t)(Npad / 32));
             if (h->nh.xi) (void)hipFree(h->nh.xi);
             if (h->nh.part) (void)hipFree(h->nh.part);
             h->nh.xi = h->nh.part = nullptr;

@@ -108,16 +108,16 @@ hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int 
                              hipStream_t s);
 // Nose-Hoover thermostat of a run (eqs. (6)-(8)): xi in FP64 [2][Rpad] (slot 0
 // holds the start and the final value), partial sums of y^2 [at least
-// max(kNHGroups, 2 Npad/64)][Rpad]; c = dt / M and NT = N T.
+// max(kNHGroups, 2 Npad/32)][Rpad]; c = dt / M and NT = N T.
 constexpr int kNHGroups = 16;
 struct NHState {
     double *xi = nullptr, *part = nullptr;
     double c = 0.0, NT = 0.0;
 };
 // One thermostat step fused into a step kernel (integer-digit plan): the
-// kernel forms xi(t_k) = xi_in + c (sum of part_in's nparts 64-row partials -
-// NT), or takes xi_in as it is on the first step, heats at the rate -xi(t_k),
-// stores xi(t_k) in xi_out (row block 0) and the 64-row partials of
+// kernel forms xi(t_k) = xi_in + c (sum of part_in's nparts per-wave partials
+// - NT), or takes xi_in as it is on the first step, heats at the rate -xi(t_k),
+// stores xi(t_k) in xi_out (row block 0) and the per-wave partials of
 // sum_i y_i(t_k)^2 of the state it reads in part_out.  Consecutive steps swap
 // the slots, so no launch reads what it writes.
 struct NHFused {
