@@ -147,29 +147,26 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_field(
     const int nkb = Npad / 16;
     const int S = Npad / (32 * KC);  // stages (even: Npad is a multiple of 256)
     // thermostat: xi(t_k) of this lane's replica, formed before the products so
-    // that its loads overlap them
+    // that its loads overlap them.  The eight half-waves of the workgroup (all
+    // on the same 32 replicas) each add every eighth partial; the eight sums
+    // are then added in a fixed order (no wave has left the kernel yet, so
+    // the barrier is reached by all).
     double xi_k = 0.0;
     if constexpr (NH) {
-        const int rr = r0 + l32;
+        __shared__ double s_part[8][32];
+        const int rr = r0 + l32, grp = 2 * w + h;
         xi_k = nhf.xi_in[rr];
         if (!nhf.first) {
-            // partials added in the order q = 0, 1, ...; loaded 8 at a time so
-            // that the loads overlap
-            const double *pp = nhf.part_in + rr;
             double Ssum = 0.0;
-            int q = 0;
-            for (; q + 8 <= nhf.nparts; q += 8) {
-                double v[8];
+            for (int q = grp; q < nhf.nparts; q += 8) Ssum += nhf.part_in[(size_t)q * Rpad + rr];
+            s_part[grp][l32] = Ssum;
+            __syncthreads();
+            double S8 = 0.0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = pp[(size_t)(q + u) * Rpad];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) Ssum += v[u];
-            }
-            for (; q < nhf.nparts; ++q) Ssum += pp[(size_t)q * Rpad];
-            xi_k = xi_k + nhf.c * (Ssum - nhf.NT);
+            for (int q = 0; q < 8; ++q) S8 += s_part[q][l32];
+            xi_k = xi_k + nhf.c * (S8 - nhf.NT);
         }
     }
-
     v16i acc[NT][NW];
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt)
