@@ -286,6 +286,8 @@ int hsb_plan_info(hsb_ctx *h, int variant, int *precision);
  * and jobs[j].energy [R] double.  Validation failures return HSB_EINVAL before
  * any device work; HSB_ENUMERIC if any replica of any job became non-finite.
  * Contexts' own options (amplitude, interval, return mode) are not changed.
+ * Jobs run heated SB at their constant rate (HSB_THERMO_HEAT) and give no
+ * traces; runs with the thermostat or traces go through hsb_run_ex.
  */
 typedef struct {
     int32_t instance; /* index into hs[] */
