@@ -378,9 +378,9 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
     const bool nh = a->thermostat == HSB_THERMO_NOSE_HOOVER;
     if (nh) {
         if (h->nh_cap < Rpad) {
-            // xi: two slots; partials: the per-step plan's groups, or two sets
-            // of per-wave (32- or 64-row) partials for the digit plan's fused steps
-            const size_t parts = std::max<size_t>(hsb::kNHGroups, 2 * (size_t)(Npad / 32));
+            // xi: two slots; partials: two sets of per-wave (32- or 64-row)
+            // partials for the fused steps
+            const size_t parts = 2 * (size_t)(Npad / 32);
             if (h->nh.xi) (void)hipFree(h->nh.xi);
             if (h->nh.part) (void)hipFree(h->nh.part);
             h->nh.xi = h->nh.part = nullptr;
@@ -392,7 +392,7 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
         // dt as the step kernels use it: a float
         h->nh.c = (double)a->dt * a->nh_inv_mass;
         h->nh.NT = (double)N * a->nh_temperature;
-        HIP_TRY(hsb::launch_nh_init(h->nh, a->xi0, b.gamma, R, s));
+        HIP_TRY(hsb::launch_nh_init(h->nh, a->xi0, b.gamma, R, Rpad, s));
     }
 
     b.trace_e = a->trace_energy;
@@ -473,11 +473,24 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
                 // a(t_k) = a0 k / Ns in single precision; p = a0 - a(t_k)
                 const float ak = (a0 * (float)k) / (float)Ns;
                 const float p = a0 - ak;
-                if (nh)  // this step's heating rate -xi(t_k) from the state before it
-                    HIP_TRY(hsb::launch_nh_step(h->nh, b.Y, b.gamma, N, R, Rpad, s));
                 HIP_TRY(h->timer.begin(s));
-                HIP_TRY(hsb::launch_step_fp32(a->variant, h->dJ, b.B[cur], b.B[cur ^ 1], b.X, b.Y,
-                                              b.gamma, Npad, Rpad, p, c0, dt, a0dt, s));
+                if (nh) {  // the thermostat fused into the step: slots alternate
+                    const int j = k - k0, np = Npad / 32;
+                    hsb::NHFused f;
+                    f.xi_in = h->nh.xi + (size_t)(j & 1) * Rpad;
+                    f.xi_out = h->nh.xi + (size_t)((j + 1) & 1) * Rpad;
+                    f.part_out = h->nh.part + (size_t)(j & 1) * np * Rpad;
+                    f.part_in = h->nh.part + (size_t)((j + 1) & 1) * np * Rpad;
+                    f.nparts = np;
+                    f.first = j == 0;
+                    f.c = h->nh.c;
+                    f.NT = h->nh.NT;
+                    HIP_TRY(hsb::launch_step_fp32(a->variant, h->dJ, b.B[cur], b.B[cur ^ 1], b.X,
+                                                  b.Y, b.gamma, Npad, Rpad, p, c0, dt, a0dt, s, &f));
+                } else {
+                    HIP_TRY(hsb::launch_step_fp32(a->variant, h->dJ, b.B[cur], b.B[cur ^ 1], b.X,
+                                                  b.Y, b.gamma, Npad, Rpad, p, c0, dt, a0dt, s));
+                }
                 ++nrun;
                 cur ^= 1;
                 if (is_sample(k + 1)) {
@@ -486,6 +499,12 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
                     rc = sample(k + 1);
                     if (rc) return rc;
                 }
+            }
+            if (nh) {  // xi after the last step, from its slot and partials, into slot 0
+                const int steps = k1 - k0, np = Npad / 32;
+                HIP_TRY(hsb::launch_nh_final(h->nh.xi + (size_t)(steps & 1) * Rpad,
+                                             h->nh.part + (size_t)((steps - 1) & 1) * np * Rpad,
+                                             np, R, Rpad, h->nh.xi, h->nh.c, h->nh.NT, s));
             }
         }
     }

@@ -107,14 +107,13 @@ hipError_t launch_make_operand(float *B, const float *X, int variant, int Npad, 
 hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int R, int Rpad,
                              hipStream_t s);
 // Nose-Hoover thermostat of a run (eqs. (6)-(8)): xi in FP64 [2][Rpad] (slot 0
-// holds the start and the final value), partial sums of y^2 [at least
-// max(kNHGroups, 2 Npad/32)][Rpad]; c = dt / M and NT = N T.
-constexpr int kNHGroups = 16;
+// holds the start and the final value), partial sums of y^2 [2 Npad/32][Rpad];
+// c = dt / M and NT = N T.
 struct NHState {
     double *xi = nullptr, *part = nullptr;
     double c = 0.0, NT = 0.0;
 };
-// One thermostat step fused into a step kernel (integer-digit plan): the
+// One thermostat step fused into a step kernel (FP32 and digit plans): the
 // kernel forms xi(t_k) = xi_in + c (sum of part_in's nparts per-wave partials
 // - NT), or takes xi_in as it is on the first step, heats at the rate -xi(t_k),
 // stores xi(t_k) in xi_out (row block 0) and the per-wave partials of
@@ -132,13 +131,9 @@ struct NHFused {
 // after the last fused step
 hipError_t launch_nh_final(const double *xi_in, const double *part_in, int nparts, int R,
                            int Rpad, double *xi_dst, double c, double NT, hipStream_t s);
-// xi = xi0 (device [R]) if given, else -gamma[r]
+// xi = xi0 (device [R]) if given, else -gamma[r]; 0 in the padding columns [R, Rpad)
 hipError_t launch_nh_init(const NHState &nh, const double *xi0, const float *gamma, int R,
-                          hipStream_t s);
-// before step k: gamma[r] = fl32(-xi(t_k)); xi(t_k+1) = xi(t_k) + c (sum_i y_i(t_k)^2 - NT)
-// over rows [0, N) of Y [.][Rpad]
-hipError_t launch_nh_step(const NHState &nh, const float *Y, float *gamma, int N, int R, int Rpad,
-                          hipStream_t s);
+                          int Rpad, hipStream_t s);
 hipError_t launch_copy_f64(double *dst, const double *src, int n, hipStream_t s);
 // allocation of the run state for Npad rows and Rpad columns (all or nothing);
 // without the FP32 plan's operand and energy buffers (B, epart) if !fp32_plan
@@ -166,9 +161,11 @@ void free_state_bufs(StateBufs &b);
 hipError_t launch_reset_tracking(const StateBufs &b, int Rpad, hipStream_t s);
 // *flag (device) = 1 if any of X[0 .. n) has |x| > 1 or is not finite, else 0
 hipError_t launch_bound_check(const float *X, size_t n, int32_t *flag, hipStream_t s);
+// one step of the FP32 plan; with nh, the thermostat fused into it (32-row
+// partials, see NHFused)
 hipError_t launch_step_fp32(int variant, const float *J, const float *Bin, float *Bout, float *X,
                             float *Y, const float *gamma, int Npad, int Rpad, float p, float c0,
-                            float dt, float a0dt, hipStream_t s);
+                            float dt, float a0dt, hipStream_t s, const NHFused *nh = nullptr);
 // energy partials: exact path (FP32 products, J integer-valued) -> nblk = Npad/32
 hipError_t launch_energy_fp32(const float *J, const float *X, double *epart, int Npad, int Rpad,
                               hipStream_t s);

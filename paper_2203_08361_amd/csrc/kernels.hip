@@ -64,40 +64,11 @@ __global__ void k_fill_gamma(float *__restrict__ g, const float *__restrict__ ga
 //   xi(t_k+1) = xi(t_k) + c (sum_i y_i(t_k)^2 - N T),  c = dt / M,
 // with the sum of the state before the step (explicit Euler on eq. (8)).
 // Start value: xi0[r], or -gamma_r (so that 1/M = 0 is heated SB itself).
+// Padding columns get xi = 0, so that the steps read defined values there.
 __global__ void k_nh_init(double *__restrict__ xi, const double *__restrict__ xi0,
-                          const float *__restrict__ g, int R) {
+                          const float *__restrict__ g, int R, int Rpad) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < R) xi[r] = xi0 ? xi0[r] : -(double)g[r];
-}
-
-// Partial sums of y^2 of row group blockIdx.y (rows [y rows_per, ...)) for 64
-// replicas: 4 waves split the group's rows, combined in a fixed order.
-__global__ __launch_bounds__(256) void k_nh_partial(const float *__restrict__ Y, int N, int Rpad,
-                                                    int rows_per, double *__restrict__ part) {
-    __shared__ double s_p[4][64];
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int r = blockIdx.x * 64 + l;
-    const int i0 = blockIdx.y * rows_per;
-    const int i1 = i0 + rows_per < N ? i0 + rows_per : N;
-    double t = 0.0;
-    for (int i = i0 + w; i < i1; i += 4) {
-        const double y = Y[(size_t)i * Rpad + r];
-        t += y * y;
-    }
-    s_p[w][l] = t;
-    __syncthreads();
-    if (w == 0) part[(size_t)blockIdx.y * Rpad + r] = ((s_p[0][l] + s_p[1][l]) + s_p[2][l]) + s_p[3][l];
-}
-
-__global__ void k_nh_update(const double *__restrict__ part, int groups, int R, int Rpad,
-                            double *__restrict__ xi, float *__restrict__ g, double c, double NT) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    double S = 0.0;
-    for (int q = 0; q < groups; ++q) S += part[(size_t)q * Rpad + r];
-    const double x = xi[r];
-    g[r] = (float)(-x);
-    xi[r] = x + c * (S - NT);
+    if (r < Rpad) xi[r] = r >= R ? 0.0 : (xi0 ? xi0[r] : -(double)g[r]);
 }
 
 __global__ void k_nh_final(const double *__restrict__ xi_in, const double *__restrict__ part_in,
@@ -186,22 +157,43 @@ __device__ __forceinline__ v16f gemm_tile_fp32(const float *__restrict__ J,
 }
 
 // One time step (field + fused eqs. (16)-(22)).  Grid (Rpad/64, Npad/64).
-template <int VARIANT>
+template <int VARIANT, bool NH>
 __global__ __launch_bounds__(256) void k_step_fp32(const float *__restrict__ J,
                                                    const float *__restrict__ Bin,
                                                    float *__restrict__ Bout, float *__restrict__ X,
                                                    float *__restrict__ Y,
                                                    const float *__restrict__ gam, int Npad,
                                                    int Rpad, float p, float c0, float dt,
-                                                   float a0dt) {
+                                                   float a0dt, NHFused nhf) {
     __shared__ float As[2][32][68];
     __shared__ float Bs[2][32][68];
     const int r0 = blockIdx.x * kTile, i0 = blockIdx.y * kTile;
-    const v16f acc = gemm_tile_fp32<false>(J, Bin, Npad, Rpad, i0, r0, As, Bs);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = w >> 1, wc = w & 1;
     const int r = r0 + 32 * wc + (lane & 31);
-    const float gdt = gam[r] * dt;
+    // thermostat: xi(t_k) of this lane's replica from the previous step's
+    // 32-row partials; the four half-waves on the same replicas each add every
+    // fourth, combined in a fixed order (before the products, so that the
+    // loads overlap them)
+    double xi_k = 0.0;
+    if constexpr (NH) {
+        __shared__ double s_part[2][4][32];
+        const int grp = 2 * wr + (lane >> 5);
+        xi_k = nhf.xi_in[r];
+        if (!nhf.first) {
+            double Ssum = 0.0;
+            for (int q = grp; q < nhf.nparts; q += 4) Ssum += nhf.part_in[(size_t)q * Rpad + r];
+            s_part[wc][grp][lane & 31] = Ssum;
+            __syncthreads();
+            double S4 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) S4 += s_part[wc][q][lane & 31];
+            xi_k = xi_k + nhf.c * (S4 - nhf.NT);
+        }
+        if (i0 == 0 && wr == 0 && (lane >> 5) == 0) nhf.xi_out[r] = xi_k;
+    }
+    const v16f acc = gemm_tile_fp32<false>(J, Bin, Npad, Rpad, i0, r0, As, Bs);
+    const float gdt = NH ? (float)(-xi_k) * dt : gam[r] * dt;
     // all loads of the tile's state before the first store (they overlap)
     float xs[16], ys[16];
 #pragma unroll
@@ -209,6 +201,13 @@ __global__ __launch_bounds__(256) void k_step_fp32(const float *__restrict__ J,
         const int i = i0 + 32 * wr + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         xs[v] = X[(size_t)i * Rpad + r];
         ys[v] = Y[(size_t)i * Rpad + r];
+    }
+    if constexpr (NH) {  // sum of y_i(t_k)^2 over this wave's 32 rows (exact squares)
+        double t2 = 0.0;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) t2 += (double)ys[v] * (double)ys[v];
+        t2 += __shfl_xor(t2, 32);
+        if ((lane >> 5) == 0) nhf.part_out[(size_t)((i0 + 32 * wr) / 32) * Rpad + r] = t2;
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -549,18 +548,9 @@ hipError_t launch_fill_gamma(float *g, const float *gamma_rep, float gamma, int 
 }
 
 hipError_t launch_nh_init(const NHState &nh, const double *xi0, const float *gamma, int R,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_nh_init, dim3(cdiv(R, 256)), dim3(256), 0, s, nh.xi, xi0, gamma, R);
-    return hipGetLastError();
-}
-
-hipError_t launch_nh_step(const NHState &nh, const float *Y, float *gamma, int N, int R, int Rpad,
-                          hipStream_t s) {
-    const int rows_per = (N + kNHGroups - 1) / kNHGroups;
-    hipLaunchKernelGGL(k_nh_partial, dim3(cdiv(Rpad, 64), kNHGroups), dim3(256), 0, s, Y, N, Rpad,
-                       rows_per, nh.part);
-    hipLaunchKernelGGL(k_nh_update, dim3(cdiv(R, 256)), dim3(256), 0, s, nh.part, kNHGroups, R,
-                       Rpad, nh.xi, gamma, nh.c, nh.NT);
+                          int Rpad, hipStream_t s) {
+    hipLaunchKernelGGL(k_nh_init, dim3(cdiv(Rpad, 256)), dim3(256), 0, s, nh.xi, xi0, gamma, R,
+                       Rpad);
     return hipGetLastError();
 }
 
@@ -590,14 +580,21 @@ hipError_t launch_reset_tracking(const StateBufs &b, int Rpad, hipStream_t s) {
 
 hipError_t launch_step_fp32(int variant, const float *J, const float *Bin, float *Bout, float *X,
                             float *Y, const float *gamma, int Npad, int Rpad, float p, float c0,
-                            float dt, float a0dt, hipStream_t s) {
+                            float dt, float a0dt, hipStream_t s, const NHFused *nh) {
     const dim3 grid(Rpad / kTile, Npad / kTile);
-    if (variant == 0)
-        hipLaunchKernelGGL(k_step_fp32<0>, grid, dim3(256), 0, s, J, Bin, Bout, X, Y, gamma, Npad,
-                           Rpad, p, c0, dt, a0dt);
+    const NHFused f = nh ? *nh : NHFused{};
+    if (variant == 0 && !nh)
+        hipLaunchKernelGGL((k_step_fp32<0, false>), grid, dim3(256), 0, s, J, Bin, Bout, X, Y,
+                           gamma, Npad, Rpad, p, c0, dt, a0dt, f);
+    else if (variant == 0)
+        hipLaunchKernelGGL((k_step_fp32<0, true>), grid, dim3(256), 0, s, J, Bin, Bout, X, Y,
+                           gamma, Npad, Rpad, p, c0, dt, a0dt, f);
+    else if (!nh)
+        hipLaunchKernelGGL((k_step_fp32<1, false>), grid, dim3(256), 0, s, J, Bin, Bout, X, Y,
+                           gamma, Npad, Rpad, p, c0, dt, a0dt, f);
     else
-        hipLaunchKernelGGL(k_step_fp32<1>, grid, dim3(256), 0, s, J, Bin, Bout, X, Y, gamma, Npad,
-                           Rpad, p, c0, dt, a0dt);
+        hipLaunchKernelGGL((k_step_fp32<1, true>), grid, dim3(256), 0, s, J, Bin, Bout, X, Y,
+                           gamma, Npad, Rpad, p, c0, dt, a0dt, f);
     return hipGetLastError();
 }
 
