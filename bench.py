@@ -339,7 +339,7 @@ def main() -> int:
     def evaluation_workload():
         # the 700-spin comparison of the Results: 100 instances, the energy at
         # the last step, the four forms at the paper's parameters over a range
-        # of N_s; one hsb_run_batch call per (form, N_s)
+        # of N_s; one hsb_run_batch call per (variant, dt, N_s)
         from paper_2203_08361_amd import evaluate as ev
 
         n_inst, n_spins, trials, grid = 100, 700, 1024, (200, 500, 1000, 2000)
