@@ -129,3 +129,16 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         hsb.load_library()
     with pytest.raises(RuntimeError, match="not built"):
         hsb.Context(np.zeros((4, 4), dtype=np.float32))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message
+    (before touching any device)."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
