@@ -110,7 +110,12 @@ typedef enum {
     HSB_PREC_MIXED = 2, /* J exact in FP4 (entries in {0, +-0.5, +-1, +-1.5, +-2, +-3, +-4,
                            +-6}) and N <= 2048: the FP4 plan (dSB exact; bSB from base-8
                            digits of x); otherwise, N <= 16384: the integer-digit plan */
-    HSB_PREC_DIGITS = 3 /* the integer-digit plan (N <= 16384) whatever J */
+    HSB_PREC_DIGITS = 3, /* the integer-digit plan (N <= 16384) whatever J */
+    HSB_PREC_INCREMENTAL = 4 /* dSB with integer J in [-127, 127], N <= 16384: the exact
+                                integer field of the current signs is carried from step
+                                to step, changed by 2 s_j J[:, j] for each spin j that
+                                flipped (never chosen by AUTO; bSB, other J or the
+                                thermostat: HSB_EUNSUPPORTED) */
 } hsb_precision;
 
 /*
@@ -131,7 +136,13 @@ typedef enum {
  *                    does bSB on HSB_PLAN_FP4: otherwise MIXED and DIGITS return
  *                    HSB_EUNSUPPORTED and AUTO runs FP32.
  */
-typedef enum { HSB_PLAN_FP32 = 0, HSB_PLAN_FP4 = 1, HSB_PLAN_DIGITS = 2 } hsb_plan;
+typedef enum {
+    HSB_PLAN_FP32 = 0,
+    HSB_PLAN_FP4 = 1,
+    HSB_PLAN_DIGITS = 2,
+    HSB_PLAN_INCREMENTAL = 3 /* HSB_PREC_INCREMENTAL: two launches per step, work per
+                                step proportional to the number of flipped spins */
+} hsb_plan;
 
 /*
  * hsb_create -- validate J and build its device copies (the J store).
@@ -260,7 +271,7 @@ int hsb_num_samples(hsb_ctx *h, int start_step, int steps, int *n);
 
 /*
  * hsb_plan_info -- the precision plan AUTO (or the forced option) would use
- * for `variant` on this J: HSB_PREC_FP32 or HSB_PREC_MIXED.
+ * for `variant` on this J: HSB_PREC_FP32, HSB_PREC_MIXED or HSB_PREC_INCREMENTAL.
  */
 int hsb_plan_info(hsb_ctx *h, int variant, int *precision);
 

@@ -65,6 +65,8 @@ struct hsb_ctx {
     size_t bjobs_cap = 0;
     int32_t *d_flag = nullptr;             // start-state bound check
     hsb::NHState nh{};                     // thermostat of the current run
+    hsb::IncState inc{};                   // incremental dSB field
+    size_t inc_cap = 0;                    // its capacity in Rpad * Npad elements
     int nh_cap = 0;                        // its capacity in columns
     std::vector<float> hJ;      // host copy kept for lazy device re-layouts
     // options
@@ -209,6 +211,9 @@ extern "C" void hsb_destroy(hsb_ctx *h) {
     if (h->d_flag) (void)hipFree(h->d_flag);
     if (h->nh.xi) (void)hipFree(h->nh.xi);
     if (h->nh.part) (void)hipFree(h->nh.part);
+    if (h->inc.F) (void)hipFree(h->inc.F);
+    if (h->inc.list) (void)hipFree(h->inc.list);
+    if (h->inc.cnt) (void)hipFree(h->inc.cnt);
     graph_drop(h);
     if (h->gev_in) (void)hipEventDestroy(h->gev_in);
     if (h->gev_out) (void)hipEventDestroy(h->gev_out);
@@ -239,8 +244,9 @@ extern "C" int hsb_set_option(hsb_ctx *h, int key, double v) {
         return HSB_OK;
     case HSB_OPT_PRECISION:
         if (!(v == HSB_PREC_AUTO || v == HSB_PREC_FP32 || v == HSB_PREC_MIXED ||
-              v == HSB_PREC_DIGITS))
-            return fail(HSB_EINVAL, "PRECISION must be AUTO (0), FP32 (1), MIXED (2) or DIGITS (3)");
+              v == HSB_PREC_DIGITS || v == HSB_PREC_INCREMENTAL))
+            return fail(HSB_EINVAL, "PRECISION must be AUTO (0), FP32 (1), MIXED (2), DIGITS (3) "
+                                    "or INCREMENTAL (4)");
         h->precision = (int)v;
         return HSB_OK;
     case HSB_OPT_TIMING:
@@ -303,7 +309,12 @@ namespace {
 
 // Execution plans (hsb_plan); the precision reported for both mixed plans is
 // HSB_PREC_MIXED.
-enum Plan { PLAN_FP32 = HSB_PLAN_FP32, PLAN_FP4 = HSB_PLAN_FP4, PLAN_DIGITS = HSB_PLAN_DIGITS };
+enum Plan {
+    PLAN_FP32 = HSB_PLAN_FP32,
+    PLAN_FP4 = HSB_PLAN_FP4,
+    PLAN_DIGITS = HSB_PLAN_DIGITS,
+    PLAN_INCREMENTAL = HSB_PLAN_INCREMENTAL
+};
 
 // Which plan runs (variant, this J, the precision option), or HSB_EUNSUPPORTED.
 //   FP32:  the plain FP32 per-step plan, always.
@@ -317,6 +328,11 @@ int choose_plan(const hsb_ctx *h, int variant, int *plan) {
     const bool dig_ok = h->N <= hsb::i8_max_n();
     if (h->precision == HSB_PREC_FP32) {
         *plan = PLAN_FP32;
+    } else if (h->precision == HSB_PREC_INCREMENTAL) {
+        if (variant != HSB_DSB || !h->j_i8_exact || !dig_ok)
+            return fail(HSB_EUNSUPPORTED, "INCREMENTAL precision needs dSB, integer J in "
+                                          "[-127, 127] and N <= %d", hsb::i8_max_n());
+        *plan = PLAN_INCREMENTAL;
     } else if (h->precision == HSB_PREC_DIGITS) {
         if (!dig_ok) return fail(HSB_EUNSUPPORTED, "DIGITS precision needs N <= %d", hsb::i8_max_n());
         *plan = PLAN_DIGITS;
@@ -346,7 +362,9 @@ extern "C" int hsb_plan_info(hsb_ctx *h, int variant, int *precision) {
         return fail(HSB_EINVAL, "variant must be HSB_BSB (0) or HSB_DSB (1)");
     int plan = 0;
     const int rc = choose_plan(h, variant, &plan);
-    if (rc == HSB_OK) *precision = plan == PLAN_FP32 ? HSB_PREC_FP32 : HSB_PREC_MIXED;
+    if (rc == HSB_OK)
+        *precision = plan == PLAN_FP32 ? HSB_PREC_FP32
+                     : plan == PLAN_INCREMENTAL ? HSB_PREC_INCREMENTAL : HSB_PREC_MIXED;
     return rc;
 }
 
@@ -447,6 +465,39 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
         ir.nh = nh ? &h->nh : nullptr;
         rc = hsb::i8_run(h->i8, ir, b, h->dJ, s, h->timer);
         if (rc != HSB_OK) return fail(rc, "%s", hsb::i8_error());
+    } else if (plan == PLAN_INCREMENTAL) {
+        const size_t need = (size_t)Rpad * Npad;
+        if (h->inc_cap < need) {
+            if (h->inc.F) (void)hipFree(h->inc.F);
+            if (h->inc.list) (void)hipFree(h->inc.list);
+            if (h->inc.cnt) (void)hipFree(h->inc.cnt);
+            h->inc = hsb::IncState{};
+            h->inc_cap = 0;
+            HIP_TRY(hipMalloc((void **)&h->inc.F, sizeof(int32_t) * need));
+            HIP_TRY(hipMalloc((void **)&h->inc.list, sizeof(int32_t) * need));
+            HIP_TRY(hipMalloc((void **)&h->inc.cnt, sizeof(int32_t) * 2 * Rpad));
+            h->inc_cap = need;
+        }
+        HIP_TRY(hsb::launch_inc_init(h->dJ, b.X, h->inc, N, Npad, Rpad, R, s));
+        if (a->steps == 0) {
+            rc = sample(k0);
+            if (rc) return rc;
+        }
+        size_t nrun = 0;
+        for (int k = k0; k < k1; ++k) {
+            const float ak = (a0 * (float)k) / (float)Ns;
+            const float p = a0 - ak;
+            HIP_TRY(h->timer.begin(s));
+            HIP_TRY(hsb::launch_inc_step(h->dJ, b.X, b.Y, b.gamma, h->inc, k - k0, N, Npad, Rpad,
+                                         R, p, c0, dt, a0dt, s));
+            ++nrun;
+            if (is_sample(k + 1)) {
+                HIP_TRY(h->timer.end(s, nrun));
+                nrun = 0;
+                rc = sample(k + 1);
+                if (rc) return rc;
+            }
+        }
     } else if (plan == PLAN_FP4) {
         if (!h->pj) {
             rc = hsb::persistent_create(h->hJ.data(), N, &h->pj);
@@ -645,6 +696,8 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
     if (rc != HSB_OK) return rc;
     if (a->thermostat == HSB_THERMO_NOSE_HOOVER && plan == PLAN_FP4)
         plan = h->N <= hsb::i8_max_n() ? PLAN_DIGITS : PLAN_FP32;
+    if (a->thermostat == HSB_THERMO_NOSE_HOOVER && plan == PLAN_INCREMENTAL)
+        return fail(HSB_EUNSUPPORTED, "the thermostat does not run on the INCREMENTAL plan");
     HIP_TRY(hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)a->stream;
     const int R = a->R;

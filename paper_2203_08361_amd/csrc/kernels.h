@@ -134,6 +134,20 @@ hipError_t launch_nh_final(const double *xi_in, const double *part_in, int npart
 // xi = xi0 (device [R]) if given, else -gamma[r]; 0 in the padding columns [R, Rpad)
 hipError_t launch_nh_init(const NHState &nh, const double *xi0, const float *gamma, int R,
                           int Rpad, hipStream_t s);
+// Incremental dSB field (integer J, |J_ij| <= 127, N <= 16384, so every field
+// is an exact int32): the field of the current signs F [Rpad][Npad], the
+// per-replica lists of flipped spins [Rpad][Npad] and their counters [2][Rpad]
+// (one set per step parity).  J is the zero-padded FP32 store [Npad][Npad].
+struct IncState {
+    int32_t *F = nullptr, *list = nullptr, *cnt = nullptr;
+};
+// F = J sgn(X) for replicas < R; counters to 0
+hipError_t launch_inc_init(const float *J, const float *X, IncState &inc, int N, int Npad,
+                           int Rpad, int R, hipStream_t s);
+// step j of the call: update X, Y from F, list the flips, add them to F
+hipError_t launch_inc_step(const float *J, float *X, float *Y, const float *gamma, IncState &inc,
+                           int j, int N, int Npad, int Rpad, int R, float p, float c0, float dt,
+                           float a0dt, hipStream_t s);
 hipError_t launch_copy_f64(double *dst, const double *src, int n, hipStream_t s);
 // allocation of the run state for Npad rows and Rpad columns (all or nothing);
 // without the FP32 plan's operand and energy buffers (B, epart) if !fp32_plan

@@ -81,6 +81,80 @@ __global__ void k_nh_final(const double *__restrict__ xi_in, const double *__res
     xi_dst[r] = xi_in[r] + c * (S - NT);
 }
 
+// ---------------------------------------------- incremental dSB field
+// For integer J the dSB field f = J sgn(x) (eq. (5)) is an exact integer, so
+// it can be carried from step to step: when the spins j flip to s_j, f
+// changes by 2 s_j J[:, j].  The field of the current signs is kept as int32,
+// replica-major ([Rpad][Npad]); every integer sum is exact in any order.
+// J is symmetric, so its column j is the contiguous row j.
+
+// F[r][i] = sum_j J[i][j] sgn(x_j of replica r), rows i < Npad, replicas r < R.
+__global__ __launch_bounds__(256) void k_inc_init(const float *__restrict__ J,
+                                                  const float *__restrict__ X,
+                                                  int32_t *__restrict__ F, int N, int Npad,
+                                                  int Rpad) {
+    const int i = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
+    if (i >= Npad) return;
+    int acc = 0;
+    for (int j = 0; j < N; ++j) {
+        const int Jv = (int)J[(size_t)j * Npad + i];
+        acc += X[(size_t)j * Rpad + r] >= 0.0f ? Jv : -Jv;
+    }
+    F[(size_t)r * Npad + i] = acc;
+}
+
+// One step from the exact field: the update of eqs. (16)-(22) (the common
+// canonical form), then every spin whose sign changed goes on its replica's
+// list as +(i+1) (now +1) or -(i+1) (now -1).
+__global__ __launch_bounds__(256) void k_inc_step(float *__restrict__ X, float *__restrict__ Y,
+                                                  const int32_t *__restrict__ F,
+                                                  const float *__restrict__ gam,
+                                                  int32_t *__restrict__ cnt,
+                                                  int32_t *__restrict__ list, int N, int Npad,
+                                                  int Rpad, int R, float p, float c0, float dt,
+                                                  float a0dt) {
+    const int r = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+    if (r >= R || i >= N) return;
+    const size_t idx = (size_t)i * Rpad + r;
+    float x = X[idx], y = Y[idx];
+    const bool was = x >= 0.0f;
+    sb_update((float)F[(size_t)r * Npad + i], p, c0, dt, a0dt, gam[r] * dt, x, y);
+    X[idx] = x;
+    Y[idx] = y;
+    const bool now = x >= 0.0f;
+    if (now != was) {
+        const int pos = atomicAdd(cnt + r, 1);
+        list[(size_t)r * Npad + pos] = now ? i + 1 : -(i + 1);
+    }
+}
+
+// F[r][i] += 2 s_j J[j][i] over the listed flips of replica r; the block of
+// row 0 also clears the next step's counter of r.
+__global__ __launch_bounds__(256) void k_inc_field(int32_t *__restrict__ F,
+                                                   const float *__restrict__ J,
+                                                   const int32_t *__restrict__ cnt,
+                                                   const int32_t *__restrict__ list,
+                                                   int32_t *__restrict__ cnt_next, int Npad) {
+    const int i = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
+    if (blockIdx.x == 0 && threadIdx.x == 0) cnt_next[r] = 0;
+    if (i >= Npad) return;
+    const int n = cnt[r];
+    const int32_t *L = list + (size_t)r * Npad;
+    int acc = F[(size_t)r * Npad + i];
+    for (int q = 0; q < n; ++q) {
+        const int e = L[q];
+        const int j = (e > 0 ? e : -e) - 1;
+        const int Jv = (int)J[(size_t)j * Npad + i];
+        acc += e > 0 ? 2 * Jv : -2 * Jv;
+    }
+    F[(size_t)r * Npad + i] = acc;
+}
+
+__global__ void k_zero_i32n(int32_t *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 __global__ void k_copy_f64(double *__restrict__ dst, const double *__restrict__ src, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
@@ -558,6 +632,26 @@ hipError_t launch_nh_final(const double *xi_in, const double *part_in, int npart
                            int Rpad, double *xi_dst, double c, double NT, hipStream_t s) {
     hipLaunchKernelGGL(k_nh_final, dim3(cdiv(R, 256)), dim3(256), 0, s, xi_in, part_in, nparts,
                        R, Rpad, xi_dst, c, NT);
+    return hipGetLastError();
+}
+
+hipError_t launch_inc_init(const float *J, const float *X, IncState &inc, int N, int Npad,
+                          int Rpad, int R, hipStream_t s) {
+    hipLaunchKernelGGL(k_inc_init, dim3(cdiv(Npad, 256), R), dim3(256), 0, s, J, X, inc.F, N,
+                       Npad, Rpad);
+    hipLaunchKernelGGL(k_zero_i32n, dim3(cdiv(2 * (size_t)Rpad, 256)), dim3(256), 0, s, inc.cnt,
+                       2 * Rpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_inc_step(const float *J, float *X, float *Y, const float *gamma, IncState &inc,
+                           int j, int N, int Npad, int Rpad, int R, float p, float c0, float dt,
+                           float a0dt, hipStream_t s) {
+    int32_t *cnt = inc.cnt + (size_t)(j & 1) * Rpad, *next = inc.cnt + (size_t)((j + 1) & 1) * Rpad;
+    hipLaunchKernelGGL(k_inc_step, dim3(cdiv(R, 256), N), dim3(256), 0, s, X, Y, inc.F, gamma,
+                       cnt, inc.list, N, Npad, Rpad, R, p, c0, dt, a0dt);
+    hipLaunchKernelGGL(k_inc_field, dim3(cdiv(Npad, 256), R), dim3(256), 0, s, inc.F, J, cnt,
+                       inc.list, next, Npad);
     return hipGetLastError();
 }
 

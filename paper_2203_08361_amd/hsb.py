@@ -21,9 +21,11 @@ HSB_OPT_TIMING, HSB_OPT_KERNEL_MS, HSB_OPT_KERNEL_LAUNCHES, HSB_OPT_LAST_PLAN = 
 HSB_OPT_LOCAL_EXCHANGE = 8
 HSB_OPT_GRAPH = 9
 HSB_OPT_GRAPH_LAUNCHES = 10
-HSB_PLAN_FP32, HSB_PLAN_FP4, HSB_PLAN_DIGITS = 0, 1, 2
-PLAN_NAMES = {HSB_PLAN_FP32: "fp32", HSB_PLAN_FP4: "fp4", HSB_PLAN_DIGITS: "digits"}
+HSB_PLAN_FP32, HSB_PLAN_FP4, HSB_PLAN_DIGITS, HSB_PLAN_INCREMENTAL = 0, 1, 2, 3
+PLAN_NAMES = {HSB_PLAN_FP32: "fp32", HSB_PLAN_FP4: "fp4", HSB_PLAN_DIGITS: "digits",
+              HSB_PLAN_INCREMENTAL: "incremental"}
 HSB_PREC_AUTO, HSB_PREC_FP32, HSB_PREC_MIXED, HSB_PREC_DIGITS = 0, 1, 2, 3
+HSB_PREC_INCREMENTAL = 4
 HSB_THERMO_HEAT, HSB_THERMO_NOSE_HOOVER = 0, 1
 
 EXPORTED = ("hsb_create", "hsb_destroy", "hsb_last_error", "hsb_set_option", "hsb_get_option",
@@ -308,7 +310,7 @@ class Context:
              "local_exchange": HSB_OPT_LOCAL_EXCHANGE, "graph": HSB_OPT_GRAPH,
              "graph_launches": HSB_OPT_GRAPH_LAUNCHES}
     _PREC = {"auto": HSB_PREC_AUTO, "fp32": HSB_PREC_FP32, "mixed": HSB_PREC_MIXED,
-             "digits": HSB_PREC_DIGITS}
+             "digits": HSB_PREC_DIGITS, "incremental": HSB_PREC_INCREMENTAL}
 
     def set_option(self, key, value):
         if isinstance(value, str):
@@ -319,10 +321,12 @@ class Context:
         return hsb_get_option(self.h, self._KEYS.get(key, key))
 
     def plan(self, variant):
-        return {HSB_PREC_FP32: "fp32", HSB_PREC_MIXED: "mixed"}[hsb_plan_info(self.h, variant)]
+        return {HSB_PREC_FP32: "fp32", HSB_PREC_MIXED: "mixed",
+                HSB_PREC_INCREMENTAL: "incremental"}[hsb_plan_info(self.h, variant)]
 
     def last_plan(self):
-        """Execution plan of the last successful run: "fp32", "fp4" or "digits"."""
+        """Execution plan of the last successful run: "fp32", "fp4", "digits" or
+        "incremental"."""
         return PLAN_NAMES.get(int(self.get_option("last_plan")))
 
     def run(self, variant, a0, c0, dt, gamma, steps, R, seed, allow_numeric=False):
