@@ -92,15 +92,18 @@ __global__ void k_nh_final(const double *__restrict__ xi_in, const double *__res
 __global__ __launch_bounds__(256) void k_inc_init(const float *__restrict__ J,
                                                   const float *__restrict__ X,
                                                   int32_t *__restrict__ F, int N, int Npad,
-                                                  int Rpad) {
-    const int i = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
+                                                  int Rpad, int R) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= Npad) return;
-    int acc = 0;
-    for (int j = 0; j < N; ++j) {
-        const int Jv = (int)J[(size_t)j * Npad + i];
-        acc += X[(size_t)j * Rpad + r] >= 0.0f ? Jv : -Jv;
+    // replicas r = blockIdx.y, blockIdx.y + gridDim.y, ... (grid.y is capped)
+    for (int r = blockIdx.y; r < R; r += gridDim.y) {
+        int acc = 0;
+        for (int j = 0; j < N; ++j) {
+            const int Jv = (int)J[(size_t)j * Npad + i];
+            acc += X[(size_t)j * Rpad + r] >= 0.0f ? Jv : -Jv;
+        }
+        F[(size_t)r * Npad + i] = acc;
     }
-    F[(size_t)r * Npad + i] = acc;
 }
 
 // One step from the exact field: the update of eqs. (16)-(22) (the common
@@ -134,20 +137,24 @@ __global__ __launch_bounds__(256) void k_inc_field(int32_t *__restrict__ F,
                                                    const float *__restrict__ J,
                                                    const int32_t *__restrict__ cnt,
                                                    const int32_t *__restrict__ list,
-                                                   int32_t *__restrict__ cnt_next, int Npad) {
-    const int i = blockIdx.x * 256 + threadIdx.x, r = blockIdx.y;
-    if (blockIdx.x == 0 && threadIdx.x == 0) cnt_next[r] = 0;
-    if (i >= Npad) return;
-    const int n = cnt[r];
-    const int32_t *L = list + (size_t)r * Npad;
-    int acc = F[(size_t)r * Npad + i];
-    for (int q = 0; q < n; ++q) {
-        const int e = L[q];
-        const int j = (e > 0 ? e : -e) - 1;
-        const int Jv = (int)J[(size_t)j * Npad + i];
-        acc += e > 0 ? 2 * Jv : -2 * Jv;
+                                                   int32_t *__restrict__ cnt_next, int Npad,
+                                                   int R) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    // replicas r = blockIdx.y, blockIdx.y + gridDim.y, ... (grid.y is capped)
+    for (int r = blockIdx.y; r < R; r += gridDim.y) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) cnt_next[r] = 0;
+        if (i >= Npad) continue;
+        const int n = cnt[r];
+        const int32_t *L = list + (size_t)r * Npad;
+        int acc = F[(size_t)r * Npad + i];
+        for (int q = 0; q < n; ++q) {
+            const int e = L[q];
+            const int j = (e > 0 ? e : -e) - 1;
+            const int Jv = (int)J[(size_t)j * Npad + i];
+            acc += e > 0 ? 2 * Jv : -2 * Jv;
+        }
+        F[(size_t)r * Npad + i] = acc;
     }
-    F[(size_t)r * Npad + i] = acc;
 }
 
 __global__ void k_zero_i32n(int32_t *p, int n) {
@@ -635,10 +642,14 @@ hipError_t launch_nh_final(const double *xi_in, const double *part_in, int npart
     return hipGetLastError();
 }
 
+// grid.y of the per-replica incremental launches: at most 32768 (the
+// hardware limit is 65535); the kernels stride over the remaining replicas
+static unsigned inc_grid_y(int R) { return (unsigned)(R < 32768 ? R : 32768); }
+
 hipError_t launch_inc_init(const float *J, const float *X, IncState &inc, int N, int Npad,
                           int Rpad, int R, hipStream_t s) {
-    hipLaunchKernelGGL(k_inc_init, dim3(cdiv(Npad, 256), R), dim3(256), 0, s, J, X, inc.F, N,
-                       Npad, Rpad);
+    hipLaunchKernelGGL(k_inc_init, dim3(cdiv(Npad, 256), inc_grid_y(R)), dim3(256), 0, s, J, X,
+                       inc.F, N, Npad, Rpad, R);
     hipLaunchKernelGGL(k_zero_i32n, dim3(cdiv(2 * (size_t)Rpad, 256)), dim3(256), 0, s, inc.cnt,
                        2 * Rpad);
     return hipGetLastError();
@@ -650,8 +661,8 @@ hipError_t launch_inc_step(const float *J, float *X, float *Y, const float *gamm
     int32_t *cnt = inc.cnt + (size_t)(j & 1) * Rpad, *next = inc.cnt + (size_t)((j + 1) & 1) * Rpad;
     hipLaunchKernelGGL(k_inc_step, dim3(cdiv(R, 256), N), dim3(256), 0, s, X, Y, inc.F, gamma,
                        cnt, inc.list, N, Npad, Rpad, R, p, c0, dt, a0dt);
-    hipLaunchKernelGGL(k_inc_field, dim3(cdiv(Npad, 256), R), dim3(256), 0, s, inc.F, J, cnt,
-                       inc.list, next, Npad);
+    hipLaunchKernelGGL(k_inc_field, dim3(cdiv(Npad, 256), inc_grid_y(R)), dim3(256), 0, s, inc.F,
+                       J, cnt, inc.list, next, Npad, R);
     return hipGetLastError();
 }
 

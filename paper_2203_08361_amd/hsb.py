@@ -6,8 +6,11 @@ fallback: if libhsb.so is missing or the device is not usable, calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -292,14 +295,31 @@ def hsb_run_batch(contexts, jobs, variant, steps, a0, dt, init_amp=0.1, energy_i
     return outs, rc
 
 
+# Contexts still open; closed by an exit handler that runs before the
+# interpreter (and the HIP runtime beneath it) starts tearing down, so that
+# hsb_destroy never runs during finalisation.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for c in list(_live):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
     """Owns one hsb_ctx (the J store) and its options."""
 
     def __init__(self, J, **options):
         J = np.ascontiguousarray(J, dtype=np.float32)
         self.N = J.shape[0]
+        self.h = None
         self.h = hsb_create(J)
         _sizes[self.h.value] = self.N
+        _live.add(self)
         for k, v in options.items():
             self.set_option(k, v)
 
@@ -339,10 +359,12 @@ class Context:
         return hsb_run_ex(self.h, variant, steps, R, a0, c0, dt, gamma, seed, **kw)
 
     def close(self):
-        if self.h is not None and self.h.value:
-            _sizes.pop(self.h.value, None)
-            hsb_destroy(self.h)
-        self.h = None
+        """Destroy the context now (its device memory, streams and graphs)."""
+        h, self.h = self.h, None
+        _live.discard(self)
+        if h is not None and h.value:
+            _sizes.pop(h.value, None)
+            hsb_destroy(h)
 
     def __enter__(self):
         return self
@@ -351,6 +373,10 @@ class Context:
         self.close()
 
     def __del__(self):
+        # during interpreter shutdown the runtime below may already be gone:
+        # contexts are closed by the exit handler before that, never here
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -85,3 +85,23 @@ def test_incremental_unsupported_cases():
         with pytest.raises(hsb.HSBError) as e:
             ctx.run_ex(hsb.HSB_DSB, 10, 4, 1.0, 0.5, 1.0, 0.0, 1)
         assert e.value.code == hsb.HSB_EUNSUPPORTED
+
+
+def test_incremental_more_replicas_than_a_grid_dimension():
+    """R = 70000 > 65535: the per-replica launches stride over the replicas
+    beyond their capped grid.y; every replica equals the FP4 plan's run and a
+    sample of them the oracle's FP32 mirror."""
+    N, R, steps = 64, 70000, 30
+    J = synth.sk_instance(N, 5)
+    say("incremental R > 65535", N, R, steps)
+    a = run(J, "incremental", steps, R, interval=10)
+    assert a["plan"] == "incremental"
+    b = run(J, "mixed", steps, R, interval=10)
+    assert b["plan"] == "fp4"
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k]), k
+    for r in (0, 32767, 32768, 65535, 65536, R - 1):
+        o = oracle.run(J, oracle.DSB, 1.0, np.float32(0.5 / np.sqrt(N)), 1.0, 0.01, steps, 1,
+                       seed=1, amp=0.1, interval=10, precision=oracle.FP32, r0=r)
+        assert np.array_equal(a["x"][r].astype(np.float64), o["x"][0]), r
+        assert a["best_energy"][r] == o["best_e"][0], r
