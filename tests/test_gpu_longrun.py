@@ -1,0 +1,117 @@
+"""Full-size long runs against stored oracle results (marked `gpu`).
+
+The bench configuration (N = 2000, R = 1024, 10^4 steps, energy every 100
+steps) is too long for the oracle to rerun inside a test, so its results are
+stored in tests/golden/longrun_*.json, written by tests/golden/make_longrun.py,
+which calls the oracle only.
+
+  * dSB: the field of eq. (5) is an exact integer, so every plan's final state
+    must be bitwise the oracle's FP32 mirror: 64 replicas (every 16th of the
+    1024) are compared by the SHA-256 of their final x and y, with their best
+    and final energies and best step.  On the FP4 plan the run is made twice,
+    the second time launched as a HIP graph, exactly as the bench times it.
+  * bSB is chaotic over 10^4 steps, so the comparison is in distribution: the
+    GPU's 1024 replicas (seed 2) against the FP64 oracle's 128 (seed 1, an
+    independent sample).  Welch's 95% interval of the difference of mean best
+    energies contains 0, and Newcombe's interval of the difference of
+    P(E <= t) contains 0 at the pooled deciles t, Bonferroni-corrected so
+    that the family of levels is at 95%.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2203_08361_amd import hsb, metrics  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+N, R, STEPS = 2000, 1024, 10000
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    hsb.load_library()
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def golden(name):
+    with open(os.path.join(HERE, "golden", f"longrun_{name}.json")) as f:
+        return json.load(f)
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.float32).tobytes()).hexdigest()
+
+
+@pytest.mark.parametrize("plan,expect", [("mixed", "fp4"), ("digits", "digits"), ("fp32", "fp32")])
+def test_dsb_bench_run_matches_the_mirror(plan, expect):
+    g = golden("dsb_sk2000_mirror")
+    J = synth.sk_instance(N, 2000)
+    say("dsb full run vs stored mirror", plan)
+    dev = torch.device("cuda", 0)
+    buf = {"x": torch.empty((R, N), dtype=torch.float32, device=dev),
+           "y": torch.empty((R, N), dtype=torch.float32, device=dev)}
+    with hsb.Context(J, precision=plan, init_amp=g["amp"], energy_interval=g["interval"]) as ctx:
+        outs = []
+        for _ in range(2 if plan == "mixed" else 1):
+            # the same output buffers: the second identical call is a graph launch
+            o = ctx.run_ex(hsb.HSB_DSB, STEPS, R, g["a0"], g["c0"], g["dt"], g["gamma"], g["seed"],
+                           want_state=True, out=buf)
+            torch.cuda.synchronize()
+            assert ctx.last_plan() == expect
+            outs.append({k: v.cpu().numpy() for k, v in o.items() if hasattr(v, "cpu")})
+        if plan == "mixed":
+            assert ctx.get_option("graph_launches") == 1
+    for out in outs:
+        for row in g["replicas"]:
+            r = row["replica"]
+            assert sha(out["x"][r]) == row["x_sha256"], r
+            assert sha(out["y"][r]) == row["y_sha256"], r
+            assert out["best_energy"][r] == row["best_e"], r
+            assert out["final_energy"][r] == row["final_e"], r
+            assert out["best_step"][r] == row["best_step"], r
+            assert out["energy"][r] == row["best_e"], r
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[-1][k]), k
+
+
+@pytest.mark.parametrize("case,plan,expect", [("bsb_sk2000_fp64", "mixed", "fp4"),
+                                              ("bsb_gauss2000_fp64", "mixed", "digits"),
+                                              ("bsb_sk2000_fp64", "digits", "digits")])
+def test_bsb_bench_runs_match_the_oracle_in_distribution(case, plan, expect):
+    g = golden(case)
+    J = synth.sk_instance(N, 2000) if "sk" in case else synth.gaussian_instance(N, 3)
+    say("bsb full run statistics", case, plan)
+    with hsb.Context(J, precision=plan, init_amp=g["amp"], energy_interval=g["interval"]) as ctx:
+        o = ctx.run_ex(hsb.HSB_BSB, STEPS, R, g["a0"], g["c0"], g["dt"], g["gamma"], 2)
+        torch.cuda.synchronize()
+        assert ctx.last_plan() == expect
+        eg = o["best_energy"].cpu().numpy()
+    eo = np.array(g["best_e"])
+    assert np.all(np.isfinite(eg)) and np.std(eo) > 0.0
+    lo, hi = metrics.welch_interval(eg, eo)
+    say(f"mean best E: gpu {eg.mean():.3f} (R={eg.size}) oracle {eo.mean():.3f} "
+        f"(R={eo.size}), difference in [{lo:.3f}, {hi:.3f}]")
+    assert lo <= 0.0 <= hi
+    levels = np.quantile(np.concatenate([eg, eo]), np.linspace(0.1, 0.9, 9))
+    z = stats.norm.ppf(1.0 - 0.025 / len(levels))
+    for t in levels:
+        kg, ko = int((eg <= t).sum()), int((eo <= t).sum())
+        plo, phi = metrics.newcombe_interval(kg, eg.size, ko, eo.size, z=z)
+        say(f"P(E <= {t:.3f}): gpu {kg}/{eg.size} oracle {ko}/{eo.size}, "
+            f"difference in [{plo:.4f}, {phi:.4f}]")
+        assert plo <= 0.0 <= phi
