@@ -64,7 +64,11 @@ def test_dsb_bench_run_matches_the_mirror(plan, expect):
     say("dsb full run vs stored mirror", plan)
     dev = torch.device("cuda", 0)
     buf = {"x": torch.empty((R, N), dtype=torch.float32, device=dev),
-           "y": torch.empty((R, N), dtype=torch.float32, device=dev)}
+           "y": torch.empty((R, N), dtype=torch.float32, device=dev),
+           "spins": torch.empty((R, N), dtype=torch.int8, device=dev),
+           "best_step": torch.empty(R, dtype=torch.int32, device=dev)}
+    for k in ("energy", "best_energy", "final_energy"):
+        buf[k] = torch.empty(R, dtype=torch.float64, device=dev)
     with hsb.Context(J, precision=plan, init_amp=g["amp"], energy_interval=g["interval"]) as ctx:
         outs = []
         for _ in range(2 if plan == "mixed" else 1):
