@@ -19,8 +19,9 @@ Reported next to it:
     FP32, with the FP64 energies checked against the oracle's eq. (1);
   - a batched workload: 256 SK instances with N uniform in [100, 2000], each
     with 64 replicas at each of 8 heating rates (2048 jobs), 5000 steps of
-    heated dSB in one hsb_run_batch call, against per-job runs on the FP32
-    plan (timed on a sample of jobs and scaled to all of them);
+    heated dSB in one hsb_run_batch call (one persistent launch), against the
+    per-size class scheduler and, measured on every 8th instance, one
+    FP32-plan run per instance;
   - the roofline of the dominant kernel (FP4 MFMA field + fused update),
     its launch duration measured with HIP events on the run's stream;
   - the CPU oracle timed on a bounded sample of the same workload.
@@ -245,57 +246,91 @@ def main() -> int:
 
     def batch_workload():
         """2048 jobs: 256 SK instances (N uniform in [100, 2000], stream 3, seed 4),
-        8 heating rates, R = 64, 5000 steps of heated dSB, c0 = 0.5/sqrt(N_i)."""
+        8 heating rates, R = 64, 5000 steps of heated dSB, c0 = 0.5/sqrt(N_i): one
+        hsb_run_batch call (one persistent launch fed by the job queues; the
+        repeated call is a graph launch).  Also the previous per-size class
+        scheduler, and -- measured, on every 8th instance -- the baseline form:
+        one FP32-plan run per instance with its 8 x 64 replicas (per-replica
+        gamma), against the batch call of the same 32 instances."""
         sizes = synth.uneven_sizes(256, 4)
         gammas = [0.0, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1, 0.2]
         steps_b, R_b = 5000, 64
         log("batch: building 256 instances")
         Js = [synth.sk_instance(int(n), 10000 + k) for k, n in enumerate(sizes)]
         ctxs = [hsb.Context(Jk) for Jk in Js]
-        jobs = [dict(instance=k, R=R_b, c0=0.5 / math.sqrt(int(n)), gamma=g, seed=100 * k + q)
-                for k, n in enumerate(sizes) for q, g in enumerate(gammas)]
-        spin_updates = sum(int(sizes[j["instance"]]) for j in jobs) * R_b * steps_b
-        flops = sum(2.0 * int(sizes[j["instance"]]) ** 2 for j in jobs) * R_b * (steps_b + 1)
+
+        def jobs_of(insts):
+            return [dict(instance=k, R=R_b, c0=0.5 / math.sqrt(int(sizes[k])), gamma=g,
+                         seed=100 * k + q) for k in insts for q, g in enumerate(gammas)]
+
+        def work(jobs):
+            su = sum(int(sizes[j["instance"]]) for j in jobs) * R_b * steps_b
+            fl = sum(2.0 * int(sizes[j["instance"]]) ** 2 for j in jobs) * R_b * (steps_b + 1)
+            return su, fl
+
+        def time_batch(jobs, sched, reps):
+            outs, _ = hsb.hsb_run_batch(ctxs, jobs, hsb.HSB_DSB, steps_b, A0, DT,
+                                        energy_interval=100, scheduler=sched)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                hsb.hsb_run_batch(ctxs, jobs, hsb.HSB_DSB, steps_b, A0, DT, energy_interval=100,
+                                  scheduler=sched, outs=outs)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+
+        jobs = jobs_of(range(256))
+        spin_updates, flops = work(jobs)
+        g0 = ctxs[0].get_option("graph_launches")
+        t_batch = time_batch(jobs, hsb.HSB_SCHED_QUEUE, 3)
+        graphed = int(ctxs[0].get_option("graph_launches") - g0)
+        log(f"batch: {t_batch * 1e3:.1f} ms per batch (queue)")
+        t_classes = time_batch(jobs, hsb.HSB_SCHED_CLASSES, 1)
+        log(f"batch: {t_classes * 1e3:.1f} ms per batch (per-size classes)")
+        ctxs[0].set_option("timing", 1)
         hsb.hsb_run_batch(ctxs, jobs, hsb.HSB_DSB, steps_b, A0, DT, energy_interval=100)
-        torch.cuda.synchronize()
-        log("batch: warmup done")
-        nt = 2
-        t0 = time.perf_counter()
-        for _ in range(nt):
-            hsb.hsb_run_batch(ctxs, jobs, hsb.HSB_DSB, steps_b, A0, DT, energy_interval=100)
-        torch.cuda.synchronize()
-        t_batch = (time.perf_counter() - t0) / nt
-        log(f"batch: {t_batch * 1e3:.1f} ms per batch")
-        # baseline form: each job on its own through the FP32 plan; every 32nd
-        # instance's first job is timed and scaled to the batch by its share of
-        # the per-job work (N_i^2 with the tile padding of that plan)
-        sample = list(range(0, 256, 32))
-        t_sample, w_sample = 0.0, 0.0
-        for k in sample:
-            ctxs[k].set_option("precision", "fp32")
-            jd = jobs[8 * k]
-            ctxs[k].run_ex(hsb.HSB_DSB, 200, R_b, A0, jd["c0"], DT, jd["gamma"], jd["seed"])
+        kern_ms = ctxs[0].get_option("kernel_ms")
+        ctxs[0].set_option("timing", 0)
+        # like for like on every 8th instance: the batch call, and one FP32-plan
+        # run per instance with its 8 heating rates as per-replica gamma
+        sub = list(range(0, 256, 8))
+        sub_jobs = jobs_of(sub)
+        su_sub, _ = work(sub_jobs)
+        t_sub = time_batch(sub_jobs, hsb.HSB_SCHED_QUEUE, 2)
+        gam = torch.tensor(np.repeat(np.array(gammas, dtype=np.float32), R_b), device="cuda")
+        t_fp32 = 0.0
+        for k in sub:
+            c = ctxs[k]
+            c.set_option("precision", "fp32")
+            c0k = 0.5 / math.sqrt(int(sizes[k]))
+            c.run_ex(hsb.HSB_DSB, 100, 8 * R_b, A0, c0k, DT, 0.0, 100 * k, gamma_rep=gam)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            ctxs[k].run_ex(hsb.HSB_DSB, steps_b, R_b, A0, jd["c0"], DT, jd["gamma"], jd["seed"])
+            c.run_ex(hsb.HSB_DSB, steps_b, 8 * R_b, A0, c0k, DT, 0.0, 100 * k, gamma_rep=gam)
             torch.cuda.synchronize()
-            t_sample += time.perf_counter() - t1
-            w_sample += (math.ceil(int(sizes[k]) / 64) * 64) ** 2
-        w_all = sum((math.ceil(int(sizes[j["instance"]]) / 64) * 64) ** 2 for j in jobs)
-        t_fp32 = t_sample * w_all / w_sample
+            t_fp32 += time.perf_counter() - t1
+            c.set_option("precision", "auto")
+        log(f"batch subset: {t_sub * 1e3:.1f} ms batched, {t_fp32 * 1e3:.1f} ms FP32 per instance")
         for c in ctxs:
             c.close()
         return {"workload": "256 SK +-1 instances, N uniform in [100, 2000] (E[N] ~ 1050), "
                             "8 gamma values {0, .0025, .005, .01, .02, .05, .1, .2} x R=64, "
                             "5000 steps heated dSB, one hsb_run_batch call",
                 "jobs": len(jobs), "value": spin_updates / t_batch, "unit": "spin-updates/s",
-                "ms_per_batch": t_batch * 1e3,
+                "ms_per_batch": t_batch * 1e3, "graph_launched_batches": graphed,
+                "kernel_ms": kern_ms,
                 "algorithmic_tflops": flops / t_batch / 1e12,
                 "frac_fp4_peak": flops / t_batch / 1e12 / KERNELS["fp4"][1],
-                "fp32_per_job_s_estimated": t_fp32,
-                "fp32_estimate_basis": f"{len(sample)} jobs timed on the FP32 plan "
-                                       f"({t_sample:.2f} s), scaled by padded N^2",
-                "speedup_vs_fp32_per_job": t_fp32 / t_batch}
+                "classes_scheduler_ms_per_batch": t_classes * 1e3,
+                "speedup_vs_classes": t_classes / t_batch,
+                "fp32_per_instance_subset": {
+                    "instances": len(sub), "jobs": len(sub_jobs),
+                    "batched_s": t_sub, "fp32_per_instance_s": t_fp32,
+                    "speedup": t_fp32 / t_sub,
+                    "basis": "measured: every 8th instance, the batch call of its 8 jobs vs one "
+                             "FP32-plan hsb_run_ex per instance (R = 512, per-replica gamma)",
+                    "batched_spin_updates_per_s": su_sub / t_sub,
+                    "fp32_spin_updates_per_s": su_sub / t_fp32}}
 
     def gaussian_workload():
         """Gaussian couplings (N = 2000, seed 3), R = 1024, 10^4 steps of heated bSB,

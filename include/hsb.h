@@ -290,9 +290,20 @@ int hsb_plan_info(hsb_ctx *h, int variant, int *precision);
  * variant, steps, R, a0, c0, dt, gamma and seed (and the batch's amplitude,
  * interval and return mode), under the plan its instance's precision option
  * selects.  Jobs on the FP4 plan (J exact in FP4 with N <= 2048; for bSB also
- * initial amplitude <= 1) run together, one persistent launch sequence per
- * padded size for all their instances, so a batch of small instances fills
- * the device.  Other jobs run one after another.
+ * initial amplitude <= 1) run together:
+ *   dSB  all of them in ONE persistent launch (scheduler HSB_SCHED_QUEUE, the
+ *        default): every 32 replicas of a job form a team; the teams are
+ *        placed longest-first on eight device job queues (one per XCD slot,
+ *        balanced by workgroups x estimated step time), and the resident
+ *        workgroups take a team's parts from their queue until it is empty.
+ *        The initial state, the energy samples of eq. (1) and the best sample
+ *        are formed inside that launch.  A batch identical to the previous one
+ *        of the same lead context hs[0] (same jobs, arguments and buffers) is
+ *        captured and replayed as one HIP graph, as hsb_run_ex does under
+ *        HSB_OPT_GRAPH of hs[0].  HSB_SCHED_CLASSES runs them as bSB does;
+ *   bSB  one persistent launch sequence per padded size for all their
+ *        instances, so a batch of small instances fills the device.
+ * Other jobs run one after another.
  * Outputs are device pointers owned by the caller: jobs[j].spins [R][N] int8
  * and jobs[j].energy [R] double.  Validation failures return HSB_EINVAL before
  * any device work; HSB_ENUMERIC if any replica of any job became non-finite.
@@ -319,7 +330,13 @@ typedef struct {
     int32_t energy_interval; /* >= 1 (0 means 100) */
     int32_t return_best;     /* 1: best sample, 0: final state */
     void *stream;            /* hipStream_t, or NULL for the null stream */
+    int32_t scheduler;       /* hsb_scheduler of the dSB jobs on the FP4 plan */
 } hsb_batch_args;
+
+typedef enum {
+    HSB_SCHED_QUEUE = 0,   /* one persistent launch fed by job queues (default) */
+    HSB_SCHED_CLASSES = 1  /* one launch sequence per padded size, one class after another */
+} hsb_scheduler;
 
 int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs, int n_jobs,
                   const hsb_batch_args *args);

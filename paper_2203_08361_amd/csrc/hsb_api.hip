@@ -11,6 +11,7 @@
 #include <new>
 #include <vector>
 
+#include "batch.h"
 #include "digits.h"
 #include "hsb.h"
 #include "kernels.h"
@@ -59,6 +60,11 @@ struct hsb_ctx {
     hsb::PersistentJ *pj = nullptr;  // FP4 J store for the persistent dSB path (lazy)
     hsb::I8J *i8 = nullptr;          // integer-digit J store (lazy)
     hsb::PersistentWork *bwork = nullptr;  // scratch of batched FP4 runs led by this context
+    hsb::QueueWork *qwork = nullptr;       // tables and buffers of queued dSB batches it leads
+    // graph of the last repeated queued batch led by this context
+    std::vector<uint64_t> bgkey;
+    bool bgseen = false;
+    hipGraphExec_t bgexec = nullptr;
     hsb::StateBufs bstate{};               // state of batch classes led by this context
     size_t bstate_ns = 0, bstate_nr = 0;   // its capacity: elements, columns
     hsb::BatchJob *bjobs = nullptr;        // device job table of a batch class
@@ -126,6 +132,13 @@ void graph_drop(hsb_ctx *h) {
     h->gexec = nullptr;
     h->gseen = false;
     h->gkey.clear();
+}
+
+void batch_graph_drop(hsb_ctx *h) {
+    if (h->bgexec) (void)hipGraphExecDestroy(h->bgexec);
+    h->bgexec = nullptr;
+    h->bgseen = false;
+    h->bgkey.clear();
 }
 
 }  // namespace
@@ -206,6 +219,8 @@ extern "C" void hsb_destroy(hsb_ctx *h) {
     if (h->pj) hsb::persistent_free(h->pj);
     if (h->i8) hsb::i8_free(h->i8);
     if (h->bwork) hsb::persistent_work_free(h->bwork);
+    batch_graph_drop(h);
+    if (h->qwork) hsb::queue_work_free(h->qwork);
     hsb::free_state_bufs(h->bstate);
     if (h->bjobs) (void)hipFree(h->bjobs);
     if (h->d_flag) (void)hipFree(h->d_flag);
@@ -260,7 +275,10 @@ extern "C" int hsb_set_option(hsb_ctx *h, int key, double v) {
     case HSB_OPT_GRAPH:
         if (!(v == 0.0 || v == 1.0)) return fail(HSB_EINVAL, "GRAPH must be 0 or 1");
         h->graph = (int)v;
-        if (!h->graph) graph_drop(h);
+        if (!h->graph) {
+            graph_drop(h);
+            batch_graph_drop(h);
+        }
         return HSB_OK;
     case HSB_OPT_KERNEL_MS:
     case HSB_OPT_KERNEL_LAUNCHES:
@@ -655,14 +673,101 @@ int run_graph(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
     return HSB_OK;
 }
 
+// Everything a queued batch's device work depends on: the team table (the
+// instances' J stores, the outputs, seeds and parameters), the shared run
+// arguments and the generation of the lead context's queue buffers.
+std::vector<uint64_t> batch_key(const hsb_ctx *lead, const std::vector<hsb::QTeam> &qt,
+                                const hsb::QRun &qr) {
+    static_assert(sizeof(hsb::QTeam) % 8 == 0, "team records are whole words");
+    std::vector<uint64_t> k(qt.size() * sizeof(hsb::QTeam) / 8 + 8);
+    if (!qt.empty()) std::memcpy(k.data(), qt.data(), qt.size() * sizeof(hsb::QTeam));
+    uint64_t *t = k.data() + qt.size() * sizeof(hsb::QTeam) / 8;
+    uint32_t f[3];
+    std::memcpy(&f[0], &qr.a0, 4);
+    std::memcpy(&f[1], &qr.dt, 4);
+    std::memcpy(&f[2], &qr.amp, 4);
+    t[0] = (uint64_t)(uint32_t)qr.steps;
+    t[1] = (uint64_t)(uint32_t)qr.interval;
+    t[2] = (uint64_t)qr.return_best | ((uint64_t)qr.local_exchange << 8);
+    t[3] = f[0];
+    t[4] = f[1];
+    t[5] = f[2];
+    t[6] = lead->qwork ? hsb::queue_gen(lead->qwork) : 0;
+    t[7] = (uint64_t)qt.size();
+    return k;
+}
+
+int ensure_graph_stream(hsb_ctx *h) {
+    if (!h->gstream) {
+        HIP_TRY(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&h->gev_in, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&h->gev_out, hipEventDisableTiming));
+    }
+    return HSB_OK;
+}
+
+// A queued batch through the lead context's graph cache: the first call with a
+// key runs eagerly (allocating and uploading what it needs), the next call
+// with that key captures the same work on the context's stream and launches
+// it, later calls launch it again; any other key drops the graph.
+int batch_graph(hsb_ctx *lead, const std::vector<hsb::QTeam> &qt, const hsb::QRun &qr,
+                hipStream_t s) {
+    const std::vector<uint64_t> key = batch_key(lead, qt, qr);
+    auto launch = [&]() -> int {
+        HIP_TRY(hipEventRecord(lead->gev_in, s));
+        HIP_TRY(hipStreamWaitEvent(lead->gstream, lead->gev_in, 0));
+        HIP_TRY(hipGraphLaunch(lead->bgexec, lead->gstream));
+        HIP_TRY(hipEventRecord(lead->gev_out, lead->gstream));
+        HIP_TRY(hipStreamWaitEvent(s, lead->gev_out, 0));
+        ++lead->glaunches;
+        return HSB_OK;
+    };
+    if (lead->bgexec && key == lead->bgkey) return launch();
+    if (lead->bgseen && key == lead->bgkey) {
+        int rc = ensure_graph_stream(lead);
+        if (rc != HSB_OK) return rc;
+        HIP_TRY(hipEventRecord(lead->gev_in, s));
+        HIP_TRY(hipStreamWaitEvent(lead->gstream, lead->gev_in, 0));
+        HIP_TRY(hipStreamBeginCapture(lead->gstream, hipStreamCaptureModeThreadLocal));
+        hsb::KernelTimer off;
+        rc = hsb::queue_run(lead->qwork, qt, qr, 0, lead->gstream, off);
+        if (rc != HSB_OK) (void)fail(rc, "%s", hsb::queue_error());
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(lead->gstream, &g);
+        if (rc == HSB_OK && e != hipSuccess) rc = hip_fail(e, "capturing the batch");
+        if (rc == HSB_OK && batch_key(lead, qt, qr) != key)
+            rc = fail(HSB_EDEVICE, "batch buffers changed while capturing");
+        if (rc == HSB_OK) {
+            const hipError_t ei = hipGraphInstantiate(&lead->bgexec, g, nullptr, nullptr, 0);
+            if (ei != hipSuccess) {
+                lead->bgexec = nullptr;
+                rc = hip_fail(ei, "instantiating the batch graph");
+            }
+        }
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != HSB_OK) {  // nothing of a failed capture ran: queue it eagerly
+            batch_graph_drop(lead);
+            (void)hipGetLastError();
+            const int r2 = hsb::queue_run(lead->qwork, qt, qr, 0, s, lead->timer);
+            return r2 == HSB_OK ? HSB_OK : fail(r2, "%s", hsb::queue_error());
+        }
+        return launch();
+    }
+    batch_graph_drop(lead);
+    const int rc = hsb::queue_run(lead->qwork, qt, qr, 0, s, lead->timer);
+    if (rc != HSB_OK) return fail(rc, "%s", hsb::queue_error());
+    lead->bgkey = batch_key(lead, qt, qr);  // after the run: what it grew is part of it
+    lead->bgseen = true;
+    return HSB_OK;
+}
+
 }  // namespace
 
-extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
-    g_err[0] = 0;
-    if (!h || !a) return fail(HSB_EINVAL, "hsb_run_ex: NULL argument");
-    if (a->struct_size != sizeof(hsb_run_args))
-        return fail(HSB_EINVAL, "hsb_run_ex: struct_size %zu != %zu", a->struct_size,
-                    sizeof(hsb_run_args));
+namespace {
+
+// The argument checks shared by the run entry points (all on the
+// host, before any device work).
+int check_run_args(const hsb_run_args *a) {
     if (a->variant != HSB_BSB && a->variant != HSB_DSB)
         return fail(HSB_EINVAL, "variant must be HSB_BSB (0) or HSB_DSB (1)");
     if (a->steps < 0) return fail(HSB_EINVAL, "steps must be >= 0");
@@ -690,6 +795,21 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
     } else if (a->nh_inv_mass != 0.0 || a->nh_temperature != 0.0 || a->xi0 || a->xi_out) {
         return fail(HSB_EINVAL, "nh_inv_mass, nh_temperature, xi0 and xi_out need "
                                 "HSB_THERMO_NOSE_HOOVER");
+    }
+    return HSB_OK;
+}
+
+}  // namespace
+
+extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
+    g_err[0] = 0;
+    if (!h || !a) return fail(HSB_EINVAL, "hsb_run_ex: NULL argument");
+    if (a->struct_size != sizeof(hsb_run_args))
+        return fail(HSB_EINVAL, "hsb_run_ex: struct_size %zu != %zu", a->struct_size,
+                    sizeof(hsb_run_args));
+    {
+        const int rc = check_run_args(a);
+        if (rc != HSB_OK) return rc;
     }
     int plan = 0;
     int rc = choose_plan(h, a->variant, &plan);
@@ -798,6 +918,8 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
     if (interval < 1) return fail(HSB_EINVAL, "energy_interval must be >= 1");
     if (a->return_best != 0 && a->return_best != 1)
         return fail(HSB_EINVAL, "return_best must be 0 or 1");
+    if (a->scheduler != HSB_SCHED_QUEUE && a->scheduler != HSB_SCHED_CLASSES)
+        return fail(HSB_EINVAL, "scheduler must be HSB_SCHED_QUEUE (0) or HSB_SCHED_CLASSES (1)");
     for (int i = 0; i < n_inst; ++i) {
         if (!hs[i]) return fail(HSB_EINVAL, "hs[%d] is NULL", i);
         if (hs[i]->device != hs[0]->device)
@@ -805,7 +927,7 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
     }
     // plan of every job (the instance's precision option), FP4 jobs grouped by padded size
     std::map<int, std::vector<int>> classes;  // K blocks of 64 -> jobs
-    std::vector<int> singles;
+    std::vector<int> singles, queued;
     for (int j = 0; j < n_jobs; ++j) {
         const hsb_job &jb = jobs[j];
         if (jb.instance < 0 || jb.instance >= n_inst)
@@ -819,7 +941,9 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
         const int rc = choose_plan(hs[jb.instance], a->variant, &plan);
         if (rc != HSB_OK) return rc;
         // bSB's digit representation of x needs |x| <= 1 at the start
-        if (plan == PLAN_FP4 && !(a->variant == HSB_BSB && amp > 1.0))
+        if (plan == PLAN_FP4 && a->variant == HSB_DSB && a->scheduler == HSB_SCHED_QUEUE)
+            queued.push_back(j);
+        else if (plan == PLAN_FP4 && !(a->variant == HSB_BSB && amp > 1.0))
             classes[(hs[jb.instance]->N + 255) / 256 * 4].push_back(j);
         else
             singles.push_back(j);
@@ -864,9 +988,57 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
             return rc;
     }
 
-    // FP4 jobs: one persistent launch sequence per padded size; the lead
-    // context's timer (TIMING on) records those launches
+    // FP4 jobs; the lead context's timer (TIMING on) records their launches
     lead->timer.reset(lead->timing != 0);
+    // dSB: every job in one persistent launch fed by the job queues
+    if (!queued.empty()) {
+        std::vector<hsb::QTeam> qt;
+        for (int j : queued) {
+            const hsb_job &jb = jobs[j];
+            hsb_ctx *h = hs[jb.instance];
+            if (!h->pj) {
+                const int rc = hsb::persistent_create(h->hJ.data(), h->N, &h->pj);
+                if (rc != HSB_OK) return fail(rc, "%s", hsb::persistent_error());
+            }
+            const int nkb = hsb::persistent_nkb(h->pj);
+            for (int t0 = 0; t0 < jb.R; t0 += 32)
+                qt.push_back(hsb::QTeam{hsb::persistent_jpk(h->pj), jb.spins, jb.energy, jb.seed,
+                                        h->N, nkb, t0, std::min(32, jb.R - t0), jb.c0, jb.gamma});
+        }
+        if (!lead->qwork) {
+            const int rc = hsb::queue_work_create(&lead->qwork);
+            if (rc != HSB_OK) return fail(rc, "%s", hsb::queue_error());
+        }
+        hsb::QRun qr{};
+        qr.steps = a->steps;
+        qr.interval = interval;
+        qr.return_best = a->return_best;
+        qr.a0 = a->a0;
+        qr.dt = a->dt;
+        qr.amp = (float)amp;
+        qr.local_exchange = lead->local_exchange;
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(s, &cap));
+        const bool graphable = lead->graph && !lead->timing && singles.empty() &&
+                               classes.empty() && cap == hipStreamCaptureStatusNone;
+        int rc;
+        if (graphable) {
+            rc = batch_graph(lead, qt, qr, s);
+        } else {
+            batch_graph_drop(lead);
+            rc = hsb::queue_run(lead->qwork, qt, qr, 0, s, lead->timer);
+            if (rc != HSB_OK) rc = fail(rc, "%s", hsb::queue_error());
+        }
+        if (rc != HSB_OK) return rc;
+        int32_t status = 0;
+        HIP_TRY(hipMemcpyAsync(&status, hsb::queue_status(lead->qwork), sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (status & 2) return fail(HSB_EDEVICE, "batch queue kernel: exchange wait timed out");
+        any_bad |= status & 1;
+        lead->last_plan = PLAN_FP4;
+    }
+    // the rest: one persistent launch sequence per padded size
     // The classes' state: kept by the lead context and grown only when a class
     // needs more elements or columns than it holds (the FP4 plan uses neither
     // the FP32 operand nor its energy buffers).  Class c uses Nst Rtot elements

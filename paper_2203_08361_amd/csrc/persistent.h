@@ -26,9 +26,13 @@ struct PersistentRun {
     float a0, c0, dt;
     double *epart;         // unused by this path (its own partials are kept per sample)
     int local_exchange = 1;  // 0: device-scope exchange even for XCD-local teams
+    int tile = 0;            // kernel variant, 0 .. persistent_tiles(variant) - 1
 };
 
 bool persistent_supported(int N);
+// Number of result-invariant kernel variants of the plan (the autotuner's
+// candidates; 0 is the default).
+int persistent_tiles(int variant);
 int persistent_max_n();
 const char *persistent_error();
 int persistent_create(const float *J, int N, PersistentJ **out);

@@ -30,6 +30,7 @@
 // the sampled state; a small kernel then forms E, keeps the best sample
 // (strict improvement, earliest wins) and its spins.
 #include "hsb.h"
+#include "fp4_device.h"
 #include "hsb_device.h"
 #include "persistent.h"
 
@@ -42,8 +43,6 @@
 namespace hsb {
 
 constexpr int kMaxKB = 32;  // K blocks of 64 spins: N <= 2048
-constexpr uint32_t kNoTag = 0xFFFFFFFFu;
-constexpr uint64_t kTimeoutTicks = 400000000ull;  // 4 s of the 100 MHz wall clock
 
 // Scratch of one persistent run (a single instance or a batch of teams).
 struct PersistentWork {
@@ -96,102 +95,11 @@ int perr(int code, const char *fmt, ...) {
 }  // namespace
 
 const char *persistent_error() { return p_err; }
+int persistent_tiles(int variant) { return variant == HSB_BSB ? 2 : 3; }
 int persistent_max_n() { return kMaxKB * 64; }
 bool persistent_supported(int N) { return N >= 1 && N <= kMaxKB * 64; }
 
 // ----------------------------------------------------------------- device
-
-__device__ __forceinline__ uint64_t ld_tagged(const uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_tagged(uint64_t *p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// Store for a team whose workgroups all run on one XCD: the word only has to
-// reach that XCD's L2, where the readers' device-scope loads find it (about
-// half the round trip of a device-scope store, which writes through).
-__device__ __forceinline__ void st_tagged_xcd(uint64_t *p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-// Id of the XCD (accelerator complex die) this wave runs on.
-__device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20); }
-
-// F tile update on the FP4 matrix cores: acc (VGPRs) += j (J fragment, AGPRs)
-// x b (+-1 operand, VGPRs), 32 rows x 32 replicas x 64 spins, unit block
-// scales.  Inline assembly keeps the loop-invariant J fragments in the
-// accumulation register file for the whole kernel, feeding the MFMA directly
-// (the compiler would otherwise copy them to VGPRs before every use).
-// Hazards: exactly overlapping srcC/vdst chains are interlocked by the
-// hardware; the first product of a step uses an inline zero for srcC; VALU
-// reads of the results wait behind mfma_drain().  A VGPR source written by a
-// vector instruction needs two wait states before an MFMA reads it, and the
-// compiler does not insert them around inline assembly: the B operands here
-// come from LDS loads and the scale is loop-invariant, so none arise.
-__device__ __forceinline__ void mfma_fp4_first(v16f &acc, const v4i &j, const v4i &b, int one) {
-    asm volatile(
-        "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, 0, %3, %3 op_sel_hi:[0,0,0] cbsz:4 blgp:4"
-        : "=&v"(acc)
-        : "a"(j), "v"(b), "v"(one));
-}
-__device__ __forceinline__ void mfma_fp4(v16f &acc, const v4i &j, const v4i &b, int one) {
-    asm volatile(
-        "v_mfma_scale_f32_32x32x64_f8f6f4 %0, %1, %2, %0, %3, %3 op_sel_hi:[0,0,0] cbsz:4 blgp:4"
-        : "+v"(acc)
-        : "a"(j), "v"(b), "v"(one));
-}
-
-// 21 wait states: more than an XDL write needs before a VALU read of its vdst.
-__device__ __forceinline__ void mfma_drain(v16f &acc0, v16f &acc1) {
-    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 4" : "+v"(acc0), "+v"(acc1));
-}
-__device__ __forceinline__ void mfma_drain(v16f &acc) {
-    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 4" : "+v"(acc));
-}
-
-// FP4 encoding of the values exact in E2M1.
-__device__ __forceinline__ uint32_t fp4_code(float v) {
-    const float a = fabsf(v);
-    uint32_t m = a == 0.5f ? 1u : a == 1.0f ? 2u : a == 1.5f ? 3u : a == 2.0f ? 4u
-               : a == 3.0f ? 5u : a == 4.0f ? 6u : a == 6.0f ? 7u : 0u;
-    return m | (v < 0.0f ? 8u : 0u);
-}
-
-// Sign words.  The word of (replica, 32-row chunk) holds one bit per row, set
-// iff x < 0.  Its bit order follows the accumulator layout of the writer
-// (lane l holds rows 8j + 4(l/32) + i, j, i = 0..3, of replica l%32): bit
-// b < 16 is row 8(b/4) + b%4, bit b >= 16 is row 8((b-16)/4) + 4 + b%4.
-__host__ __device__ constexpr int word_bit_row(int b) {
-    return b < 16 ? 8 * (b >> 2) + (b & 3) : 8 * ((b - 16) >> 2) + 4 + (b & 3);
-}
-__host__ __device__ constexpr int row_word_bit(int t) {
-    return (t & 4) ? 16 + 4 * (t >> 3) + (t & 3) : 4 * (t >> 3) + (t & 3);
-}
-
-// Packing convention shared by both MFMA operands.  Within a 32-spin chunk,
-// nibble n of fragment dword q holds the spin of word bit 4n + 3 - q.  The
-// +-1 operand of a chunk is then
-//   dword q = ((w << q) & 0x88888888) | 0x22222222
-// (0x2 = +1.0, 0xA = -1.0 in E2M1): seven integer operations per chunk.
-__device__ __forceinline__ v4i expand_signs(uint32_t w) {
-    v4i a;
-    a[0] = (int)((w & 0x88888888u) | 0x22222222u);
-    a[1] = (int)(((w << 1) & 0x88888888u) | 0x22222222u);
-    a[2] = (int)(((w << 2) & 0x88888888u) | 0x22222222u);
-    a[3] = (int)(((w << 3) & 0x88888888u) | 0x22222222u);
-    return a;
-}
-
-// The same expansion at one operation per dword: v_and_or_b32 computes
-// (a & b) | c, but its encoding takes no literal, so the two constants come in
-// registers (the mask in a scalar one, the +1.0 pattern in a vector one).
-__device__ __forceinline__ v4i expand_signs_fast(uint32_t w, uint32_t mask, uint32_t ones) {
-    v4i a;
-    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a[0]) : "v"(w), "s"(mask), "v"(ones));
-    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a[1]) : "v"(w << 1), "s"(mask), "v"(ones));
-    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a[2]) : "v"(w << 2), "s"(mask), "v"(ones));
-    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a[3]) : "v"(w << 3), "s"(mask), "v"(ones));
-    return a;
-}
 
 // J fragment for (row block rb, row tile rt, K block kb, lane): lane l holds
 // row 64 rb + 32 rt + l%32 and the 32 spins of chunk 2 kb + l/32, in the order
@@ -236,61 +144,6 @@ __device__ __forceinline__ int seg_sample_index(const SegArgs &g, int m) {
                                                  : g.nmult;
 }
 
-// Gather, for state m, the tagged sign words of the K blocks this wave
-// expands (its share: every 4th block), wv[q] holding block w + 4q.  All
-// words are loaded together and every stale one is reloaded together until
-// all carry tag m, so the wait costs about one round trip after the last
-// writer.  Returns false on timeout (4 s) or when another wave has flagged an
-// error.
-template <int NQ>
-__device__ __forceinline__ bool gather_words(uint64_t (&wv)[NQ], const uint64_t *src,
-                                             size_t stride, int nq, uint32_t m, int32_t *err) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        if (q < nq) wv[q] = ld_tagged(src + q * stride);
-    uint32_t stale = 0;  // bit q: some lane's word q is stale
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        if (q < nq && __any((uint32_t)(wv[q] >> 32) != m)) stale |= 1u << q;
-    if (stale == 0) return true;
-    const uint64_t t0 = wall_clock64();
-    for (int it = 1;; ++it) {
-        __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            if ((stale >> q) & 1u) wv[q] = ld_tagged(src + q * stride);
-        uint32_t still = 0;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            if (((stale >> q) & 1u) && __any((uint32_t)(wv[q] >> 32) != m)) still |= 1u << q;
-        stale = still;
-        if (stale == 0) return true;
-        if ((it & 31) == 0) {
-            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-                return false;
-            if (wall_clock64() - t0 > kTimeoutTicks) {
-                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                return false;
-            }
-        }
-    }
-}
-
-// sb_update (the same operations and roundings) with the last FMA written
-// so that y' lands in the register of y: the compiler would otherwise
-// accumulate into the register of y~~ and copy every y back each step.
-__device__ __forceinline__ void sb_update_tied(float f, float p, float c0, float dt, float a0dt,
-                                               float gdt, float &x, float &y) {
-    const float c0f = c0 * f;
-    const float u = __fmaf_rn(-p, x, c0f);
-    const float yt = __fmaf_rn(u, dt, y);
-    const float xt = __fmaf_rn(a0dt, yt, x);
-    const bool wall = fabsf(xt) > 1.0f;
-    x = __builtin_amdgcn_fmed3f(xt, -1.0f, 1.0f);
-    const float ytt = wall ? 0.0f : yt;
-    asm("v_fma_f32 %0, %1, %0, %2" : "+v"(y) : "v"(gdt), "v"(ytt));  // y' = (gamma dt) y + y~~
-}
-
 // One workgroup = 4 waves = 4 consecutive 32-row blocks of one team, so the
 // four waves need the same +-1 operand (the team's signs).  Each step every
 // wave gathers and expands a quarter of the K blocks into LDS (ping-pong by
@@ -303,7 +156,7 @@ __device__ __forceinline__ void sb_update_tied(float f, float p, float c0, float
 // core while this one waits for its team's signs.  That is why a wave holds
 // 32 rows rather than 64: 32 rows of J take 128 of the 256 registers two waves
 // per SIMD leave each.
-template <int NKB>
+template <int NKB, int KPRE>
 __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, uint64_t *xb, uint32_t *__restrict__ snap,
@@ -431,7 +284,7 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         // its chain that its team waits for -- issue first.
         __builtin_amdgcn_s_setprio(0);
         // operand reads from LDS run kPre K blocks ahead of the products
-        constexpr int kPre = 2;
+        constexpr int kPre = KPRE < NKB ? KPRE : NKB;
         v4i af[kPre];
 #pragma unroll
         for (int q = 0; q < kPre; ++q) af[q] = a_lds[buf][q][lane];
@@ -624,7 +477,7 @@ __device__ __forceinline__ uint32_t make_digits(const float (&xs)[16], int half,
     return (uint32_t)(E + 128);
 }
 
-template <int NKB>
+template <int NKB, int KPRE>
 __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, v4i *xd, uint8_t *xe, uint32_t *flags,
@@ -844,7 +697,7 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
         // the products of phase ph, operands from its buffer
         auto products = [&](const v4i(&src)[kPB][kXD][64], int ph) {
             // operand reads from LDS run kPre fragments ahead of the products
-            constexpr int kPre = 4, kFr = kPB * kXD;
+            constexpr int kPre = KPRE, kFr = kPB * kXD;
             v4i af[kPre];
 #pragma unroll
             for (int q = 0; q < kPre; ++q) af[q] = src[q / kXD][q % kXD][lane];
@@ -1055,39 +908,50 @@ __global__ __launch_bounds__(256) void k_fp4_best(
 
 namespace {
 
+// Result-invariant variants of the persistent kernels (the autotuner's
+// candidates): how many K blocks (dSB) or digit fragments (bSB) ahead of the
+// products the operand is read from LDS.  Candidate 0 is the default.
+constexpr int kDsbPre[] = {2, 1, 4};
+constexpr int kBsbPre[] = {4, 2};
+
 template <int NKB>
-const void *kernel_ptr() {
-    return reinterpret_cast<const void *>(&k_dsb_fp4<NKB>);
+const void *dsb_ptr(int tile) {
+    switch (tile) {
+    case 1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[1]>);
+    case 2: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[2]>);
+    default: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[0]>);
+    }
 }
 
-const void *pick_kernel(int nkb) {
+const void *pick_kernel(int nkb, int tile) {
     switch (nkb) {
-    case 4: return kernel_ptr<4>();
-    case 8: return kernel_ptr<8>();
-    case 12: return kernel_ptr<12>();
-    case 16: return kernel_ptr<16>();
-    case 20: return kernel_ptr<20>();
-    case 24: return kernel_ptr<24>();
-    case 28: return kernel_ptr<28>();
-    default: return kernel_ptr<32>();
+    case 4: return dsb_ptr<4>(tile);
+    case 8: return dsb_ptr<8>(tile);
+    case 12: return dsb_ptr<12>(tile);
+    case 16: return dsb_ptr<16>(tile);
+    case 20: return dsb_ptr<20>(tile);
+    case 24: return dsb_ptr<24>(tile);
+    case 28: return dsb_ptr<28>(tile);
+    default: return dsb_ptr<32>(tile);
     }
 }
 
 template <int NKB>
-const void *bsb_kernel_ptr() {
-    return reinterpret_cast<const void *>(&k_bsb_fp4<NKB>);
+const void *bsb_ptr(int tile) {
+    if (tile == 1) return reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[1]>);
+    return reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[0]>);
 }
 
-const void *pick_bsb_kernel(int nkb) {
+const void *pick_bsb_kernel(int nkb, int tile) {
     switch (nkb) {
-    case 4: return bsb_kernel_ptr<4>();
-    case 8: return bsb_kernel_ptr<8>();
-    case 12: return bsb_kernel_ptr<12>();
-    case 16: return bsb_kernel_ptr<16>();
-    case 20: return bsb_kernel_ptr<20>();
-    case 24: return bsb_kernel_ptr<24>();
-    case 28: return bsb_kernel_ptr<28>();
-    default: return bsb_kernel_ptr<32>();
+    case 4: return bsb_ptr<4>(tile);
+    case 8: return bsb_ptr<8>(tile);
+    case 12: return bsb_ptr<12>(tile);
+    case 16: return bsb_ptr<16>(tile);
+    case 20: return bsb_ptr<20>(tile);
+    case 24: return bsb_ptr<24>(tile);
+    case 28: return bsb_ptr<28>(tile);
+    default: return bsb_ptr<32>(tile);
     }
 }
 
@@ -1224,98 +1088,47 @@ int persistent_run(PersistentJ *pj, int variant, const PersistentRun &run, State
                                 b, N, s, timer);
 }
 
-int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team *host_teams,
-                         int nteams_total, const PersistentRun &run, StateBufs &b, int Nrows,
-                         hipStream_t s, KernelTimer &timer) {
-    const bool bsb = variant == HSB_BSB;
-    const int Rpad = run.Rpad, nrb = nkb, nchunk = 2 * nrb;
-    if (nteams_total * 32 > Rpad) return perr(HSB_EINVAL, "FP4 path: teams exceed the columns");
+namespace {
+
+// Teams per launch and workgroups per team of a persistent launch: a multiple
+// of 8 teams (one slot per XCD) whose workgroups all fit on the device at once.
+// Waves hold 64 rows (bSB) or 32 rows (dSB); so do the energy partials.
+int launch_shape(bool bsb, int nkb, int tile, int *teams_per_launch, int *wpt, int *wg_capacity) {
     int dev = 0, ncu = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, bsb ? pick_bsb_kernel(nkb) : pick_kernel(nkb), 256, 0);
+            &nb, bsb ? pick_bsb_kernel(nkb, tile) : pick_kernel(nkb, tile), 256, 0);
     if (e != hipSuccess) return perr(HSB_EDEVICE, "FP4 path: %s", hipGetErrorString(e));
-    // teams per launch: a multiple of 8 (one slot per XCD) whose workgroups all
-    // fit on the device at once.  Waves hold 64 rows (bSB) or 32 rows (dSB);
-    // so do the energy partials
-    const int nparts = bsb ? nrb : nchunk;
-    const int wg_capacity = nb * ncu, wpt = nparts / 4;
-    const int teams_per_launch = 8 * (wg_capacity / (8 * wpt));
-    if (teams_per_launch < 8)
+    const int nparts = bsb ? nkb : 2 * nkb;
+    *wg_capacity = nb * ncu;
+    *wpt = nparts / 4;
+    *teams_per_launch = 8 * (*wg_capacity / (8 * *wpt));
+    if (*teams_per_launch < 8)
         return perr(HSB_EUNSUPPORTED, "FP4 path: %d resident workgroups < 8 teams of %d",
-                    wg_capacity, wpt);
+                    *wg_capacity, *wpt);
+    return HSB_OK;
+}
+
+// The launch sequence of a run whose buffers in pw are in place (sized for
+// nteams_total teams over run.Rpad columns and seg_samples samples per
+// segment) and whose team table is on the device: per segment of at most
+// seg_samples sample points, the persistent launches of all teams, then the
+// sample energies, the best-sample update and the traces.
+int run_segments(PersistentWork *pw, int variant, int nkb, int nteams_total, int teams_per_launch,
+                 int wpt, size_t seg_samples, const PersistentRun &run, StateBufs &b, int Nrows,
+                 hipStream_t s, KernelTimer &timer) {
+    const bool bsb = variant == HSB_BSB;
+    const int Rpad = run.Rpad, nrb = nkb, nchunk = 2 * nrb;
+    const int nparts = bsb ? nrb : nchunk;
     const int interval = run.interval;
-    // samples per launch bounded by a 512 MiB snapshot budget (and 4096)
-    const size_t snap_per_sample = (size_t)nchunk * Rpad;
-    size_t seg_samples = ((size_t)512 << 20) / (snap_per_sample * 4);
-    if (seg_samples > 4096) seg_samples = 4096;
-    if (seg_samples < 1) seg_samples = 1;
     const bool traces = b.trace_e || b.trace_t;
-    const void *const before[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->tp, pw->ptab, pw->err,
-                                  pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
-    int rc = grow(&pw->xb, &pw->xb_words, (size_t)2 * nchunk * Rpad);
-    if (!rc) rc = grow(&pw->snap, &pw->snap_words, (seg_samples + 1) * snap_per_sample);
-    if (!rc) rc = grow(&pw->ep, &pw->ep_elems, (seg_samples + 1) * (size_t)nparts * Rpad);
-    if (!rc) rc = grow(&pw->es, &pw->es_elems, (seg_samples + 1) * (size_t)Rpad);
-    if (!rc && traces) {  // partials of at most the run's own samples per segment
-        const size_t run_samples = (size_t)(run.k1 / interval - run.k0 / interval) + 1;
-        const size_t tps = run_samples < seg_samples + 1 ? run_samples : seg_samples + 1;
-        rc = grow(&pw->tp, &pw->tp_elems, tps * (size_t)nparts * Rpad);
-    }
-    const long long max_seg_steps = (long long)seg_samples * interval;
-    const int ptab_need = (int)((long long)(run.k1 - run.k0) < max_seg_steps
-                                    ? (run.k1 - run.k0)
-                                    : max_seg_steps);
-    if (!rc) rc = grow(&pw->ptab, &pw->ptab_elems, (size_t)(ptab_need > 0 ? ptab_need : 1));
-    size_t one = 0;
-    if (!rc && !pw->err) rc = grow(&pw->err, &one, 1);
-    if (!rc) {
-        const FP4Team *before = pw->teams;
-        rc = grow(&pw->teams, &pw->teams_n, (size_t)nteams_total);
-        if (pw->teams != before) pw->teams_up.clear();  // a new buffer holds no table yet
-    }
-    if (!rc && bsb) rc = grow(&pw->xd, &pw->xd_n, (size_t)2 * nkb * 8 * 2 * Rpad);
-    if (!rc && bsb) rc = grow(&pw->xe, &pw->xe_n, (size_t)2 * 2 * Rpad * nkb);
-    if (!rc && bsb) rc = grow(&pw->flags, &pw->flags_n, (size_t)nteams_total * nrb);
-    if (!rc && !pw->epoch) {
-        rc = grow(&pw->epoch, &pw->epoch_n, 1);
-        if (!rc) {
-            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, pw->epoch, (size_t)1, 0u);
-            if (hipGetLastError() != hipSuccess) rc = perr(HSB_EDEVICE, "epoch fill failed");
-        }
-    }
-    if (!rc && pw->xslot_n < (size_t)wg_capacity + 8 * (size_t)wpt) {
-        rc = grow(&pw->xslot, &pw->xslot_n, (size_t)wg_capacity + 8 * (size_t)wpt);
-        if (!rc) {  // epoch 0xFFFFFFFF in every slot: never a launch's epoch
-            hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((pw->xslot_n + 255) / 256)), dim3(256), 0,
-                               s, pw->xslot, pw->xslot_n);
-            if (hipGetLastError() != hipSuccess) rc = perr(HSB_EDEVICE, "xslot fill failed");
-        }
-    }
-    if (rc) return rc;
-    {
-        const void *const after[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->tp, pw->ptab, pw->err,
-                                     pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
-        if (std::memcmp(before, after, sizeof(before)) != 0) ++pw->gen;
-    }
-    // the team table, uploaded only when it differs from the last upload (a
-    // repeated run then queues no host-to-device copy)
-    if (pw->teams_up.size() != (size_t)nteams_total ||
-        std::memcmp(pw->teams_up.data(), host_teams, sizeof(FP4Team) * (size_t)nteams_total) != 0) {
-        e = hipMemcpyAsync(pw->teams, host_teams, sizeof(FP4Team) * (size_t)nteams_total,
-                           hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);  // host_teams may go away after return
-        if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
-        pw->teams_up.assign(host_teams, host_teams + nteams_total);
-        ++pw->gen;
-    }
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, pw->err);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
     const float a0dt = run.a0 * run.dt;
-    const void *kfn = bsb ? pick_bsb_kernel(nkb) : pick_kernel(nkb);
+    const void *kfn = bsb ? pick_bsb_kernel(nkb, run.tile) : pick_kernel(nkb, run.tile);
     int a = run.k0;
     for (;;) {
         // segment [a, e]: at most seg_samples multiples of interval in (a, e]
@@ -1404,6 +1217,87 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     // an exchange wait that timed out sets bit 1 of the run's status word,
     // which the caller reads with the rest of the status after its output
     return HSB_OK;
+}
+
+}  // namespace
+
+int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team *host_teams,
+                         int nteams_total, const PersistentRun &run, StateBufs &b, int Nrows,
+                         hipStream_t s, KernelTimer &timer) {
+    const bool bsb = variant == HSB_BSB;
+    const int Rpad = run.Rpad, nrb = nkb, nchunk = 2 * nrb;
+    if (nteams_total * 32 > Rpad) return perr(HSB_EINVAL, "FP4 path: teams exceed the columns");
+    int teams_per_launch = 0, wpt = 0, wg_capacity = 0;
+    int rc = launch_shape(bsb, nkb, run.tile, &teams_per_launch, &wpt, &wg_capacity);
+    if (rc) return rc;
+    const int nparts = bsb ? nrb : nchunk;
+    const int interval = run.interval;
+    // samples per launch bounded by a 512 MiB snapshot budget (and 4096)
+    const size_t snap_per_sample = (size_t)nchunk * Rpad;
+    size_t seg_samples = ((size_t)512 << 20) / (snap_per_sample * 4);
+    if (seg_samples > 4096) seg_samples = 4096;
+    if (seg_samples < 1) seg_samples = 1;
+    const bool traces = b.trace_e || b.trace_t;
+    const void *const before[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->tp, pw->ptab, pw->err,
+                                  pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
+    rc = grow(&pw->xb, &pw->xb_words, (size_t)2 * nchunk * Rpad);
+    if (!rc) rc = grow(&pw->snap, &pw->snap_words, (seg_samples + 1) * snap_per_sample);
+    if (!rc) rc = grow(&pw->ep, &pw->ep_elems, (seg_samples + 1) * (size_t)nparts * Rpad);
+    if (!rc) rc = grow(&pw->es, &pw->es_elems, (seg_samples + 1) * (size_t)Rpad);
+    if (!rc && traces) {  // partials of at most the run's own samples per segment
+        const size_t run_samples = (size_t)(run.k1 / interval - run.k0 / interval) + 1;
+        const size_t tps = run_samples < seg_samples + 1 ? run_samples : seg_samples + 1;
+        rc = grow(&pw->tp, &pw->tp_elems, tps * (size_t)nparts * Rpad);
+    }
+    const long long max_seg_steps = (long long)seg_samples * interval;
+    const int ptab_need = (int)((long long)(run.k1 - run.k0) < max_seg_steps
+                                    ? (run.k1 - run.k0)
+                                    : max_seg_steps);
+    if (!rc) rc = grow(&pw->ptab, &pw->ptab_elems, (size_t)(ptab_need > 0 ? ptab_need : 1));
+    size_t one = 0;
+    if (!rc && !pw->err) rc = grow(&pw->err, &one, 1);
+    if (!rc) {
+        const FP4Team *before = pw->teams;
+        rc = grow(&pw->teams, &pw->teams_n, (size_t)nteams_total);
+        if (pw->teams != before) pw->teams_up.clear();  // a new buffer holds no table yet
+    }
+    if (!rc && bsb) rc = grow(&pw->xd, &pw->xd_n, (size_t)2 * nkb * 8 * 2 * Rpad);
+    if (!rc && bsb) rc = grow(&pw->xe, &pw->xe_n, (size_t)2 * 2 * Rpad * nkb);
+    if (!rc && bsb) rc = grow(&pw->flags, &pw->flags_n, (size_t)nteams_total * nrb);
+    if (!rc && !pw->epoch) {
+        rc = grow(&pw->epoch, &pw->epoch_n, 1);
+        if (!rc) {
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, pw->epoch, (size_t)1, 0u);
+            if (hipGetLastError() != hipSuccess) rc = perr(HSB_EDEVICE, "epoch fill failed");
+        }
+    }
+    if (!rc && pw->xslot_n < (size_t)wg_capacity + 8 * (size_t)wpt) {
+        rc = grow(&pw->xslot, &pw->xslot_n, (size_t)wg_capacity + 8 * (size_t)wpt);
+        if (!rc) {  // epoch 0xFFFFFFFF in every slot: never a launch's epoch
+            hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((pw->xslot_n + 255) / 256)), dim3(256), 0,
+                               s, pw->xslot, pw->xslot_n);
+            if (hipGetLastError() != hipSuccess) rc = perr(HSB_EDEVICE, "xslot fill failed");
+        }
+    }
+    if (rc) return rc;
+    {
+        const void *const after[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->tp, pw->ptab, pw->err,
+                                     pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
+        if (std::memcmp(before, after, sizeof(before)) != 0) ++pw->gen;
+    }
+    // the team table, uploaded only when it differs from the last upload (a
+    // repeated run then queues no host-to-device copy)
+    if (pw->teams_up.size() != (size_t)nteams_total ||
+        std::memcmp(pw->teams_up.data(), host_teams, sizeof(FP4Team) * (size_t)nteams_total) != 0) {
+        hipError_t e = hipMemcpyAsync(pw->teams, host_teams, sizeof(FP4Team) * (size_t)nteams_total,
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // host_teams may go away after return
+        if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
+        pw->teams_up.assign(host_teams, host_teams + nteams_total);
+        ++pw->gen;
+    }
+    return run_segments(pw, variant, nkb, nteams_total, teams_per_launch, wpt, seg_samples, run, b,
+                        Nrows, s, timer);
 }
 
 }  // namespace hsb

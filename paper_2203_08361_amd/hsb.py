@@ -30,6 +30,7 @@ PLAN_NAMES = {HSB_PLAN_FP32: "fp32", HSB_PLAN_FP4: "fp4", HSB_PLAN_DIGITS: "digi
 HSB_PREC_AUTO, HSB_PREC_FP32, HSB_PREC_MIXED, HSB_PREC_DIGITS = 0, 1, 2, 3
 HSB_PREC_INCREMENTAL = 4
 HSB_THERMO_HEAT, HSB_THERMO_NOSE_HOOVER = 0, 1
+HSB_SCHED_QUEUE, HSB_SCHED_CLASSES = 0, 1
 
 EXPORTED = ("hsb_create", "hsb_destroy", "hsb_last_error", "hsb_set_option", "hsb_get_option",
             "hsb_run", "hsb_run_ex", "hsb_plan_info", "hsb_run_batch", "hsb_num_samples")
@@ -80,7 +81,7 @@ class hsb_batch_args(ctypes.Structure):
         ("a0", ctypes.c_float), ("dt", ctypes.c_float),
         ("init_amp", ctypes.c_double),
         ("energy_interval", ctypes.c_int32), ("return_best", ctypes.c_int32),
-        ("stream", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p), ("scheduler", ctypes.c_int32),
     ]
 
 
@@ -261,25 +262,32 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
 
 
 def hsb_run_batch(contexts, jobs, variant, steps, a0, dt, init_amp=0.1, energy_interval=100,
-                  return_best=True, stream=None, allow_numeric=False):
+                  return_best=True, stream=None, allow_numeric=False, scheduler=HSB_SCHED_QUEUE,
+                  outs=None):
     """Batch of jobs over several instances (hsb_run_batch).
 
     contexts: list of Context; jobs: list of dicts with keys instance, R, c0,
     gamma, seed.  Returns (list of {"spins", "energy"} device tensors, status).
+    outs may pass the output tensors of an earlier call (the same buffers let
+    a repeated batch run as one graph launch).
     """
     import torch
 
     dev = torch.device("cuda", torch.cuda.current_device())
     hs = (ctypes.c_void_p * len(contexts))(*[c.h.value for c in contexts])
     arr = (hsb_job * max(len(jobs), 1))()
-    outs = []
+    reuse = outs is not None
+    outs = list(outs) if reuse else []
     for k, jd in enumerate(jobs):
         i = jd["instance"]
         N = contexts[i].N if 0 <= i < len(contexts) else 1  # the library rejects bad indices
         R = max(jd["R"], 1)
-        o = {"spins": torch.empty((R, N), dtype=torch.int8, device=dev),
-             "energy": torch.empty(R, dtype=torch.float64, device=dev)}
-        outs.append(o)
+        if reuse:
+            o = outs[k]
+        else:
+            o = {"spins": torch.empty((R, N), dtype=torch.int8, device=dev),
+                 "energy": torch.empty(R, dtype=torch.float64, device=dev)}
+            outs.append(o)
         j = arr[k]
         j.instance, j.R, j.c0, j.gamma = jd["instance"], jd["R"], jd["c0"], jd["gamma"]
         j.seed = jd["seed"] & (2**64 - 1)
@@ -288,6 +296,7 @@ def hsb_run_batch(contexts, jobs, variant, steps, a0, dt, init_amp=0.1, energy_i
     a.struct_size = ctypes.sizeof(hsb_batch_args)
     a.variant, a.steps, a.a0, a.dt = variant, steps, a0, dt
     a.init_amp, a.energy_interval, a.return_best = init_amp, energy_interval, int(return_best)
+    a.scheduler = scheduler
     s = stream if stream is not None else torch.cuda.current_stream()
     a.stream = s.cuda_stream
     rc = load_library().hsb_run_batch(hs, len(contexts), arr, len(jobs), ctypes.byref(a))
