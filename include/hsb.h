@@ -260,6 +260,36 @@ typedef enum { HSB_THERMO_HEAT = 0, HSB_THERMO_NOSE_HOOVER = 1 } hsb_thermostat;
 int hsb_run_ex(hsb_ctx *h, const hsb_run_args *args);
 
 /*
+ * hsb_run_ex_noalloc -- hsb_run_ex for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  It runs what hsb_run_ex runs on the FP4 plan and gives
+ * bitwise the same outputs, but every buffer of the run besides the caller's
+ * inputs and outputs (the state x, y, the exchange words, the sample
+ * snapshots and energies, the best-sample tracking) lives in one fixed array
+ * of HSB_NOALLOC_SCRATCH_BYTES per device, which the library holds from its
+ * first context on that device until the process ends.  No hipMalloc,
+ * hipFree, host-pinned allocation, event, stream or graph is created.
+ *
+ *   h, args  as for hsb_run_ex (device pointers, the caller's stream).
+ *
+ * Scope: dSB (HSB_DSB) on the FP4 plan, i.e. J exact in FP4 with N <= 2048 and
+ * precision AUTO or MIXED (the FP4 J store is built by hsb_create); constant
+ * heating (HSB_THERMO_HEAT), no traces.  Otherwise HSB_EUNSUPPORTED.  A run
+ * whose state (about 18 (N rounded up to 64) bytes per replica, R rounded up to
+ * 64) does not fit, together with the exchange words and at least one sample,
+ * returns HSB_EINVAL before any device work: at N = 2000 up to about 3000
+ * replicas fit.  Longer runs take more launches (fewer samples per launch);
+ * the results are the same.  The timing options are ignored.
+ *
+ * Every call on a device shares that device's array and leaves its contents
+ * behind: each call initialises what it reads.  Calls that overlap on one
+ * device (from several threads or on several streams) race on the array and
+ * must be serialised by the caller.
+ */
+#define HSB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hsb_run_ex_noalloc(hsb_ctx *h, const hsb_run_args *args);
+
+/*
  * hsb_num_samples -- number of sample points of a call of hsb_run_ex with this
  * start_step and steps under the context's HSB_OPT_ENERGY_INTERVAL I: the
  * multiples of I in (start_step, start_step + steps], plus the last state if

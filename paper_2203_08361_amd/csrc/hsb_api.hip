@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -47,6 +48,45 @@ bool fp4_exact(float v) {
     const float a = std::fabs(v);
     return a == 0.0f || a == 0.5f || a == 1.0f || a == 1.5f || a == 2.0f || a == 3.0f ||
            a == 4.0f || a == 6.0f;
+}
+
+}  // namespace
+
+// Work space of hsb_run_ex_noalloc: one fixed array per device, held from the
+// library's first use of the device until the process ends.  Host code never
+// passes this name to a kernel (on the host it is only a stand-in for the
+// device symbol): it uses the address hipGetSymbolAddress returns per device.
+static __device__ __align__(256) unsigned char scratch[HSB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current (looked up
+// once per device, at the first context created on it).
+int scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(HSB_EDEVICE, "device %d beyond the %d the library supports", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(HSB_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return HSB_OK;
+}
+
+__global__ void k_flag_clear(int32_t *flag) { flag[0] = 0; }
+
+// flag = 1 if some gamma_rep[r], r < R, is not finite or is negative
+__global__ void k_flag_bad_gamma(const float *__restrict__ g, int R, int32_t *flag) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R && !(isfinite(g[r]) && g[r] >= 0.0f)) atomicOr(flag, 1);
 }
 
 }  // namespace
@@ -204,6 +244,22 @@ extern "C" int hsb_create(const float *J, int N, hsb_ctx **out) {
         return rc;
     }
     h->hJ.assign(J, J + (size_t)N * N);
+    // the FP4 J store is built here when it applies, so that a run never has
+    // to allocate it (hsb_run_ex_noalloc relies on that)
+    if (h->j_fp4_exact && hsb::persistent_supported(N)) {
+        const int rc = hsb::persistent_create(h->hJ.data(), N, &h->pj);
+        if (rc != HSB_OK) {
+            fail(rc, "hsb_create: %s", hsb::persistent_error());
+            hsb_destroy(h);
+            return rc;
+        }
+    }
+    void *scr = nullptr;
+    const int rc = scratch_address(dev, &scr);
+    if (rc != HSB_OK) {
+        hsb_destroy(h);
+        return rc;
+    }
     *out = h;
     return HSB_OK;
 }
@@ -896,6 +952,96 @@ extern "C" int hsb_run(hsb_ctx *h, int variant, float a0, float c0, float dt, fl
                            h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return rc;
+}
+
+extern "C" int hsb_run_ex_noalloc(hsb_ctx *h, const hsb_run_args *a) {
+    g_err[0] = 0;
+    if (!h || !a) return fail(HSB_EINVAL, "hsb_run_ex_noalloc: NULL argument");
+    if (a->struct_size != sizeof(hsb_run_args))
+        return fail(HSB_EINVAL, "hsb_run_ex_noalloc: struct_size %zu != %zu", a->struct_size,
+                    sizeof(hsb_run_args));
+    int rc = check_run_args(a);
+    if (rc != HSB_OK) return rc;
+    if (a->variant != HSB_DSB)
+        return fail(HSB_EUNSUPPORTED, "hsb_run_ex_noalloc runs dSB only");
+    if (a->thermostat != HSB_THERMO_HEAT || a->trace_energy || a->trace_tinst)
+        return fail(HSB_EUNSUPPORTED, "hsb_run_ex_noalloc runs neither the thermostat nor traces");
+    int plan = 0;
+    rc = choose_plan(h, HSB_DSB, &plan);
+    if (rc != HSB_OK) return rc;
+    if (plan != PLAN_FP4 || !h->pj)
+        return fail(HSB_EUNSUPPORTED, "hsb_run_ex_noalloc needs the FP4 plan (J exact in FP4, "
+                                      "N <= %d, precision AUTO or MIXED)",
+                    hsb::persistent_max_n());
+    HIP_TRY(hipSetDevice(h->device));
+    void *base = nullptr;
+    rc = scratch_address(h->device, &base);
+    if (rc != HSB_OK) return rc;
+    const int N = h->N, Npad = h->Npad, R = a->R;
+    const int Rpad = round_up(R, hsb::kTile);
+    // the state of the run, carved from the front of the scratch
+    uint8_t *const s0 = static_cast<uint8_t *>(base);
+    size_t used = 0;
+    auto take = [&](size_t bytes) {
+        used = (used + 255) / 256 * 256;
+        void *p = s0 + used;
+        used += bytes;
+        return p;
+    };
+    const size_t nr = (size_t)Rpad, ns = (size_t)Npad * nr;
+    hsb::StateBufs b{};
+    b.X = static_cast<float *>(take(ns * sizeof(float)));
+    b.Y = static_cast<float *>(take(ns * sizeof(float)));
+    b.gamma = static_cast<float *>(take(nr * sizeof(float)));
+    b.best_e = static_cast<double *>(take(nr * sizeof(double)));
+    b.last_e = static_cast<double *>(take(nr * sizeof(double)));
+    b.best_step = static_cast<int32_t *>(take(nr * sizeof(int32_t)));
+    b.bad = static_cast<int32_t *>(take(nr * sizeof(int32_t)));
+    b.best_s = static_cast<int8_t *>(take(ns));
+    b.status = static_cast<int32_t *>(take(sizeof(int32_t)));
+    int32_t *flag = static_cast<int32_t *>(take(sizeof(int32_t)));
+    used = (used + 255) / 256 * 256;
+    if (used >= HSB_NOALLOC_SCRATCH_BYTES)
+        return fail(HSB_EINVAL, "hsb_run_ex_noalloc: R = %d at N = %d needs %zu bytes of state, "
+                                "more than the %zu-byte scratch", R, N, used,
+                    (size_t)HSB_NOALLOC_SCRATCH_BYTES);
+    hipStream_t s = (hipStream_t)a->stream;
+    if (a->gamma_rep) {  // checked on the device: no host copy of the array
+        int32_t bad = 0;
+        hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, s, flag);
+        hipLaunchKernelGGL(k_flag_bad_gamma, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s,
+                           a->gamma_rep, R, flag);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (bad) return fail(HSB_EINVAL, "gamma_rep must be finite and >= 0");
+    }
+    const float amp = (float)h->init_amp;
+    if (a->x0)
+        HIP_TRY(hsb::launch_load_state(b.X, b.Y, a->x0, a->y0, N, R, Npad, Rpad, s));
+    else
+        HIP_TRY(hsb::launch_init_seeded(b.X, b.Y, N, R, Npad, Rpad, Rpad, a->seed, amp, s));
+    HIP_TRY(hsb::launch_fill_gamma(b.gamma, a->gamma_rep, a->gamma, R, Rpad, s));
+    HIP_TRY(hsb::launch_reset_tracking(b, Rpad, s));
+    hsb::PersistentRun pr{};
+    pr.X = b.X; pr.Y = b.Y; pr.gamma = b.gamma;
+    pr.Npad = Npad; pr.Rpad = Rpad; pr.R = R;
+    pr.k0 = a->start_step; pr.k1 = a->start_step + a->steps;
+    pr.Ns = a->schedule_steps > 0 ? a->schedule_steps : a->start_step + a->steps;
+    pr.interval = h->interval;
+    pr.a0 = a->a0; pr.c0 = a->c0; pr.dt = a->dt;
+    pr.local_exchange = h->local_exchange;
+    rc = hsb::persistent_run_in(s0 + used, HSB_NOALLOC_SCRATCH_BYTES - used, h->pj, pr, b, N, s);
+    if (rc != HSB_OK) return fail(rc, "hsb_run_ex_noalloc: %s", hsb::persistent_error());
+    HIP_TRY(hsb::launch_output(b, N, R, Rpad, h->return_best, a->spins, a->energy, a->x_out,
+                               a->y_out, a->best_energy, a->final_energy, a->best_step, s));
+    int32_t status = 0;
+    HIP_TRY(hipMemcpyAsync(&status, b.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (status & 2) return fail(HSB_EDEVICE, "FP4 persistent kernel: exchange wait timed out");
+    h->last_plan = PLAN_FP4;
+    if (status) return fail(HSB_ENUMERIC, "a replica's state became non-finite");
+    return HSB_OK;
 }
 
 extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs, int n_jobs,

@@ -48,6 +48,12 @@ int persistent_run(PersistentJ *pj, int variant, const PersistentRun &run, State
 int persistent_run_teams(PersistentWork *w, int variant, int nkb, const FP4Team *host_teams,
                          int nteams, const PersistentRun &run, StateBufs &b, int Nrows,
                          hipStream_t s, KernelTimer &timer);
+// A dSB run of the FP4 plan (every team on pj's instance, c0 = run.c0) whose
+// work buffers are carved from `scratch` (device memory of `bytes` bytes, 256-byte
+// aligned) instead of being allocated: nothing is allocated or freed.  The
+// samples per launch shrink to what fits; HSB_EINVAL if not even one does.
+int persistent_run_in(void *scratch, size_t bytes, const PersistentJ *pj, const PersistentRun &run,
+                      StateBufs &b, int Nrows, hipStream_t s);
 int persistent_work_create(PersistentWork **out);
 void persistent_work_free(PersistentWork *w);
 int persistent_nkb(const PersistentJ *pj);

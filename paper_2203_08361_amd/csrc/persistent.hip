@@ -1219,6 +1219,12 @@ int run_segments(PersistentWork *pw, int variant, int nkb, int nteams_total, int
     return HSB_OK;
 }
 
+// Every entry of the team table: the same instance (J fragments, N, c0).
+__global__ void k_fill_teams(FP4Team *teams, int n, const void *jpk, int N, float c0) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) teams[t] = FP4Team{jpk, N, c0};
+}
+
 }  // namespace
 
 int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team *host_teams,
@@ -1298,6 +1304,81 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     }
     return run_segments(pw, variant, nkb, nteams_total, teams_per_launch, wpt, seg_samples, run, b,
                         Nrows, s, timer);
+}
+
+// Scratch layout of a dSB run of the FP4 plan in caller-given memory: every
+// buffer of the run's work, 256-byte aligned, carved in order from `base`.
+// With base == nullptr only the size is computed.
+namespace {
+struct Carver {
+    uint8_t *base;
+    size_t used = 0;
+    template <typename T>
+    T *take(size_t n) {
+        used = (used + 255) / 256 * 256;
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used += n * sizeof(T);
+        return p;
+    }
+};
+void carve_dsb_work(Carver &c, PersistentWork &w, int nkb, int nteams, int Rpad, size_t seg,
+                    size_t ptab_n, size_t nslots) {
+    const size_t nchunk = 2 * (size_t)nkb;
+    w.xb = c.take<uint64_t>(2 * nchunk * Rpad);
+    w.snap = c.take<uint32_t>((seg + 1) * nchunk * Rpad);
+    w.ep = c.take<float>((seg + 1) * nchunk * Rpad);
+    w.es = c.take<double>((seg + 1) * (size_t)Rpad);
+    w.ptab = c.take<float>(ptab_n);
+    w.err = c.take<int32_t>(1);
+    w.epoch = c.take<uint32_t>(1);
+    w.xslot = c.take<uint64_t>(nslots);
+    w.teams = c.take<FP4Team>((size_t)nteams);
+}
+}  // namespace
+
+int persistent_run_in(void *scratch, size_t bytes, const PersistentJ *pj, const PersistentRun &run,
+                      StateBufs &b, int Nrows, hipStream_t s) {
+    const int nkb = pj->nkb, Rpad = run.Rpad, nteams = Rpad / 32;
+    int teams_per_launch = 0, wpt = 0, wg_capacity = 0;
+    int rc = launch_shape(false, nkb, run.tile, &teams_per_launch, &wpt, &wg_capacity);
+    if (rc) return rc;
+    const size_t nslots = (size_t)wg_capacity + 8 * (size_t)wpt;
+    const int interval = run.interval;
+    // the most samples per segment that fit (at most the run's own, and 4096)
+    const size_t run_samples = (size_t)(run.k1 / interval - run.k0 / interval) + 1;
+    size_t seg = run_samples < 4096 ? run_samples : 4096;
+    auto need = [&](size_t sg) {
+        const long long steps = (long long)sg * interval;
+        const size_t ptab_n = (size_t)((long long)(run.k1 - run.k0) < steps ? (run.k1 - run.k0)
+                                                                            : steps) + 1;
+        Carver c{nullptr};
+        PersistentWork w;
+        carve_dsb_work(c, w, nkb, nteams, Rpad, sg, ptab_n, nslots);
+        return std::pair<size_t, size_t>(c.used, ptab_n);
+    };
+    while (seg > 1 && need(seg).first > bytes) seg /= 2;
+    const auto nd = need(seg);
+    if (nd.first > bytes)
+        return perr(HSB_EINVAL, "the run needs %zu bytes of work space, %zu are left in the "
+                                "fixed scratch", nd.first, bytes);
+    Carver c{static_cast<uint8_t *>(scratch)};
+    PersistentWork w;
+    carve_dsb_work(c, w, nkb, nteams, Rpad, seg, nd.second, nslots);
+    // the buffers sit wherever this call's sizes put them, so the placement
+    // slots and the launch epoch start afresh (slot tag 0xFFFFFFFF is never an
+    // epoch), and the team table is written on the device
+    hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s,
+                       w.xslot, nslots);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, w.epoch, (size_t)1, 0u);
+    hipLaunchKernelGGL(k_fill_teams, dim3((unsigned)((nteams + 255) / 256)), dim3(256), 0, s,
+                       w.teams, nteams, (const void *)pj->jpk, pj->N, run.c0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
+    KernelTimer off;
+    rc = run_segments(&w, HSB_DSB, nkb, nteams, teams_per_launch, wpt, seg, run, b, Nrows, s, off);
+    // w points into the caller's scratch: nothing of it is freed
+    w = PersistentWork{};
+    return rc;
 }
 
 }  // namespace hsb

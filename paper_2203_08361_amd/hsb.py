@@ -33,7 +33,9 @@ HSB_THERMO_HEAT, HSB_THERMO_NOSE_HOOVER = 0, 1
 HSB_SCHED_QUEUE, HSB_SCHED_CLASSES = 0, 1
 
 EXPORTED = ("hsb_create", "hsb_destroy", "hsb_last_error", "hsb_set_option", "hsb_get_option",
-            "hsb_run", "hsb_run_ex", "hsb_plan_info", "hsb_run_batch", "hsb_num_samples")
+            "hsb_run", "hsb_run_ex", "hsb_plan_info", "hsb_run_batch", "hsb_num_samples",
+            "hsb_run_ex_noalloc")
+HSB_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 
@@ -108,6 +110,8 @@ def load_library():
     L.hsb_run.argtypes = [vp, i32, f32, f32, f32, f32, i32, i32, ctypes.c_uint64, vp, vp]
     L.hsb_run_ex.restype = i32
     L.hsb_run_ex.argtypes = [vp, ctypes.POINTER(hsb_run_args)]
+    L.hsb_run_ex_noalloc.restype = i32
+    L.hsb_run_ex_noalloc.argtypes = [vp, ctypes.POINTER(hsb_run_args)]
     L.hsb_plan_info.restype = i32
     L.hsb_plan_info.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.hsb_num_samples.restype = i32
@@ -184,7 +188,8 @@ def hsb_num_samples(h, start_step: int, steps: int) -> int:
 
 def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=None, x0=None,
                y0=None, start_step=0, schedule_steps=0, want_state=False, stream=None,
-               allow_numeric=False, out=None, traces=False, nose_hoover=None, xi0=None):
+               allow_numeric=False, out=None, traces=False, nose_hoover=None, xi0=None,
+               noalloc=False):
     """Device run through hsb_run_ex.  Tensors are torch CUDA tensors.
 
     Returns a dict of device tensors: spins [R][N] int8, energy/best_energy/
@@ -196,6 +201,10 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
     nose_hoover=(inv_mass, T) runs the thermostat of eqs. (6)-(8) in place of
     the constant heating rate (xi starts at -gamma, or at xi0 [R] float64);
     the result then has xi [R] float64, its value after the last step.
+
+    noalloc=True calls hsb_run_ex_noalloc instead (the library allocates no
+    device memory for the run; pass preallocated outputs in `out` to keep
+    this call itself free of allocations).
     """
     import torch
 
@@ -255,7 +264,8 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
         a.trace_tinst = o["trace_tinst"].data_ptr()
     s = stream if stream is not None else torch.cuda.current_stream()
     a.stream = s.cuda_stream
-    rc = load_library().hsb_run_ex(h, ctypes.byref(a))
+    L = load_library()
+    rc = (L.hsb_run_ex_noalloc if noalloc else L.hsb_run_ex)(h, ctypes.byref(a))
     _check(rc, (HSB_ENUMERIC,) if allow_numeric else ())
     o["status"] = rc
     return o

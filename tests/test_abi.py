@@ -102,6 +102,7 @@ def test_calls_on_null_context_are_rejected():
     L = hsb.load_library()
     assert L.hsb_run(None, 0, 1.0, 0.1, 1.0, 0.0, 10, 4, 0, None, None) == hsb.HSB_EINVAL
     assert L.hsb_run_ex(None, None) == hsb.HSB_EINVAL
+    assert L.hsb_run_ex_noalloc(None, None) == hsb.HSB_EINVAL
     assert L.hsb_set_option(None, 0, 0.1) == hsb.HSB_EINVAL
     a = hsb.hsb_batch_args()
     a.struct_size = ctypes.sizeof(a)
@@ -110,6 +111,12 @@ def test_calls_on_null_context_are_rejected():
     assert L.hsb_num_samples(None, 0, 10, ctypes.byref(n)) == hsb.HSB_EINVAL
     assert n.value == -7
     L.hsb_destroy(None)  # ignored
+
+
+def test_noalloc_scratch_size_matches_header():
+    text = open(os.path.join(ROOT, "include", "hsb.h")).read()
+    m = re.search(r"#define HSB_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == hsb.HSB_NOALLOC_SCRATCH_BYTES
 
 
 def test_valid_J_without_gpu_is_a_device_error():
