@@ -65,6 +65,9 @@ typedef enum {
     HSB_EDEVICE = -3,     /* HIP runtime error or no usable gfx950 device */
     HSB_ENUMERIC = -4,    /* a replica's state became non-finite; its energy is NaN,
                              all other outputs are valid */
+    HSB_ECANCELED = -5,   /* the run was stopped by hsb_cancel at a sample point; the
+                             outputs hold the state and samples up to where each replica
+                             stopped (hsb_run_args.stop_step) */
     HSB_EUNSUPPORTED = -6 /* a requested precision plan cannot run this problem */
 } hsb_status;
 
@@ -100,7 +103,25 @@ typedef enum {
                                     context, or one that reallocates a buffer the graph uses,
                                     drops the graph.  Not used while timing is on or while
                                     the caller's stream is being captured.  0: always eager */
-    HSB_OPT_GRAPH_LAUNCHES = 10  /* read only: runs of this context served by a graph launch */
+    HSB_OPT_GRAPH_LAUNCHES = 10, /* read only: runs of this context served by a graph launch */
+    HSB_OPT_AUTOTUNE = 11,       /* 1: pick the kernel variant of each run (hsb_run_ex, and the
+                                    queue placement of batches led by this context) from an
+                                    on-disk cache, timing every variant on the first 200
+                                    steps of the run's own shape the first time a (plan,
+                                    variant, padded N, padded R, J kind, thermostat) shape
+                                    is seen and storing the fastest.  The variants give
+                                    bitwise the same results; only the time differs.  The
+                                    cache file is $HSB_TUNE_CACHE, else
+                                    $XDG_CACHE_HOME/hsb/tune.txt, else
+                                    $HOME/.cache/hsb/tune.txt.  0 (default): variant 0 */
+    HSB_OPT_TILE = 12,           /* -1 (default): variant from AUTOTUNE (else 0); k >= 0: force
+                                    variant k.  FP4 dSB: 0..2 = operand read 2, 1, 4 K blocks
+                                    ahead of the products; FP4 bSB: 0..1 = 4, 2 fragments
+                                    ahead; DIGITS: 0..1 = the default wave height of the digit
+                                    combination, the other one (32 or 64 rows: two or one
+                                    workgroups per CU); batch queues: 0..1 = longest-first,
+                                    round robin.  A variant the plan lacks: HSB_EINVAL */
+    HSB_OPT_LAST_TILE = 13       /* read only: the variant of the last successful run */
 } hsb_option;
 
 typedef enum {
@@ -226,6 +247,8 @@ typedef struct {
     double nh_temperature;  /* T >= 0 of eq. (8), finite */
     const double *xi0;      /* optional [R] xi at start_step; default -gamma (per replica) */
     double *xi_out;         /* optional [R] xi after the last step (to resume) */
+    int32_t *stop_step;     /* optional [R]: the step count each replica reached:
+                               start_step + steps, or where hsb_cancel stopped it */
 } hsb_run_args;
 
 /*
@@ -240,10 +263,13 @@ typedef struct {
  *                             xi(t_k+1) = xi(t_k) + (dt/M)(sum_i y_i(t_k)^2 - N T),
  *                           explicit Euler on eq. (8) with the state before the
  *                           step.  xi starts at -gamma, so 1/M = 0 is exactly
- *                           heated SB.  The thermostat needs the sum over all
- *                           spins every step, which the persistent FP4 plan does
- *                           not form: where AUTO or MIXED would take that plan,
- *                           the integer-digit plan runs instead.
+ *                           heated SB.  The sum over all spins is formed every
+ *                           step in FP64 from per-32-row partials in a fixed
+ *                           order.  dSB runs it on every plan (on the FP4 plan
+ *                           inside the persistent kernel: each workgroup's
+ *                           partial is exchanged with the sign words); for bSB,
+ *                           where AUTO or MIXED would take the FP4 plan, the
+ *                           integer-digit plan runs instead.
  */
 typedef enum { HSB_THERMO_HEAT = 0, HSB_THERMO_NOSE_HOOVER = 1 } hsb_thermostat;
 
@@ -258,6 +284,35 @@ typedef enum { HSB_THERMO_HEAT = 0, HSB_THERMO_NOSE_HOOVER = 1 } hsb_thermostat;
  * the entries of a replica that became non-finite are unspecified.
  */
 int hsb_run_ex(hsb_ctx *h, const hsb_run_args *args);
+
+/*
+ * hsb_cancel -- ask the run in progress on h (hsb_run, hsb_run_ex,
+ * hsb_run_ex_noalloc) to stop early.  Callable from any thread at any time; it
+ * only sets a request word that the device reads.
+ *
+ * The run stops at a sample point: a step count m, start_step < m <
+ * start_step + steps, that is a multiple of HSB_OPT_ENERGY_INTERVAL.
+ *   - Per-step plans (FP32, DIGITS, INCREMENTAL): the request is read after
+ *     each sample; the first sample point at which it is seen is where every
+ *     replica stops.
+ *   - FP4 plan: the replicas of each 32-replica team stop together at the
+ *     first sample point after the team's first wave has seen the request
+ *     (read one step before each sample point); different teams may stop at
+ *     different sample points.
+ * A stopped replica's outputs are those of a run of that many steps: its
+ * state (x_out, y_out), its samples up to the stop (energy, best and final
+ * energies, best step, traces; later trace rows are unspecified), and xi.
+ * stop_step[r] receives the step count replica r reached, and the run
+ * returns HSB_ECANCELED (before HSB_ENUMERIC) if any replica stopped early.
+ * A run resumes from there with x0 = x_out, y0 = y_out, start_step = the stop
+ * step, and the same schedule_steps.
+ *
+ * The request belongs to the context's next or current run and is cleared
+ * when that run returns, whether or not it stopped the run (a request that
+ * arrives after the run's last sample point has no effect).  Batches
+ * (hsb_run_batch) are not cancelled.  NULL: HSB_EINVAL.
+ */
+int hsb_cancel(hsb_ctx *h);
 
 /*
  * hsb_run_ex_noalloc -- hsb_run_ex for callers that cannot allocate device

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsb.so")
-SOURCES = ["hsb_api.hip", "kernels.hip", "persistent.hip", "digits.hip", "batch.hip"]
+SOURCES = ["hsb_api.hip", "kernels.hip", "persistent.hip", "digits.hip", "batch.hip", "tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -310,17 +310,24 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4_queue(
     const int qbeg = qoff[q], qlen = qoff[q + 1] - qbeg;
     const uint32_t epoch = __hip_atomic_load(epoch_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int my_xcc = xcc_id();
+    // The first unit of workgroup j of a queue is entry j: block 8 j + q runs
+    // part j % wpt of the queue's team j / wpt when all teams have wpt parts,
+    // the placement of the single-run kernel (the two workgroups a CU holds,
+    // blocks b and b + 256, then belong to different teams, out of step with
+    // each other).  Later entries go to whichever workgroup is free first.
+    int first = (int)(blockIdx.x >> 3);
     for (;;) {
         __syncthreads();  // nothing of the previous unit is read any more
         if (threadIdx.x == 0) {
             int u = -1;
             if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-                const int k = atomicAdd(head + q, 1);
+                const int k = first >= 0 ? first : atomicAdd(head + q, 1);
                 if (k < qlen) u = (int)units[qbeg + k];
             }
             sh.unit = u;
             sh.abort = 0;
         }
+        first = -1;
         __syncthreads();
         // wave-uniform values (scalar registers): the unit, the team record
         const int unit = __builtin_amdgcn_readfirstlane(sh.unit);
@@ -590,7 +597,9 @@ int queue_run(QueueWork *w, const std::vector<QTeam> &teams, const QRun &run, in
     const size_t nxb = nt * kTeamWords;
     hipLaunchKernelGGL(k_q_fill_u64, dim3(cdiv(nxb, 256)), dim3(256), 0, s, w->xb, nxb,
                        (uint64_t)kNoTag << 32);
-    hipLaunchKernelGGL(k_q_fill_i32, dim3(1), dim3(64), 0, s, (int32_t *)w->head, (size_t)8, 0);
+    // the queues' counters start past the entries taken statically (one per workgroup)
+    hipLaunchKernelGGL(k_q_fill_i32, dim3(1), dim3(64), 0, s, (int32_t *)w->head, (size_t)8,
+                       grid / 8);
     hipLaunchKernelGGL(k_q_fill_i32, dim3(cdiv(nt * 32, 256)), dim3(256), 0, s, w->bad, nt * 32, 0);
     hipLaunchKernelGGL(k_q_fill_i32, dim3(1), dim3(64), 0, s, w->status, (size_t)1, 0);
     hipLaunchKernelGGL(k_q_fill_i32, dim3(1), dim3(64), 0, s, w->err, (size_t)1, 0);

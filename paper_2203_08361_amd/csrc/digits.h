@@ -31,6 +31,9 @@ void i8_free(I8J *p);
 const char *i8_error();
 bool i8_exact(const I8J *p);  // J held exactly (one digit)
 int i8_max_n();
+// Number of result-invariant variants of the step kernel (the autotuner's
+// candidates; 0 is the default): 32-row or 64-row waves.
+int i8_tiles();
 
 struct I8Run {
     int variant;          // HSB_BSB / HSB_DSB
@@ -39,6 +42,8 @@ struct I8Run {
     int k0, k1, Ns, interval;
     float a0, c0, dt;
     const NHState *nh = nullptr;  // Nose-Hoover thermostat: rate -xi(t_k) per step
+    int tile = 0;  // 0: the default wave height of the digit combination, 1: the other
+    const int32_t *cancel = nullptr;  // cancel request polled after each sample (b.stop set)
 };
 
 // Run steps k0..k1-1 of the digit plan on the state in `b` (X, Y in

@@ -83,7 +83,9 @@ __device__ __forceinline__ int x_fixed(float x) { return (int)rintf(x * 0x1p30f)
 template <int NXD>
 __global__ __launch_bounds__(64) void k_i8_digits(const float *__restrict__ X,
                                                   int8_t *__restrict__ xd, int Nst, int Npad,
-                                                  int Rpad, int nsets) {
+                                                  int Rpad, int nsets,
+                                                  const int32_t *__restrict__ stop) {
+    if (stop && stop[0] >= 0) return;  // a cancelled run: no more samples
     const int r = blockIdx.x * 64 + threadIdx.x;
     const int kb = blockIdx.y, nkb = Npad / 16;
     uint32_t w[NXD][4];
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_field(
     const v4i *__restrict__ jd, const double *__restrict__ rowscale, const v4i *__restrict__ xin,
     int8_t *__restrict__ xout, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gam, double *__restrict__ epart, int Nst, int Npad, int Rpad,
-    float p, float c0, float dt, float a0dt, NHFused nhf) {
+    float p, float c0, float dt, float a0dt, NHFused nhf, const int32_t *__restrict__ stop) {
     constexpr int NW = (NJD + NXD - 1) < 4 ? (NJD + NXD - 1) : 4;  // accumulated weights
     constexpr int KB = 2 * KC;                                       // K blocks per stage
     constexpr int BTOT = NXD * KB * 32;                              // B records per stage
@@ -133,6 +135,8 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_field(
     constexpr double kXs = NXD == 4 ? 0x1p-30 : 1.0;
     constexpr double kTrunc = (NJD + NXD - 1 - NW) == 3 ? 0x1p24 : 1.0;
     __shared__ v4i bs[2][NXD][KB][32];
+    // a run stopped by a cancel request: every later step and sample returns
+    if (stop && __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, l32 = lane & 31;
     // XCD-aware tile order: block L runs on XCD L % 8; each XCD takes a
@@ -376,19 +380,34 @@ constexpr int tiles_per_wave(int njd, int nxd, bool energy) {
     return energy ? 2 : ((njd == 4 || nxd == 1) ? 1 : 2);
 }
 
-template <int NJD, int NXD, int KC, bool ENERGY, bool NH = false>
+template <int NJD, int NXD, int KC, bool ENERGY, bool NH = false,
+          int NT = tiles_per_wave(NJD, NXD, ENERGY)>
 hipError_t launch_field(const I8J *p, const int8_t *xin, int8_t *xout, StateBufs &b, int Nst,
                         int Rpad, float pk, float c0, float dt, float a0dt, hipStream_t s,
                         const NHFused &nhf = NHFused{}) {
-    constexpr int NT = tiles_per_wave(NJD, NXD, ENERGY);
     const dim3 grid(p->Npad / (128 * NT), Rpad / 32);
     hipLaunchKernelGGL((k_i8_field<NJD, NXD, KC, ENERGY, NH, NT>), grid, dim3(256), 0, s, p->jd,
                        p->rowscale, reinterpret_cast<const v4i *>(xin), xout, b.X, b.Y, b.gamma,
-                       b.epart, Nst, p->Npad, Rpad, pk, c0, dt, a0dt, nhf);
+                       b.epart, Nst, p->Npad, Rpad, pk, c0, dt, a0dt, nhf, b.stop);
     return hipGetLastError();
 }
 
+// One step of the plan with nt 32-row tiles per wave (1: 32-row waves, two
+// workgroups per CU; 2: 64-row waves, one): both give the same exact sums.
+template <int NJD, int NXD, int KC, bool NH>
+hipError_t launch_step(int nt, const I8J *p, const int8_t *xin, int8_t *xout, StateBufs &b,
+                       int Nst, int Rpad, float pk, float c0, float dt, float a0dt, hipStream_t s,
+                       const NHFused &nhf) {
+    if (nt == 1)
+        return launch_field<NJD, NXD, KC, false, NH, 1>(p, xin, xout, b, Nst, Rpad, pk, c0, dt, a0dt,
+                                                        s, nhf);
+    return launch_field<NJD, NXD, KC, false, NH, 2>(p, xin, xout, b, Nst, Rpad, pk, c0, dt, a0dt, s,
+                                                    nhf);
+}
+
 }  // namespace
+
+int i8_tiles() { return 2; }
 
 int i8_create(const float *hJ, int N, I8J **out) {
     *out = nullptr;
@@ -463,9 +482,11 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
     hipError_t e = hipSuccess;
     const dim3 dgrid(Rpad / 64, nkb);
     if (bsb)
-        hipLaunchKernelGGL(k_i8_digits<4>, dgrid, dim3(64), 0, s, b.X, p->xd, Nst, Np, Rpad, 2);
+        hipLaunchKernelGGL(k_i8_digits<4>, dgrid, dim3(64), 0, s, b.X, p->xd, Nst, Np, Rpad, 2,
+                           (const int32_t *)nullptr);
     else
-        hipLaunchKernelGGL(k_i8_digits<1>, dgrid, dim3(64), 0, s, b.X, p->xd, Nst, Np, Rpad, 2);
+        hipLaunchKernelGGL(k_i8_digits<1>, dgrid, dim3(64), 0, s, b.X, p->xd, Nst, Np, Rpad, 2,
+                           (const int32_t *)nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return derr(HSB_EDEVICE, "%s", hipGetErrorString(e));
 
@@ -478,23 +499,29 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
         int nblk;
         if (p->njd == 1) {
             hipLaunchKernelGGL(k_i8_digits<1>, dgrid, dim3(64), 0, s, b.X, p->sd, Nst, Np, Rpad,
-                               1);
+                               1, b.stop);
             ee = hipGetLastError();
             if (ee == hipSuccess)
                 ee = launch_field<1, 1, 4, true>(p, p->sd, nullptr, b, Nst, Rpad, 0.f, 0.f, 0.f,
                                                  0.f, s);
             nblk = Nst / 64;
         } else {
-            ee = launch_energy_f64(fp32J, b.X, b.epart, Nst, Rpad, s);
+            ee = launch_energy_f64(fp32J, b.X, b.epart, Nst, Rpad, s, b.stop);
             nblk = Nst / 64;
         }
         if (ee == hipSuccess) ee = launch_best(b, nblk, run.N, run.R, Rpad, m, s);
+        // a cancel request seen here stops the run at this sample point
+        if (ee == hipSuccess && run.cancel && m < k1) ee = launch_poll_cancel(run.cancel, b.stop, m, s);
         if (ee != hipSuccess) return derr(HSB_EDEVICE, "%s", hipGetErrorString(ee));
         return HSB_OK;
     };
     if (k1 == k0) return sample(k0);
+    // 32-row tiles per wave: the default of the digit combination, or the
+    // other height (tile 1)
+    const int nt_def = tiles_per_wave(p->njd, bsb ? 4 : 1, false);
+    const int nt = run.tile == 1 ? 3 - nt_def : nt_def;
     // per-wave partials of the thermostat's sum (32 or 64 rows)
-    const int nh_parts = Nst / (32 * tiles_per_wave(p->njd, bsb ? 4 : 1, false));
+    const int nh_parts = Nst / (32 * nt);
     int cur = 0;
     size_t nrun = 0;  // step launches since the last energy sample
     for (int k = k0; k < k1; ++k) {
@@ -517,26 +544,27 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
             f.c = run.nh->c;
             f.NT = run.nh->NT;
             if (p->njd == 1)
-                e = bsb ? launch_field<1, 4, 4, false, true>(p, xin, xout, b, Nst, Rpad, pk, c0,
-                                                             dt, a0dt, s, f)
-                        : launch_field<1, 1, 4, false, true>(p, xin, xout, b, Nst, Rpad, pk, c0,
-                                                             dt, a0dt, s, f);
+                e = bsb ? launch_step<1, 4, 4, true>(nt, p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                     a0dt, s, f)
+                        : launch_step<1, 1, 4, true>(nt, p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                     a0dt, s, f);
             else
-                e = bsb ? launch_field<4, 4, 2, false, true>(p, xin, xout, b, Nst, Rpad, pk, c0,
-                                                             dt, a0dt, s, f)
-                        : launch_field<4, 1, 2, false, true>(p, xin, xout, b, Nst, Rpad, pk, c0,
-                                                             dt, a0dt, s, f);
+                e = bsb ? launch_step<4, 4, 2, true>(nt, p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                     a0dt, s, f)
+                        : launch_step<4, 1, 2, true>(nt, p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                     a0dt, s, f);
         } else if (e == hipSuccess) {
+            const NHFused none{};
             if (p->njd == 1)
-                e = bsb ? launch_field<1, 4, 4, false>(p, xin, xout, b, Nst, Rpad, pk, c0, dt,
-                                                       a0dt, s)
-                        : launch_field<1, 1, 4, false>(p, xin, xout, b, Nst, Rpad, pk, c0, dt,
-                                                       a0dt, s);
+                e = bsb ? launch_step<1, 4, 4, false>(nt, p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                      a0dt, s, none)
+                        : launch_step<1, 1, 4, false>(nt, p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                      a0dt, s, none);
             else
-                e = bsb ? launch_field<4, 4, 2, false>(p, xin, xout, b, Nst, Rpad, pk, c0, dt,
-                                                       a0dt, s)
-                        : launch_field<4, 1, 2, false>(p, xin, xout, b, Nst, Rpad, pk, c0, dt,
-                                                       a0dt, s);
+                e = bsb ? launch_step<4, 4, 2, false>(nt, p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                      a0dt, s, none)
+                        : launch_step<4, 1, 2, false>(nt, p, xin, xout, b, Nst, Rpad, pk, c0, dt,
+                                                      a0dt, s, none);
         }
         if (e != hipSuccess) return derr(HSB_EDEVICE, "digit step: %s", hipGetErrorString(e));
         ++nrun;
@@ -550,10 +578,8 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
         }
     }
     if (run.nh) {  // xi after the last step, from its slot and partials, into slot 0
-        const int steps = k1 - k0;
-        e = launch_nh_final(run.nh->xi + (size_t)(steps & 1) * Rpad,
-                            run.nh->part + (size_t)((steps - 1) & 1) * nh_parts * Rpad, nh_parts,
-                            run.R, Rpad, run.nh->xi, run.nh->c, run.nh->NT, s);
+        e = launch_nh_final(run.nh->xi, run.nh->part, nh_parts, run.R, Rpad, run.nh->xi,
+                            run.nh->c, run.nh->NT, k1 - k0, k0, b.stop, s);
         if (e != hipSuccess) return derr(HSB_EDEVICE, "thermostat: %s", hipGetErrorString(e));
     }
     return HSB_OK;

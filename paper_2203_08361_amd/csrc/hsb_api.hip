@@ -17,6 +17,7 @@
 #include "hsb.h"
 #include "kernels.h"
 #include "persistent.h"
+#include "tune.h"
 
 namespace {
 
@@ -124,6 +125,9 @@ struct hsb_ctx {
     int last_plan = -1;
     int local_exchange = 1;
     int graph = 1;
+    int autotune = 0;   // HSB_OPT_AUTOTUNE
+    int tile = -1;      // HSB_OPT_TILE: -1 default / tuned, else a forced variant
+    int last_tile = 0;  // variant of the last successful run
     hsb::KernelTimer timer;
     // graph of the last repeated run (HSB_OPT_GRAPH): the key of that run, whether
     // it ran once eagerly, the instantiated graph, its stream and the events that
@@ -138,6 +142,12 @@ struct hsb_ctx {
     // the initialiser (a graph launch then takes the seed of its call)
     uint64_t *h_seed = nullptr;
     uint64_t *d_seed = nullptr;
+    // cancellation: the request (pinned host word and its device view), the
+    // per-step plans' stop word, and whether runs of this context poll it
+    int32_t *h_cancel = nullptr;
+    const int32_t *d_cancel = nullptr;
+    int32_t *d_stop = nullptr;
+    bool cancellable = true;
     // workspace
     int Rpad_cap = 0;
     uint64_t state_gen = 0;  // raised when the state buffers are reallocated
@@ -186,6 +196,12 @@ void batch_graph_drop(hsb_ctx *h) {
 // --------------------------------------------------------------------- API
 
 extern "C" const char *hsb_last_error(void) { return g_err; }
+
+extern "C" int hsb_cancel(hsb_ctx *h) {
+    if (!h || !h->h_cancel) return fail(HSB_EINVAL, "hsb_cancel: NULL context");
+    __atomic_store_n(h->h_cancel, 1, __ATOMIC_SEQ_CST);
+    return HSB_OK;
+}
 
 extern "C" int hsb_create(const float *J, int N, hsb_ctx **out) {
     g_err[0] = 0;
@@ -238,6 +254,16 @@ extern "C" int hsb_create(const float *J, int N, hsb_ctx **out) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
     if (e == hipSuccess)
         e = hipMemcpy(h->dJ, padded.data(), np * np * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&h->h_cancel, sizeof(int32_t),
+                          hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+        *h->h_cancel = 0;
+        void *dv = nullptr;
+        e = hipHostGetDevicePointer(&dv, h->h_cancel, 0);
+        h->d_cancel = static_cast<const int32_t *>(dv);
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&h->d_stop, sizeof(int32_t));
     if (e != hipSuccess) {
         int rc = hip_fail(e, "hsb_create: J store");
         hsb_destroy(h);
@@ -291,6 +317,8 @@ extern "C" void hsb_destroy(hsb_ctx *h) {
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     if (h->h_seed) (void)hipHostFree(h->h_seed);
     if (h->d_seed) (void)hipFree(h->d_seed);
+    if (h->h_cancel) (void)hipHostFree(h->h_cancel);
+    if (h->d_stop) (void)hipFree(h->d_stop);
     h->timer.release();
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -336,10 +364,20 @@ extern "C" int hsb_set_option(hsb_ctx *h, int key, double v) {
             batch_graph_drop(h);
         }
         return HSB_OK;
+    case HSB_OPT_AUTOTUNE:
+        if (!(v == 0.0 || v == 1.0)) return fail(HSB_EINVAL, "AUTOTUNE must be 0 or 1");
+        h->autotune = (int)v;
+        return HSB_OK;
+    case HSB_OPT_TILE:
+        if (!(v == std::floor(v) && v >= -1.0 && v <= 15.0))
+            return fail(HSB_EINVAL, "TILE must be -1 or a variant index 0 .. 15");
+        h->tile = (int)v;
+        return HSB_OK;
     case HSB_OPT_KERNEL_MS:
     case HSB_OPT_KERNEL_LAUNCHES:
     case HSB_OPT_LAST_PLAN:
     case HSB_OPT_GRAPH_LAUNCHES:
+    case HSB_OPT_LAST_TILE:
         return fail(HSB_EINVAL, "option %d is read only", key);
     default:
         return fail(HSB_EINVAL, "unknown option key %d", key);
@@ -366,6 +404,9 @@ extern "C" int hsb_get_option(hsb_ctx *h, int key, double *v) {
     case HSB_OPT_LOCAL_EXCHANGE: *v = h->local_exchange; return HSB_OK;
     case HSB_OPT_GRAPH: *v = h->graph; return HSB_OK;
     case HSB_OPT_GRAPH_LAUNCHES: *v = (double)h->glaunches; return HSB_OK;
+    case HSB_OPT_AUTOTUNE: *v = h->autotune; return HSB_OK;
+    case HSB_OPT_TILE: *v = h->tile; return HSB_OK;
+    case HSB_OPT_LAST_TILE: *v = h->last_tile; return HSB_OK;
     default: return fail(HSB_EINVAL, "unknown option key %d", key);
     }
 }
@@ -447,7 +488,7 @@ namespace {
 // Queue the device work of one run on s: state set-up, the plan's steps and
 // the output.  Returns without waiting for it, except where the bSB digit
 // plans check the start state.
-int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
+int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s, int tile) {
     const int Ns = a->schedule_steps > 0 ? a->schedule_steps : a->start_step + a->steps;
     const int N = h->N, Npad = h->Npad, R = a->R;
     const int Rpad = round_up(R, hsb::kTile);
@@ -467,6 +508,11 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
     }
     HIP_TRY(hsb::launch_fill_gamma(b.gamma, a->gamma_rep, a->gamma, R, Rpad, s));
     HIP_TRY(hsb::launch_reset_tracking(b, Rpad, s));
+    // cancellation: the stop word of the per-step plans, polled after samples
+    const int32_t *cancel = h->cancellable ? h->d_cancel : nullptr;
+    b.stop = h->d_stop;
+    b.tstop = nullptr;
+    HIP_TRY(hsb::launch_stop_init(b.stop, s));
     const bool nh = a->thermostat == HSB_THERMO_NOSE_HOOVER;
     if (nh) {
         if (h->nh_cap < Rpad) {
@@ -499,13 +545,15 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
     auto sample = [&](int m) -> int {
         int nblk;
         if (h->j_int_exact) {
-            HIP_TRY(hsb::launch_energy_fp32(h->dJ, b.X, b.epart, Npad, Rpad, s));
+            HIP_TRY(hsb::launch_energy_fp32(h->dJ, b.X, b.epart, Npad, Rpad, s, b.stop));
             nblk = Npad / 32;
         } else {
-            HIP_TRY(hsb::launch_energy_f64(h->dJ, b.X, b.epart, Npad, Rpad, s));
+            HIP_TRY(hsb::launch_energy_f64(h->dJ, b.X, b.epart, Npad, Rpad, s, b.stop));
             nblk = Npad / 64;
         }
         HIP_TRY(hsb::launch_best(b, nblk, N, R, Rpad, m, s));
+        // a cancel request seen here stops the run at this sample point
+        if (cancel && m < k1) HIP_TRY(hsb::launch_poll_cancel(cancel, b.stop, m, s));
         return HSB_OK;
     };
 
@@ -537,6 +585,8 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
         ir.k0 = k0; ir.k1 = k1; ir.Ns = Ns; ir.interval = interval;
         ir.a0 = a0; ir.c0 = c0; ir.dt = dt;
         ir.nh = nh ? &h->nh : nullptr;
+        ir.tile = tile;
+        ir.cancel = cancel;
         rc = hsb::i8_run(h->i8, ir, b, h->dJ, s, h->timer);
         if (rc != HSB_OK) return fail(rc, "%s", hsb::i8_error());
     } else if (plan == PLAN_INCREMENTAL) {
@@ -563,7 +613,7 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
             const float p = a0 - ak;
             HIP_TRY(h->timer.begin(s));
             HIP_TRY(hsb::launch_inc_step(h->dJ, b.X, b.Y, b.gamma, h->inc, k - k0, N, Npad, Rpad,
-                                         R, p, c0, dt, a0dt, s));
+                                         R, p, c0, dt, a0dt, s, b.stop));
             ++nrun;
             if (is_sample(k + 1)) {
                 HIP_TRY(h->timer.end(s, nrun));
@@ -584,6 +634,9 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
         pr.a0 = a0; pr.c0 = c0; pr.dt = dt;
         pr.epart = b.epart;
         pr.local_exchange = h->local_exchange;
+        pr.tile = tile;
+        pr.cancel = cancel;
+        pr.nh = nh ? &h->nh : nullptr;
         rc = hsb::persistent_run(h->pj, a->variant, pr, b, N, s, h->timer);
         if (rc != HSB_OK) return fail(rc, "%s", hsb::persistent_error());
     } else {
@@ -611,10 +664,12 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
                     f.c = h->nh.c;
                     f.NT = h->nh.NT;
                     HIP_TRY(hsb::launch_step_fp32(a->variant, h->dJ, b.B[cur], b.B[cur ^ 1], b.X,
-                                                  b.Y, b.gamma, Npad, Rpad, p, c0, dt, a0dt, s, &f));
+                                                  b.Y, b.gamma, Npad, Rpad, p, c0, dt, a0dt, s, &f,
+                                                  b.stop));
                 } else {
                     HIP_TRY(hsb::launch_step_fp32(a->variant, h->dJ, b.B[cur], b.B[cur ^ 1], b.X,
-                                                  b.Y, b.gamma, Npad, Rpad, p, c0, dt, a0dt, s));
+                                                  b.Y, b.gamma, Npad, Rpad, p, c0, dt, a0dt, s,
+                                                  nullptr, b.stop));
                 }
                 ++nrun;
                 cur ^= 1;
@@ -625,16 +680,14 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
                     if (rc) return rc;
                 }
             }
-            if (nh) {  // xi after the last step, from its slot and partials, into slot 0
-                const int steps = k1 - k0, np = Npad / 32;
-                HIP_TRY(hsb::launch_nh_final(h->nh.xi + (size_t)(steps & 1) * Rpad,
-                                             h->nh.part + (size_t)((steps - 1) & 1) * np * Rpad,
-                                             np, R, Rpad, h->nh.xi, h->nh.c, h->nh.NT, s));
-            }
+            if (nh)  // xi after the last step, from its slot and partials, into slot 0
+                HIP_TRY(hsb::launch_nh_final(h->nh.xi, h->nh.part, Npad / 32, R, Rpad, h->nh.xi,
+                                             h->nh.c, h->nh.NT, k1 - k0, k0, b.stop, s));
         }
     }
     HIP_TRY(hsb::launch_output(b, N, R, Rpad, h->return_best, a->spins, a->energy, a->x_out,
                                a->y_out, a->best_energy, a->final_energy, a->best_step, s));
+    HIP_TRY(hsb::launch_output_stop(b.stop, b.tstop, R, k1, a->stop_step, b.status, s));
     if (nh && a->xi_out) HIP_TRY(hsb::launch_copy_f64(a->xi_out, h->nh.xi, R, s));
     // status: bit 0 a non-finite state, bit 1 an exchange wait of the
     // persistent kernels that timed out
@@ -643,7 +696,7 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
 
 // Everything the device work queued by enqueue_run depends on: the arguments,
 // the options, the plan, and the buffers it uses (by address and generation).
-std::vector<uint64_t> run_key(const hsb_ctx *h, const hsb_run_args *a, int plan) {
+std::vector<uint64_t> run_key(const hsb_ctx *h, const hsb_run_args *a, int plan, int tile) {
     auto fb = [](float v) {
         uint32_t u;
         std::memcpy(&u, &v, sizeof u);
@@ -662,11 +715,12 @@ std::vector<uint64_t> run_key(const hsb_ctx *h, const hsb_run_args *a, int plan)
             (uint64_t)a->schedule_steps, fb(a->a0), fb(a->c0), fb(a->dt), fb(a->gamma),
             pb(a->gamma_rep), pb(a->x0), pb(a->y0), pb(a->x_out), pb(a->y_out), pb(a->spins),
             pb(a->energy), pb(a->best_energy), pb(a->final_energy), pb(a->best_step),
-            pb(a->trace_energy), pb(a->trace_tinst), (uint64_t)a->thermostat, db(a->nh_inv_mass),
+            pb(a->trace_energy), pb(a->trace_tinst), pb(a->stop_step), (uint64_t)a->thermostat,
+            db(a->nh_inv_mass),
             db(a->nh_temperature), pb(a->xi0), pb(a->xi_out), amp,
             (uint64_t)h->interval, (uint64_t)h->return_best, (uint64_t)h->local_exchange,
             (uint64_t)plan, pb(h->b.X), (uint64_t)h->Rpad_cap, h->state_gen, pb(h->pj),
-            h->pj ? hsb::persistent_gen(h->pj) : 0};
+            h->pj ? hsb::persistent_gen(h->pj) : 0, (uint64_t)tile};
 }
 
 // Launch the cached graph on the context's stream, ordered after the work
@@ -686,8 +740,8 @@ int graph_launch(hsb_ctx *h, hipStream_t s) {
 // the same queued work on the context's stream into a graph and launches it;
 // later calls with that key launch the graph again.  Any other key, or a
 // buffer reallocated in between (a new generation), drops the graph.
-int run_graph(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
-    const std::vector<uint64_t> key = run_key(h, a, plan);
+int run_graph(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s, int tile) {
+    const std::vector<uint64_t> key = run_key(h, a, plan, tile);
     if (h->gexec && key == h->gkey) return graph_launch(h, s);
     if (h->gseen && key == h->gkey) {
         if (!h->gstream) {
@@ -698,12 +752,12 @@ int run_graph(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
         HIP_TRY(hipEventRecord(h->gev_in, s));
         HIP_TRY(hipStreamWaitEvent(h->gstream, h->gev_in, 0));
         HIP_TRY(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_run(h, a, plan, h->gstream);
+        int rc = enqueue_run(h, a, plan, h->gstream, tile);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(h->gstream, &g);
         if (rc == HSB_OK && e != hipSuccess) rc = hip_fail(e, "capturing the run");
         // the captured work must be that of the key: nothing reallocated
-        if (rc == HSB_OK && run_key(h, a, plan) != key)
+        if (rc == HSB_OK && run_key(h, a, plan, tile) != key)
             rc = fail(HSB_EDEVICE, "run buffers changed while capturing");
         if (rc == HSB_OK) {
             const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
@@ -717,15 +771,112 @@ int run_graph(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s) {
             // nothing of a failed capture ran: queue the run eagerly instead
             graph_drop(h);
             (void)hipGetLastError();
-            return enqueue_run(h, a, plan, s);
+            return enqueue_run(h, a, plan, s, tile);
         }
         return graph_launch(h, s);
     }
     graph_drop(h);
-    const int rc = enqueue_run(h, a, plan, s);
+    const int rc = enqueue_run(h, a, plan, s, tile);
     if (rc != HSB_OK) return rc;
-    h->gkey = run_key(h, a, plan);  // after the run: the buffers it grew are part of it
+    h->gkey = run_key(h, a, plan, tile);  // after the run: the buffers it grew are part of it
     h->gseen = true;
+    return HSB_OK;
+}
+
+// Result-invariant kernel variants of a plan (the autotuner's candidates).
+int tile_count(int plan, int variant, int thermostat) {
+    if (plan == PLAN_FP4) return thermostat == HSB_THERMO_NOSE_HOOVER ? 1 : hsb::persistent_tiles(variant);
+    if (plan == PLAN_DIGITS) return hsb::i8_tiles();
+    return 1;
+}
+
+// Device staging of R replicas' spins and energies (hsb_run's outputs, and
+// the tuner's throw-away outputs).
+int ensure_staging(hsb_ctx *h, int R) {
+    const size_t need = (size_t)R * h->N;
+    if (need <= h->run_cap && h->d_energy) return HSB_OK;  // N is fixed: R fits too
+    if (h->d_spins) (void)hipFree(h->d_spins);
+    if (h->d_energy) (void)hipFree(h->d_energy);
+    h->d_spins = nullptr;
+    h->d_energy = nullptr;
+    h->run_cap = 0;
+    HIP_TRY(hipMalloc((void **)&h->d_spins, need));
+    HIP_TRY(hipMalloc((void **)&h->d_energy, sizeof(double) * (size_t)R));
+    h->run_cap = need;
+    return HSB_OK;
+}
+
+// The kernel variant of a run: the forced option; else, with AUTOTUNE on, the
+// tuned choice for this plan and shape (timed now on a short run of the same
+// shape if the cache has none); else the default 0.
+int choose_tile(hsb_ctx *h, const hsb_run_args *a, int plan, hipStream_t s, int *tile) {
+    const int n = tile_count(plan, a->variant, a->thermostat);
+    *tile = 0;
+    if (h->tile >= 0) {
+        if (h->tile >= n)
+            return fail(HSB_EINVAL, "TILE = %d, but this plan has %d kernel variants", h->tile, n);
+        *tile = h->tile;
+        return HSB_OK;
+    }
+    if (!h->autotune || n <= 1 || a->steps == 0) return HSB_OK;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cap));
+    static const char *plan_name[] = {"fp32", "fp4", "digits", "incremental"};
+    const int Npad = plan == PLAN_FP4 ? (h->N + 255) / 256 * 256
+                                      : (h->N + hsb::kI8SpinTile - 1) / hsb::kI8SpinTile * hsb::kI8SpinTile;
+    char key[160];
+    std::snprintf(key, sizeof key, "gfx950/%s/%s/N%d/R%d/J%s/T%d", plan_name[plan],
+                  a->variant == HSB_BSB ? "bsb" : "dsb", Npad, round_up(a->R, hsb::kTile),
+                  h->j_i8_exact ? "int8" : "real", a->thermostat);
+    int c = 0;
+    if (hsb::tune_lookup(key, &c) && c < n) {
+        *tile = c;
+        return HSB_OK;
+    }
+    if (cap != hipStreamCaptureStatusNone) return HSB_OK;  // no timing inside a capture
+    // time every variant on the first steps of this run's schedule (outputs
+    // to the context's staging, nothing of the caller's written)
+    int rc = ensure_staging(h, a->R);
+    if (rc != HSB_OK) return rc;
+    hsb_run_args t = *a;
+    t.steps = std::min(a->steps, 200);
+    t.schedule_steps = a->schedule_steps > 0 ? a->schedule_steps : a->start_step + a->steps;
+    t.spins = h->d_spins;
+    t.energy = h->d_energy;
+    t.x_out = t.y_out = nullptr;
+    t.best_energy = t.final_energy = nullptr;
+    t.best_step = nullptr;
+    t.trace_energy = t.trace_tinst = nullptr;
+    t.xi_out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "tuner events");
+    }
+    const int timing = h->timing;
+    h->timing = 0;
+    std::vector<double> ms(n, 0.0);
+    for (int v = 0; v < n && rc == HSB_OK; ++v) {
+        for (int rep = 0; rep < 2 && rc == HSB_OK; ++rep) {  // the first warms up
+            int p = plan;
+            he = hipEventRecord(e0, s);
+            if (he == hipSuccess) rc = enqueue_run(h, &t, p, s, v);
+            if (rc == HSB_OK && he == hipSuccess) he = hipEventRecord(e1, s);
+            if (rc == HSB_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+            float f = 0.0f;
+            if (rc == HSB_OK && he == hipSuccess) he = hipEventElapsedTime(&f, e0, e1);
+            if (rc == HSB_OK && he != hipSuccess) rc = hip_fail(he, "timing a kernel variant");
+            ms[v] = f;
+        }
+    }
+    h->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != HSB_OK) return rc;
+    *tile = (int)(std::min_element(ms.begin(), ms.end()) - ms.begin());
+    (void)hsb::tune_store(key, *tile, ms);  // unwritable cache: tuned again next process
     return HSB_OK;
 }
 
@@ -767,8 +918,9 @@ int ensure_graph_stream(hsb_ctx *h) {
 // with that key captures the same work on the context's stream and launches
 // it, later calls launch it again; any other key drops the graph.
 int batch_graph(hsb_ctx *lead, const std::vector<hsb::QTeam> &qt, const hsb::QRun &qr,
-                hipStream_t s) {
-    const std::vector<uint64_t> key = batch_key(lead, qt, qr);
+                hipStream_t s, int policy) {
+    std::vector<uint64_t> key = batch_key(lead, qt, qr);
+    key.push_back((uint64_t)policy);
     auto launch = [&]() -> int {
         HIP_TRY(hipEventRecord(lead->gev_in, s));
         HIP_TRY(hipStreamWaitEvent(lead->gstream, lead->gev_in, 0));
@@ -786,12 +938,14 @@ int batch_graph(hsb_ctx *lead, const std::vector<hsb::QTeam> &qt, const hsb::QRu
         HIP_TRY(hipStreamWaitEvent(lead->gstream, lead->gev_in, 0));
         HIP_TRY(hipStreamBeginCapture(lead->gstream, hipStreamCaptureModeThreadLocal));
         hsb::KernelTimer off;
-        rc = hsb::queue_run(lead->qwork, qt, qr, 0, lead->gstream, off);
+        rc = hsb::queue_run(lead->qwork, qt, qr, policy, lead->gstream, off);
         if (rc != HSB_OK) (void)fail(rc, "%s", hsb::queue_error());
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(lead->gstream, &g);
         if (rc == HSB_OK && e != hipSuccess) rc = hip_fail(e, "capturing the batch");
-        if (rc == HSB_OK && batch_key(lead, qt, qr) != key)
+        std::vector<uint64_t> key_after = batch_key(lead, qt, qr);
+        key_after.push_back((uint64_t)policy);
+        if (rc == HSB_OK && key_after != key)
             rc = fail(HSB_EDEVICE, "batch buffers changed while capturing");
         if (rc == HSB_OK) {
             const hipError_t ei = hipGraphInstantiate(&lead->bgexec, g, nullptr, nullptr, 0);
@@ -804,15 +958,16 @@ int batch_graph(hsb_ctx *lead, const std::vector<hsb::QTeam> &qt, const hsb::QRu
         if (rc != HSB_OK) {  // nothing of a failed capture ran: queue it eagerly
             batch_graph_drop(lead);
             (void)hipGetLastError();
-            const int r2 = hsb::queue_run(lead->qwork, qt, qr, 0, s, lead->timer);
+            const int r2 = hsb::queue_run(lead->qwork, qt, qr, policy, s, lead->timer);
             return r2 == HSB_OK ? HSB_OK : fail(r2, "%s", hsb::queue_error());
         }
         return launch();
     }
     batch_graph_drop(lead);
-    const int rc = hsb::queue_run(lead->qwork, qt, qr, 0, s, lead->timer);
+    const int rc = hsb::queue_run(lead->qwork, qt, qr, policy, s, lead->timer);
     if (rc != HSB_OK) return fail(rc, "%s", hsb::queue_error());
     lead->bgkey = batch_key(lead, qt, qr);  // after the run: what it grew is part of it
+    lead->bgkey.push_back((uint64_t)policy);
     lead->bgseen = true;
     return HSB_OK;
 }
@@ -870,7 +1025,8 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
     int plan = 0;
     int rc = choose_plan(h, a->variant, &plan);
     if (rc != HSB_OK) return rc;
-    if (a->thermostat == HSB_THERMO_NOSE_HOOVER && plan == PLAN_FP4)
+    // the persistent bSB kernel has no thermostat: the digit plan runs it
+    if (a->thermostat == HSB_THERMO_NOSE_HOOVER && plan == PLAN_FP4 && a->variant == HSB_BSB)
         plan = h->N <= hsb::i8_max_n() ? PLAN_DIGITS : PLAN_FP32;
     if (a->thermostat == HSB_THERMO_NOSE_HOOVER && plan == PLAN_INCREMENTAL)
         return fail(HSB_EUNSUPPORTED, "the thermostat does not run on the INCREMENTAL plan");
@@ -900,16 +1056,23 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
     const bool graphable = h->graph && plan == PLAN_FP4 && !h->timing &&
                            cap == hipStreamCaptureStatusNone &&
                            (a->variant == HSB_DSB || (!a->x0 && h->init_amp <= 1.0));
-    rc = graphable ? run_graph(h, a, plan, s) : enqueue_run(h, a, plan, s);
+    int tile = 0;
+    rc = choose_tile(h, a, plan, s, &tile);
+    if (rc != HSB_OK) return rc;
+    rc = graphable ? run_graph(h, a, plan, s, tile) : enqueue_run(h, a, plan, s, tile);
     if (rc != HSB_OK) return rc;
     // status: bit 0 a non-finite state, bit 1 an exchange wait of the
     // persistent kernels that timed out
     int32_t status = 0;
     HIP_TRY(hipMemcpyAsync(&status, h->b.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    // a cancel request is used up by the run in progress, seen or not
+    __atomic_store_n(h->h_cancel, 0, __ATOMIC_SEQ_CST);
     if (status & 2) return fail(HSB_EDEVICE, "FP4 persistent kernel: exchange wait timed out");
     h->last_plan = plan;
-    if (status) return fail(HSB_ENUMERIC, "a replica's state became non-finite");
+    h->last_tile = tile;
+    if (status & 4) return fail(HSB_ECANCELED, "the run was cancelled at a sample point");
+    if (status & 1) return fail(HSB_ENUMERIC, "a replica's state became non-finite");
     return HSB_OK;
 }
 
@@ -921,15 +1084,9 @@ extern "C" int hsb_run(hsb_ctx *h, int variant, float a0, float c0, float dt, fl
     if (R < 1 || R > (1 << 22)) return fail(HSB_EINVAL, "R must be in [1, 4194304]");
     HIP_TRY(hipSetDevice(h->device));
     const size_t need = (size_t)R * h->N;
-    if (need > h->run_cap) {
-        if (h->d_spins) (void)hipFree(h->d_spins);
-        if (h->d_energy) (void)hipFree(h->d_energy);
-        h->d_spins = nullptr;
-        h->d_energy = nullptr;
-        h->run_cap = 0;
-        HIP_TRY(hipMalloc((void **)&h->d_spins, need));
-        HIP_TRY(hipMalloc((void **)&h->d_energy, sizeof(double) * (size_t)R));
-        h->run_cap = need;
+    {
+        const int rc = ensure_staging(h, R);
+        if (rc != HSB_OK) return rc;
     }
     hsb_run_args a;
     std::memset(&a, 0, sizeof(a));
@@ -946,7 +1103,7 @@ extern "C" int hsb_run(hsb_ctx *h, int variant, float a0, float c0, float dt, fl
     a.energy = h->d_energy;
     a.stream = h->stream;
     const int rc = hsb_run_ex(h, &a);
-    if (rc != HSB_OK && rc != HSB_ENUMERIC) return rc;
+    if (rc != HSB_OK && rc != HSB_ENUMERIC && rc != HSB_ECANCELED) return rc;
     HIP_TRY(hipMemcpyAsync(spins, h->d_spins, need, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipMemcpyAsync(energy, h->d_energy, sizeof(double) * R, hipMemcpyDeviceToHost,
                            h->stream));
@@ -1031,16 +1188,20 @@ extern "C" int hsb_run_ex_noalloc(hsb_ctx *h, const hsb_run_args *a) {
     pr.interval = h->interval;
     pr.a0 = a->a0; pr.c0 = a->c0; pr.dt = a->dt;
     pr.local_exchange = h->local_exchange;
+    pr.cancel = h->cancellable ? h->d_cancel : nullptr;
     rc = hsb::persistent_run_in(s0 + used, HSB_NOALLOC_SCRATCH_BYTES - used, h->pj, pr, b, N, s);
     if (rc != HSB_OK) return fail(rc, "hsb_run_ex_noalloc: %s", hsb::persistent_error());
     HIP_TRY(hsb::launch_output(b, N, R, Rpad, h->return_best, a->spins, a->energy, a->x_out,
                                a->y_out, a->best_energy, a->final_energy, a->best_step, s));
+    HIP_TRY(hsb::launch_output_stop(nullptr, b.tstop, R, pr.k1, a->stop_step, b.status, s));
     int32_t status = 0;
     HIP_TRY(hipMemcpyAsync(&status, b.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    __atomic_store_n(h->h_cancel, 0, __ATOMIC_SEQ_CST);
     if (status & 2) return fail(HSB_EDEVICE, "FP4 persistent kernel: exchange wait timed out");
     h->last_plan = PLAN_FP4;
-    if (status) return fail(HSB_ENUMERIC, "a replica's state became non-finite");
+    if (status & 4) return fail(HSB_ECANCELED, "the run was cancelled at a sample point");
+    if (status & 1) return fail(HSB_ENUMERIC, "a replica's state became non-finite");
     return HSB_OK;
 }
 
@@ -1109,6 +1270,7 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
         h->interval = interval;
         h->return_best = a->return_best;
         h->timing = 0;
+        h->cancellable = false;  // batches are not cancelled
         hsb_run_args ra;
         std::memset(&ra, 0, sizeof(ra));
         ra.struct_size = sizeof(ra);
@@ -1124,6 +1286,7 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
         ra.energy = jb.energy;
         ra.stream = a->stream;
         const int rc = hsb_run_ex(h, &ra);
+        h->cancellable = true;
         h->init_amp = amp0;
         h->interval = int0;
         h->return_best = rb0;
@@ -1165,16 +1328,60 @@ extern "C" int hsb_run_batch(hsb_ctx *const *hs, int n_inst, const hsb_job *jobs
         qr.local_exchange = lead->local_exchange;
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         HIP_TRY(hipStreamIsCapturing(s, &cap));
+        // the queue placement policy: forced (TILE of the lead context), tuned
+        // (AUTOTUNE), or longest-first
+        int policy = 0;
+        if (lead->tile >= 0) {
+            if (lead->tile >= 2) return fail(HSB_EINVAL, "TILE = %d, but batch queues have 2 "
+                                                         "placement policies", lead->tile);
+            policy = lead->tile;
+        } else if (lead->autotune && a->steps > 0) {
+            long long wg = 0;
+            for (const hsb::QTeam &q : qt) wg += q.nkb / 2;
+            char key[160];
+            std::snprintf(key, sizeof key, "gfx950/queue/dsb/teams%zu/wg%lld/S%d", qt.size(), wg,
+                          a->steps < 1000 ? a->steps : 1000);
+            if (!hsb::tune_lookup(key, &policy) || policy > 1) {
+                policy = 0;
+                if (cap == hipStreamCaptureStatusNone) {
+                    hsb::QRun tr = qr;
+                    tr.steps = std::min(a->steps, 200);
+                    std::vector<double> ms(2, 0.0);
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    HIP_TRY(hipEventCreate(&e0));
+                    HIP_TRY(hipEventCreate(&e1));
+                    hsb::KernelTimer off;
+                    int trc = HSB_OK;
+                    for (int v = 0; v < 2 && trc == HSB_OK; ++v)
+                        for (int rep = 0; rep < 2 && trc == HSB_OK; ++rep) {
+                            float f = 0.0f;
+                            hipError_t he = hipEventRecord(e0, s);
+                            if (he == hipSuccess) trc = hsb::queue_run(lead->qwork, qt, tr, v, s, off);
+                            if (trc == HSB_OK && he == hipSuccess) he = hipEventRecord(e1, s);
+                            if (trc == HSB_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+                            if (trc == HSB_OK && he == hipSuccess) he = hipEventElapsedTime(&f, e0, e1);
+                            if (trc == HSB_OK && he != hipSuccess) trc = hip_fail(he, "timing a policy");
+                            ms[v] = f;
+                        }
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    if (trc != HSB_OK) return trc == HSB_EDEVICE ? trc : fail(trc, "%s", hsb::queue_error());
+                    policy = ms[1] < ms[0] ? 1 : 0;
+                    (void)hsb::tune_store(key, policy, ms);
+                }
+            }
+        }
         const bool graphable = lead->graph && !lead->timing && singles.empty() &&
                                classes.empty() && cap == hipStreamCaptureStatusNone;
         int rc;
         if (graphable) {
-            rc = batch_graph(lead, qt, qr, s);
+            rc = batch_graph(lead, qt, qr, s, policy);
         } else {
             batch_graph_drop(lead);
-            rc = hsb::queue_run(lead->qwork, qt, qr, 0, s, lead->timer);
+            rc = hsb::queue_run(lead->qwork, qt, qr, policy, s, lead->timer);
             if (rc != HSB_OK) rc = fail(rc, "%s", hsb::queue_error());
         }
+        lead->last_tile = policy;
         if (rc != HSB_OK) return rc;
         int32_t status = 0;
         HIP_TRY(hipMemcpyAsync(&status, hsb::queue_status(lead->qwork), sizeof(int32_t),

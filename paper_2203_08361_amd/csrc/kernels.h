@@ -81,7 +81,14 @@ struct StateBufs {
     int32_t *best_step;   // [Rpad]
     int32_t *bad;         // [Rpad] non-finite flag per replica
     int8_t *best_s;       // [Npad][Rpad]
-    int32_t *status;      // [1] any replica non-finite
+    int32_t *status;      // [1] bit 0: a replica non-finite; bit 1: an exchange wait timed
+                          // out; bit 2: the run was cancelled
+    // the run's stop word (per-step plans): -1, or the sample step at which a
+    // cancel request stopped it; every later step and sample kernel returns
+    // at once.  nullptr: the run cannot stop early.
+    int32_t *stop = nullptr;
+    // FP4 plan: the stop step of each 32-replica team (-1: not stopped)
+    int32_t *tstop = nullptr;
     // optional per-call traces, [n_samples][R] (caller memory, not owned):
     // energy and T_inst of every sample point of the run steps trace_k0 ..
     double *trace_e = nullptr, *trace_t = nullptr;
@@ -129,8 +136,9 @@ struct NHFused {
 };
 // xi_dst[r] = xi_in[r] + c (sum of part_in's nparts partials - NT): the value
 // after the last fused step
-hipError_t launch_nh_final(const double *xi_in, const double *part_in, int nparts, int R,
-                           int Rpad, double *xi_dst, double c, double NT, hipStream_t s);
+hipError_t launch_nh_final(const double *xi, const double *part, int nparts, int R, int Rpad,
+                           double *xi_dst, double c, double NT, int steps, int k0,
+                           const int32_t *stop, hipStream_t s);
 // xi = xi0 (device [R]) if given, else -gamma[r]; 0 in the padding columns [R, Rpad)
 hipError_t launch_nh_init(const NHState &nh, const double *xi0, const float *gamma, int R,
                           int Rpad, hipStream_t s);
@@ -147,7 +155,7 @@ hipError_t launch_inc_init(const float *J, const float *X, IncState &inc, int N,
 // step j of the call: update X, Y from F, list the flips, add them to F
 hipError_t launch_inc_step(const float *J, float *X, float *Y, const float *gamma, IncState &inc,
                            int j, int N, int Npad, int Rpad, int R, float p, float c0, float dt,
-                           float a0dt, hipStream_t s);
+                           float a0dt, hipStream_t s, const int32_t *stop = nullptr);
 hipError_t launch_copy_f64(double *dst, const double *src, int n, hipStream_t s);
 // allocation of the run state for Npad rows and Rpad columns (all or nothing);
 // without the FP32 plan's operand and energy buffers (B, epart) if !fp32_plan
@@ -179,15 +187,25 @@ hipError_t launch_bound_check(const float *X, size_t n, int32_t *flag, hipStream
 // partials, see NHFused)
 hipError_t launch_step_fp32(int variant, const float *J, const float *Bin, float *Bout, float *X,
                             float *Y, const float *gamma, int Npad, int Rpad, float p, float c0,
-                            float dt, float a0dt, hipStream_t s, const NHFused *nh = nullptr);
+                            float dt, float a0dt, hipStream_t s, const NHFused *nh = nullptr,
+                            const int32_t *stop = nullptr);
 // energy partials: exact path (FP32 products, J integer-valued) -> nblk = Npad/32
 hipError_t launch_energy_fp32(const float *J, const float *X, double *epart, int Npad, int Rpad,
-                              hipStream_t s);
+                              hipStream_t s, const int32_t *stop = nullptr);
 // energy partials in FP64 (any J) -> nblk = Npad/64
 hipError_t launch_energy_f64(const float *J, const float *X, double *epart, int Npad, int Rpad,
-                             hipStream_t s);
+                             hipStream_t s, const int32_t *stop = nullptr);
 hipError_t launch_best(const StateBufs &b, int nblk, int N, int R, int Rpad, int step,
                        hipStream_t s);
+// Cancellation (the stop word of StateBufs): set it to -1; after the sample
+// at step m, record m in it if the cancel request (pinned host word) is set;
+// finally stop_step[r] (optional) = the step replica r reached (the stop
+// word, or its team's entry of tstop [R/32] on the FP4 plan, else k1), and
+// bit 2 of status if any replica stopped before k1.
+hipError_t launch_stop_init(int32_t *stop, hipStream_t s);
+hipError_t launch_poll_cancel(const int32_t *cancel, int32_t *stop, int m, hipStream_t s);
+hipError_t launch_output_stop(const int32_t *stop, const int32_t *tstop, int R, int k1,
+                              int32_t *stop_step, int32_t *status, hipStream_t s);
 hipError_t launch_output(const StateBufs &b, int N, int R, int Rpad, int return_best,
                          int8_t *spins, double *energy, float *x_out, float *y_out,
                          double *best_energy, double *final_energy, int32_t *best_step,

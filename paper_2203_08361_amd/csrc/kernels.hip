@@ -13,6 +13,41 @@
 
 namespace hsb {
 
+// ------------------------------------------------------------ cancellation
+//
+// A run stops at a sample point when its context's cancel request (a word of
+// pinned host memory) is seen there: the per-step plans enqueue a poll after
+// each sample, which records the step in the run's stop word, and every later
+// step and sample kernel of the run returns at once when that word is set.
+
+__device__ __forceinline__ bool stopped(const int32_t *stop) {
+    return stop && __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0;
+}
+
+__global__ void k_stop_init(int32_t *stop) { stop[0] = -1; }
+
+// after the sample at step m: stop here if the request is set (and no earlier
+// sample has stopped the run)
+__global__ void k_poll_cancel(const int32_t *cancel, int32_t *stop, int m) {
+    if (stop[0] < 0 && __hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+        stop[0] = m;
+}
+
+// stop_step[r]: the step each replica reached -- the run's stop word (per-step
+// plans) or its team's (tstop[r / 32], FP4 plan), else k1 -- and bit 2 of the
+// status word if any replica stopped before k1
+__global__ void k_output_stop(const int32_t *__restrict__ stop, const int32_t *__restrict__ tstop,
+                              int R, int k1, int32_t *__restrict__ stop_step,
+                              int32_t *__restrict__ status) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    int m = k1;
+    if (stop && stop[0] >= 0) m = stop[0];
+    if (tstop && tstop[r >> 5] >= 0 && tstop[r >> 5] < m) m = tstop[r >> 5];
+    if (stop_step) stop_step[r] = m;
+    if (m < k1) __hip_atomic_fetch_or(status, 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ------------------------------------------------------------ state set-up
 
 // Columns [0, ncols) of a state with leading dimension ld: replica r < R of
@@ -71,11 +106,17 @@ __global__ void k_nh_init(double *__restrict__ xi, const double *__restrict__ xi
     if (r < Rpad) xi[r] = r >= R ? 0.0 : (xi0 ? xi0[r] : -(double)g[r]);
 }
 
-__global__ void k_nh_final(const double *__restrict__ xi_in, const double *__restrict__ part_in,
+// xi after the n >= 1 fused steps done (n = steps, or up to the stop word's
+// step): the step-(n-1) value in slot n % 2 plus c (its partials in slot
+// (n-1) % 2 - N T), into xi_dst.
+__global__ void k_nh_final(const double *__restrict__ xi, const double *__restrict__ part,
                            int nparts, int R, int Rpad, double *__restrict__ xi_dst, double c,
-                           double NT) {
+                           double NT, int steps, int k0, const int32_t *__restrict__ stop) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
+    const int n = (stop && stop[0] >= 0) ? stop[0] - k0 : steps;
+    const double *xi_in = xi + (size_t)(n & 1) * Rpad;
+    const double *part_in = part + (size_t)((n - 1) & 1) * nparts * Rpad;
     double S = 0.0;
     for (int q = 0; q < nparts; ++q) S += part_in[(size_t)q * Rpad + r];
     xi_dst[r] = xi_in[r] + c * (S - NT);
@@ -115,9 +156,9 @@ __global__ __launch_bounds__(256) void k_inc_step(float *__restrict__ X, float *
                                                   int32_t *__restrict__ cnt,
                                                   int32_t *__restrict__ list, int N, int Npad,
                                                   int Rpad, int R, float p, float c0, float dt,
-                                                  float a0dt) {
+                                                  float a0dt, const int32_t *__restrict__ stop) {
     const int r = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
-    if (r >= R || i >= N) return;
+    if (r >= R || i >= N || stopped(stop)) return;
     const size_t idx = (size_t)i * Rpad + r;
     float x = X[idx], y = Y[idx];
     const bool was = x >= 0.0f;
@@ -138,7 +179,8 @@ __global__ __launch_bounds__(256) void k_inc_field(int32_t *__restrict__ F,
                                                    const int32_t *__restrict__ cnt,
                                                    const int32_t *__restrict__ list,
                                                    int32_t *__restrict__ cnt_next, int Npad,
-                                                   int R) {
+                                                   int R, const int32_t *__restrict__ stop) {
+    if (stopped(stop)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     // replicas r = blockIdx.y, blockIdx.y + gridDim.y, ... (grid.y is capped)
     for (int r = blockIdx.y; r < R; r += gridDim.y) {
@@ -245,9 +287,11 @@ __global__ __launch_bounds__(256) void k_step_fp32(const float *__restrict__ J,
                                                    float *__restrict__ Y,
                                                    const float *__restrict__ gam, int Npad,
                                                    int Rpad, float p, float c0, float dt,
-                                                   float a0dt, NHFused nhf) {
+                                                   float a0dt, NHFused nhf,
+                                                   const int32_t *__restrict__ stop) {
     __shared__ float As[2][32][68];
     __shared__ float Bs[2][32][68];
+    if (stopped(stop)) return;
     const int r0 = blockIdx.x * kTile, i0 = blockIdx.y * kTile;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = w >> 1, wc = w & 1;
@@ -308,9 +352,10 @@ __global__ __launch_bounds__(256) void k_step_fp32(const float *__restrict__ J,
 __global__ __launch_bounds__(256) void k_energy_fp32(const float *__restrict__ J,
                                                      const float *__restrict__ X,
                                                      double *__restrict__ epart, int Npad,
-                                                     int Rpad) {
+                                                     int Rpad, const int32_t *__restrict__ stop) {
     __shared__ float As[2][32][68];
     __shared__ float Bs[2][32][68];
+    if (stopped(stop)) return;
     const int r0 = blockIdx.x * kTile, i0 = blockIdx.y * kTile;
     const v16f acc = gemm_tile_fp32<true>(J, X, Npad, Rpad, i0, r0, As, Bs);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -331,10 +376,11 @@ __global__ __launch_bounds__(256) void k_energy_fp32(const float *__restrict__ J
 __global__ __launch_bounds__(256) void k_energy_f64(const float *__restrict__ J,
                                                     const float *__restrict__ X,
                                                     double *__restrict__ epart, int Npad,
-                                                    int Rpad) {
+                                                    int Rpad, const int32_t *__restrict__ stop) {
     __shared__ double As[16][65];
     __shared__ double Bs[16][65];
     __shared__ double red[16][65];
+    if (stopped(stop)) return;
     const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
     const int r0 = blockIdx.x * kTile, i0 = blockIdx.y * kTile;
     double acc[4][4] = {};
@@ -398,8 +444,10 @@ __global__ __launch_bounds__(1024) void k_best(const double *__restrict__ epart,
                                                int8_t *__restrict__ best_s,
                                                int32_t *__restrict__ status, int step,
                                                double *__restrict__ trace_e,
-                                               double *__restrict__ trace_t, int trow) {
+                                               double *__restrict__ trace_t, int trow,
+                                               const int32_t *__restrict__ stop) {
     __shared__ int s_bad[16][64];
+    if (stopped(stop)) return;
     __shared__ double s_t[16][64];
     __shared__ int s_take[64];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -635,10 +683,11 @@ hipError_t launch_nh_init(const NHState &nh, const double *xi0, const float *gam
     return hipGetLastError();
 }
 
-hipError_t launch_nh_final(const double *xi_in, const double *part_in, int nparts, int R,
-                           int Rpad, double *xi_dst, double c, double NT, hipStream_t s) {
-    hipLaunchKernelGGL(k_nh_final, dim3(cdiv(R, 256)), dim3(256), 0, s, xi_in, part_in, nparts,
-                       R, Rpad, xi_dst, c, NT);
+hipError_t launch_nh_final(const double *xi, const double *part, int nparts, int R, int Rpad,
+                           double *xi_dst, double c, double NT, int steps, int k0,
+                           const int32_t *stop, hipStream_t s) {
+    hipLaunchKernelGGL(k_nh_final, dim3(cdiv(R, 256)), dim3(256), 0, s, xi, part, nparts, R, Rpad,
+                       xi_dst, c, NT, steps, k0, stop);
     return hipGetLastError();
 }
 
@@ -657,12 +706,12 @@ hipError_t launch_inc_init(const float *J, const float *X, IncState &inc, int N,
 
 hipError_t launch_inc_step(const float *J, float *X, float *Y, const float *gamma, IncState &inc,
                            int j, int N, int Npad, int Rpad, int R, float p, float c0, float dt,
-                           float a0dt, hipStream_t s) {
+                           float a0dt, hipStream_t s, const int32_t *stop) {
     int32_t *cnt = inc.cnt + (size_t)(j & 1) * Rpad, *next = inc.cnt + (size_t)((j + 1) & 1) * Rpad;
     hipLaunchKernelGGL(k_inc_step, dim3(cdiv(R, 256), N), dim3(256), 0, s, X, Y, inc.F, gamma,
-                       cnt, inc.list, N, Npad, Rpad, R, p, c0, dt, a0dt);
+                       cnt, inc.list, N, Npad, Rpad, R, p, c0, dt, a0dt, stop);
     hipLaunchKernelGGL(k_inc_field, dim3(cdiv(Npad, 256), inc_grid_y(R)), dim3(256), 0, s, inc.F,
-                       J, cnt, inc.list, next, Npad, R);
+                       J, cnt, inc.list, next, Npad, R, stop);
     return hipGetLastError();
 }
 
@@ -685,35 +734,36 @@ hipError_t launch_reset_tracking(const StateBufs &b, int Rpad, hipStream_t s) {
 
 hipError_t launch_step_fp32(int variant, const float *J, const float *Bin, float *Bout, float *X,
                             float *Y, const float *gamma, int Npad, int Rpad, float p, float c0,
-                            float dt, float a0dt, hipStream_t s, const NHFused *nh) {
+                            float dt, float a0dt, hipStream_t s, const NHFused *nh,
+                            const int32_t *stop) {
     const dim3 grid(Rpad / kTile, Npad / kTile);
     const NHFused f = nh ? *nh : NHFused{};
     if (variant == 0 && !nh)
         hipLaunchKernelGGL((k_step_fp32<0, false>), grid, dim3(256), 0, s, J, Bin, Bout, X, Y,
-                           gamma, Npad, Rpad, p, c0, dt, a0dt, f);
+                           gamma, Npad, Rpad, p, c0, dt, a0dt, f, stop);
     else if (variant == 0)
         hipLaunchKernelGGL((k_step_fp32<0, true>), grid, dim3(256), 0, s, J, Bin, Bout, X, Y,
-                           gamma, Npad, Rpad, p, c0, dt, a0dt, f);
+                           gamma, Npad, Rpad, p, c0, dt, a0dt, f, stop);
     else if (!nh)
         hipLaunchKernelGGL((k_step_fp32<1, false>), grid, dim3(256), 0, s, J, Bin, Bout, X, Y,
-                           gamma, Npad, Rpad, p, c0, dt, a0dt, f);
+                           gamma, Npad, Rpad, p, c0, dt, a0dt, f, stop);
     else
         hipLaunchKernelGGL((k_step_fp32<1, true>), grid, dim3(256), 0, s, J, Bin, Bout, X, Y,
-                           gamma, Npad, Rpad, p, c0, dt, a0dt, f);
+                           gamma, Npad, Rpad, p, c0, dt, a0dt, f, stop);
     return hipGetLastError();
 }
 
 hipError_t launch_energy_fp32(const float *J, const float *X, double *epart, int Npad, int Rpad,
-                              hipStream_t s) {
+                              hipStream_t s, const int32_t *stop) {
     hipLaunchKernelGGL(k_energy_fp32, dim3(Rpad / kTile, Npad / kTile), dim3(256), 0, s, J, X,
-                       epart, Npad, Rpad);
+                       epart, Npad, Rpad, stop);
     return hipGetLastError();
 }
 
 hipError_t launch_energy_f64(const float *J, const float *X, double *epart, int Npad, int Rpad,
-                             hipStream_t s) {
+                             hipStream_t s, const int32_t *stop) {
     hipLaunchKernelGGL(k_energy_f64, dim3(Rpad / kTile, Npad / kTile), dim3(256), 0, s, J, X,
-                       epart, Npad, Rpad);
+                       epart, Npad, Rpad, stop);
     return hipGetLastError();
 }
 
@@ -722,7 +772,25 @@ hipError_t launch_best(const StateBufs &b, int nblk, int N, int R, int Rpad, int
     hipLaunchKernelGGL(k_best, dim3(cdiv(R, 64)), dim3(1024), 0, s, b.epart, nblk, b.X, b.Y, N, R,
                        Rpad, b.best_e, b.last_e, b.best_step, b.bad, b.best_s, b.status, step,
                        b.trace_e, b.trace_t,
-                       (b.trace_e || b.trace_t) ? trace_row(step, b.trace_k0, b.trace_interval) : 0);
+                       (b.trace_e || b.trace_t) ? trace_row(step, b.trace_k0, b.trace_interval) : 0,
+                       b.stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_stop_init(int32_t *stop, hipStream_t s) {
+    hipLaunchKernelGGL(k_stop_init, dim3(1), dim3(1), 0, s, stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_poll_cancel(const int32_t *cancel, int32_t *stop, int m, hipStream_t s) {
+    hipLaunchKernelGGL(k_poll_cancel, dim3(1), dim3(1), 0, s, cancel, stop, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_output_stop(const int32_t *stop, const int32_t *tstop, int R, int k1,
+                              int32_t *stop_step, int32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_output_stop, dim3(cdiv(R, 256)), dim3(256), 0, s, stop, tstop, R, k1,
+                       stop_step, status);
     return hipGetLastError();
 }
 

@@ -27,6 +27,11 @@ struct PersistentRun {
     double *epart;         // unused by this path (its own partials are kept per sample)
     int local_exchange = 1;  // 0: device-scope exchange even for XCD-local teams
     int tile = 0;            // kernel variant, 0 .. persistent_tiles(variant) - 1
+    const int32_t *cancel = nullptr;  // the cancel request (device view of pinned host
+                                      // memory), or nullptr: the run cannot stop early
+    // dSB only: the Nose-Hoover thermostat (eqs. (6)-(8)) with xi in nh->xi[0 .. Rpad)
+    // (its value at k0 in, at the last step out), or nullptr: constant heating
+    const NHState *nh = nullptr;
 };
 
 bool persistent_supported(int N);

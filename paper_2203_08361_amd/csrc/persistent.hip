@@ -75,6 +75,10 @@ struct PersistentWork {
     size_t xe_n = 0;
     uint32_t *flags = nullptr;
     size_t flags_n = 0;
+    int32_t *tstop = nullptr;    // [nteams] stop step of each team (-1: running)
+    size_t tstop_n = 0;
+    double *ypart = nullptr;     // thermostat: [2][nchunk / 4][Rpad] partial sums of y^2
+    size_t ypart_n = 0;
 };
 
 struct PersistentJ {
@@ -136,6 +140,16 @@ struct SegArgs {
     int seg_k0, seg_k1, final_k, interval, nmult;
 };
 
+// The Nose-Hoover thermostat inside the persistent dSB kernel (eqs. (6)-(8)):
+// xi per replica ([Rpad], FP64: its value at the segment's first step in, at
+// its last out), the per-step partial sums of y^2 of every workgroup's 128
+// rows ([2 step parities][nchunk / 4][Rpad]), c = dt / M and N T.
+struct FP4NH {
+    double *xi;
+    double *ypart;
+    double c, NT;
+};
+
 __device__ __forceinline__ bool seg_is_sample(const SegArgs &g, int m) {
     return m == g.final_k || (m > g.seg_k0 && m % g.interval == 0);
 }
@@ -156,19 +170,26 @@ __device__ __forceinline__ int seg_sample_index(const SegArgs &g, int m) {
 // core while this one waits for its team's signs.  That is why a wave holds
 // 32 rows rather than 64: 32 rows of J take 128 of the 256 registers two waves
 // per SIMD leave each.
-template <int NKB, int KPRE>
+template <int NKB, int KPRE, bool NH>
 __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, uint64_t *xb, uint32_t *__restrict__ snap,
     float *__restrict__ ep, double *__restrict__ tp, const float *__restrict__ ptab,
     int32_t *__restrict__ bad,
     int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, const uint32_t *epoch_p,
-    int local_ok,
+    int local_ok, const int32_t *cancel, int32_t *tstop, FP4NH nhp,
     int nkb, int nchunk, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
     static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
     constexpr int NQ = NKB / 4;  // K blocks expanded by each wave
     __shared__ v4i a_lds[2][NKB][64];
     __shared__ int wg_abort;
+    // thermostat: each wave's y^2 partial of the current state (two step
+    // parities), and the eight half-waves' sums of the team's partials
+    __shared__ double s_yw[NH ? 2 : 1][4][32];
+    __shared__ double s_ysum[NH ? 8 : 1][32];
+    // thermostat: xi(t_k) of the workgroup's 32 replicas (every wave of the
+    // team forms the same value; kept here rather than in registers)
+    __shared__ double s_xi[NH ? 4 : 1][32];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     // Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
     // b % 8).  All workgroups of a team are placed on one XCD so that the sign
@@ -189,6 +210,10 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     const int r0 = team * 32;
     const int half = lane >> 5, l32 = lane & 31;
     if (threadIdx.x == 0) wg_abort = 0;
+    // a team stopped by a cancel request in an earlier launch of the run keeps
+    // its state; a stop step never lies beyond the end of its segment
+    const int ts0 = __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ts0 >= 0 && ts0 <= g.seg_k0) return;  // whole workgroup
 
     // Are all workgroups of this team on one XCD?  Each records (launch epoch,
     // XCD id) in its slot; lane k reads member k's slot.  Only then may the team
@@ -226,7 +251,12 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     // across the step loop instead of copying them every step)
     v16f xs, ys;
     const int rep = r0 + l32;
-    const float gdt = gamma[rep] * dt;
+    const float gdt_heat = gamma[rep] * dt;
+    // Nose-Hoover: xi(t_k) of this lane's replica; the heating rate of step k
+    // is -xi(t_k) rounded to float, in eq. (22)'s place
+    if constexpr (NH) {
+        if (half == 0) s_xi[w][l32] = nhp.xi[rep];
+    }
     const int rowb = rb * 32 + 4 * half;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -246,6 +276,14 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
 #pragma unroll
         for (int v = 15; v >= 0; --v) b = __builtin_amdgcn_alignbit(b, __float_as_uint(xs[v]), 31);
         const uint32_t got = (uint32_t)__shfl_xor((int)b, 32);
+        if constexpr (NH) {  // wave 0 stored the workgroup's y^2 partial before its words
+            if (w == 0) {
+                if (xcd_local)
+                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                else
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            }
+        }
         if (half == 0) {
             const uint32_t word = b | (got << 16);
             const size_t slot = (size_t)rb * Rpad + rep;
@@ -259,8 +297,27 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         }
     };
 
+    // thermostat: this wave's sum of y_i(t_m)^2 over its 32 rows (exact squares,
+    // fixed order) into LDS, for the state about to be published
+    auto y2_partial = [&](int m) {
+        if constexpr (NH) {
+            double t2 = 0.0;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) t2 += (double)ys[v] * (double)ys[v];
+            t2 += __shfl_xor(t2, 32);
+            if (half == 0) s_yw[m & 1][w][l32] = t2;
+        }
+    };
+    y2_partial(g.seg_k0);
     publish(g.seg_k0);
     __syncthreads();
+    // Cancellation: the team's first wave reads the request on the step before
+    // each sample point and, if it is set, records that sample point as the
+    // team's stop step before it publishes the state of that step; every wave
+    // reads the record once it has gathered that state, stops after the sample
+    // and writes its state back.
+    int stop_at = 0x7FFFFFFF;
+    const bool decider = cancel && rb == 0;
     for (int m = g.seg_k0;; ++m) {
         const int buf = m & 1;
         // this wave's share: K block kb = w + 4q is chunk 2 kb + l/32
@@ -277,6 +334,47 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         }
         __syncthreads();
         if (wg_abort) break;
+        if (cancel && m > g.seg_k0 && seg_is_sample(g, m)) {
+            if (!xcd_local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const int ts = __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ts == m) stop_at = m;
+        }
+        // Thermostat.  Wave 0 stores the workgroup's partial of y(t_m)^2 (the
+        // four waves' in a fixed order); it publishes x_{m+1} only after that
+        // store.  The team's partials of y(t_{m-1})^2 are all in (x_m is), and
+        // half-wave q = 2 w + half loads those of workgroups q, q + 8 (they
+        // arrive during the products).
+        constexpr int WPT = NKB / 2;                 // workgroups of a team
+        constexpr int NPL = (WPT + 7) / 8;          // partials per half-wave
+        double pl[NPL];
+        if constexpr (NH) {
+            const int wg = kx % wpt, nwg = nchunk / 4;
+            if (w == 0 && half == 0) {
+                const double wsum = ((s_yw[m & 1][0][l32] + s_yw[m & 1][1][l32]) +
+                                     s_yw[m & 1][2][l32]) + s_yw[m & 1][3][l32];
+                uint64_t *dst = reinterpret_cast<uint64_t *>(
+                    nhp.ypart + ((size_t)(m & 1) * nwg + wg) * Rpad + rep);
+                const uint64_t bits = (uint64_t)__double_as_longlong(wsum);
+                if (xcd_local)
+                    __hip_atomic_store(dst, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                else
+                    __hip_atomic_store(dst, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (m > g.seg_k0) {
+                if (!xcd_local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const int q0 = 2 * w + half;
+#pragma unroll
+                for (int q = 0; q < NPL; ++q) {
+                    const int src_wg = q0 + 8 * q;
+                    pl[q] = 0.0;
+                    if (src_wg < nwg)
+                        pl[q] = __longlong_as_double((long long)__hip_atomic_load(
+                            reinterpret_cast<const uint64_t *>(
+                                nhp.ypart + ((size_t)((m - 1) & 1) * nwg + src_wg) * Rpad + rep),
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                }
+            }
+        }
         v16f acc;
         // The products run at the lowest issue priority and the rest of the
         // step at a raised one: while the other wave on this SIMD is in its
@@ -299,6 +397,22 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         }
         mfma_drain(acc);
         __builtin_amdgcn_s_setprio(3);
+        if constexpr (NH) {
+            // xi(t_m) = xi(t_{m-1}) + (dt/M)(sum_i y_i(t_{m-1})^2 - N T): the eight
+            // half-wave sums in a fixed order, the same in every wave of the team
+            if (m > g.seg_k0) {
+                double gs = 0.0;
+#pragma unroll
+                for (int q = 0; q < NPL; ++q) gs += pl[q];
+                s_ysum[2 * w + half][l32] = gs;
+                __syncthreads();
+                double S = 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) S += s_ysum[q][l32];
+                const double xi_k = s_xi[w][l32] + nhp.c * (S - nhp.NT);
+                if (half == 0) s_xi[w][l32] = xi_k;
+            }
+        }
         if (seg_is_sample(g, m)) {
             // eq. (1) partial over this wave's 32 rows of s_i f_i (exact integers/halves)
             const int j = seg_sample_index(g, m);
@@ -323,13 +437,25 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
                 __hip_atomic_fetch_or(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        if (m == g.seg_k1) break;
+        if (m == g.seg_k1 || m == stop_at) break;
+        float gdt = gdt_heat;
+        if constexpr (NH) gdt = (float)(-s_xi[w][l32]) * dt;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             float x = xs[v], y = ys[v];
             sb_update_tied(acc[v], p, c0, dt, a0dt, gdt, x, y);
             xs[v] = x;
             ys[v] = y;
+        }
+        y2_partial(m + 1);
+        if (decider && m + 1 < g.final_k && seg_is_sample(g, m + 1)) {
+            const int c = __hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (__builtin_amdgcn_readfirstlane(c) != 0) {
+                if (lane == 0)
+                    __hip_atomic_store(tstop + team, m + 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // before the words of m + 1
+            }
         }
         publish(m + 1);
     }
@@ -341,6 +467,9 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
             X[(size_t)row * Rpad + rep] = xs[v];
             Y[(size_t)row * Rpad + rep] = ys[v];
         }
+    }
+    if constexpr (NH) {  // xi after the segment's last step (every wave read it at the start)
+        if (rb == 0 && half == 0 && !wg_abort) nhp.xi[rep] = s_xi[w][l32];
     }
 }
 
@@ -484,7 +613,7 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     uint32_t *__restrict__ snap, double *__restrict__ tp, const float *__restrict__ ptab,
     int32_t *__restrict__ bad,
     int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, const uint32_t *epoch_p,
-    int local_ok,
+    int local_ok, const int32_t *cancel, int32_t *tstop,
     int nkb, int nrb, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
     static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
     constexpr int NPH = NKB / kPB;  // staging phases per step
@@ -511,6 +640,9 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     const int col = team * 64 + lane;
     uint32_t *myflag = flags + (size_t)team * nrb + rb;
     if (threadIdx.x == 0) wg_abort = 0;
+    // a team stopped by a cancel request in an earlier launch keeps its state
+    const int ts0 = __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ts0 >= 0 && ts0 <= g.seg_k0) return;  // whole workgroup
 
     const int my_xcc = xcc_id();
     // this launch's epoch (advanced on the stream before the launch, so that a
@@ -641,6 +773,13 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
             // readers on another L2: invalidate for the data written there
             if (!xcd_local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
+        // cancellation (as in the dSB kernel): the first wave of the team has
+        // recorded this sample point as the stop step before publishing x_m;
+        // the state x_m and its sample are kept
+        if (cancel && m > g.seg_k0 && seg_is_sample(g, m)) {
+            const int ts = __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__builtin_amdgcn_readfirstlane(ts) == m) break;
+        }
         // chunk exponents of this lane's column for every K block (device-scope
         // loads: no stale L1 lines)
         uint32_t ed[NKB / 4];
@@ -754,6 +893,12 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
             sb_update(acc0[v], p, c0, dt, a0dt, gdt, xs0[v], ys0[v]);
             sb_update(acc1[v], p, c0, dt, a0dt, gdt, xs1[v], ys1[v]);
         }
+        if (cancel && rb == 0 && m + 1 < g.seg_k1 && seg_is_sample(g, m + 1)) {
+            const int c = __hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (__builtin_amdgcn_readfirstlane(c) != 0 && lane == 0)
+                __hip_atomic_store(tstop + team, m + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // publish's release orders it before the step flag
+        }
         if (m + 1 < g.seg_k1) publish(m + 1);
     }
 #pragma unroll
@@ -858,17 +1003,25 @@ __global__ __launch_bounds__(256) void k_fp4_trace(const double *__restrict__ es
 __global__ __launch_bounds__(256) void k_fp4_best(
     const double *__restrict__ es, const uint32_t *__restrict__ snap, int ns, int nchunk,
     int N, int R, int Rpad, SegArgs g, double *__restrict__ best_e, double *__restrict__ last_e,
-    int32_t *__restrict__ best_step, const int32_t *__restrict__ bad, int8_t *__restrict__ best_s) {
+    int32_t *__restrict__ best_step, const int32_t *__restrict__ bad, int8_t *__restrict__ best_s,
+    const int32_t *__restrict__ tstop) {
     __shared__ double s_e[8][32];
     __shared__ int s_j[8][32];
     const int rl = threadIdx.x & 31, grp = threadIdx.x >> 5;
     const int r = blockIdx.x * 32 + rl;
     double emin = __builtin_huge_val();
     int jmin = -1;
+    // a team stopped by a cancel request: only its samples up to the stop step
+    // exist, and the one at the stop step is its last
+    const int ts = tstop[blockIdx.x];  // 32 replicas = one team
+    auto step_of = [&](int j) {
+        return j < g.nmult ? (g.seg_k0 / g.interval + 1 + j) * g.interval : g.final_k;
+    };
     if (r < R) {
         for (int j = grp; j < ns; j += 8) {
+            if (ts >= 0 && step_of(j) > ts) continue;
             const double e = es[(size_t)j * Rpad + r];
-            if (j == ns - 1) last_e[r] = bad[r] ? __builtin_nan("") : e;
+            if (ts >= 0 ? step_of(j) == ts : j == ns - 1) last_e[r] = bad[r] ? __builtin_nan("") : e;
             if (e < emin) {
                 emin = e;
                 jmin = j;
@@ -914,12 +1067,15 @@ namespace {
 constexpr int kDsbPre[] = {2, 1, 4};
 constexpr int kBsbPre[] = {4, 2};
 
+// tile -1: the thermostat's kernel (operand read one K block ahead: the
+// registers of a further prefetch hold the thermostat's partials)
 template <int NKB>
 const void *dsb_ptr(int tile) {
     switch (tile) {
-    case 1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[1]>);
-    case 2: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[2]>);
-    default: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[0]>);
+    case -1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, 1, true>);
+    case 1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[1], false>);
+    case 2: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[2], false>);
+    default: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[0], false>);
     }
 }
 
@@ -1060,7 +1216,7 @@ int persistent_work_create(PersistentWork **out) {
 void persistent_work_free(PersistentWork *w) {
     if (!w) return;
     void *ptrs[] = {w->xb, w->snap, w->ep, w->es, w->tp, w->ptab, w->err, w->xslot, w->epoch,
-                    w->teams, w->xd, w->xe, w->flags};
+                    w->teams, w->xd, w->xe, w->flags, w->tstop, w->ypart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete w;
@@ -1070,7 +1226,7 @@ void persistent_free(PersistentJ *pj) {
     if (!pj) return;
     PersistentWork &w = pj->work;
     void *ptrs[] = {pj->jpk, w.xb, w.snap, w.ep, w.es, w.tp, w.ptab, w.err, w.xslot, w.epoch,
-                    w.teams, w.xd, w.xe, w.flags};
+                    w.teams, w.xd, w.xe, w.flags, w.tstop, w.ypart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete pj;
@@ -1125,10 +1281,17 @@ int run_segments(PersistentWork *pw, int variant, int nkb, int nteams_total, int
     const int interval = run.interval;
     const bool traces = b.trace_e || b.trace_t;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, pw->err);
+    // no team has stopped (cancellation), for the whole run
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nteams_total + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t *>(pw->tstop), (size_t)nteams_total, kNoTag);
+    b.tstop = pw->tstop;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
     const float a0dt = run.a0 * run.dt;
-    const void *kfn = bsb ? pick_bsb_kernel(nkb, run.tile) : pick_kernel(nkb, run.tile);
+    const bool nh = run.nh != nullptr;
+    const void *kfn = bsb ? pick_bsb_kernel(nkb, run.tile) : pick_kernel(nkb, nh ? -1 : run.tile);
+    FP4NH nhp{};
+    if (nh) nhp = FP4NH{run.nh->xi, pw->ypart, run.nh->c, run.nh->NT};
     int a = run.k0;
     for (;;) {
         // segment [a, e]: at most seg_samples multiples of interval in (a, e]
@@ -1164,6 +1327,7 @@ int run_segments(PersistentWork *pw, int variant, int nkb, int nteams_total, int
             int nkb_v = nkb, nrb_v = nrb, nchunk_v = nchunk, Rpad_v = Rpad, t0_v = t0, nt_v = nt;
             hipLaunchKernelGGL(k_next_epoch, dim3(1), dim3(1), 0, s, pw->epoch);
             int local_ok = run.local_exchange ? 1 : 0;
+            const int32_t *cancel = run.cancel;
             const float *gam = run.gamma;
             double *tpv = traces ? pw->tp : nullptr;
             void *args_d[] = {(void *)&pw->teams, (void *)&run.X,    (void *)&run.Y,
@@ -1171,7 +1335,8 @@ int run_segments(PersistentWork *pw, int variant, int nkb, int nteams_total, int
                               (void *)&pw->ep,    (void *)&tpv,      (void *)&pw->ptab,
                               (void *)&b.bad,
                               (void *)&b.status,  (void *)&pw->err,  (void *)&pw->xslot,
-                              (void *)&pw->epoch, (void *)&local_ok, (void *)&nkb_v,
+                              (void *)&pw->epoch, (void *)&local_ok, (void *)&cancel,
+                              (void *)&pw->tstop, (void *)&nhp,   (void *)&nkb_v,
                               (void *)&nchunk_v,  (void *)&Rpad_v,   (void *)&t0_v,
                               (void *)&nt_v,      (void *)&g,        (void *)&dt,
                               (void *)&a0dtv};
@@ -1181,6 +1346,7 @@ int run_segments(PersistentWork *pw, int variant, int nkb, int nteams_total, int
                               (void *)&pw->ptab,
                               (void *)&b.bad,     (void *)&b.status,  (void *)&pw->err,
                               (void *)&pw->xslot, (void *)&pw->epoch, (void *)&local_ok,
+                              (void *)&cancel,    (void *)&pw->tstop,
                               (void *)&nkb_v,     (void *)&nrb_v,     (void *)&Rpad_v,
                               (void *)&t0_v,      (void *)&nt_v,      (void *)&g,
                               (void *)&dt,        (void *)&a0dtv};
@@ -1204,7 +1370,7 @@ int run_segments(PersistentWork *pw, int variant, int nkb, int nteams_total, int
                                dim3(256), 0, s, pw->ep, pw->es, nparts, Rpad);
         hipLaunchKernelGGL(k_fp4_best, dim3((unsigned)((run.R + 31) / 32)), dim3(256), 0, s,
                            pw->es, pw->snap, ns, nchunk, Nrows, run.R, Rpad, g, b.best_e, b.last_e,
-                           b.best_step, b.bad, b.best_s);
+                           b.best_step, b.bad, b.best_s, pw->tstop);
         if (traces && ns > 0)  // rows of the segment's samples: after those of (k0, a]
             hipLaunchKernelGGL(k_fp4_trace, dim3((unsigned)((run.R + 255) / 256), (unsigned)ns),
                                dim3(256), 0, s, pw->es, pw->tp, nparts, Nrows, run.R, Rpad,
@@ -1234,7 +1400,8 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     const int Rpad = run.Rpad, nrb = nkb, nchunk = 2 * nrb;
     if (nteams_total * 32 > Rpad) return perr(HSB_EINVAL, "FP4 path: teams exceed the columns");
     int teams_per_launch = 0, wpt = 0, wg_capacity = 0;
-    int rc = launch_shape(bsb, nkb, run.tile, &teams_per_launch, &wpt, &wg_capacity);
+    if (run.nh && bsb) return perr(HSB_EUNSUPPORTED, "FP4 path: no thermostat for bSB");
+    int rc = launch_shape(bsb, nkb, run.nh ? -1 : run.tile, &teams_per_launch, &wpt, &wg_capacity);
     if (rc) return rc;
     const int nparts = bsb ? nrb : nchunk;
     const int interval = run.interval;
@@ -1245,7 +1412,8 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     if (seg_samples < 1) seg_samples = 1;
     const bool traces = b.trace_e || b.trace_t;
     const void *const before[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->tp, pw->ptab, pw->err,
-                                  pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
+                                  pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch,
+                                  pw->tstop, pw->ypart};
     rc = grow(&pw->xb, &pw->xb_words, (size_t)2 * nchunk * Rpad);
     if (!rc) rc = grow(&pw->snap, &pw->snap_words, (seg_samples + 1) * snap_per_sample);
     if (!rc) rc = grow(&pw->ep, &pw->ep_elems, (seg_samples + 1) * (size_t)nparts * Rpad);
@@ -1270,6 +1438,8 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     if (!rc && bsb) rc = grow(&pw->xd, &pw->xd_n, (size_t)2 * nkb * 8 * 2 * Rpad);
     if (!rc && bsb) rc = grow(&pw->xe, &pw->xe_n, (size_t)2 * 2 * Rpad * nkb);
     if (!rc && bsb) rc = grow(&pw->flags, &pw->flags_n, (size_t)nteams_total * nrb);
+    if (!rc) rc = grow(&pw->tstop, &pw->tstop_n, (size_t)nteams_total);
+    if (!rc && run.nh) rc = grow(&pw->ypart, &pw->ypart_n, (size_t)2 * (nchunk / 4) * Rpad);
     if (!rc && !pw->epoch) {
         rc = grow(&pw->epoch, &pw->epoch_n, 1);
         if (!rc) {
@@ -1288,7 +1458,8 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     if (rc) return rc;
     {
         const void *const after[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->tp, pw->ptab, pw->err,
-                                     pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch};
+                                     pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch,
+                                     pw->tstop, pw->ypart};
         if (std::memcmp(before, after, sizeof(before)) != 0) ++pw->gen;
     }
     // the team table, uploaded only when it differs from the last upload (a
@@ -1333,6 +1504,7 @@ void carve_dsb_work(Carver &c, PersistentWork &w, int nkb, int nteams, int Rpad,
     w.epoch = c.take<uint32_t>(1);
     w.xslot = c.take<uint64_t>(nslots);
     w.teams = c.take<FP4Team>((size_t)nteams);
+    w.tstop = c.take<int32_t>((size_t)nteams);
 }
 }  // namespace
 

@@ -19,11 +19,13 @@ LIB_PATH = os.path.join(_HERE, "libhsb.so")
 
 HSB_BSB, HSB_DSB = 0, 1
 HSB_OK, HSB_EINVAL, HSB_ENOMEM, HSB_EDEVICE, HSB_ENUMERIC, HSB_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
+HSB_ECANCELED = -5
 HSB_OPT_INIT_AMP, HSB_OPT_ENERGY_INTERVAL, HSB_OPT_RETURN_BEST, HSB_OPT_PRECISION = 0, 1, 2, 3
 HSB_OPT_TIMING, HSB_OPT_KERNEL_MS, HSB_OPT_KERNEL_LAUNCHES, HSB_OPT_LAST_PLAN = 4, 5, 6, 7
 HSB_OPT_LOCAL_EXCHANGE = 8
 HSB_OPT_GRAPH = 9
 HSB_OPT_GRAPH_LAUNCHES = 10
+HSB_OPT_AUTOTUNE, HSB_OPT_TILE, HSB_OPT_LAST_TILE = 11, 12, 13
 HSB_PLAN_FP32, HSB_PLAN_FP4, HSB_PLAN_DIGITS, HSB_PLAN_INCREMENTAL = 0, 1, 2, 3
 PLAN_NAMES = {HSB_PLAN_FP32: "fp32", HSB_PLAN_FP4: "fp4", HSB_PLAN_DIGITS: "digits",
               HSB_PLAN_INCREMENTAL: "incremental"}
@@ -34,7 +36,7 @@ HSB_SCHED_QUEUE, HSB_SCHED_CLASSES = 0, 1
 
 EXPORTED = ("hsb_create", "hsb_destroy", "hsb_last_error", "hsb_set_option", "hsb_get_option",
             "hsb_run", "hsb_run_ex", "hsb_plan_info", "hsb_run_batch", "hsb_num_samples",
-            "hsb_run_ex_noalloc")
+            "hsb_run_ex_noalloc", "hsb_cancel")
 HSB_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
@@ -64,6 +66,7 @@ class hsb_run_args(ctypes.Structure):
         ("trace_energy", ctypes.c_void_p), ("trace_tinst", ctypes.c_void_p),
         ("nh_inv_mass", ctypes.c_double), ("nh_temperature", ctypes.c_double),
         ("xi0", ctypes.c_void_p), ("xi_out", ctypes.c_void_p),
+        ("stop_step", ctypes.c_void_p),
     ]
 
 
@@ -110,6 +113,8 @@ def load_library():
     L.hsb_run.argtypes = [vp, i32, f32, f32, f32, f32, i32, i32, ctypes.c_uint64, vp, vp]
     L.hsb_run_ex.restype = i32
     L.hsb_run_ex.argtypes = [vp, ctypes.POINTER(hsb_run_args)]
+    L.hsb_cancel.restype = i32
+    L.hsb_cancel.argtypes = [vp]
     L.hsb_run_ex_noalloc.restype = i32
     L.hsb_run_ex_noalloc.argtypes = [vp, ctypes.POINTER(hsb_run_args)]
     L.hsb_plan_info.restype = i32
@@ -162,6 +167,11 @@ def hsb_plan_info(h, variant: int) -> int:
     return p.value
 
 
+def hsb_cancel(h) -> None:
+    """Ask the run in progress on h (or its next run) to stop at a sample point."""
+    _check(load_library().hsb_cancel(h))
+
+
 def hsb_run(h, variant, a0, c0, dt, gamma, steps, R, seed, allow_numeric=False):
     """Host-output run: returns (spins int8 [R][N], energy float64 [R], status)."""
     N = _ctx_n(h)
@@ -189,7 +199,7 @@ def hsb_num_samples(h, start_step: int, steps: int) -> int:
 def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=None, x0=None,
                y0=None, start_step=0, schedule_steps=0, want_state=False, stream=None,
                allow_numeric=False, out=None, traces=False, nose_hoover=None, xi0=None,
-               noalloc=False):
+               noalloc=False, allow_cancel=False):
     """Device run through hsb_run_ex.  Tensors are torch CUDA tensors.
 
     Returns a dict of device tensors: spins [R][N] int8, energy/best_energy/
@@ -205,6 +215,11 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
     noalloc=True calls hsb_run_ex_noalloc instead (the library allocates no
     device memory for the run; pass preallocated outputs in `out` to keep
     this call itself free of allocations).
+
+    With allow_cancel (or a stop_step tensor in `out`) the result also has
+    stop_step [R] int32: the step each replica reached.  A run stopped by
+    hsb_cancel raises HSBError(HSB_ECANCELED) unless allow_cancel, in which
+    case its outputs are returned with status HSB_ECANCELED.
     """
     import torch
 
@@ -215,6 +230,8 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
     for k in ("energy", "best_energy", "final_energy"):
         o.setdefault(k, torch.empty(R, dtype=torch.float64, device=dev))
     o.setdefault("best_step", torch.empty(R, dtype=torch.int32, device=dev))
+    if allow_cancel:
+        o.setdefault("stop_step", torch.empty(R, dtype=torch.int32, device=dev))
     if want_state:
         o.setdefault("x", torch.empty((R, N), dtype=torch.float32, device=dev))
         o.setdefault("y", torch.empty((R, N), dtype=torch.float32, device=dev))
@@ -259,6 +276,7 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
     a.best_energy = o["best_energy"].data_ptr()
     a.final_energy = o["final_energy"].data_ptr()
     a.best_step = o["best_step"].data_ptr()
+    a.stop_step = o["stop_step"].data_ptr() if "stop_step" in o else None
     if traces:
         a.trace_energy = o["trace_energy"].data_ptr()
         a.trace_tinst = o["trace_tinst"].data_ptr()
@@ -266,7 +284,7 @@ def hsb_run_ex(h, variant, steps, R, a0, c0, dt, gamma=0.0, seed=0, gamma_rep=No
     a.stream = s.cuda_stream
     L = load_library()
     rc = (L.hsb_run_ex_noalloc if noalloc else L.hsb_run_ex)(h, ctypes.byref(a))
-    _check(rc, (HSB_ENUMERIC,) if allow_numeric else ())
+    _check(rc, ((HSB_ENUMERIC,) if allow_numeric else ()) + ((HSB_ECANCELED,) if allow_cancel else ()))
     o["status"] = rc
     return o
 
@@ -318,6 +336,7 @@ def hsb_run_batch(contexts, jobs, variant, steps, a0, dt, init_amp=0.1, energy_i
 # interpreter (and the HIP runtime beneath it) starts tearing down, so that
 # hsb_destroy never runs during finalisation.
 _live = weakref.WeakSet()
+_is_finalizing = sys.is_finalizing
 
 
 @atexit.register
@@ -347,7 +366,8 @@ class Context:
              "timing": HSB_OPT_TIMING, "kernel_ms": HSB_OPT_KERNEL_MS,
              "kernel_launches": HSB_OPT_KERNEL_LAUNCHES, "last_plan": HSB_OPT_LAST_PLAN,
              "local_exchange": HSB_OPT_LOCAL_EXCHANGE, "graph": HSB_OPT_GRAPH,
-             "graph_launches": HSB_OPT_GRAPH_LAUNCHES}
+             "graph_launches": HSB_OPT_GRAPH_LAUNCHES, "autotune": HSB_OPT_AUTOTUNE,
+             "tile": HSB_OPT_TILE, "last_tile": HSB_OPT_LAST_TILE}
     _PREC = {"auto": HSB_PREC_AUTO, "fp32": HSB_PREC_FP32, "mixed": HSB_PREC_MIXED,
              "digits": HSB_PREC_DIGITS, "incremental": HSB_PREC_INCREMENTAL}
 
@@ -371,6 +391,10 @@ class Context:
     def run(self, variant, a0, c0, dt, gamma, steps, R, seed, allow_numeric=False):
         return hsb_run(self.h, variant, a0, c0, dt, gamma, steps, R, seed, allow_numeric)
 
+    def cancel(self):
+        """hsb_cancel: stop the run in progress (or the next one) at a sample point."""
+        hsb_cancel(self.h)
+
     def num_samples(self, start_step, steps):
         return hsb_num_samples(self.h, start_step, steps)
 
@@ -392,11 +416,12 @@ class Context:
         self.close()
 
     def __del__(self):
-        # during interpreter shutdown the runtime below may already be gone:
-        # contexts are closed by the exit handler before that, never here
-        if sys.is_finalizing():
-            return
+        # during interpreter shutdown the runtime below may already be gone
+        # (and this module's globals cleared): contexts are closed by the exit
+        # handler before that, never here
         try:
+            if self.h is None or _is_finalizing():
+                return
             self.close()
         except Exception:
             pass

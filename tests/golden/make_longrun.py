@@ -16,8 +16,9 @@ Cases (file longrun_<case>.json):
                      final energy, best step.  (The field of eq. (5) is an exact
                      integer, so the GPU state must hash the same.)
   bsb_sk2000_fp64    the same instance, heated bSB, FP64, seed 1, replicas
-                     0 .. 127: best and final energies (statistical parity of
-                     long chaotic runs).
+                     0 .. 127: best and final energies, the step of the best
+                     sample, and the energy of eq. (1) every 1000 steps
+                     (statistical parity of long chaotic runs).
   bsb_gauss2000_fp64 Gaussian couplings N = 2000 (instance seed 3), heated
                      bSB with c0 = 0.5, FP64, seed 1, replicas 0 .. 127.
 """
@@ -68,12 +69,16 @@ def case_dsb_sk2000_mirror():
 def _bsb_stats(J, c0, desc):
     R = 128
     o = oracle.run(J, oracle.BSB, 1.0, c0, 1.0, GAMMA, STEPS, R, seed=1, interval=INTERVAL,
-                   precision=oracle.FP64)
+                   precision=oracle.FP64, traces=True)
+    rows = list(range(9, STEPS // INTERVAL, 10))  # samples after 1000, 2000, ... steps
     return {"instance": desc, "variant": "bsb", "precision": "fp64", "a0": 1.0, "c0": c0,
             "dt": 1.0, "gamma": GAMMA, "steps": STEPS, "interval": INTERVAL, "seed": 1,
             "amp": 0.1, "replicas": list(range(R)),
             "best_e": [float(v) for v in o["best_e"]],
-            "final_e": [float(v) for v in o["final_e"]]}
+            "final_e": [float(v) for v in o["final_e"]],
+            "best_step": [int(v) for v in o["best_step"]],
+            "trace_steps": [(r + 1) * INTERVAL for r in rows],
+            "trace_e": [[float(v) for v in o["trace_e"][r]] for r in rows]}
 
 
 def case_bsb_sk2000_fp64():

@@ -103,6 +103,7 @@ def test_calls_on_null_context_are_rejected():
     assert L.hsb_run(None, 0, 1.0, 0.1, 1.0, 0.0, 10, 4, 0, None, None) == hsb.HSB_EINVAL
     assert L.hsb_run_ex(None, None) == hsb.HSB_EINVAL
     assert L.hsb_run_ex_noalloc(None, None) == hsb.HSB_EINVAL
+    assert L.hsb_cancel(None) == hsb.HSB_EINVAL
     assert L.hsb_set_option(None, 0, 0.1) == hsb.HSB_EINVAL
     a = hsb.hsb_batch_args()
     a.struct_size = ctypes.sizeof(a)

@@ -1,8 +1,9 @@
 """Nose-Hoover thermostat (eqs. (6)-(8)) through hsb_run_ex (marked `gpu`).
 
 Bars:
-  - dSB: the state is bitwise the oracle's FP32 mirror on the FP32 and the
-    integer-digit plans.  xi is summed in another order than the oracle's
+  - dSB: the state is bitwise the oracle's FP32 mirror on the FP32, the
+    integer-digit and the FP4 plans (on the last inside the persistent
+    kernel, with the workgroups' y^2 partials exchanged every step).  xi is summed in another order than the oracle's
     (FP64 partial sums of y^2), so it agrees to 1e-12 relative; the rate the
     step uses, xi rounded to float, is then the same except in the rare case
     of a rounding boundary between the two values, which these seeded runs
@@ -11,8 +12,8 @@ Bars:
     and y after 1 and 50 steps against the FP64 oracle, and xi to 1e-6
     relative.
   - 1/M = 0 is heated SB bitwise; a run split into two calls (xi_out fed back
-    as xi0) equals one call; where MIXED would take the FP4 plan the digit
-    plan runs.
+    as xi0) equals one call; for bSB, where MIXED would take the FP4 plan the
+    digit plan runs.
 """
 import numpy as np
 import pytest
@@ -39,8 +40,12 @@ def say(*a):
 
 
 # 1/M, T: xi moves from -gamma = -0.02 to between 0.01 and 0.16 (the
-# thermostat cools) and the runs stay finite; at 1/M = 2e-3 xi and y diverge
+# thermostat cools) and the runs stay finite; at 1/M = 2e-3 xi and y diverge.
+# The rate of xi grows with N (the sum of y^2 over N spins), so larger
+# instances take a proportionally heavier bath, NH_LARGE, at N = 700 and
+# N = 1100 (at 1e-4 there xi and y diverge on both sides).
 NH = (1e-4, 0.05)
+NH_LARGE = (2e-5, 0.05)
 
 
 GAMMA = float(np.float32(0.02))  # exact in float: both sides start xi at -GAMMA
@@ -71,14 +76,17 @@ def rel_err(a, b):
 
 
 @pytest.mark.parametrize("plan,expect", [("fp32", "fp32"), ("digits", "digits"),
-                                         ("mixed", "digits")])
-@pytest.mark.parametrize("N,R,steps", [(100, 16, 400), (257, 33, 300)])
+                                         ("mixed", "fp4")])
+@pytest.mark.parametrize("N,R,steps", [(100, 16, 400), (257, 33, 300), (1100, 64, 250),
+                                     (1700, 32, 120)])
 def test_dsb_thermostat_equals_mirror(plan, expect, N, R, steps):
     J = synth.sk_instance(N, 100 + N)
     say("dsb thermostat", plan, N, R, steps)
-    g = gpu(J, hsb.HSB_DSB, plan, steps, R)
+    nh = NH if N < 700 else NH_LARGE
+    g = gpu(J, hsb.HSB_DSB, plan, steps, R, nose_hoover=nh)
     assert g["plan"] == expect
-    o = orc(J, oracle.DSB, oracle.FP32, steps, R)
+    o = orc(J, oracle.DSB, oracle.FP32, steps, R, nose_hoover=nh)
+    assert np.all(np.isfinite(o["y"]))
     assert np.array_equal(g["x"].astype(np.float64), o["x"])
     assert np.array_equal(g["y"].astype(np.float64), o["y"])
     assert np.array_equal(g["best_energy"], o["best_e"])
@@ -88,7 +96,7 @@ def test_dsb_thermostat_equals_mirror(plan, expect, N, R, steps):
     assert np.all(np.abs(o["xi"] + GAMMA) > 1e-3)
 
 
-@pytest.mark.parametrize("plan", ["fp32", "digits"])
+@pytest.mark.parametrize("plan", ["fp32", "digits", "mixed"])
 def test_infinite_mass_is_heated_sb(plan):
     J = synth.sk_instance(150, 7)
     say("thermostat at infinite mass", plan)
@@ -99,7 +107,7 @@ def test_infinite_mass_is_heated_sb(plan):
     assert np.all(nh["xi"] == -np.float64(np.float32(0.05)))
 
 
-@pytest.mark.parametrize("plan", ["fp32", "digits"])
+@pytest.mark.parametrize("plan", ["fp32", "digits", "mixed"])
 def test_split_run_equals_one_run(plan):
     J = synth.sk_instance(200, 8)
     say("thermostat resume", plan)
@@ -131,20 +139,21 @@ def test_bsb_thermostat_within_bar(plan, N, seed, R, Ns, steps):
     np.testing.assert_allclose(g["xi"], o["xi"], rtol=1e-6, atol=0)
 
 
-def test_given_start_xi_and_per_replica_gamma():
+@pytest.mark.parametrize("plan", ["fp32", "mixed"])
+def test_given_start_xi_and_per_replica_gamma(plan):
     N, R = 120, 12
     J = synth.sk_instance(N, 10)
-    say("thermostat xi0 and gamma_rep")
+    say("thermostat xi0 and gamma_rep", plan)
     dev = torch.device("cuda", 0)
     xi0 = np.linspace(-0.1, 0.05, R)
     grep = np.linspace(0.0, 0.06, R).astype(np.float32)
-    g = gpu(J, hsb.HSB_DSB, "fp32", 200, R, xi0=torch.from_numpy(xi0).to(dev),
+    g = gpu(J, hsb.HSB_DSB, plan, 200, R, xi0=torch.from_numpy(xi0).to(dev),
             gamma_rep=torch.from_numpy(grep).to(dev))
     o = orc(J, oracle.DSB, oracle.FP32, 200, R, xi0=xi0)
     assert np.array_equal(g["x"].astype(np.float64), o["x"])
     np.testing.assert_allclose(g["xi"], o["xi"], rtol=1e-12, atol=0)
     # without xi0 the start value is -gamma_rep
-    g2 = gpu(J, hsb.HSB_DSB, "fp32", 0, R, gamma_rep=torch.from_numpy(grep).to(dev))
+    g2 = gpu(J, hsb.HSB_DSB, plan, 0, R, gamma_rep=torch.from_numpy(grep).to(dev))
     assert np.array_equal(g2["xi"], -grep.astype(np.float64))
 
 
@@ -173,20 +182,28 @@ def test_thermostat_argument_errors():
         assert L.hsb_run_ex(ctx.h, ctypes.byref(a)) == hsb.HSB_OK
 
 
-def test_bench_configuration_sampled_replicas():
+@pytest.mark.parametrize("plan,expect", [("mixed", "fp4"), ("digits", "digits")])
+def test_bench_configuration_sampled_replicas(plan, expect):
     """The thermostat at the size the bench times (dSB, N = 2000, R = 1024,
-    digit plan, 1/M = 1e-8, T = 0.02): the first 2000 steps of the 10^4-step
-    schedule, replicas 0, 511 and 1023 against the FP32 mirror."""
+    1/M = 1e-8, T = 0.02): the first 2000 steps of the 10^4-step schedule,
+    replicas 0, 511 and 1023 against the FP32 mirror; the two plans agree on
+    every replica."""
     N, R, steps, Ns = 2000, 1024, 2000, 10000
     J = synth.sk_instance(N, 2000)
     c0 = 0.5 / np.sqrt(N)
-    say("thermostat at the bench size", N, R, steps)
-    with hsb.Context(J, precision="mixed", init_amp=0.1, energy_interval=100) as ctx:
+    say("thermostat at the bench size", plan, N, R, steps)
+    with hsb.Context(J, precision=plan, init_amp=0.1, energy_interval=100) as ctx:
         g = ctx.run_ex(hsb.HSB_DSB, steps, R, 1.0, c0, 1.0, GAMMA, 1, want_state=True,
                        schedule_steps=Ns, nose_hoover=(1e-8, 0.02))
         torch.cuda.synchronize()
-        assert ctx.last_plan() == "digits"
+        assert ctx.last_plan() == expect
         g = {k: v.cpu().numpy() for k, v in g.items() if hasattr(v, "cpu")}
+    _bench_runs[plan] = g
+    if len(_bench_runs) == 2:
+        a, b = _bench_runs.values()
+        for k in ("x", "y", "spins", "best_energy"):
+            assert np.array_equal(a[k], b[k]), k
+        np.testing.assert_allclose(a["xi"], b["xi"], rtol=1e-12, atol=0)
     for r in (0, 511, 1023):
         o = oracle.run(J, oracle.DSB, 1.0, np.float32(c0), 1.0, GAMMA, steps, 1, seed=1, amp=0.1,
                        interval=100, precision=oracle.FP32, r0=r, schedule_steps=Ns,
@@ -197,7 +214,29 @@ def test_bench_configuration_sampled_replicas():
         np.testing.assert_allclose(g["xi"][r:r + 1], o["xi"], rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("plan", ["fp32", "digits"])
+_bench_runs = {}
+
+
+def test_fp4_thermostat_device_scope_exchange():
+    """LOCAL_EXCHANGE = 0: the FP4 thermostat's partials go through device-scope
+    stores with release/acquire fences; the run must not change."""
+    J = synth.sk_instance(700, 19)
+    outs = []
+    say("fp4 thermostat device scope")
+    for local in (1, 0):
+        with hsb.Context(J, precision="mixed", init_amp=0.3, energy_interval=50,
+                         local_exchange=local) as ctx:
+            o = ctx.run_ex(hsb.HSB_DSB, 200, 40, 1.0, 0.5 / np.sqrt(700), 1.0, GAMMA, 3,
+                           want_state=True, nose_hoover=NH_LARGE)
+            torch.cuda.synchronize()
+            assert ctx.last_plan() == "fp4"
+            outs.append({k: v.cpu().numpy() for k, v in o.items() if hasattr(v, "cpu")})
+    assert np.all(np.isfinite(outs[0]["y"]))
+    for k in ("x", "y", "xi", "spins", "best_energy"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+@pytest.mark.parametrize("plan", ["fp32", "digits", "mixed"])
 def test_thermostat_with_traces(plan):
     """Traces of a thermostat run: energy rows equal the mirror's, T_inst rows
     agree to FP64 summation order."""
