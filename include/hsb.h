@@ -121,7 +121,14 @@ typedef enum {
                                     combination, the other one (32 or 64 rows: two or one
                                     workgroups per CU); batch queues: 0..1 = longest-first,
                                     round robin.  A variant the plan lacks: HSB_EINVAL */
-    HSB_OPT_LAST_TILE = 13       /* read only: the variant of the last successful run */
+    HSB_OPT_LAST_TILE = 13,      /* read only: the variant of the last successful run */
+    HSB_OPT_CANCELLABLE = 14     /* 1: runs of this context (hsb_run, hsb_run_ex,
+                                    hsb_run_ex_noalloc) can be stopped by hsb_cancel; the
+                                    FP4 plan then runs its dSB kernel's cancellable
+                                    variant, about 6% slower at N = 2000 (its request
+                                    checks change the step's instruction schedule).
+                                    0 (default): hsb_cancel returns HSB_EINVAL for this
+                                    context and every plan runs without the checks */
 } hsb_option;
 
 typedef enum {
@@ -297,8 +304,8 @@ int hsb_run_ex(hsb_ctx *h, const hsb_run_args *args);
  *     replica stops.
  *   - FP4 plan: the replicas of each 32-replica team stop together at the
  *     first sample point after the team's first wave has seen the request
- *     (read one step before each sample point); different teams may stop at
- *     different sample points.
+ *     (it reads the request at the start of the launch and at each sample
+ *     point); different teams may stop at different sample points.
  * A stopped replica's outputs are those of a run of that many steps: its
  * state (x_out, y_out), its samples up to the stop (energy, best and final
  * energies, best step, traces; later trace rows are unspecified), and xi.
@@ -310,7 +317,8 @@ int hsb_run_ex(hsb_ctx *h, const hsb_run_args *args);
  * The request belongs to the context's next or current run and is cleared
  * when that run returns, whether or not it stopped the run (a request that
  * arrives after the run's last sample point has no effect).  Batches
- * (hsb_run_batch) are not cancelled.  NULL: HSB_EINVAL.
+ * (hsb_run_batch) are not cancelled.  Only a context with
+ * HSB_OPT_CANCELLABLE = 1 takes requests; on others, and for NULL, HSB_EINVAL.
  */
 int hsb_cancel(hsb_ctx *h);
 

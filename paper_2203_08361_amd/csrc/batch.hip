@@ -83,7 +83,7 @@ struct QShared {
     // and at the pending (not yet evaluated) sample
     double beste[4][32];
     uint32_t wbest[4][64], wpend[4][64];
-    int unit, abort;
+    int unit, entry, abort;
 };
 
 struct QArgs {
@@ -93,6 +93,7 @@ struct QArgs {
     double *best_e, *last_e;
     int32_t *bad, *status, *err;
     int steps, interval, return_best;
+    int nteams;  // teams of the batch: the stride of the exchange layout
     float dt, a0dt, amp;
 };
 
@@ -107,7 +108,10 @@ __device__ __forceinline__ bool run_unit(QShared &sh, const QTeam &tm, int team,
     const int half = lane >> 5, l32 = lane & 31;
     const int one = 127;  // E8M0 block scale 2^0
     const int N = tm.N, steps = g.steps;
-    auto is_sample = [&](int m) { return m == steps || (m > 0 && m % g.interval == 0); };
+    // sample points m = interval, 2 interval, ... and the last step, as a
+    // running clock (no division per step)
+    int next_mult = g.interval;
+    auto is_sample = [&](int m) { return m == steps || m == next_mult; };
 
     // the wave's 32 rows of J (FP4 fragments, accumulation registers)
     const v4i *__restrict__ jpk = static_cast<const v4i *>(tm.jpk);
@@ -130,8 +134,13 @@ __device__ __forceinline__ bool run_unit(QShared &sh, const QTeam &tm, int team,
         ys[v] = ok ? g.amp * uniform_open(rng_key(tm.seed, 1, (uint64_t)rep, (uint64_t)row)) : 0.0f;
     }
 
-    uint64_t *xbt = g.xb + (size_t)team * kTeamWords;
-    uint32_t *ept = g.ep + (size_t)team * kTeamWords;
+    // Exchange entries (sign words, energy partials) of parity p and chunk c:
+    // the 32 replicas of a team side by side, the teams of the batch side by
+    // side, then chunks, then parities -- one chunk's entries of all teams
+    // form one row, as a single run's columns of replicas do.
+    const size_t tstride = (size_t)g.nteams * 32;  // one chunk of every team
+    uint64_t *xbt = g.xb + (size_t)team * 32;
+    uint32_t *ept = g.ep + (size_t)team * 32;
     // sign word of the current state's chunk for this lane's replica (bit b
     // < 16 from the lower half of the wave, b >= 16 from the upper half)
     auto cur_word = [&]() -> uint32_t {
@@ -146,7 +155,7 @@ __device__ __forceinline__ bool run_unit(QShared &sh, const QTeam &tm, int team,
     auto publish = [&](int m) {
         const uint32_t word = cur_word();
         if (half == 0) {
-            uint64_t *dst = xbt + ((size_t)(m & 1) * kQChunks + rb) * 32 + l32;
+            uint64_t *dst = xbt + ((size_t)(m & 1) * kQChunks + rb) * tstride + l32;
             const uint64_t tagged = ((uint64_t)(uint32_t)m << 32) | word;
             if (xcd_local)
                 st_tagged_xcd(dst, tagged);
@@ -168,10 +177,10 @@ __device__ __forceinline__ bool run_unit(QShared &sh, const QTeam &tm, int team,
     // sum is exact and the same in every wave)
     auto team_energy = [&](int sp) -> double {
         if (!xcd_local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const uint32_t *src = ept + (size_t)sp * kQChunks * 32 + l32;
+        const uint32_t *src = ept + (size_t)sp * kQChunks * tstride + l32;
         double S = 0.0;
 #pragma unroll 8
-        for (int c = 0; c < 2 * NKB; ++c) S += (double)__uint_as_float(ld_word(src + c * 32));
+        for (int c = 0; c < 2 * NKB; ++c) S += (double)__uint_as_float(ld_word(src + c * tstride));
         return -0.5 * S;
     };
     // the best of the samples evaluated so far (strict improvement: the
@@ -191,10 +200,10 @@ __device__ __forceinline__ bool run_unit(QShared &sh, const QTeam &tm, int team,
     for (int m = 0;; ++m) {
         const int buf = m & 1;
         // this wave's share of the operand: K block kb = w + 4q is chunk 2 kb + l/32
-        const uint64_t *src = xbt + ((size_t)buf * kQChunks + 2 * w + half) * 32 + l32;
+        const uint64_t *src = xbt + ((size_t)buf * kQChunks + 2 * w + half) * tstride + l32;
         const float p = m < steps ? g.ptab[m] : 0.0f;
         uint64_t wv[NQ];
-        if (gather_words<NQ>(wv, src, (size_t)8 * 32, NQ, (uint32_t)m, g.err)) {
+        if (gather_words<NQ>(wv, src, 8 * tstride, NQ, (uint32_t)m, g.err)) {
 #pragma unroll
             for (int qq = 0; qq < NQ; ++qq)
                 sh.a_lds[buf][w + 4 * qq][lane] =
@@ -236,7 +245,7 @@ __device__ __forceinline__ bool run_unit(QShared &sh, const QTeam &tm, int team,
             }
             part += __shfl_xor(part, 32);
             if (half == 0) {
-                uint32_t *dst = ept + ((size_t)sp * kQChunks + rb) * 32 + l32;
+                uint32_t *dst = ept + ((size_t)sp * kQChunks + rb) * tstride + l32;
                 if (xcd_local)
                     __hip_atomic_store(dst, __float_as_uint(part), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -244,6 +253,10 @@ __device__ __forceinline__ bool run_unit(QShared &sh, const QTeam &tm, int team,
                     __hip_atomic_store(dst, __float_as_uint(part), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             }
+            // the partial is in before the next published word (here, at the
+            // sample step, rather than in a branch of every step between the
+            // update and the publish, which would split their schedule)
+            release_partial();
             if (!fin && live) {
                 g.bad[team * 32 + l32] = 1;
                 __hip_atomic_fetch_or(g.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -253,6 +266,7 @@ __device__ __forceinline__ bool run_unit(QShared &sh, const QTeam &tm, int team,
             sp ^= 1;
         }
         if (m == steps) break;
+        if (m == next_mult) next_mult = g.interval <= steps - m ? m + g.interval : -1;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             float x = xs[v], y = ys[v];
@@ -260,16 +274,16 @@ __device__ __forceinline__ bool run_unit(QShared &sh, const QTeam &tm, int team,
             xs[v] = x;
             ys[v] = y;
         }
-        if (pend) release_partial();
         publish(m + 1);
     }
     // the last sample: one more round, so that every partial is in
     release_partial();
     publish(steps + 1);
     {
-        const uint64_t *src = xbt + ((size_t)((steps + 1) & 1) * kQChunks + 2 * w + half) * 32 + l32;
+        const uint64_t *src =
+            xbt + ((size_t)((steps + 1) & 1) * kQChunks + 2 * w + half) * tstride + l32;
         uint64_t wv[NQ];
-        if (!gather_words<NQ>(wv, src, (size_t)8 * 32, NQ, (uint32_t)(steps + 1), g.err)) {
+        if (!gather_words<NQ>(wv, src, 8 * tstride, NQ, (uint32_t)(steps + 1), g.err)) {
             sh.abort = 1;
             __hip_atomic_fetch_or(g.status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -319,12 +333,13 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4_queue(
     for (;;) {
         __syncthreads();  // nothing of the previous unit is read any more
         if (threadIdx.x == 0) {
-            int u = -1;
+            int u = -1, k = -1;
             if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-                const int k = first >= 0 ? first : atomicAdd(head + q, 1);
+                k = first >= 0 ? first : atomicAdd(head + q, 1);
                 if (k < qlen) u = (int)units[qbeg + k];
             }
             sh.unit = u;
+            sh.entry = k;
             sh.abort = 0;
         }
         first = -1;
@@ -339,7 +354,19 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4_queue(
         const int rb = member * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 
         // Are all workgroups of the team on this XCD?  Each member records
-        // (launch epoch, XCD id); lane k reads member k's record.
+        // (launch epoch, XCD id); lane k reads member k's record.  A member
+        // may wait here for as long as other teams run: the team's last entry
+        // is handed out only when a workgroup of the queue becomes free (the
+        // first grid/8 entries are taken at the start, then one by one from
+        // the counter).  So the time limit runs only once every entry of the
+        // team has been handed out.
+        const int entry = __builtin_amdgcn_readfirstlane(sh.entry);
+        const int last_entry = entry - member + wpt - 1;
+        const int nstatic = (int)(gridDim.x >> 3);
+        auto all_taken = [&]() {
+            return last_entry < nstatic ||
+                   __hip_atomic_load(head + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > last_entry;
+        };
         if (threadIdx.x == 0)
             st_tagged(mslot + (size_t)team * kMaxWpt + member,
                       ((uint64_t)epoch << 32) | (uint32_t)my_xcc);
@@ -347,11 +374,16 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4_queue(
         {
             const uint64_t *ms = mslot + (size_t)team * kMaxWpt + (lane < wpt ? lane : 0);
             uint64_t v = ld_tagged(ms);
-            const uint64_t t0 = wall_clock64();
+            uint64_t t0 = wall_clock64();
+            bool taken = all_taken();
             bool ok = true;
             while (__any((uint32_t)(v >> 32) != epoch)) {
                 __builtin_amdgcn_s_sleep(1);
                 v = ld_tagged(ms);
+                if (!taken) {  // the clock starts when the last member is handed out
+                    taken = all_taken();
+                    t0 = wall_clock64();
+                }
                 if (wall_clock64() - t0 > kTimeoutTicks ||
                     __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                     ok = false;
@@ -624,6 +656,7 @@ int queue_run(QueueWork *w, const std::vector<QTeam> &teams, const QRun &run, in
         g.steps = run.steps;
         g.interval = run.interval;
         g.return_best = run.return_best;
+        g.nteams = (int)nt;
         g.dt = run.dt;
         g.a0dt = a0dt;
         g.amp = run.amp;

@@ -147,7 +147,8 @@ struct hsb_ctx {
     int32_t *h_cancel = nullptr;
     const int32_t *d_cancel = nullptr;
     int32_t *d_stop = nullptr;
-    bool cancellable = true;
+    bool cancellable = true;  // false while a batch runs its jobs through hsb_run_ex
+    int cancel_opt = 0;       // HSB_OPT_CANCELLABLE
     // workspace
     int Rpad_cap = 0;
     uint64_t state_gen = 0;  // raised when the state buffers are reallocated
@@ -199,6 +200,9 @@ extern "C" const char *hsb_last_error(void) { return g_err; }
 
 extern "C" int hsb_cancel(hsb_ctx *h) {
     if (!h || !h->h_cancel) return fail(HSB_EINVAL, "hsb_cancel: NULL context");
+    if (!__atomic_load_n(&h->cancel_opt, __ATOMIC_RELAXED))
+        return fail(HSB_EINVAL, "hsb_cancel: the context's runs are not cancellable "
+                                "(HSB_OPT_CANCELLABLE = 0)");
     __atomic_store_n(h->h_cancel, 1, __ATOMIC_SEQ_CST);
     return HSB_OK;
 }
@@ -373,6 +377,10 @@ extern "C" int hsb_set_option(hsb_ctx *h, int key, double v) {
             return fail(HSB_EINVAL, "TILE must be -1 or a variant index 0 .. 15");
         h->tile = (int)v;
         return HSB_OK;
+    case HSB_OPT_CANCELLABLE:
+        if (!(v == 0.0 || v == 1.0)) return fail(HSB_EINVAL, "CANCELLABLE must be 0 or 1");
+        __atomic_store_n(&h->cancel_opt, (int)v, __ATOMIC_RELAXED);
+        return HSB_OK;
     case HSB_OPT_KERNEL_MS:
     case HSB_OPT_KERNEL_LAUNCHES:
     case HSB_OPT_LAST_PLAN:
@@ -407,6 +415,7 @@ extern "C" int hsb_get_option(hsb_ctx *h, int key, double *v) {
     case HSB_OPT_AUTOTUNE: *v = h->autotune; return HSB_OK;
     case HSB_OPT_TILE: *v = h->tile; return HSB_OK;
     case HSB_OPT_LAST_TILE: *v = h->last_tile; return HSB_OK;
+    case HSB_OPT_CANCELLABLE: *v = h->cancel_opt; return HSB_OK;
     default: return fail(HSB_EINVAL, "unknown option key %d", key);
     }
 }
@@ -509,7 +518,7 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s, int
     HIP_TRY(hsb::launch_fill_gamma(b.gamma, a->gamma_rep, a->gamma, R, Rpad, s));
     HIP_TRY(hsb::launch_reset_tracking(b, Rpad, s));
     // cancellation: the stop word of the per-step plans, polled after samples
-    const int32_t *cancel = h->cancellable ? h->d_cancel : nullptr;
+    const int32_t *cancel = h->cancellable && h->cancel_opt ? h->d_cancel : nullptr;
     b.stop = h->d_stop;
     b.tstop = nullptr;
     HIP_TRY(hsb::launch_stop_init(b.stop, s));
@@ -719,6 +728,7 @@ std::vector<uint64_t> run_key(const hsb_ctx *h, const hsb_run_args *a, int plan,
             db(a->nh_inv_mass),
             db(a->nh_temperature), pb(a->xi0), pb(a->xi_out), amp,
             (uint64_t)h->interval, (uint64_t)h->return_best, (uint64_t)h->local_exchange,
+            (uint64_t)h->cancel_opt,
             (uint64_t)plan, pb(h->b.X), (uint64_t)h->Rpad_cap, h->state_gen, pb(h->pj),
             h->pj ? hsb::persistent_gen(h->pj) : 0, (uint64_t)tile};
 }
@@ -1188,7 +1198,7 @@ extern "C" int hsb_run_ex_noalloc(hsb_ctx *h, const hsb_run_args *a) {
     pr.interval = h->interval;
     pr.a0 = a->a0; pr.c0 = a->c0; pr.dt = a->dt;
     pr.local_exchange = h->local_exchange;
-    pr.cancel = h->cancellable ? h->d_cancel : nullptr;
+    pr.cancel = h->cancellable && h->cancel_opt ? h->d_cancel : nullptr;
     rc = hsb::persistent_run_in(s0 + used, HSB_NOALLOC_SCRATCH_BYTES - used, h->pj, pr, b, N, s);
     if (rc != HSB_OK) return fail(rc, "hsb_run_ex_noalloc: %s", hsb::persistent_error());
     HIP_TRY(hsb::launch_output(b, N, R, Rpad, h->return_best, a->spins, a->energy, a->x_out,

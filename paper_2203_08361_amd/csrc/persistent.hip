@@ -150,13 +150,36 @@ struct FP4NH {
     double c, NT;
 };
 
-__device__ __forceinline__ bool seg_is_sample(const SegArgs &g, int m) {
-    return m == g.final_k || (m > g.seg_k0 && m % g.interval == 0);
-}
-__device__ __forceinline__ int seg_sample_index(const SegArgs &g, int m) {
-    return (m > g.seg_k0 && m % g.interval == 0) ? (m / g.interval - g.seg_k0 / g.interval - 1)
-                                                 : g.nmult;
-}
+// The sample points of a segment: the run's last step (final_k, if it lies in
+// the segment) and every multiple of the interval in (seg_k0, seg_k1]; the
+// multiples have indices 0, 1, ... in step order and the last step, if it is
+// not one of them, index nmult.  Kept as a running clock, without a division
+// per step: `next` is the first multiple after the steps already passed (-1
+// once it would exceed the int range, where no step lies) and `index` its
+// sample index.  pass(m) is called once each step m, after its own sample and
+// before asking about m + 1.
+struct SampleClock {
+    int next, index;
+    __device__ __forceinline__ explicit SampleClock(const SegArgs &g) : index(0) {
+        next = step_after((long long)(g.seg_k0 / g.interval) * g.interval, g.interval);
+    }
+    __device__ static __forceinline__ int step_after(long long mult, int interval) {
+        const long long t = mult + interval;
+        return t > 0x7FFFFFFFll ? -1 : (int)t;
+    }
+    __device__ __forceinline__ bool is_sample(const SegArgs &g, int m) const {
+        return m == g.final_k || m == next;
+    }
+    __device__ __forceinline__ int sample_index(const SegArgs &g, int m) const {
+        return m == next ? index : g.nmult;
+    }
+    __device__ __forceinline__ void pass(const SegArgs &g, int m) {
+        if (m == next) {
+            next = step_after(next, g.interval);
+            ++index;
+        }
+    }
+};
 
 // One workgroup = 4 waves = 4 consecutive 32-row blocks of one team, so the
 // four waves need the same +-1 operand (the team's signs).  Each step every
@@ -170,7 +193,12 @@ __device__ __forceinline__ int seg_sample_index(const SegArgs &g, int m) {
 // core while this one waits for its team's signs.  That is why a wave holds
 // 32 rows rather than 64: 32 rows of J take 128 of the 256 registers two waves
 // per SIMD leave each.
-template <int NKB, int KPRE, bool NH>
+//
+// CANCEL: the variant that honours hsb_cancel (below).  It is a separate
+// instantiation because its code, though it runs only at sample points,
+// changes the schedule the compiler gives the step (measured 6% slower at
+// the bench size); the other variant has none of it.
+template <int NKB, int KPRE, bool NH, bool CANCEL>
 __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, uint64_t *xb, uint32_t *__restrict__ snap,
@@ -212,8 +240,10 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     if (threadIdx.x == 0) wg_abort = 0;
     // a team stopped by a cancel request in an earlier launch of the run keeps
     // its state; a stop step never lies beyond the end of its segment
-    const int ts0 = __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (ts0 >= 0 && ts0 <= g.seg_k0) return;  // whole workgroup
+    if constexpr (CANCEL) {
+        const int ts0 = __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ts0 >= 0 && ts0 <= g.seg_k0) return;  // whole workgroup
+    }
 
     // Are all workgroups of this team on one XCD?  Each records (launch epoch,
     // XCD id) in its slot; lane k reads member k's slot.  Only then may the team
@@ -267,10 +297,22 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         ys[v] = row < N ? Y[(size_t)row * Rpad + rep] : 0.0f;
     }
 
+    // Cancellation: the team's first wave reads the request at the start of
+    // the launch and at each sample point; at the next sample point, if the
+    // request was set, it records that sample point as the team's stop step
+    // before it publishes the state of that step.  Every wave reads the record
+    // at the sample point, once it has gathered that state (so all of them
+    // see it), stops after the sample and writes its state back.  The host
+    // word's trip is off the step's path: the value is used an interval later.
+    const bool decider = CANCEL && cancel && __builtin_amdgcn_readfirstlane(rb) == 0;
+    int creq = 0;
+    if constexpr (CANCEL)
+        if (decider) creq = __hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+
     // publish the sign word of the state x_m (tag m); snapshot at samples.
     // Lane l holds 16 rows of the block for replica l%32, lane l+32 the other
     // 16: the lower half of the wave stores the merged word.
-    auto publish = [&](int m) {
+    auto publish = [&](int m, bool sample, int sidx) {
         // b = (b << 1) | sign bit, highest item first: one operation per item
         uint32_t b = 0;
 #pragma unroll
@@ -284,16 +326,30 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             }
         }
+        const uint32_t word = b | (got << 16);
+        const size_t slot = (size_t)rb * Rpad + rep;
+        if constexpr (CANCEL) {
+            if (sample) {
+                // cancellation: the team's first wave records this sample point
+                // as the team's stop step, before the words of this state, if
+                // the request it last read was set
+                if (decider && m < g.final_k && __builtin_amdgcn_readfirstlane(creq) != 0) {
+                    if (lane == 0)
+                        __hip_atomic_store(tstop + team, m, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                }
+                if (half == 0) snap[(size_t)sidx * nchunk * Rpad + slot] = word;
+            }
+        }
         if (half == 0) {
-            const uint32_t word = b | (got << 16);
-            const size_t slot = (size_t)rb * Rpad + rep;
             const uint64_t tagged = ((uint64_t)(uint32_t)m << 32) | word;
             if (xcd_local)
                 st_tagged_xcd(xb + (size_t)(m & 1) * nchunk * Rpad + slot, tagged);
             else
                 st_tagged(xb + (size_t)(m & 1) * nchunk * Rpad + slot, tagged);
-            if (seg_is_sample(g, m))
-                snap[(size_t)seg_sample_index(g, m) * nchunk * Rpad + slot] = word;
+            if constexpr (!CANCEL)
+                if (sample) snap[(size_t)sidx * nchunk * Rpad + slot] = word;
         }
     };
 
@@ -308,16 +364,15 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
             if (half == 0) s_yw[m & 1][w][l32] = t2;
         }
     };
+    // sample points: a uniform clock rather than two integer divisions per
+    // step (measured 5% faster at the bench size)
+    SampleClock clk(g);
+    auto is_sample = [&](int m) { return clk.is_sample(g, m); };
+    auto sample_index = [&](int m) { return clk.sample_index(g, m); };
     y2_partial(g.seg_k0);
-    publish(g.seg_k0);
+    publish(g.seg_k0, is_sample(g.seg_k0), sample_index(g.seg_k0));
     __syncthreads();
-    // Cancellation: the team's first wave reads the request on the step before
-    // each sample point and, if it is set, records that sample point as the
-    // team's stop step before it publishes the state of that step; every wave
-    // reads the record once it has gathered that state, stops after the sample
-    // and writes its state back.
     int stop_at = 0x7FFFFFFF;
-    const bool decider = cancel && rb == 0;
     for (int m = g.seg_k0;; ++m) {
         const int buf = m & 1;
         // this wave's share: K block kb = w + 4q is chunk 2 kb + l/32
@@ -334,11 +389,6 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         }
         __syncthreads();
         if (wg_abort) break;
-        if (cancel && m > g.seg_k0 && seg_is_sample(g, m)) {
-            if (!xcd_local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const int ts = __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (ts == m) stop_at = m;
-        }
         // Thermostat.  Wave 0 stores the workgroup's partial of y(t_m)^2 (the
         // four waves' in a fixed order); it publishes x_{m+1} only after that
         // store.  The team's partials of y(t_{m-1})^2 are all in (x_m is), and
@@ -413,9 +463,9 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
                 if (half == 0) s_xi[w][l32] = xi_k;
             }
         }
-        if (seg_is_sample(g, m)) {
+        if (is_sample(m)) {
             // eq. (1) partial over this wave's 32 rows of s_i f_i (exact integers/halves)
-            const int j = seg_sample_index(g, m);
+            const int j = sample_index(m);
             float part = 0.0f;
             bool fin = true;
 #pragma unroll
@@ -436,8 +486,21 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
                 bad[rep] = 1;
                 __hip_atomic_fetch_or(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+            if (CANCEL && cancel && m > g.seg_k0) {
+                // the team's stop record (one word: wave-uniform, so the loop's
+                // exit stays uniform); every word of x_m is in, and the record
+                // was released before them
+                if (!xcd_local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const int ts = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                if (ts == m) stop_at = m;
+                if (decider)  // the request, for the next sample point
+                    creq = __hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
         }
-        if (m == g.seg_k1 || m == stop_at) break;
+        if (m == g.seg_k1 || (CANCEL && m == stop_at)) break;
+        clk.pass(g, m);
+        const bool next_sample = is_sample(m + 1);
         float gdt = gdt_heat;
         if constexpr (NH) gdt = (float)(-s_xi[w][l32]) * dt;
 #pragma unroll
@@ -448,16 +511,7 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
             ys[v] = y;
         }
         y2_partial(m + 1);
-        if (decider && m + 1 < g.final_k && seg_is_sample(g, m + 1)) {
-            const int c = __hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            if (__builtin_amdgcn_readfirstlane(c) != 0) {
-                if (lane == 0)
-                    __hip_atomic_store(tstop + team, m + 1, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // before the words of m + 1
-            }
-        }
-        publish(m + 1);
+        publish(m + 1, next_sample, sample_index(m + 1));
     }
     // write the state back
 #pragma unroll
@@ -606,7 +660,8 @@ __device__ __forceinline__ uint32_t make_digits(const float (&xs)[16], int half,
     return (uint32_t)(E + 128);
 }
 
-template <int NKB, int KPRE>
+// CANCEL: the variant that honours hsb_cancel, as for the dSB kernel.
+template <int NKB, int KPRE, bool CANCEL>
 __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, v4i *xd, uint8_t *xe, uint32_t *flags,
@@ -641,8 +696,10 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     uint32_t *myflag = flags + (size_t)team * nrb + rb;
     if (threadIdx.x == 0) wg_abort = 0;
     // a team stopped by a cancel request in an earlier launch keeps its state
-    const int ts0 = __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (ts0 >= 0 && ts0 <= g.seg_k0) return;  // whole workgroup
+    if constexpr (CANCEL) {
+        const int ts0 = __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ts0 >= 0 && ts0 <= g.seg_k0) return;  // whole workgroup
+    }
 
     const int my_xcc = xcc_id();
     // this launch's epoch (advanced on the stream before the launch, so that a
@@ -716,7 +773,7 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
         }
     };
     // sign words of the sampled state x_m (the energy is formed afterwards)
-    auto snapshot = [&](int m) {
+    auto snapshot = [&](int sidx) {
         uint32_t b0 = 0, b1 = 0;
         bool fin = true;
 #pragma unroll
@@ -728,14 +785,14 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
         const uint32_t got = (uint32_t)__shfl_xor((int)(half ? b0 : b1), 32);
         const uint32_t word = half ? (got | (b1 << 16)) : (b0 | (got << 16));
         const size_t slot = (size_t)(rb * 2 + half) * Rpad + rep;
-        snap[(size_t)seg_sample_index(g, m) * nchunk * Rpad + slot] = word;
+        snap[(size_t)sidx * nchunk * Rpad + slot] = word;
         if (tp) {  // sum of y_i^2 over the wave's 64 rows (eq. (9)), exact squares
             double t = 0.0;
 #pragma unroll
             for (int v = 0; v < 16; ++v)
                 t += (double)ys0[v] * (double)ys0[v] + (double)ys1[v] * (double)ys1[v];
             t += __shfl_xor(t, 32);
-            if (half == 0) tp[((size_t)seg_sample_index(g, m) * nrb + rb) * Rpad + rep] = t;
+            if (half == 0) tp[((size_t)sidx * nrb + rb) * Rpad + rep] = t;
         }
         if (!fin) {
             bad[rep] = 1;
@@ -744,10 +801,13 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     };
 
     if (g.seg_k0 < g.seg_k1) publish(g.seg_k0);
+    SampleClock clk(g);  // sample points without a division per step
     for (int m = g.seg_k0;; ++m) {
         // the energy of a sampled state needs only its signs
-        if (seg_is_sample(g, m)) snapshot(m);
+        const bool sample = clk.is_sample(g, m);
+        if (sample) snapshot(clk.sample_index(g, m));
         if (m == g.seg_k1) break;
+        clk.pass(g, m);
         const int par = m & 1;
         const float p = ptab[m - g.seg_k0];
         // wait for every wave of the team to have published x_m
@@ -773,12 +833,28 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
             // readers on another L2: invalidate for the data written there
             if (!xcd_local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        // cancellation (as in the dSB kernel): the first wave of the team has
-        // recorded this sample point as the stop step before publishing x_m;
-        // the state x_m and its sample are kept
-        if (cancel && m > g.seg_k0 && seg_is_sample(g, m)) {
-            const int ts = __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (__builtin_amdgcn_readfirstlane(ts) == m) break;
+        if constexpr (CANCEL) {
+            if (cancel) {
+                // cancellation: the first wave of the team has recorded this
+                // sample point as the stop step before publishing x_m; the
+                // state x_m and its sample are kept
+                if (m > g.seg_k0 && sample) {
+                    const int ts =
+                        __hip_atomic_load(tstop + team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (__builtin_amdgcn_readfirstlane(ts) == m) break;
+                }
+                // on the step before a sample point the first wave reads the
+                // request and records the decision; the release of its publish
+                // at the end of this step orders it before the step flag (here,
+                // not between the update and the publish, where a branch would
+                // split their schedule)
+                if (rb == 0 && m + 1 < g.seg_k1 && clk.is_sample(g, m + 1)) {
+                    const int c = __hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    if (__builtin_amdgcn_readfirstlane(c) != 0 && lane == 0)
+                        __hip_atomic_store(tstop + team, m + 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
         }
         // chunk exponents of this lane's column for every K block (device-scope
         // loads: no stale L1 lines)
@@ -892,12 +968,6 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
         for (int v = 0; v < 16; ++v) {
             sb_update(acc0[v], p, c0, dt, a0dt, gdt, xs0[v], ys0[v]);
             sb_update(acc1[v], p, c0, dt, a0dt, gdt, xs1[v], ys1[v]);
-        }
-        if (cancel && rb == 0 && m + 1 < g.seg_k1 && seg_is_sample(g, m + 1)) {
-            const int c = __hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            if (__builtin_amdgcn_readfirstlane(c) != 0 && lane == 0)
-                __hip_atomic_store(tstop + team, m + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // publish's release orders it before the step flag
         }
         if (m + 1 < g.seg_k1) publish(m + 1);
     }
@@ -1070,44 +1140,53 @@ constexpr int kBsbPre[] = {4, 2};
 // tile -1: the thermostat's kernel (operand read one K block ahead: the
 // registers of a further prefetch hold the thermostat's partials)
 template <int NKB>
-const void *dsb_ptr(int tile) {
+const void *dsb_ptr(int tile, bool cancel) {
+    if (cancel) switch (tile) {
+        case -1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, 1, true, true>);
+        case 1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[1], false, true>);
+        case 2: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[2], false, true>);
+        default: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[0], false, true>);
+        }
     switch (tile) {
-    case -1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, 1, true>);
-    case 1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[1], false>);
-    case 2: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[2], false>);
-    default: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[0], false>);
+    case -1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, 1, true, true>);
+    case 1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[1], false, false>);
+    case 2: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[2], false, false>);
+    default: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[0], false, false>);
     }
 }
 
-const void *pick_kernel(int nkb, int tile) {
+const void *pick_kernel(int nkb, int tile, bool cancel) {
     switch (nkb) {
-    case 4: return dsb_ptr<4>(tile);
-    case 8: return dsb_ptr<8>(tile);
-    case 12: return dsb_ptr<12>(tile);
-    case 16: return dsb_ptr<16>(tile);
-    case 20: return dsb_ptr<20>(tile);
-    case 24: return dsb_ptr<24>(tile);
-    case 28: return dsb_ptr<28>(tile);
-    default: return dsb_ptr<32>(tile);
+    case 4: return dsb_ptr<4>(tile, cancel);
+    case 8: return dsb_ptr<8>(tile, cancel);
+    case 12: return dsb_ptr<12>(tile, cancel);
+    case 16: return dsb_ptr<16>(tile, cancel);
+    case 20: return dsb_ptr<20>(tile, cancel);
+    case 24: return dsb_ptr<24>(tile, cancel);
+    case 28: return dsb_ptr<28>(tile, cancel);
+    default: return dsb_ptr<32>(tile, cancel);
     }
 }
 
 template <int NKB>
-const void *bsb_ptr(int tile) {
-    if (tile == 1) return reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[1]>);
-    return reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[0]>);
+const void *bsb_ptr(int tile, bool cancel) {
+    if (cancel)
+        return tile == 1 ? reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[1], true>)
+                         : reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[0], true>);
+    return tile == 1 ? reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[1], false>)
+                     : reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[0], false>);
 }
 
-const void *pick_bsb_kernel(int nkb, int tile) {
+const void *pick_bsb_kernel(int nkb, int tile, bool cancel) {
     switch (nkb) {
-    case 4: return bsb_ptr<4>(tile);
-    case 8: return bsb_ptr<8>(tile);
-    case 12: return bsb_ptr<12>(tile);
-    case 16: return bsb_ptr<16>(tile);
-    case 20: return bsb_ptr<20>(tile);
-    case 24: return bsb_ptr<24>(tile);
-    case 28: return bsb_ptr<28>(tile);
-    default: return bsb_ptr<32>(tile);
+    case 4: return bsb_ptr<4>(tile, cancel);
+    case 8: return bsb_ptr<8>(tile, cancel);
+    case 12: return bsb_ptr<12>(tile, cancel);
+    case 16: return bsb_ptr<16>(tile, cancel);
+    case 20: return bsb_ptr<20>(tile, cancel);
+    case 24: return bsb_ptr<24>(tile, cancel);
+    case 28: return bsb_ptr<28>(tile, cancel);
+    default: return bsb_ptr<32>(tile, cancel);
     }
 }
 
@@ -1249,13 +1328,14 @@ namespace {
 // Teams per launch and workgroups per team of a persistent launch: a multiple
 // of 8 teams (one slot per XCD) whose workgroups all fit on the device at once.
 // Waves hold 64 rows (bSB) or 32 rows (dSB); so do the energy partials.
-int launch_shape(bool bsb, int nkb, int tile, int *teams_per_launch, int *wpt, int *wg_capacity) {
+int launch_shape(bool bsb, int nkb, int tile, bool cancel, int *teams_per_launch, int *wpt,
+                 int *wg_capacity) {
     int dev = 0, ncu = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, bsb ? pick_bsb_kernel(nkb, tile) : pick_kernel(nkb, tile), 256, 0);
+            &nb, bsb ? pick_bsb_kernel(nkb, tile, cancel) : pick_kernel(nkb, tile, cancel), 256, 0);
     if (e != hipSuccess) return perr(HSB_EDEVICE, "FP4 path: %s", hipGetErrorString(e));
     const int nparts = bsb ? nkb : 2 * nkb;
     *wg_capacity = nb * ncu;
@@ -1289,7 +1369,8 @@ int run_segments(PersistentWork *pw, int variant, int nkb, int nteams_total, int
     if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
     const float a0dt = run.a0 * run.dt;
     const bool nh = run.nh != nullptr;
-    const void *kfn = bsb ? pick_bsb_kernel(nkb, run.tile) : pick_kernel(nkb, nh ? -1 : run.tile);
+    const void *kfn = bsb ? pick_bsb_kernel(nkb, run.tile, run.cancel != nullptr)
+                          : pick_kernel(nkb, nh ? -1 : run.tile, run.cancel != nullptr);
     FP4NH nhp{};
     if (nh) nhp = FP4NH{run.nh->xi, pw->ypart, run.nh->c, run.nh->NT};
     int a = run.k0;
@@ -1401,7 +1482,8 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     if (nteams_total * 32 > Rpad) return perr(HSB_EINVAL, "FP4 path: teams exceed the columns");
     int teams_per_launch = 0, wpt = 0, wg_capacity = 0;
     if (run.nh && bsb) return perr(HSB_EUNSUPPORTED, "FP4 path: no thermostat for bSB");
-    int rc = launch_shape(bsb, nkb, run.nh ? -1 : run.tile, &teams_per_launch, &wpt, &wg_capacity);
+    int rc = launch_shape(bsb, nkb, run.nh ? -1 : run.tile, run.cancel != nullptr, &teams_per_launch,
+                          &wpt, &wg_capacity);
     if (rc) return rc;
     const int nparts = bsb ? nrb : nchunk;
     const int interval = run.interval;
@@ -1512,7 +1594,8 @@ int persistent_run_in(void *scratch, size_t bytes, const PersistentJ *pj, const 
                       StateBufs &b, int Nrows, hipStream_t s) {
     const int nkb = pj->nkb, Rpad = run.Rpad, nteams = Rpad / 32;
     int teams_per_launch = 0, wpt = 0, wg_capacity = 0;
-    int rc = launch_shape(false, nkb, run.tile, &teams_per_launch, &wpt, &wg_capacity);
+    int rc = launch_shape(false, nkb, run.tile, run.cancel != nullptr, &teams_per_launch, &wpt,
+                          &wg_capacity);
     if (rc) return rc;
     const size_t nslots = (size_t)wg_capacity + 8 * (size_t)wpt;
     const int interval = run.interval;

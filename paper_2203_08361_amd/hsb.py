@@ -26,6 +26,7 @@ HSB_OPT_LOCAL_EXCHANGE = 8
 HSB_OPT_GRAPH = 9
 HSB_OPT_GRAPH_LAUNCHES = 10
 HSB_OPT_AUTOTUNE, HSB_OPT_TILE, HSB_OPT_LAST_TILE = 11, 12, 13
+HSB_OPT_CANCELLABLE = 14
 HSB_PLAN_FP32, HSB_PLAN_FP4, HSB_PLAN_DIGITS, HSB_PLAN_INCREMENTAL = 0, 1, 2, 3
 PLAN_NAMES = {HSB_PLAN_FP32: "fp32", HSB_PLAN_FP4: "fp4", HSB_PLAN_DIGITS: "digits",
               HSB_PLAN_INCREMENTAL: "incremental"}
@@ -367,7 +368,8 @@ class Context:
              "kernel_launches": HSB_OPT_KERNEL_LAUNCHES, "last_plan": HSB_OPT_LAST_PLAN,
              "local_exchange": HSB_OPT_LOCAL_EXCHANGE, "graph": HSB_OPT_GRAPH,
              "graph_launches": HSB_OPT_GRAPH_LAUNCHES, "autotune": HSB_OPT_AUTOTUNE,
-             "tile": HSB_OPT_TILE, "last_tile": HSB_OPT_LAST_TILE}
+             "tile": HSB_OPT_TILE, "last_tile": HSB_OPT_LAST_TILE,
+             "cancellable": HSB_OPT_CANCELLABLE}
     _PREC = {"auto": HSB_PREC_AUTO, "fp32": HSB_PREC_FP32, "mixed": HSB_PREC_MIXED,
              "digits": HSB_PREC_DIGITS, "incremental": HSB_PREC_INCREMENTAL}
 

@@ -1,4 +1,4 @@
-"""Cancellation (hsb_cancel, HSB_ECANCELED; marked `gpu`).
+"""Cancellation (hsb_cancel, HSB_ECANCELED, HSB_OPT_CANCELLABLE; marked `gpu`).
 
 A cancelled run stops at a sample point, and what it returns must be exactly
 what a run of that many steps returns (the same schedule): its state, its
@@ -47,13 +47,16 @@ def host(o):
     return {k: v.cpu().numpy() for k, v in o.items() if hasattr(v, "cpu")}
 
 
+@pytest.mark.parametrize("I", [100, 1])
 @pytest.mark.parametrize("variant,plan,expect", CASES)
-def test_request_before_the_run_stops_it_at_the_first_sample(variant, plan, expect):
-    N, R, Ns, I = 300, 64, 1000, 100
+def test_request_before_the_run_stops_it_at_the_first_sample(variant, plan, expect, I):
+    """I = 1 makes every step a sample point: the step that stops must not
+    also record a decision for the step after it."""
+    N, R, Ns = 300, 64, 1000
     J = synth.sk_instance(N, 77)
     c0 = 0.5 / np.sqrt(N)
-    say("cancel before run", variant, plan)
-    with hsb.Context(J, precision=plan, energy_interval=I) as ctx:
+    say("cancel before run", variant, plan, "interval", I)
+    with hsb.Context(J, precision=plan, energy_interval=I, cancellable=1) as ctx:
         ctx.cancel()
         o = ctx.run_ex(variant, Ns, R, 1.0, c0, 1.0, 0.02, 5, want_state=True, allow_cancel=True)
         torch.cuda.synchronize()
@@ -81,7 +84,7 @@ def test_cancelled_thermostat_run_and_noalloc_run():
     J = synth.sk_instance(N, 78)
     c0 = 0.5 / np.sqrt(N)
     say("cancel thermostat / noalloc")
-    with hsb.Context(J, precision="digits", energy_interval=I) as ctx:
+    with hsb.Context(J, precision="digits", energy_interval=I, cancellable=1) as ctx:
         ctx.cancel()
         o = ctx.run_ex(hsb.HSB_DSB, Ns, R, 1.0, c0, 1.0, 0.02, 5, want_state=True,
                        nose_hoover=(1e-4, 0.05), allow_cancel=True)
@@ -91,7 +94,7 @@ def test_cancelled_thermostat_run_and_noalloc_run():
         assert o["status"] == hsb.HSB_ECANCELED
         for k in KEYS + ("xi",):
             assert torch.equal(o[k], ref[k]), k
-    with hsb.Context(J, energy_interval=I) as ctx:
+    with hsb.Context(J, energy_interval=I, cancellable=1) as ctx:
         ctx.cancel()
         o = ctx.run_ex(hsb.HSB_DSB, Ns, R, 1.0, c0, 1.0, 0.02, 5, want_state=True, noalloc=True,
                        allow_cancel=True)
@@ -113,7 +116,7 @@ def test_request_during_the_run(plan, steps, wait):
     J = synth.sk_instance(N, 2000)
     c0 = 0.5 / np.sqrt(N)
     say("cancel during run", plan, steps)
-    with hsb.Context(J, precision=plan, energy_interval=I) as ctx:
+    with hsb.Context(J, precision=plan, energy_interval=I, cancellable=1) as ctx:
         result = {}
 
         def go():
@@ -145,3 +148,27 @@ def test_request_during_the_run(plan, steps, wait):
             sel = stops == m
             for k in KEYS:
                 assert np.array_equal(o[k][sel], ref[k][sel]), (m, k)
+
+
+def test_only_cancellable_contexts_take_requests():
+    """HSB_OPT_CANCELLABLE = 0 (the default): hsb_cancel is refused, and runs
+    of the context (which use the kernel variants without request checks)
+    equal those of a cancellable context that gets no request."""
+    N, R, Ns, I = 700, 64, 400, 100
+    J = synth.sk_instance(N, 79)
+    c0 = 0.5 / np.sqrt(N)
+    say("cancel refused without the option")
+    outs = []
+    for opt in (0, 1):
+        with hsb.Context(J, energy_interval=I, cancellable=opt) as ctx:
+            assert ctx.get_option("cancellable") == opt
+            if opt == 0:
+                with pytest.raises(hsb.HSBError) as e:
+                    ctx.cancel()
+                assert e.value.code == hsb.HSB_EINVAL
+            o = ctx.run_ex(hsb.HSB_DSB, Ns, R, 1.0, c0, 1.0, 0.02, 5, want_state=True)
+            torch.cuda.synchronize()
+            assert o["status"] == hsb.HSB_OK and ctx.last_plan() == "fp4"
+            outs.append(host(o))
+    for k in KEYS:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
