@@ -379,6 +379,7 @@ def main() -> int:
             for name, kw in (("heated", {}), ("nose_hoover", {"nose_hoover": nh})):
                 o = cd.run_ex(hsb.HSB_DSB, Ns, R, A0, c0, DT, GAMMA, 1, **kw)
                 buf = {k: v for k, v in o.items() if hasattr(v, "data_ptr")}
+                cd.run_ex(hsb.HSB_DSB, Ns, R, A0, c0, DT, GAMMA, 1, out=buf, **kw)  # the graph
                 torch.cuda.synchronize()
                 ts = []
                 for rep in range(reps):  # same buffers: repeated runs are graph launches

@@ -77,7 +77,7 @@ struct PersistentWork {
     size_t flags_n = 0;
     int32_t *tstop = nullptr;    // [nteams] stop step of each team (-1: running)
     size_t tstop_n = 0;
-    double *ypart = nullptr;     // thermostat: [2][nchunk / 4][Rpad] partial sums of y^2
+    uint64_t *ypart = nullptr;   // thermostat: [2][nchunk / 4][Rpad][2] tagged partials of y^2
     size_t ypart_n = 0;
 };
 
@@ -143,10 +143,11 @@ struct SegArgs {
 // The Nose-Hoover thermostat inside the persistent dSB kernel (eqs. (6)-(8)):
 // xi per replica ([Rpad], FP64: its value at the segment's first step in, at
 // its last out), the per-step partial sums of y^2 of every workgroup's 128
-// rows ([2 step parities][nchunk / 4][Rpad]), c = dt / M and N T.
+// rows as pairs of tagged words ([2 step parities][nchunk / 4][Rpad][2]:
+// (step << 32) | low and high halves of the FP64 partial), c = dt / M and N T.
 struct FP4NH {
     double *xi;
-    double *ypart;
+    uint64_t *ypart;
     double c, NT;
 };
 
@@ -211,10 +212,10 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     constexpr int NQ = NKB / 4;  // K blocks expanded by each wave
     __shared__ v4i a_lds[2][NKB][64];
     __shared__ int wg_abort;
-    // thermostat: each wave's y^2 partial of the current state (two step
-    // parities), and the eight half-waves' sums of the team's partials
+    // thermostat: each wave's y^2 partial of the current state, and the eight
+    // half-waves' sums of the team's partials (both by step parity)
     __shared__ double s_yw[NH ? 2 : 1][4][32];
-    __shared__ double s_ysum[NH ? 8 : 1][32];
+    __shared__ double s_ysum[NH ? 2 : 1][8][32];
     // thermostat: xi(t_k) of the workgroup's 32 replicas (every wave of the
     // team forms the same value; kept here rather than in registers)
     __shared__ double s_xi[NH ? 4 : 1][32];
@@ -318,14 +319,6 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
 #pragma unroll
         for (int v = 15; v >= 0; --v) b = __builtin_amdgcn_alignbit(b, __float_as_uint(xs[v]), 31);
         const uint32_t got = (uint32_t)__shfl_xor((int)b, 32);
-        if constexpr (NH) {  // wave 0 stored the workgroup's y^2 partial before its words
-            if (w == 0) {
-                if (xcd_local)
-                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                else
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            }
-        }
         const uint32_t word = b | (got << 16);
         const size_t slot = (size_t)rb * Rpad + rep;
         if constexpr (CANCEL) {
@@ -378,8 +371,72 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         // this wave's share: K block kb = w + 4q is chunk 2 kb + l/32
         const uint64_t *src = xb + ((size_t)buf * nchunk + 2 * w + half) * Rpad + r0 + l32;
         const float p = m < g.seg_k1 ? ptab[m - g.seg_k0] : 0.0f;  // issued early
+        // Thermostat: half-wave q = 2 w + half needs the partials of
+        // y(t_{m-1})^2 of workgroups q, q + 8 for xi(t_m).  Wave 0 of each
+        // workgroup stored them a step ago, as tagged word pairs; they are
+        // loaded here with the sign words and polled by their tags, and each
+        // half-wave's sum goes to LDS before the barrier below.
+        constexpr int WPT = NKB / 2;                 // workgroups of a team
+        constexpr int NPL = (WPT + 7) / 8;          // partials per half-wave
+        const bool nh_sum = NH && m > g.seg_k0;
+        uint64_t pw_lo[NPL], pw_hi[NPL];
+        auto part_slot = [&](int par, int wgi) {
+            return nhp.ypart + (((size_t)par * (nchunk / 4) + wgi) * Rpad + rep) * 2;
+        };
+        if constexpr (NH) {
+            if (nh_sum) {
+#pragma unroll
+                for (int q = 0; q < NPL; ++q) {
+                    const int src_wg = 2 * w + half + 8 * q;
+                    pw_lo[q] = pw_hi[q] = (uint64_t)(uint32_t)(m - 1) << 32;  // absent: zero
+                    if (src_wg < nchunk / 4) {
+                        const uint64_t *ps = part_slot((m - 1) & 1, src_wg);
+                        pw_lo[q] = ld_tagged(ps);
+                        pw_hi[q] = ld_tagged(ps + 1);
+                    }
+                }
+            }
+        }
         uint64_t wv[NQ];
-        if (gather_words<NQ>(wv, src, (size_t)8 * Rpad, NQ, (uint32_t)m, err)) {
+        bool ok = gather_words<NQ>(wv, src, (size_t)8 * Rpad, NQ, (uint32_t)m, err);
+        if constexpr (NH) {
+            if (nh_sum && ok) {
+                const uint32_t want = (uint32_t)(m - 1);
+                const uint64_t t0 = wall_clock64();
+                for (int it = 0;; ++it) {
+                    bool stale = false;
+#pragma unroll
+                    for (int q = 0; q < NPL; ++q)
+                        stale = stale || (uint32_t)(pw_lo[q] >> 32) != want ||
+                                (uint32_t)(pw_hi[q] >> 32) != want;
+                    if (!__any(stale)) break;
+                    if ((it & 31) == 31 &&
+                        (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                         wall_clock64() - t0 > kTimeoutTicks)) {
+                        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                    for (int q = 0; q < NPL; ++q) {
+                        const int src_wg = 2 * w + half + 8 * q;
+                        if (src_wg < nchunk / 4) {
+                            const uint64_t *ps = part_slot((m - 1) & 1, src_wg);
+                            pw_lo[q] = ld_tagged(ps);
+                            pw_hi[q] = ld_tagged(ps + 1);
+                        }
+                    }
+                }
+                double gs = 0.0;
+#pragma unroll
+                for (int q = 0; q < NPL; ++q)
+                    gs += __longlong_as_double(
+                        (long long)(((pw_hi[q] & 0xFFFFFFFFull) << 32) | (pw_lo[q] & 0xFFFFFFFFull)));
+                s_ysum[m & 1][2 * w + half][l32] = gs;
+            }
+        }
+        if (ok) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
                 a_lds[buf][w + 4 * q][lane] = expand_signs_fast((uint32_t)wv[q], 0x88888888u, 0x22222222u);
@@ -389,40 +446,35 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         }
         __syncthreads();
         if (wg_abort) break;
-        // Thermostat.  Wave 0 stores the workgroup's partial of y(t_m)^2 (the
-        // four waves' in a fixed order); it publishes x_{m+1} only after that
-        // store.  The team's partials of y(t_{m-1})^2 are all in (x_m is), and
-        // half-wave q = 2 w + half loads those of workgroups q, q + 8 (they
-        // arrive during the products).
-        constexpr int WPT = NKB / 2;                 // workgroups of a team
-        constexpr int NPL = (WPT + 7) / 8;          // partials per half-wave
-        double pl[NPL];
+        // Thermostat: wave 0 stores the workgroup's partial of y(t_m)^2 (the
+        // four waves' in a fixed order) as a tagged word pair for step m + 1
         if constexpr (NH) {
-            const int wg = kx % wpt, nwg = nchunk / 4;
             if (w == 0 && half == 0) {
                 const double wsum = ((s_yw[m & 1][0][l32] + s_yw[m & 1][1][l32]) +
                                      s_yw[m & 1][2][l32]) + s_yw[m & 1][3][l32];
-                uint64_t *dst = reinterpret_cast<uint64_t *>(
-                    nhp.ypart + ((size_t)(m & 1) * nwg + wg) * Rpad + rep);
                 const uint64_t bits = (uint64_t)__double_as_longlong(wsum);
-                if (xcd_local)
-                    __hip_atomic_store(dst, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                else
-                    __hip_atomic_store(dst, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (m > g.seg_k0) {
-                if (!xcd_local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                const int q0 = 2 * w + half;
-#pragma unroll
-                for (int q = 0; q < NPL; ++q) {
-                    const int src_wg = q0 + 8 * q;
-                    pl[q] = 0.0;
-                    if (src_wg < nwg)
-                        pl[q] = __longlong_as_double((long long)__hip_atomic_load(
-                            reinterpret_cast<const uint64_t *>(
-                                nhp.ypart + ((size_t)((m - 1) & 1) * nwg + src_wg) * Rpad + rep),
-                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                const uint64_t tag = (uint64_t)(uint32_t)m << 32;
+                uint64_t *dst = part_slot(m & 1, kx % wpt);
+                if (xcd_local) {
+                    st_tagged_xcd(dst, tag | (bits & 0xFFFFFFFFull));
+                    st_tagged_xcd(dst + 1, tag | (bits >> 32));
+                } else {
+                    st_tagged(dst, tag | (bits & 0xFFFFFFFFull));
+                    st_tagged(dst + 1, tag | (bits >> 32));
                 }
+            }
+        }
+        if constexpr (NH) {
+            // xi(t_m) = xi(t_{m-1}) + (dt/M)(sum_i y_i(t_{m-1})^2 - N T): the eight
+            // half-wave sums (in LDS since the barrier) in a fixed order, the
+            // same in every wave of the team; formed before the products, so
+            // that only its use remains for the update after them
+            if (m > g.seg_k0) {
+                double S = 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) S += s_ysum[m & 1][q][l32];
+                const double xi_k = s_xi[w][l32] + nhp.c * (S - nhp.NT);
+                if (half == 0) s_xi[w][l32] = xi_k;
             }
         }
         v16f acc;
@@ -447,22 +499,6 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         }
         mfma_drain(acc);
         __builtin_amdgcn_s_setprio(3);
-        if constexpr (NH) {
-            // xi(t_m) = xi(t_{m-1}) + (dt/M)(sum_i y_i(t_{m-1})^2 - N T): the eight
-            // half-wave sums in a fixed order, the same in every wave of the team
-            if (m > g.seg_k0) {
-                double gs = 0.0;
-#pragma unroll
-                for (int q = 0; q < NPL; ++q) gs += pl[q];
-                s_ysum[2 * w + half][l32] = gs;
-                __syncthreads();
-                double S = 0.0;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) S += s_ysum[q][l32];
-                const double xi_k = s_xi[w][l32] + nhp.c * (S - nhp.NT);
-                if (half == 0) s_xi[w][l32] = xi_k;
-            }
-        }
         if (is_sample(m)) {
             // eq. (1) partial over this wave's 32 rows of s_i f_i (exact integers/halves)
             const int j = sample_index(m);
@@ -510,8 +546,10 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
             xs[v] = x;
             ys[v] = y;
         }
-        y2_partial(m + 1);
         publish(m + 1, next_sample, sample_index(m + 1));
+        // after the publish, off the team's path: wave 0 reads it after the
+        // next barrier
+        y2_partial(m + 1);
     }
     // write the state back
 #pragma unroll
@@ -1142,13 +1180,13 @@ constexpr int kBsbPre[] = {4, 2};
 template <int NKB>
 const void *dsb_ptr(int tile, bool cancel) {
     if (cancel) switch (tile) {
-        case -1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, 1, true, true>);
+        case -1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, 2, true, true>);
         case 1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[1], false, true>);
         case 2: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[2], false, true>);
         default: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[0], false, true>);
         }
     switch (tile) {
-    case -1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, 1, true, true>);
+    case -1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, 2, true, true>);
     case 1: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[1], false, false>);
     case 2: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[2], false, false>);
     default: return reinterpret_cast<const void *>(&k_dsb_fp4<NKB, kDsbPre[0], false, false>);
@@ -1401,6 +1439,11 @@ int run_segments(PersistentWork *pw, int variant, int nkb, int nteams_total, int
                 const size_t nxb = (size_t)2 * nchunk * Rpad;
                 hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((nxb + 255) / 256)), dim3(256), 0,
                                    s, pw->xb, nxb);
+                if (nh) {  // no thermostat partial of an earlier launch carries a live tag
+                    const size_t np = (size_t)4 * (nchunk / 4) * Rpad;
+                    hipLaunchKernelGGL(k_fill_tags, dim3((unsigned)((np + 255) / 256)), dim3(256), 0,
+                                       s, pw->ypart, np);
+                }
             }
             // block b -> team (b/8)/wpt*8 + b%8: round the team count up to 8
             const dim3 grid((unsigned)(8 * ((nt + 7) / 8) * wpt)), block(256);
@@ -1521,7 +1564,7 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     if (!rc && bsb) rc = grow(&pw->xe, &pw->xe_n, (size_t)2 * 2 * Rpad * nkb);
     if (!rc && bsb) rc = grow(&pw->flags, &pw->flags_n, (size_t)nteams_total * nrb);
     if (!rc) rc = grow(&pw->tstop, &pw->tstop_n, (size_t)nteams_total);
-    if (!rc && run.nh) rc = grow(&pw->ypart, &pw->ypart_n, (size_t)2 * (nchunk / 4) * Rpad);
+    if (!rc && run.nh) rc = grow(&pw->ypart, &pw->ypart_n, (size_t)4 * (nchunk / 4) * Rpad);
     if (!rc && !pw->epoch) {
         rc = grow(&pw->epoch, &pw->epoch_n, 1);
         if (!rc) {
