@@ -403,6 +403,39 @@ def main() -> int:
                 "overhead": main["overhead"], "xi_final_range": main["xi_final_range"],
                 "per_plan": res}
 
+    def incremental_late_workload():
+        """The incremental dSB field (the exact int32 field, changed by the
+        spins that flipped) on the last 2000 of the 10^4 steps, from the state
+        the FP4 plan reached at step 8000, against the FP4 plan on the same
+        steps: the results are equal bit for bit, and the time says whether
+        the late schedule's few flips pay."""
+        k0 = 8000
+        cf = hsb.Context(J, precision=args.plan, init_amp=0.1, energy_interval=100)
+        head = cf.run_ex(hsb.HSB_DSB, k0, R, A0, c0, DT, GAMMA, 1, want_state=True,
+                         schedule_steps=Ns)
+        x8 = head["x"].float().cpu().numpy()
+        res = {}
+        for name, prec in (("fp4", args.plan), ("incremental", "incremental")):
+            cf.set_option("precision", prec)
+            kw = dict(want_state=True, x0=head["x"], y0=head["y"], start_step=k0,
+                      schedule_steps=Ns)
+            cf.run_ex(hsb.HSB_DSB, Ns - k0, R, A0, c0, DT, GAMMA, 1, **kw)  # allocation, warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = cf.run_ex(hsb.HSB_DSB, Ns - k0, R, A0, c0, DT, GAMMA, 1, **kw)
+            torch.cuda.synchronize()
+            res[name] = (1e3 * (time.perf_counter() - t0), cf.last_plan(), o)
+        cf.close()
+        a, b = res["fp4"][2], res["incremental"][2]
+        same = all(torch.equal(a[k], b[k]) for k in ("x", "y", "spins", "best_energy", "best_step"))
+        flipped = float(np.mean(np.signbit(x8) != np.signbit(a["x"].cpu().numpy())))
+        return {"workload": f"SK +-1 N={N}, R={R}: steps {k0}..{Ns} of a {Ns}-step heated dSB "
+                            f"run, resumed from the FP4 plan's state at step {k0}",
+                "ms_fp4": res["fp4"][0], "plan_fp4": res["fp4"][1],
+                "ms_incremental": res["incremental"][0], "plan_incremental": res["incremental"][1],
+                "identical": bool(same), "speedup_incremental": res["fp4"][0] / res["incremental"][0],
+                "spins_differing_between_steps_8000_and_10000": flipped}
+
     def evaluation_workload():
         # the 700-spin comparison of the Results: 100 instances, the energy at
         # the last step, the four forms at the paper's parameters over a range
@@ -517,6 +550,7 @@ def main() -> int:
         result["batch"] = batch_workload()
     if args.variant == "dsb" and not args.no_thermostat:
         result["thermostat"] = thermostat_workload()
+        result["incremental_late"] = incremental_late_workload()
     if args.variant == "dsb" and not args.no_evaluation:
         result["evaluation"] = evaluation_workload()
         result["k2000"] = k2000_workload()
