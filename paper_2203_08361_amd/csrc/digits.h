@@ -31,9 +31,11 @@ void i8_free(I8J *p);
 const char *i8_error();
 bool i8_exact(const I8J *p);  // J held exactly (one digit)
 int i8_max_n();
-// Number of result-invariant variants of the step kernel (the autotuner's
-// candidates; 0 is the default): 32-row or 64-row waves.
-int i8_tiles();
+// Number of result-invariant kernel variants (the autotuner's candidates; 0
+// is the default): 0, 1 = the persistent kernel with the default or the
+// other wave height (32 or 64 rows), 2, 3 = one launch per step with those
+// heights; with the thermostat only the per-step kernel (0, 1: the heights).
+int i8_tiles(bool thermostat);
 
 struct I8Run {
     int variant;          // HSB_BSB / HSB_DSB
@@ -42,12 +44,17 @@ struct I8Run {
     int k0, k1, Ns, interval;
     float a0, c0, dt;
     const NHState *nh = nullptr;  // Nose-Hoover thermostat: rate -xi(t_k) per step
-    int tile = 0;  // 0: the default wave height of the digit combination, 1: the other
+    int tile = 0;  // kernel variant, 0 .. i8_tiles(nh != nullptr) - 1
     const int32_t *cancel = nullptr;  // cancel request polled after each sample (b.stop set)
+    int local_exchange = 1;  // 0: device-scope exchange in the persistent kernel even for
+                             // XCD-local teams
 };
 
 // Run steps k0..k1-1 of the digit plan on the state in `b` (X, Y in
 // [Nst][Rpad]); samples energies at the sample points (as the FP32 plan).
+// Without the thermostat the steps between two sample points run in one
+// persistent launch that keeps the state on chip (when its teams of
+// workgroups fit one XCD: N <= 8192), else one launch per step.
 // `fp32J` is the FP32 J store ([Nst][Nst]) used for FP64 energies of real J.
 int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream_t s,
            KernelTimer &timer);

@@ -45,6 +45,13 @@ struct I8J {
     size_t xd_bytes = 0;
     int8_t *sd = nullptr;        // [Npad/16][Rpad][16] sign digits of sampled states
     size_t sd_bytes = 0;
+    // persistent kernel: placement slots and step flags, p_k of a segment, error word
+    uint32_t *sync = nullptr;
+    size_t sync_n = 0;
+    float *ptab = nullptr;
+    size_t ptab_n = 0;
+    int32_t *err = nullptr;
+    size_t err_n = 0;
 };
 
 namespace {
@@ -344,6 +351,327 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_field(
         }
 }
 
+// ------------------------------------------------------- persistent step kernel
+//
+// The same step as k_i8_field (no thermostat) for a whole segment of steps
+// between two sample points in one launch.  A team of workgroups owns one
+// 32-replica block: workgroup k of the team computes spins [128 NT k,
+// 128 NT (k + 1)) of those replicas, as in k_i8_field, and keeps its part of
+// x and y in registers for the whole segment.  The x digits of each step go
+// through the ping-pong digit buffers (the layout k_i8_field reads), and each
+// wave sets its step flag once its digits are stored; before a step's
+// products every wave waits for the flags of its team.  The digits of step m
+// + 1 overwrite those of step m - 1: their writer has seen every flag of
+// step m, set only after the step-(m - 1) products that read them.
+//   The team's workgroups are placed on one XCD (block b runs on XCD b % 8;
+// team t takes blocks 8 (wpt floor(t / 8) + k) + t % 8), and at start-up
+// each one records its XCD id and reads its teammates'.  When they share an
+// XCD the digits and flags only have to reach its L2: stores are waited for
+// (vmcnt) before the flag, and the readers' loads bypass the L1 (device
+// scope).  Otherwise a device-scope release and acquire order them.  Every
+// wait is bounded (4 s); a timeout sets the run's error word and bit 1 of its
+// status, and every wave then leaves.  The host launches at most as many
+// workgroups as are resident at once and clears the flags and the placement
+// slots before every launch.
+
+constexpr uint64_t kI8TimeoutTicks = 400000000ull;  // 4 s of the 100 MHz wall clock
+constexpr uint32_t kI8NoFlag = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t i8_flag_ld(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int i8_xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20); }
+
+// 16 bytes per lane from global memory (wave-uniform base plus the lane's
+// 32-bit byte offset) straight into LDS at lds_base + 16 lane, device scope
+// (the L1 is bypassed).  Assembly, so that the compiler does not track it:
+// the caller waits for it (vmcnt(0)) and synchronises the workgroup before
+// any wave reads the bytes; the compiler's own vmcnt waits for its tracked
+// loads only get stricter from it.
+__device__ __forceinline__ void i8_lds_direct16(const void *base, uint32_t lane_off,
+                                                uint32_t lds_base) {
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1 sc1"
+                 :
+                 : "v"(lane_off), "s"(base), "s"(lds_base)
+                 : "memory", "m0");
+}
+
+template <int NJD, int NXD, int KC, int NT>
+__global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_persist(
+    const v4i *__restrict__ jd, const double *__restrict__ rowscale, int8_t *xd,
+    uint32_t *sync, float *__restrict__ X, float *__restrict__ Y, const float *__restrict__ gam,
+    const float *__restrict__ ptab, int32_t *__restrict__ status, int32_t *err,
+    const int32_t *__restrict__ stop, int local_ok, int Nst, int Npad, int Rpad, int team0,
+    int nteams, int k0, int k1, float c0, float dt, float a0dt) {
+    constexpr int NW = (NJD + NXD - 1) < 4 ? (NJD + NXD - 1) : 4;
+    constexpr int KB = 2 * KC;
+    constexpr int BTOT = NXD * KB * 32;
+    constexpr int BPT = (BTOT + 255) / 256;
+    constexpr double kXs = NXD == 4 ? 0x1p-30 : 1.0;
+    constexpr double kTrunc = (NJD + NXD - 1 - NW) == 3 ? 0x1p24 : 1.0;
+    static_assert(BTOT % 64 == 0 && KB % 2 == 0, "a wave stages whole pairs of K blocks");
+    __shared__ v4i bs[2][NXD][KB][32];
+    // the workgroup's x and y between steps (item v of thread t at [v][t]):
+    // in LDS rather than registers, which the products need
+    __shared__ float s_x[NT * 16][256], s_y[NT * 16][256];
+    __shared__ int wg_abort;
+    // a run stopped by a cancel request at an earlier sample point
+    if (stop && __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, l32 = lane & 31;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const int wpt = Npad / (128 * NT);  // workgroups of a team
+    const int nwt = 4 * wpt;            // waves of a team (<= 256)
+    const int xcd = blockIdx.x & 7, kx = blockIdx.x >> 3;
+    const int tl = (kx / wpt) * 8 + xcd;
+    if (tl >= nteams) return;  // whole workgroup
+    const int team = team0 + tl;
+    const int sbk = kx % wpt;
+    const int i0 = sbk * (128 * NT) + w * (32 * NT), r0 = team * 32;
+    const int r = r0 + l32;
+    const int nkb = Npad / 16;
+    const int S = Npad / (32 * KC);
+    uint32_t *slots = sync;                                 // [gridDim.x]
+    uint32_t *flags = sync + gridDim.x + (size_t)tl * nwt;  // this team's
+    uint32_t *myflag = flags + sbk * 4 + wu;
+    const size_t set = (size_t)NXD * nkb * Rpad * 16;  // bytes of one digit set
+    if (t == 0) wg_abort = 0;
+
+    // do all workgroups of this team share one XCD?
+    const int my_xcc = i8_xcc_id();
+    if (t == 0) __hip_atomic_store(slots + blockIdx.x, (uint32_t)my_xcc, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    bool xcd_local;
+    {
+        const int mb = 8 * (wpt * (tl >> 3) + (lane < wpt ? lane : 0)) + (tl & 7);
+        uint32_t v = i8_flag_ld(slots + mb);
+        const uint64_t ts = wall_clock64();
+        bool ok = true;
+        while (__any(v == kI8NoFlag)) {
+            __builtin_amdgcn_s_sleep(1);
+            v = i8_flag_ld(slots + mb);
+            if (wall_clock64() - ts > kI8TimeoutTicks) {
+                ok = false;
+                break;
+            }
+        }
+        xcd_local = local_ok && ok && __all(v == (uint32_t)my_xcc);
+    }
+
+    const bool live = i0 < Nst;  // Nst is a multiple of 64: a wave's rows are wholly in or out
+    auto row_of = [&](int tt, int v) { return i0 + tt * 32 + 8 * (v >> 2) + 4 * h + (v & 3); };
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const size_t idx = (size_t)row_of(tt, v) * Rpad + r;
+            s_x[tt * 16 + v][t] = live ? X[idx] : 0.0f;
+            s_y[tt * 16 + v][t] = live ? Y[idx] : 0.0f;
+        }
+    const float gdt = gam[r] * dt;
+
+    // digits of four consecutive spins (items 4q .. 4q + 3 of tile tt) of x_m
+    // into set m & 1
+    auto put_digits = [&](int m, int tt, int q, const float (&x4)[4]) {
+        int8_t *xo = xd + (size_t)(m & 1) * set;
+        uint32_t dw[NXD];
+#pragma unroll
+        for (int b = 0; b < NXD; ++b) dw[b] = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (NXD == 1) {
+                dw[0] |= (uint32_t)(uint8_t)(x4[u] >= 0.0f ? 1 : -1) << (8 * u);
+            } else {
+                int d[4];
+                split4(x_fixed(x4[u]), d);
+#pragma unroll
+                for (int b = 0; b < NXD; ++b) dw[b] |= (uint32_t)(uint8_t)d[b] << (8 * u);
+            }
+        }
+        const int ig = i0 + tt * 32 + 8 * q + 4 * h;
+#pragma unroll
+        for (int b = 0; b < NXD; ++b)
+            *reinterpret_cast<uint32_t *>(
+                xo + (((size_t)b * nkb + (ig >> 4)) * Rpad + r) * 16 + (ig & 15)) = dw[b];
+    };
+    // this wave's digits of x_m are stored: its flag
+    auto set_flag = [&](int m) {
+        if (xcd_local) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (lane == 0)
+                __hip_atomic_store(myflag, (uint32_t)m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0)
+                __hip_atomic_store(myflag, (uint32_t)m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    };
+    // every wave of the team has published x_m (its flag is m, or already m + 1)
+    auto wait_team = [&](int m) -> bool {
+        uint32_t f[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            f[j] = lane + 64 * j < nwt ? i8_flag_ld(flags + lane + 64 * j) : (uint32_t)m;
+        const uint64_t ts = wall_clock64();
+        for (int it = 1;; ++it) {
+            bool stale = false;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) stale = stale || (f[j] - (uint32_t)m) > 1u;
+            if (!__any(stale)) break;
+            if ((it & 31) == 0 &&
+                (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                 wall_clock64() - ts > kI8TimeoutTicks)) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_or(status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (lane + 64 * j < nwt) f[j] = i8_flag_ld(flags + lane + 64 * j);
+        }
+        if (!xcd_local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        return true;
+    };
+
+    v16i acc[NT][NW];
+    v4i a0r[NT][NJD][KC], a1r[NT][NJD][KC];
+    auto loadA = [&](int s, v4i(&dst)[NT][NJD][KC]) {
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int a = 0; a < NJD; ++a)
+#pragma unroll
+                for (int c = 0; c < KC; ++c)
+                    dst[tt][a][c] =
+                        jd[((size_t)a * nkb + s * KB + 2 * c + h) * Npad + i0 + tt * 32 + l32];
+    };
+    // stage s of the x digits of the current set into LDS buffer buf: records
+    // e = 256 q + 64 w + lane (digit b, K block kb of the stage, replica e % 32)
+    auto stageB = [&](const int8_t *xin, int s, int buf) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int e0 = 256 * q + 64 * wu;
+            if (BTOT % 256 == 0 || e0 < BTOT) {
+                const int b = e0 / (KB * 32), kb = (e0 / 32) % KB;  // lanes 32-63: kb + 1
+                const int8_t *base = xin + (((size_t)b * nkb + s * KB + kb) * Rpad + r0) * 16;
+                const uint32_t off = (uint32_t)h * (uint32_t)Rpad * 16u + (uint32_t)l32 * 16u;
+                i8_lds_direct16(base, off,
+                                (uint32_t)(uintptr_t)(__attribute__((address_space(3))) void *)&bs[buf][b][kb][0]);
+            }
+        }
+    };
+    auto compute = [&](int buf, const v4i(&A)[NT][NJD][KC]) {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            v4i bf[NXD];
+#pragma unroll
+            for (int b = 0; b < NXD; ++b) bf[b] = bs[buf][b][2 * c + h][l32];
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+                for (int a = 0; a < NJD; ++a)
+#pragma unroll
+                    for (int b = 0; b < NXD; ++b)
+                        if (a + b < NW)
+                            acc[tt][a + b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                A[tt][a][c], bf[b], acc[tt][a + b], 0, 0, 0);
+        }
+    };
+
+    // the digits of the segment's first state
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float x4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x4[u] = s_x[tt * 16 + 4 * q + u][t];
+            put_digits(k0, tt, q, x4);
+        }
+    set_flag(k0);
+    for (int m = k0; m < k1; ++m) {
+        const float p = ptab[m - k0];
+        const int8_t *xin = xd + (size_t)(m & 1) * set;
+        if (!wait_team(m)) wg_abort = 1;
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int q = 0; q < NW; ++q) acc[tt][q] = v16i{};
+        loadA(0, a0r);
+        stageB(xin, 0, 0);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();  // also publishes wg_abort
+        if (wg_abort) break;
+        for (int s = 0; s < S; s += 2) {
+            loadA(s + 1, a1r);
+            stageB(xin, s + 1, 1);
+            compute(0, a0r);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            const bool more = s + 2 < S;
+            if (more) {
+                loadA(s + 2, a0r);
+                stageB(xin, s + 2, 0);
+            }
+            compute(1, a1r);
+            if (more) {
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+            }
+        }
+        // the field, exactly rounded once, the update (as k_i8_field) and the
+        // digits of x_{m+1}
+        const bool pub = m + 1 < k1;
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float x4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int v = 4 * q + u;
+                    const int i = row_of(tt, v);
+                    double Tsum = (double)acc[tt][0][v];
+#pragma unroll
+                    for (int k = 1; k < NW; ++k) Tsum = Tsum * 256.0 + (double)acc[tt][k][v];
+                    const double sc = (NJD == 1 ? 1.0 : rowscale[i]) * (kXs * kTrunc);
+                    const float f = (float)(Tsum * sc);
+                    float x = s_x[tt * 16 + v][t], y = s_y[tt * 16 + v][t];
+                    sb_update(f, p, c0, dt, a0dt, gdt, x, y);
+                    s_x[tt * 16 + v][t] = x;
+                    s_y[tt * 16 + v][t] = y;
+                    x4[u] = x;
+                }
+                if (pub) put_digits(m + 1, tt, q, x4);
+            }
+        if (pub) set_flag(m + 1);
+    }
+    if (live) {
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const size_t idx = (size_t)row_of(tt, v) * Rpad + r;
+                X[idx] = s_x[tt * 16 + v][t];
+                Y[idx] = s_y[tt * 16 + v][t];
+            }
+    }
+}
+
+__global__ void k_i8_fill_u32(uint32_t *p, size_t n, uint32_t v) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
+// p_k = a0 - (a0 k) / Ns of the steps k0 .. k0 + n - 1, with the host loop's
+// single-precision operations and rounding
+__global__ void k_i8_ptab(float *ptab, int k0, int n, float a0, float Ns_f) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ptab[i] = __fsub_rn(a0, __fdiv_rn(__fmul_rn(a0, (float)(k0 + i)), Ns_f));
+}
+
 // ------------------------------------------------------------------- host
 
 namespace {
@@ -405,9 +733,35 @@ hipError_t launch_step(int nt, const I8J *p, const int8_t *xin, int8_t *xout, St
                                                     nhf);
 }
 
+// The persistent kernel of a digit combination and wave height.
+template <int NJD, int NXD, int KC>
+const void *persist_fn(int nt) {
+    return nt == 1 ? reinterpret_cast<const void *>(k_i8_persist<NJD, NXD, KC, 1>)
+                   : reinterpret_cast<const void *>(k_i8_persist<NJD, NXD, KC, 2>);
+}
+
+const void *persist_kernel(int njd, int nxd, int nt) {
+    if (njd == 1) return nxd == 4 ? persist_fn<1, 4, 4>(nt) : persist_fn<1, 1, 4>(nt);
+    return nxd == 4 ? persist_fn<4, 4, 2>(nt) : persist_fn<4, 1, 2>(nt);
+}
+
+// Teams (32-replica blocks) per launch of the persistent kernel: a multiple of
+// 8 that keeps every workgroup of the grid resident at once; 0 when the plan
+// cannot run persistently (a team larger than one XCD's share of the chip).
+int persist_teams_per_launch(const void *fn, int wpt) {
+    if (wpt > 64) return 0;  // one lane per teammate in the placement check
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess)
+        return 0;
+    const int cap = ncu * per_cu;
+    return 8 * (cap / (8 * wpt));
+}
+
 }  // namespace
 
-int i8_tiles() { return 2; }
+int i8_tiles(bool thermostat) { return thermostat ? 2 : 4; }
 
 int i8_create(const float *hJ, int N, I8J **out) {
     *out = nullptr;
@@ -464,7 +818,7 @@ int i8_create(const float *hJ, int N, I8J **out) {
 
 void i8_free(I8J *p) {
     if (!p) return;
-    void *ptrs[] = {p->jd, p->rowscale, p->xd, p->sd};
+    void *ptrs[] = {p->jd, p->rowscale, p->xd, p->sd, p->sync, p->ptab, p->err};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -517,9 +871,71 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
     };
     if (k1 == k0) return sample(k0);
     // 32-row tiles per wave: the default of the digit combination, or the
-    // other height (tile 1)
+    // other height (odd tiles).  Without the thermostat tiles 0 and 1 run the
+    // persistent kernel, 2 and 3 one launch per step (the same results).
     const int nt_def = tiles_per_wave(p->njd, bsb ? 4 : 1, false);
-    const int nt = run.tile == 1 ? 3 - nt_def : nt_def;
+    const int nt = (run.tile & 1) ? 3 - nt_def : nt_def;
+    if (!run.nh && run.tile < 2) {
+        const void *fn = persist_kernel(p->njd, nxd, nt);
+        const int wpt = Np / (128 * nt), nwt = 4 * wpt;
+        const int tpl = persist_teams_per_launch(fn, wpt);
+        const int nteams = Rpad / 32;
+        if (tpl >= 8) {
+            const int tpl_run = nteams < tpl ? 8 * ((nteams + 7) / 8) : tpl;
+            const size_t nsync = (size_t)8 * wpt * (tpl_run / 8) + (size_t)tpl_run * nwt;
+            const long long seg_max = (long long)(k1 - k0) < interval ? (k1 - k0) : interval;
+            rc = grow(&p->sync, &p->sync_n, nsync);
+            if (!rc) rc = grow(&p->ptab, &p->ptab_n, (size_t)seg_max);
+            if (!rc) rc = grow(&p->err, &p->err_n, (size_t)1);
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_i8_fill_u32, dim3(1), dim3(1), 0, s,
+                               reinterpret_cast<uint32_t *>(p->err), (size_t)1, 0u);
+            int local_ok = run.local_exchange ? 1 : 0;
+            const float a0dt_v = a0dt;
+            for (int a = k0; a < k1;) {
+                // segment [a, e): up to the next sample point
+                const long long nxt = ((long long)a / interval + 1) * interval;
+                const int e_k = nxt < k1 ? (int)nxt : k1;
+                hipLaunchKernelGGL(k_i8_ptab, dim3((unsigned)((e_k - a + 255) / 256)), dim3(256), 0,
+                                   s, p->ptab, a, e_k - a, a0, (float)run.Ns);
+                e = timer.begin(s);
+                size_t nl = 0;
+                for (int t0 = 0; t0 < nteams && e == hipSuccess; t0 += tpl) {
+                    const int ntm = nteams - t0 < tpl ? nteams - t0 : tpl;
+                    const dim3 grid((unsigned)(8 * ((ntm + 7) / 8) * wpt));
+                    const size_t nfill = (size_t)grid.x + (size_t)ntm * nwt;
+                    hipLaunchKernelGGL(k_i8_fill_u32, dim3((unsigned)((nfill + 255) / 256)),
+                                       dim3(256), 0, s, p->sync, nfill, kI8NoFlag);
+                    int Nst_v = Nst, Np_v = Np, Rpad_v = Rpad, t0_v = t0, ntm_v = ntm, a_v = a,
+                        e_v = e_k;
+                    float c0_v = c0, dt_v = dt;
+                    const int32_t *stop = b.stop;
+                    void *args[] = {(void *)&p->jd,    (void *)&p->rowscale, (void *)&p->xd,
+                                    (void *)&p->sync,  (void *)&b.X,         (void *)&b.Y,
+                                    (void *)&b.gamma,  (void *)&p->ptab,     (void *)&b.status,
+                                    (void *)&p->err,   (void *)&stop,        (void *)&local_ok,
+                                    (void *)&Nst_v,    (void *)&Np_v,        (void *)&Rpad_v,
+                                    (void *)&t0_v,     (void *)&ntm_v,       (void *)&a_v,
+                                    (void *)&e_v,      (void *)&c0_v,        (void *)&dt_v,
+                                    (void *)&a0dt_v};
+                    // every workgroup of the grid is resident at once (the grid
+                    // never exceeds the occupancy-derived capacity), and every
+                    // wait inside the kernel is bounded
+                    e = hipLaunchKernel(fn, grid, dim3(256), args, 0, s);
+                    ++nl;
+                }
+                if (e == hipSuccess) e = timer.end(s, nl);
+                if (e != hipSuccess)
+                    return derr(HSB_EDEVICE, "digit persistent launch: %s", hipGetErrorString(e));
+                if (is_sample(e_k)) {
+                    rc = sample(e_k);
+                    if (rc) return rc;
+                }
+                a = e_k;
+            }
+            return HSB_OK;
+        }
+    }
     // per-wave partials of the thermostat's sum (32 or 64 rows)
     const int nh_parts = Nst / (32 * nt);
     int cur = 0;

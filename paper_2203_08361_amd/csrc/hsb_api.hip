@@ -596,6 +596,7 @@ int enqueue_run(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s, int
         ir.nh = nh ? &h->nh : nullptr;
         ir.tile = tile;
         ir.cancel = cancel;
+        ir.local_exchange = h->local_exchange;
         rc = hsb::i8_run(h->i8, ir, b, h->dJ, s, h->timer);
         if (rc != HSB_OK) return fail(rc, "%s", hsb::i8_error());
     } else if (plan == PLAN_INCREMENTAL) {
@@ -796,7 +797,7 @@ int run_graph(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s, int t
 // Result-invariant kernel variants of a plan (the autotuner's candidates).
 int tile_count(int plan, int variant, int thermostat) {
     if (plan == PLAN_FP4) return thermostat == HSB_THERMO_NOSE_HOOVER ? 1 : hsb::persistent_tiles(variant);
-    if (plan == PLAN_DIGITS) return hsb::i8_tiles();
+    if (plan == PLAN_DIGITS) return hsb::i8_tiles(thermostat == HSB_THERMO_NOSE_HOOVER);
     return 1;
 }
 

@@ -1,7 +1,8 @@
 """The autotuner (HSB_OPT_AUTOTUNE / HSB_OPT_TILE, marked `gpu`).
 
 Every kernel variant the tuner chooses from (operand prefetch distance of the
-FP4 kernels, wave height of the digit plan, queue placement of batches) must
+FP4 kernels, persistent or per-step kernel and wave height of the digit plan,
+queue placement of batches) must
 give bitwise the same run; the tuned choice is stored in the cache file and
 reused by the next context of the same shape.  dSB runs are also the oracle's
 FP32 mirror, as on every plan.
@@ -37,11 +38,11 @@ CASES = [
     ("dsb fp4", lambda: synth.sk_instance(700, 3), hsb.HSB_DSB, "mixed", "fp4", 3, 256, 400),
     ("bsb fp4", lambda: synth.sk_instance(700, 3), hsb.HSB_BSB, "mixed", "fp4", 2, 128, 300),
     ("bsb digits int", lambda: synth.sk_instance(600, 4) * np.float32(5), hsb.HSB_BSB, "mixed",
-     "digits", 2, 96, 300),
-    ("dsb digits sign", lambda: synth.sk_instance(600, 4), hsb.HSB_DSB, "digits", "digits", 2,
+     "digits", 4, 96, 300),
+    ("dsb digits sign", lambda: synth.sk_instance(600, 4), hsb.HSB_DSB, "digits", "digits", 4,
      96, 300),
     ("bsb digits real", lambda: synth.gaussian_instance(500, 5), hsb.HSB_BSB, "mixed", "digits",
-     2, 64, 200),
+     4, 64, 200),
 ]
 
 

@@ -1,0 +1,121 @@
+"""The digit plan's persistent kernel (marked `gpu`).
+
+Without the thermostat the digit plan runs the steps between two sample
+points in one launch (variants 0 and 1: the two wave heights) that keeps x and
+y on chip, its teams of workgroups exchanging the x digits through L2; the
+per-step kernel (variants 2 and 3) computes the same exact integer sums and
+the same update.  Every variant must give bitwise the same run, for every
+digit combination (one- or four-digit J, x or sign digits), for segments of
+every length, for teams that take more than one launch, and with the
+device-scope exchange; dSB runs are also the oracle's FP32 mirror.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2203_08361_amd import hsb  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    hsb.load_library()
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+KEYS = ("x", "y", "spins", "energy", "best_energy", "final_energy", "best_step")
+
+# (name, J, variant, precision): every combination of J digits and x digits
+COMBOS = [
+    ("bsb one-digit J", lambda n: synth.sk_instance(n, 41) * np.float32(5), hsb.HSB_BSB, "mixed"),
+    ("dsb sign digits", lambda n: synth.sk_instance(n, 42), hsb.HSB_DSB, "digits"),
+    ("bsb four-digit J", lambda n: synth.gaussian_instance(n, 43), hsb.HSB_BSB, "mixed"),
+    ("dsb four-digit J", lambda n: synth.gaussian_instance(n, 44), hsb.HSB_DSB, "mixed"),
+]
+
+
+def c0_of(J):
+    N = J.shape[0]
+    return 0.5 / np.sqrt(N) if np.all(J == np.rint(J)) else 0.5
+
+
+def run(J, variant, plan, steps, R, interval, tile, local=1, seed=3):
+    with hsb.Context(J, precision=plan, init_amp=0.1, energy_interval=interval) as ctx:
+        ctx.set_option("tile", tile)
+        ctx.set_option("local_exchange", local)
+        out = ctx.run_ex(variant, steps, R, 1.0, c0_of(J), 1.0, 0.02, seed, want_state=True,
+                         schedule_steps=4 * steps)
+        torch.cuda.synchronize()
+        res = {k: v.cpu().numpy() for k, v in out.items() if hasattr(v, "cpu")}
+        res["plan"] = ctx.last_plan()
+        res["tile"] = int(ctx.get_option("last_tile"))
+    return res
+
+
+@pytest.mark.parametrize("combo", COMBOS, ids=[c[0] for c in COMBOS])
+@pytest.mark.parametrize("N,R,steps,interval", [(700, 70, 130, 50), (300, 40, 37, 1)])
+def test_every_variant_gives_the_same_run(combo, N, R, steps, interval):
+    """interval 50: segments of 50, 50 and 30 steps; interval 1: a launch per step."""
+    name, mk, variant, plan = combo
+    J = mk(N)
+    say("digit persistent variants", name, N, R, steps, interval)
+    base = run(J, variant, plan, steps, R, interval, 0)
+    assert base["plan"] == "digits" and base["tile"] == 0
+    for t in (1, 2, 3):
+        got = run(J, variant, plan, steps, R, interval, t)
+        assert got["tile"] == t
+        for k in KEYS:
+            assert np.array_equal(got[k], base[k]), (name, t, k)
+    if variant == hsb.HSB_DSB and name.startswith("dsb sign"):
+        o = oracle.run(J, oracle.DSB, 1.0, np.float32(c0_of(J)), 1.0, 0.02, steps, R, seed=3,
+                       amp=0.1, interval=interval, precision=oracle.FP32,
+                       schedule_steps=4 * steps)
+        assert np.array_equal(base["x"].astype(np.float64), o["x"])
+        assert np.array_equal(base["energy"], o["energy"])
+        assert np.array_equal(base["best_energy"], o["best_e"])
+
+
+@pytest.mark.parametrize("combo", [COMBOS[0], COMBOS[2]], ids=[COMBOS[0][0], COMBOS[2][0]])
+def test_teams_beyond_one_launch_and_device_scope_exchange(combo):
+    """N = 2000, R = 1100: 35 teams of 32 replicas, more than one launch holds
+    (32 at either wave height), so each segment takes two launches; the
+    device-scope exchange (LOCAL_EXCHANGE = 0) gives the same run."""
+    name, mk, variant, plan = combo
+    J = mk(2000)
+    say("digit persistent two launches", name)
+    base = run(J, variant, plan, 60, 1100, 25, 2)  # one launch per step
+    for tile, local in ((0, 1), (0, 0)):
+        got = run(J, variant, plan, 60, 1100, 25, tile, local)
+        for k in KEYS:
+            assert np.array_equal(got[k], base[k]), (name, tile, local, k)
+
+
+def test_full_size_dsb_sign_digits_against_the_mirror():
+    """The bench instance on the digit plan (dSB, persistent): sampled replicas
+    bitwise equal to the oracle's FP32 mirror after 300 steps of 10^4."""
+    N, R = 2000, 1024
+    J = synth.sk_instance(N, 2000)
+    c0 = float(np.float32(0.5 / np.sqrt(N)))
+    say("digit persistent full size dsb")
+    with hsb.Context(J, precision="digits", energy_interval=100) as ctx:
+        out = ctx.run_ex(hsb.HSB_DSB, 300, R, 1.0, c0, 1.0, 0.01, 1, want_state=True,
+                         schedule_steps=10000)
+        torch.cuda.synchronize()
+        assert ctx.last_plan() == "digits" and ctx.get_option("last_tile") == 0
+        g = {k: v.cpu().numpy() for k, v in out.items() if hasattr(v, "cpu")}
+    for r in range(0, R, 97):
+        o = oracle.run(J, oracle.DSB, 1.0, c0, 1.0, 0.01, 300, 1, seed=1, r0=r, amp=0.1,
+                       interval=100, precision=oracle.FP32, schedule_steps=10000)
+        assert np.array_equal(g["x"][r].astype(np.float64), o["x"][0]), r
+        assert np.array_equal(g["y"][r].astype(np.float64), o["y"][0]), r
+        assert g["best_energy"][r] == o["best_e"][0] and g["energy"][r] == o["energy"][0], r
