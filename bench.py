@@ -84,6 +84,8 @@ def main() -> int:
     ap.add_argument("--sb-steps", type=int, default=SB_STEPS)
     ap.add_argument("--variant", choices=["dsb", "bsb"], default="dsb")
     ap.add_argument("--plan", choices=["mixed", "fp32", "auto", "digits"], default="mixed")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="kernel variant of the main runs (HSB_OPT_TILE; -1: the default)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-plan comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bsb", action="store_true",
@@ -138,6 +140,8 @@ def main() -> int:
     J = synth.sk_instance(N, 2000)
     log(f"instance N={N} built; creating context")
     ctx = hsb.Context(J, precision=args.plan, init_amp=0.1, energy_interval=100)
+    if args.tile >= 0:
+        ctx.set_option("tile", args.tile)
 
     def measure(var, steps, warmup):
         """Timed whole runs (no per-launch events), then one run with HIP-event
@@ -185,9 +189,14 @@ def main() -> int:
         kname, peak, peak_dtype = KERNELS[plan_kind]
         if plan_kind == "fp4" and var == hsb.HSB_BSB:
             kname = "k_bsb_fp4"
-        # per-launch HBM bytes: the persistent kernel's depend on the run length,
-        # a per-step kernel's do not
-        traffic = (measured_traffic(kname, f"N{N}_R{R}")
+        if plan_kind == "digits" and ctx.get_option("last_tile") < 2:
+            kname = "k_i8_persist"  # one launch per segment between sample points
+        # per-launch HBM bytes: the persistent FP4 kernels' depend on the run
+        # length; a per-step kernel's, and a digit-plan launch of one segment, do not
+        wl = f"N{N}_R{R}"
+        if plan_kind == "digits":  # digit-plan summaries are per variant
+            wl = ("bsb_" if var == hsb.HSB_BSB else "dsb_") + wl
+        traffic = (measured_traffic(kname, wl)
                    if Ns == SB_STEPS or plan_kind != "fp4" else None)
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 5), "traffic": traffic,
@@ -362,6 +371,35 @@ def main() -> int:
                 "fp64_energy_rel_err_max": max(rel),
                 "fp64_energy_check": f"eq. (1) of the returned spins of {len(rel)} replicas "
                                      f"(every 64th) recomputed by the FP64 oracle"}
+
+    def digits_workload():
+        """The integer-digit plan (exactly rounded fields, the plan of integer J
+        beyond FP4 and of real J) on the bench instance: dSB (sign digits) and
+        bSB (four x digits), R = 1024, 10^4 steps, as its persistent kernel (one
+        launch per segment between sample points) and as one launch per step;
+        the two give the same run bit for bit."""
+        cd = hsb.Context(J, precision="digits", init_amp=0.1, energy_interval=100)
+        res = {}
+        for vname, var in (("dsb", hsb.HSB_DSB), ("bsb", hsb.HSB_BSB)):
+            row, outs = {}, {}
+            for kname, tile in (("persistent", 0), ("one_launch_per_step", 2)):
+                cd.set_option("tile", tile)
+                cd.run_ex(var, 200, R, A0, c0, DT, GAMMA, 1, schedule_steps=Ns)  # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                o = cd.run_ex(var, Ns, R, A0, c0, DT, GAMMA, 1, want_state=True)
+                torch.cuda.synchronize()
+                row[f"ms_{kname}"] = 1e3 * (time.perf_counter() - t0)
+                outs[kname] = o
+            a, b = outs["persistent"], outs["one_launch_per_step"]
+            row["identical"] = bool(all(torch.equal(a[k], b[k])
+                                        for k in ("x", "y", "spins", "best_energy", "best_step")))
+            row["value"] = N * R * Ns / (row["ms_persistent"] * 1e-3)
+            row["speedup_persistent"] = row["ms_one_launch_per_step"] / row["ms_persistent"]
+            res[vname] = row
+        cd.close()
+        return {"workload": f"SK +-1 N={N}, R={R}, {Ns} steps heated dsb and bsb gamma={GAMMA}, "
+                            f"integer-digit plan", "plan": "digits", **res}
 
     def thermostat_workload():
         """The Nose-Hoover thermostat (eqs. (6)-(8)) on the bench instance: dSB,
@@ -546,6 +584,7 @@ def main() -> int:
         result["bsb"] = bsb
     if args.variant == "dsb" and not args.no_gaussian:
         result["gaussian"] = gaussian_workload()
+        result["digits"] = digits_workload()
     if args.variant == "dsb" and not args.no_batch:
         result["batch"] = batch_workload()
     if args.variant == "dsb" and not args.no_thermostat:

@@ -86,7 +86,8 @@ typedef enum {
                                     timing on (synchronises the events) */
     HSB_OPT_KERNEL_LAUNCHES = 6, /* read only: number of launches inside those brackets */
     HSB_OPT_LAST_PLAN = 7,       /* read only: plan of the last successful run, an hsb_plan */
-    HSB_OPT_LOCAL_EXCHANGE = 8,  /* FP4 plan: 1 (default): a team of workgroups that share
+    HSB_OPT_LOCAL_EXCHANGE = 8,  /* FP4 plan and the digit plan's persistent kernel: 1
+                                    (default): a team of workgroups that share
                                     one XCD exchanges its per-step data through that XCD's L2
                                     (workgroup-scope stores, no cache invalidation); 0: always
                                     device scope (slower; results are the same).  Batches use
@@ -117,10 +118,14 @@ typedef enum {
     HSB_OPT_TILE = 12,           /* -1 (default): variant from AUTOTUNE (else 0); k >= 0: force
                                     variant k.  FP4 dSB: 0..2 = operand read 2, 1, 4 K blocks
                                     ahead of the products; FP4 bSB: 0..1 = 4, 2 fragments
-                                    ahead; DIGITS: 0..1 = the default wave height of the digit
-                                    combination, the other one (32 or 64 rows: two or one
-                                    workgroups per CU); batch queues: 0..1 = longest-first,
-                                    round robin.  A variant the plan lacks: HSB_EINVAL */
+                                    ahead; DIGITS: 0..1 = one persistent launch per
+                                    segment between sample points with the default wave
+                                    height of the digit combination or the other one (32 or
+                                    64 rows: two or one workgroups per CU), 2..3 = one launch
+                                    per step with those heights (with the thermostat only
+                                    the per-step launches: 0..1 = the two heights); batch
+                                    queues: 0..1 = longest-first, round robin.  A variant
+                                    the plan lacks: HSB_EINVAL */
     HSB_OPT_LAST_TILE = 13,      /* read only: the variant of the last successful run */
     HSB_OPT_CANCELLABLE = 14     /* 1: runs of this context (hsb_run, hsb_run_ex,
                                     hsb_run_ex_noalloc) can be stopped by hsb_cancel; the
