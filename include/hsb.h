@@ -122,10 +122,9 @@ typedef enum {
                                     segment between sample points with the default wave
                                     height of the digit combination or the other one (32 or
                                     64 rows: two or one workgroups per CU), 2..3 = one launch
-                                    per step with those heights (with the thermostat only
-                                    the per-step launches: 0..1 = the two heights); batch
-                                    queues: 0..1 = longest-first, round robin.  A variant
-                                    the plan lacks: HSB_EINVAL */
+                                    per step with those heights; batch queues: 0..1 =
+                                    longest-first, round robin.  A variant the plan lacks:
+                                    HSB_EINVAL */
     HSB_OPT_LAST_TILE = 13,      /* read only: the variant of the last successful run */
     HSB_OPT_CANCELLABLE = 14     /* 1: runs of this context (hsb_run, hsb_run_ex,
                                     hsb_run_ex_noalloc) can be stopped by hsb_cancel; the

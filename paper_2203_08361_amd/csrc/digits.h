@@ -34,8 +34,8 @@ int i8_max_n();
 // Number of result-invariant kernel variants (the autotuner's candidates; 0
 // is the default): 0, 1 = the persistent kernel with the default or the
 // other wave height (32 or 64 rows), 2, 3 = one launch per step with those
-// heights; with the thermostat only the per-step kernel (0, 1: the heights).
-int i8_tiles(bool thermostat);
+// heights.
+int i8_tiles();
 
 struct I8Run {
     int variant;          // HSB_BSB / HSB_DSB
@@ -52,9 +52,9 @@ struct I8Run {
 
 // Run steps k0..k1-1 of the digit plan on the state in `b` (X, Y in
 // [Nst][Rpad]); samples energies at the sample points (as the FP32 plan).
-// Without the thermostat the steps between two sample points run in one
-// persistent launch that keeps the state on chip (when its teams of
-// workgroups fit one XCD: N <= 8192), else one launch per step.
+// The steps between two sample points run in one persistent launch that
+// keeps the state on chip (when its teams of workgroups fit one XCD:
+// N <= 8192), else one launch per step.
 // `fp32J` is the FP32 J store ([Nst][Nst]) used for FP64 energies of real J.
 int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream_t s,
            KernelTimer &timer);

@@ -396,13 +396,27 @@ __device__ __forceinline__ void i8_lds_direct16(const void *base, uint32_t lane_
                  : "memory", "m0");
 }
 
-template <int NJD, int NXD, int KC, int NT>
+// The thermostat (eqs. (6)-(8)) in the persistent kernel, in the per-step
+// kernel's slots: step j = k - k0 of the run reads xi(t_{k-1}) from slot j & 1
+// and the per-wave partials of sum_i y_i(t_{k-1})^2 from partial set
+// (j + 1) & 1, and writes the partials of y(t_k) to set j & 1.  Within a
+// segment the partials travel with the x digits (stored before the step
+// flag); at its end xi of its last step goes to slot (j + 1) & 1, so a later
+// segment, or the final xi, finds what the per-step kernel would have left.
+struct I8NH {
+    double *xi = nullptr;    // [2][Rpad]
+    double *part = nullptr;  // [2][nparts][Rpad]
+    int nparts = 0, k0 = 0;  // per-wave partials of the state rows; the run's first step
+    double c = 0.0, NT = 0.0;
+};
+
+template <int NJD, int NXD, int KC, int NT, bool NH>
 __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_persist(
     const v4i *__restrict__ jd, const double *__restrict__ rowscale, int8_t *xd,
     uint32_t *sync, float *__restrict__ X, float *__restrict__ Y, const float *__restrict__ gam,
     const float *__restrict__ ptab, int32_t *__restrict__ status, int32_t *err,
     const int32_t *__restrict__ stop, int local_ok, int Nst, int Npad, int Rpad, int team0,
-    int nteams, int k0, int k1, float c0, float dt, float a0dt) {
+    int nteams, int k0, int k1, float c0, float dt, float a0dt, I8NH nh) {
     constexpr int NW = (NJD + NXD - 1) < 4 ? (NJD + NXD - 1) : 4;
     constexpr int KB = 2 * KC;
     constexpr int BTOT = NXD * KB * 32;
@@ -411,6 +425,8 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_persist(
     constexpr double kTrunc = (NJD + NXD - 1 - NW) == 3 ? 0x1p24 : 1.0;
     static_assert(BTOT % 64 == 0 && KB % 2 == 0, "a wave stages whole pairs of K blocks");
     __shared__ v4i bs[2][NXD][KB][32];
+    // thermostat: the eight half-waves' sums of the team's partials
+    __shared__ double s_part[NH ? 8 : 1][32];
     // the workgroup's x and y between steps (item v of thread t at [v][t]):
     // in LDS rather than registers, which the products need
     __shared__ float s_x[NT * 16][256], s_y[NT * 16][256];
@@ -468,7 +484,8 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_persist(
             s_x[tt * 16 + v][t] = live ? X[idx] : 0.0f;
             s_y[tt * 16 + v][t] = live ? Y[idx] : 0.0f;
         }
-    const float gdt = gam[r] * dt;
+    const float gdt_heat = gam[r] * dt;
+    double xi_m = 0.0;  // thermostat: xi(t_m) of this lane's replica
 
     // digits of four consecutive spins (items 4q .. 4q + 3 of tile tt) of x_m
     // into set m & 1
@@ -593,7 +610,23 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_persist(
     for (int m = k0; m < k1; ++m) {
         const float p = ptab[m - k0];
         const int8_t *xin = xd + (size_t)(m & 1) * set;
+        const int j = m - nh.k0;  // thermostat: step of the run
         if (!wait_team(m)) wg_abort = 1;
+        if constexpr (NH) {
+            // xi(t_m) = xi(t_{m-1}) + c (sum_i y_i(t_{m-1})^2 - N T), the partials
+            // added as the per-step kernel adds them: half-wave g of the
+            // workgroup takes partials g, g + 8, ..., then the eight sums in order
+            if (m == k0) xi_m = nh.xi[(size_t)(j & 1) * Rpad + r];
+            if (j > 0) {
+                const uint64_t *pin = reinterpret_cast<const uint64_t *>(
+                    nh.part + (size_t)((j + 1) & 1) * nh.nparts * Rpad);
+                double Ssum = 0.0;
+                for (int q = 2 * w + h; q < nh.nparts; q += 8)
+                    Ssum += __longlong_as_double((long long)__hip_atomic_load(
+                        pin + (size_t)q * Rpad + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                s_part[2 * w + h][l32] = Ssum;
+            }
+        }
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
@@ -601,8 +634,16 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_persist(
         loadA(0, a0r);
         stageB(xin, 0, 0);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();  // also publishes wg_abort
+        __syncthreads();  // also publishes wg_abort and the thermostat's sums
         if (wg_abort) break;
+        if constexpr (NH) {
+            if (j > 0) {
+                double S8 = 0.0;
+#pragma unroll
+                for (int g = 0; g < 8; ++g) S8 += s_part[g][l32];
+                xi_m = xi_m + nh.c * (S8 - nh.NT);
+            }
+        }
         for (int s = 0; s < S; s += 2) {
             loadA(s + 1, a1r);
             stageB(xin, s + 1, 1);
@@ -623,6 +664,9 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_persist(
         // the field, exactly rounded once, the update (as k_i8_field) and the
         // digits of x_{m+1}
         const bool pub = m + 1 < k1;
+        float gdt = gdt_heat;
+        if constexpr (NH) gdt = (float)(-xi_m) * dt;  // the rate -xi(t_m) in eq. (22)'s place
+        double t2 = 0.0;  // thermostat: this wave's sum of y_i(t_m)^2 (exact squares)
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
@@ -638,6 +682,7 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_persist(
                     const double sc = (NJD == 1 ? 1.0 : rowscale[i]) * (kXs * kTrunc);
                     const float f = (float)(Tsum * sc);
                     float x = s_x[tt * 16 + v][t], y = s_y[tt * 16 + v][t];
+                    if constexpr (NH) t2 += (double)y * (double)y;
                     sb_update(f, p, c0, dt, a0dt, gdt, x, y);
                     s_x[tt * 16 + v][t] = x;
                     s_y[tt * 16 + v][t] = y;
@@ -645,6 +690,13 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_persist(
                 }
                 if (pub) put_digits(m + 1, tt, q, x4);
             }
+        if constexpr (NH) {
+            // the partial of y(t_m), before the flag that publishes x_{m+1}
+            t2 += __shfl_xor(t2, 32);
+            if (live && h == 0)
+                nh.part[((size_t)(j & 1) * nh.nparts + i0 / (32 * NT)) * Rpad + r] = t2;
+            if (m + 1 == k1 && i0 == 0 && h == 0) nh.xi[(size_t)((j + 1) & 1) * Rpad + r] = xi_m;
+        }
         if (pub) set_flag(m + 1);
     }
     if (live) {
@@ -733,16 +785,24 @@ hipError_t launch_step(int nt, const I8J *p, const int8_t *xin, int8_t *xout, St
                                                     nhf);
 }
 
-// The persistent kernel of a digit combination and wave height.
-template <int NJD, int NXD, int KC>
+// The persistent kernel of a digit combination, wave height and thermostat.
+// Four-digit J with 64-row waves stages one K block pair at a time (KC = 1):
+// two would not fit the registers.
+template <int NJD, int NXD, int KC, bool NH>
 const void *persist_fn(int nt) {
-    return nt == 1 ? reinterpret_cast<const void *>(k_i8_persist<NJD, NXD, KC, 1>)
-                   : reinterpret_cast<const void *>(k_i8_persist<NJD, NXD, KC, 2>);
+    constexpr int KC2 = NJD == 4 ? 1 : KC;
+    return nt == 1 ? reinterpret_cast<const void *>(k_i8_persist<NJD, NXD, KC, 1, NH>)
+                   : reinterpret_cast<const void *>(k_i8_persist<NJD, NXD, KC2, 2, NH>);
 }
 
-const void *persist_kernel(int njd, int nxd, int nt) {
-    if (njd == 1) return nxd == 4 ? persist_fn<1, 4, 4>(nt) : persist_fn<1, 1, 4>(nt);
-    return nxd == 4 ? persist_fn<4, 4, 2>(nt) : persist_fn<4, 1, 2>(nt);
+template <bool NH>
+const void *persist_kernel_nh(int njd, int nxd, int nt) {
+    if (njd == 1) return nxd == 4 ? persist_fn<1, 4, 4, NH>(nt) : persist_fn<1, 1, 4, NH>(nt);
+    return nxd == 4 ? persist_fn<4, 4, 2, NH>(nt) : persist_fn<4, 1, 2, NH>(nt);
+}
+
+const void *persist_kernel(int njd, int nxd, int nt, bool nh) {
+    return nh ? persist_kernel_nh<true>(njd, nxd, nt) : persist_kernel_nh<false>(njd, nxd, nt);
 }
 
 // Teams (32-replica blocks) per launch of the persistent kernel: a multiple of
@@ -761,7 +821,7 @@ int persist_teams_per_launch(const void *fn, int wpt) {
 
 }  // namespace
 
-int i8_tiles(bool thermostat) { return thermostat ? 2 : 4; }
+int i8_tiles() { return 4; }
 
 int i8_create(const float *hJ, int N, I8J **out) {
     *out = nullptr;
@@ -871,12 +931,14 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
     };
     if (k1 == k0) return sample(k0);
     // 32-row tiles per wave: the default of the digit combination, or the
-    // other height (odd tiles).  Without the thermostat tiles 0 and 1 run the
-    // persistent kernel, 2 and 3 one launch per step (the same results).
+    // other height (odd tiles).  Tiles 0 and 1 run the persistent kernel, 2
+    // and 3 one launch per step (the same results).
     const int nt_def = tiles_per_wave(p->njd, bsb ? 4 : 1, false);
     const int nt = (run.tile & 1) ? 3 - nt_def : nt_def;
-    if (!run.nh && run.tile < 2) {
-        const void *fn = persist_kernel(p->njd, nxd, nt);
+    // per-wave partials of the thermostat's sum (32 or 64 rows)
+    const int nh_parts = Nst / (32 * nt);
+    if (run.tile < 2) {
+        const void *fn = persist_kernel(p->njd, nxd, nt, run.nh != nullptr);
         const int wpt = Np / (128 * nt), nwt = 4 * wpt;
         const int tpl = persist_teams_per_launch(fn, wpt);
         const int nteams = Rpad / 32;
@@ -892,6 +954,8 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
                                reinterpret_cast<uint32_t *>(p->err), (size_t)1, 0u);
             int local_ok = run.local_exchange ? 1 : 0;
             const float a0dt_v = a0dt;
+            I8NH nhp{};
+            if (run.nh) nhp = I8NH{run.nh->xi, run.nh->part, nh_parts, k0, run.nh->c, run.nh->NT};
             for (int a = k0; a < k1;) {
                 // segment [a, e): up to the next sample point
                 const long long nxt = ((long long)a / interval + 1) * interval;
@@ -917,7 +981,7 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
                                     (void *)&Nst_v,    (void *)&Np_v,        (void *)&Rpad_v,
                                     (void *)&t0_v,     (void *)&ntm_v,       (void *)&a_v,
                                     (void *)&e_v,      (void *)&c0_v,        (void *)&dt_v,
-                                    (void *)&a0dt_v};
+                                    (void *)&a0dt_v,   (void *)&nhp};
                     // every workgroup of the grid is resident at once (the grid
                     // never exceeds the occupancy-derived capacity), and every
                     // wait inside the kernel is bounded
@@ -933,11 +997,14 @@ int i8_run(I8J *p, const I8Run &run, StateBufs &b, const float *fp32J, hipStream
                 }
                 a = e_k;
             }
+            if (run.nh) {  // xi after the last step, as after the per-step launches
+                e = launch_nh_final(run.nh->xi, run.nh->part, nh_parts, run.R, Rpad, run.nh->xi,
+                                    run.nh->c, run.nh->NT, k1 - k0, k0, b.stop, s);
+                if (e != hipSuccess) return derr(HSB_EDEVICE, "thermostat: %s", hipGetErrorString(e));
+            }
             return HSB_OK;
         }
     }
-    // per-wave partials of the thermostat's sum (32 or 64 rows)
-    const int nh_parts = Nst / (32 * nt);
     int cur = 0;
     size_t nrun = 0;  // step launches since the last energy sample
     for (int k = k0; k < k1; ++k) {

@@ -797,7 +797,7 @@ int run_graph(hsb_ctx *h, const hsb_run_args *a, int &plan, hipStream_t s, int t
 // Result-invariant kernel variants of a plan (the autotuner's candidates).
 int tile_count(int plan, int variant, int thermostat) {
     if (plan == PLAN_FP4) return thermostat == HSB_THERMO_NOSE_HOOVER ? 1 : hsb::persistent_tiles(variant);
-    if (plan == PLAN_DIGITS) return hsb::i8_tiles(thermostat == HSB_THERMO_NOSE_HOOVER);
+    if (plan == PLAN_DIGITS) return hsb::i8_tiles();
     return 1;
 }
 

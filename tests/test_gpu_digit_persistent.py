@@ -1,13 +1,14 @@
 """The digit plan's persistent kernel (marked `gpu`).
 
-Without the thermostat the digit plan runs the steps between two sample
-points in one launch (variants 0 and 1: the two wave heights) that keeps x and
-y on chip, its teams of workgroups exchanging the x digits through L2; the
-per-step kernel (variants 2 and 3) computes the same exact integer sums and
-the same update.  Every variant must give bitwise the same run, for every
-digit combination (one- or four-digit J, x or sign digits), for segments of
-every length, for teams that take more than one launch, and with the
-device-scope exchange; dSB runs are also the oracle's FP32 mirror.
+The digit plan runs the steps between two sample points in one launch
+(variants 0 and 1: the two wave heights) that keeps x and y on chip, its teams
+of workgroups exchanging the x digits (and, with the thermostat, the partial
+sums of y^2) through L2; the per-step kernel (variants 2 and 3) computes the
+same exact integer sums and the same update.  Every variant must give bitwise
+the same run, for every digit combination (one- or four-digit J, x or sign
+digits), with and without the thermostat, for segments of every length, for
+teams that take more than one launch, and with the device-scope exchange; dSB
+runs are also the oracle's FP32 mirror.
 """
 import numpy as np
 import pytest
@@ -49,12 +50,12 @@ def c0_of(J):
     return 0.5 / np.sqrt(N) if np.all(J == np.rint(J)) else 0.5
 
 
-def run(J, variant, plan, steps, R, interval, tile, local=1, seed=3):
+def run(J, variant, plan, steps, R, interval, tile, local=1, seed=3, **kw):
     with hsb.Context(J, precision=plan, init_amp=0.1, energy_interval=interval) as ctx:
         ctx.set_option("tile", tile)
         ctx.set_option("local_exchange", local)
         out = ctx.run_ex(variant, steps, R, 1.0, c0_of(J), 1.0, 0.02, seed, want_state=True,
-                         schedule_steps=4 * steps)
+                         schedule_steps=4 * steps, **kw)
         torch.cuda.synchronize()
         res = {k: v.cpu().numpy() for k, v in out.items() if hasattr(v, "cpu")}
         res["plan"] = ctx.last_plan()
@@ -83,6 +84,34 @@ def test_every_variant_gives_the_same_run(combo, N, R, steps, interval):
         assert np.array_equal(base["x"].astype(np.float64), o["x"])
         assert np.array_equal(base["energy"], o["energy"])
         assert np.array_equal(base["best_energy"], o["best_e"])
+
+
+@pytest.mark.parametrize("combo", COMBOS, ids=[c[0] for c in COMBOS])
+def test_thermostat_in_every_variant(combo):
+    """Nose-Hoover runs (eqs. (6)-(8)): segments of 50, 50 and 30 steps; x, y
+    and energies equal on every variant, and the final xi too between the
+    persistent and the per-step kernel of one wave height (the same per-wave
+    partials added in the same order; the two heights partition the sum
+    differently: within 1e-12); dSB also equals the mirror's x and y."""
+    name, mk, variant, plan = combo
+    J = mk(700)
+    nh = (2e-5, 0.05)  # a bath heavy enough for 700 spins (a light one lets dSB diverge)
+    say("digit persistent thermostat", name)
+    runs = [run(J, variant, plan, 130, 70, 50, t, nose_hoover=nh) for t in range(4)]
+    base = runs[0]
+    assert base["plan"] == "digits"
+    for t in (1, 2, 3):
+        for k in KEYS:
+            assert np.array_equal(runs[t][k], base[k]), (name, t, k)
+    assert np.array_equal(runs[2]["xi"], runs[0]["xi"]) and np.array_equal(runs[3]["xi"], runs[1]["xi"])
+    assert np.allclose(runs[1]["xi"], runs[0]["xi"], rtol=0, atol=1e-12)
+    if name.startswith("dsb sign"):
+        o = oracle.run(J, oracle.DSB, 1.0, np.float32(c0_of(J)), 1.0, 0.02, 130, 70, seed=3,
+                       amp=0.1, interval=50, precision=oracle.FP32, schedule_steps=520,
+                       nose_hoover=nh)
+        assert np.array_equal(base["x"].astype(np.float64), o["x"])
+        assert np.array_equal(base["y"].astype(np.float64), o["y"])
+        assert np.allclose(base["xi"], o["xi"], rtol=0, atol=1e-12)
 
 
 @pytest.mark.parametrize("combo", [COMBOS[0], COMBOS[2]], ids=[COMBOS[0][0], COMBOS[2][0]])
