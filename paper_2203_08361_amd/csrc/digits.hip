@@ -644,22 +644,42 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_persist(
                 xi_m = xi_m + nh.c * (S8 - nh.NT);
             }
         }
-        for (int s = 0; s < S; s += 2) {
-            loadA(s + 1, a1r);
-            stageB(xin, s + 1, 1);
-            compute(0, a0r);
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            __syncthreads();
-            const bool more = s + 2 < S;
-            if (more) {
-                loadA(s + 2, a0r);
-                stageB(xin, s + 2, 0);
-            }
-            compute(1, a1r);
-            if (more) {
+        // EARLY: each stage's x digits are loaded before its J fragments, and
+        // the barrier waits only for the digits (at most the NA J loads issued
+        // after them may be outstanding): the J fragments, which only their
+        // own wave reads, stay in flight across it (wait and barrier are one
+        // asm statement, so that no memory access moves between them).
+        // Measured at N = 2000, R = 1024: sign digits 10.5 -> 9.7 us per step,
+        // four-digit J 52.9 -> 51.9; one-digit J with x digits 20.8 -> 21.6,
+        // so that combination keeps the full wait.
+        constexpr bool EARLY = !(NJD == 1 && NXD == 4);
+        constexpr int NA = NT * NJD * KC;
+        static_assert(NA <= 63, "vmcnt counts up to 63");
+        auto stage_barrier = [&]() {
+            if constexpr (EARLY) {
+                asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(NA) : "memory");
+            } else {
                 asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                 __syncthreads();
             }
+        };
+        auto load_stage = [&](int s, int buf, v4i(&dst)[NT][NJD][KC]) {
+            if constexpr (EARLY) {
+                stageB(xin, s, buf);
+                loadA(s, dst);
+            } else {
+                loadA(s, dst);
+                stageB(xin, s, buf);
+            }
+        };
+        for (int s = 0; s < S; s += 2) {
+            load_stage(s + 1, 1, a1r);
+            compute(0, a0r);
+            stage_barrier();
+            const bool more = s + 2 < S;
+            if (more) load_stage(s + 2, 0, a0r);
+            compute(1, a1r);
+            if (more) stage_barrier();
         }
         // the field, exactly rounded once, the update (as k_i8_field) and the
         // digits of x_{m+1}
