@@ -347,12 +347,14 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
     };
 
     // thermostat: this wave's sum of y_i(t_m)^2 over its 32 rows (exact squares,
-    // fixed order) into LDS, for the state about to be published
+    // fixed order) into LDS, for the state about to be published.  A float's
+    // square is exact in FP64, so one fused multiply-add per item rounds as
+    // the product and the sum would.
     auto y2_partial = [&](int m) {
         if constexpr (NH) {
             double t2 = 0.0;
 #pragma unroll
-            for (int v = 0; v < 16; ++v) t2 += (double)ys[v] * (double)ys[v];
+            for (int v = 0; v < 16; ++v) t2 = __fma_rn((double)ys[v], (double)ys[v], t2);
             t2 += __shfl_xor(t2, 32);
             if (half == 0) s_yw[m & 1][w][l32] = t2;
         }
@@ -466,13 +468,16 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
         }
         if constexpr (NH) {
             // xi(t_m) = xi(t_{m-1}) + (dt/M)(sum_i y_i(t_{m-1})^2 - N T): the eight
-            // half-wave sums (in LDS since the barrier) in a fixed order, the
-            // same in every wave of the team; formed before the products, so
-            // that only its use remains for the update after them
+            // half-wave sums (in LDS since the barrier) added pairwise in a
+            // fixed order, the same in every wave of the team; formed before
+            // the products, so that only its use remains for the update after
+            // them
             if (m > g.seg_k0) {
-                double S = 0.0;
+                double v8[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) S += s_ysum[m & 1][q][l32];
+                for (int q = 0; q < 8; ++q) v8[q] = s_ysum[m & 1][q][l32];
+                const double S = ((v8[0] + v8[1]) + (v8[2] + v8[3])) +
+                                 ((v8[4] + v8[5]) + (v8[6] + v8[7]));
                 const double xi_k = s_xi[w][l32] + nhp.c * (S - nhp.NT);
                 if (half == 0) s_xi[w][l32] = xi_k;
             }
