@@ -129,6 +129,22 @@ def test_teams_beyond_one_launch_and_device_scope_exchange(combo):
             assert np.array_equal(got[k], base[k]), (name, tile, local, k)
 
 
+@pytest.mark.parametrize("N", [4096, 8192, 8448])
+def test_largest_teams_and_the_per_step_fallback(N):
+    """Teams of 32 and 64 workgroups (N = 4096, 8192: two and four step flags
+    per lane of the team's waves) and, beyond 8192 spins, teams too large for
+    one XCD, which run one launch per step under every variant: bitwise the
+    per-step kernel's run."""
+    J = synth.sk_instance(N, 7)
+    say("digit persistent large teams", N)
+    base = run(J, hsb.HSB_DSB, "digits", 30, 64, 10, 2)
+    for t in (0, 1):
+        got = run(J, hsb.HSB_DSB, "digits", 30, 64, 10, t)
+        assert got["plan"] == "digits"
+        for k in KEYS:
+            assert np.array_equal(got[k], base[k]), (N, t, k)
+
+
 def test_full_size_dsb_sign_digits_against_the_mirror():
     """The bench instance on the digit plan (dSB, persistent): sampled replicas
     bitwise equal to the oracle's FP32 mirror after 300 steps of 10^4."""
