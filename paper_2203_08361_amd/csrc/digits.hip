@@ -1,6 +1,7 @@
 // Integer-digit field plan: the field of eqs. (4)/(5) as an exact integer
-// product on the int8 matrix cores, one launch per time step with the update
-// of eqs. (16)-(22) fused into its epilogue.
+// product on the int8 matrix cores with the update of eqs. (16)-(22) fused
+// into its epilogue: one persistent launch per segment of steps between two
+// sample points (k_i8_persist), or one launch per step (k_i8_field).
 //
 // Digits (see digits.h): x -> four balanced base-256 digits of rint(x 2^30),
 // sgn(x) -> one digit, J -> one digit (integer J) or four digits of a per-row
@@ -353,11 +354,12 @@ __global__ __launch_bounds__(256, NT == 1 ? 2 : 1) void k_i8_field(
 
 // ------------------------------------------------------- persistent step kernel
 //
-// The same step as k_i8_field (no thermostat) for a whole segment of steps
-// between two sample points in one launch.  A team of workgroups owns one
-// 32-replica block: workgroup k of the team computes spins [128 NT k,
-// 128 NT (k + 1)) of those replicas, as in k_i8_field, and keeps its part of
-// x and y in registers for the whole segment.  The x digits of each step go
+// The same step as k_i8_field (the thermostat included) for a whole segment
+// of steps between two sample points in one launch.  A team of workgroups
+// owns one 32-replica block: workgroup k of the team computes spins
+// [128 NT k, 128 NT (k + 1)) of those replicas, as in k_i8_field, and keeps
+// its part of x and y in LDS for the whole segment (the products need the
+// registers).  The x digits of each step go
 // through the ping-pong digit buffers (the layout k_i8_field reads), and each
 // wave sets its step flag once its digits are stored; before a step's
 // products every wave waits for the flags of its team.  The digits of step m
@@ -385,9 +387,9 @@ __device__ __forceinline__ int i8_xcc_id() { return __builtin_amdgcn_s_getreg((3
 // 16 bytes per lane from global memory (wave-uniform base plus the lane's
 // 32-bit byte offset) straight into LDS at lds_base + 16 lane, device scope
 // (the L1 is bypassed).  Assembly, so that the compiler does not track it:
-// the caller waits for it (vmcnt(0)) and synchronises the workgroup before
-// any wave reads the bytes; the compiler's own vmcnt waits for its tracked
-// loads only get stricter from it.
+// the caller waits for it (vmcnt, counting the loads it issued after it) and
+// synchronises the workgroup before any wave reads the bytes; the compiler's
+// own vmcnt waits for its tracked loads only get stricter from it.
 __device__ __forceinline__ void i8_lds_direct16(const void *base, uint32_t lane_off,
                                                 uint32_t lds_base) {
     asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1 sc1"
