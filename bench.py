@@ -98,6 +98,8 @@ def main() -> int:
                     help="skip the Gaussian-coupling workload of the default run")
     ap.add_argument("--no-thermostat", action="store_true",
                     help="skip the Nose-Hoover thermostat run of the default run")
+    ap.add_argument("--digits-only", action="store_true",
+                    help="only the Gaussian-couplings and integer-digit legs (for profiling)")
     ap.add_argument("--thermostat-only", action="store_true",
                     help="run only the Nose-Hoover thermostat comparison")
     ap.add_argument("--no-evaluation", action="store_true",
@@ -543,6 +545,11 @@ def main() -> int:
 
     if args.batch_only:
         print(json.dumps({"batch": batch_workload()}), flush=True)
+        ctx.close()
+        return 0
+    if args.digits_only:
+        print(json.dumps({"gaussian": gaussian_workload(), "digits": digits_workload()}),
+              flush=True)
         ctx.close()
         return 0
     if args.thermostat_only:
