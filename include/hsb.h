@@ -40,6 +40,13 @@
  *     or the exactly rounded sum of the integer-digit plan); see
  *     hsb_set_option(HSB_OPT_PRECISION).
  *   - Thread safety: one context may be used by one thread at a time.
+ *   - Sharing the GPU: the persistent kernels (the FP4 plan, batch queues and
+ *     the digit plan's segments) need every workgroup of a launch resident at
+ *     once, and size their grids for an otherwise idle device.  Runs of other
+ *     contexts or processes executing at the same time can keep part of a
+ *     launch from being scheduled; every wait inside these kernels is bounded,
+ *     so such a run then ends with HSB_EDEVICE (after at most a few seconds)
+ *     rather than hanging.  Run one persistent run per GPU at a time.
  */
 #ifndef HSB_H
 #define HSB_H
