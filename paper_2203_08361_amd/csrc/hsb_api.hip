@@ -1036,8 +1036,10 @@ extern "C" int hsb_run_ex(hsb_ctx *h, const hsb_run_args *a) {
     int plan = 0;
     int rc = choose_plan(h, a->variant, &plan);
     if (rc != HSB_OK) return rc;
-    // the persistent bSB kernel has no thermostat: the digit plan runs it
-    if (a->thermostat == HSB_THERMO_NOSE_HOOVER && plan == PLAN_FP4 && a->variant == HSB_BSB)
+    // the persistent bSB kernel's thermostat variant takes no cancel requests:
+    // in a cancellable context the digit plan runs it
+    if (a->thermostat == HSB_THERMO_NOSE_HOOVER && plan == PLAN_FP4 && a->variant == HSB_BSB &&
+        h->cancellable && h->cancel_opt)
         plan = h->N <= hsb::i8_max_n() ? PLAN_DIGITS : PLAN_FP32;
     if (a->thermostat == HSB_THERMO_NOSE_HOOVER && plan == PLAN_INCREMENTAL)
         return fail(HSB_EUNSUPPORTED, "the thermostat does not run on the INCREMENTAL plan");

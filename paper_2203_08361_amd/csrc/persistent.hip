@@ -79,6 +79,8 @@ struct PersistentWork {
     size_t tstop_n = 0;
     uint64_t *ypart = nullptr;   // thermostat: [2][nchunk / 4][Rpad][2] tagged partials of y^2
     size_t ypart_n = 0;
+    double *bpart = nullptr;     // bSB thermostat: [2][row blocks][Rpad] partials of y^2
+    size_t bpart_n = 0;
 };
 
 struct PersistentJ {
@@ -703,18 +705,35 @@ __device__ __forceinline__ uint32_t make_digits(const float (&xs)[16], int half,
     return (uint32_t)(E + 128);
 }
 
+// The Nose-Hoover thermostat inside the persistent bSB kernel (eqs. (6)-(8)):
+// xi per replica ([Rpad], FP64: its value at the segment's first step in, at
+// the step after its last out), and every wave's partial sum of y_i(t_m)^2
+// over its 64 rows ([2 step parities][row blocks][Rpad], FP64), stored with
+// the digits of x_{m+1} before the step flag that publishes them.
+struct BsbNH {
+    double *xi;
+    double *part;
+    double c, NT;
+};
+
 // CANCEL: the variant that honours hsb_cancel, as for the dSB kernel.
-template <int NKB, int KPRE, bool CANCEL>
+// NH: the thermostat (not combined with CANCEL).
+template <int NKB, int KPRE, bool CANCEL, bool NH>
 __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
     const FP4Team *__restrict__ teams, float *__restrict__ X, float *__restrict__ Y,
     const float *__restrict__ gamma, v4i *xd, uint8_t *xe, uint32_t *flags,
     uint32_t *__restrict__ snap, double *__restrict__ tp, const float *__restrict__ ptab,
     int32_t *__restrict__ bad,
     int32_t *__restrict__ status, int32_t *err, uint64_t *xslot, const uint32_t *epoch_p,
-    int local_ok, const int32_t *cancel, int32_t *tstop,
+    int local_ok, const int32_t *cancel, int32_t *tstop, BsbNH nhp,
     int nkb, int nrb, int Rpad, int team0, int nteams, SegArgs g, float dt, float a0dt) {
     static_assert(NKB % 4 == 0, "Npad is a multiple of 256");
+    static_assert(!(NH && CANCEL), "the thermostat variant takes no cancel requests");
     constexpr int NPH = NKB / kPB;  // staging phases per step
+    // thermostat: the eight half-waves' sums of the team's partials, and
+    // xi(t_m) of the workgroup's 32 replicas (one copy per wave)
+    __shared__ double s_bpart[NH ? 2 : 1][8][32];
+    __shared__ double s_bxi[NH ? 4 : 1][32];
     // three staging buffers (phase ph uses buffer ph % 3): separate arrays, so
     // that the compiler sees that reading one does not wait for the direct
     // loads into the others
@@ -776,7 +795,12 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
 
     float xs0[16], xs1[16], ys0[16], ys1[16];
     const int rep = r0 + l32;
-    const float gdt = gamma[rep] * dt;
+    const float gdt_heat = gamma[rep] * dt;
+    // thermostat: xi(t_k) of this lane's replica; the heating rate of step k
+    // is -xi(t_k) rounded to float, in eq. (22)'s place
+    if constexpr (NH) {
+        if (half == 0) s_bxi[wu][l32] = nhp.xi[rep];
+    }
     const int rowb = rb * 64 + 4 * half;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -789,8 +813,12 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
 
     // publish the digits of x_m: fragments of chunk 2 rb + t go to K block rb,
     // consumer half t; then the step flag
-    auto publish = [&](int m) {
+    // (thermostat: with the partial t2 of y(t_{m-1})^2 over the wave's rows)
+    auto publish = [&](int m, double t2) {
         const int par = m & 1;
+        if constexpr (NH) {
+            if (half == 0) nhp.part[((size_t)((m - 1) & 1) * nrb + rb) * Rpad + rep] = t2;
+        }
         v4i fr[4];
         uint32_t eb = make_digits(xs0, half, fr);
 #pragma unroll
@@ -843,16 +871,20 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
         }
     };
 
-    if (g.seg_k0 < g.seg_k1) publish(g.seg_k0);
+    if (g.seg_k0 < g.seg_k1) publish(g.seg_k0, 0.0);
     SampleClock clk(g);  // sample points without a division per step
     for (int m = g.seg_k0;; ++m) {
         // the energy of a sampled state needs only its signs
         const bool sample = clk.is_sample(g, m);
         if (sample) snapshot(clk.sample_index(g, m));
-        if (m == g.seg_k1) break;
+        // (with the thermostat the segment's last step published x_{k1} and its
+        // partials too: xi(t_{k1}) is formed below before the loop ends)
+        if (!NH && m == g.seg_k1) break;
+        if (NH && m == g.seg_k1 && g.seg_k0 == g.seg_k1) break;  // no step: xi as it came
         clk.pass(g, m);
         const int par = m & 1;
-        const float p = ptab[m - g.seg_k0];
+        // (the thermostat's last pass, m = k1, takes no step)
+        const float p = !NH || m < g.seg_k1 ? ptab[m - g.seg_k0] : 0.0f;
         // wait for every wave of the team to have published x_m
         {
             const uint32_t *fp = flags + (size_t)team * nrb + (lane < nrb ? lane : 0);
@@ -875,6 +907,33 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
             }
             // readers on another L2: invalidate for the data written there
             if (!xcd_local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        if constexpr (NH) {
+            // thermostat: half-wave q = 2 w + h adds the partials of y(t_{m-1})^2
+            // of row blocks q, q + 8, ... (stored with x_m before the flags just
+            // seen; device-scope loads), into LDS for the barrier below
+            if (m > g.seg_k0) {
+                const uint64_t *pin =
+                    reinterpret_cast<const uint64_t *>(nhp.part + (size_t)((m - 1) & 1) * nrb * Rpad);
+                double Ssum = 0.0;
+                for (int q = 2 * wu + half; q < nrb; q += 8)
+                    Ssum += __longlong_as_double((long long)ld_tagged(pin + (size_t)q * Rpad + rep));
+                s_bpart[m & 1][2 * wu + half][l32] = Ssum;
+            }
+            if (m == g.seg_k1) {
+                // the segment's end: xi(t_{k1}) (as every step forms it) out
+                __syncthreads();
+                if (!wg_abort) {
+                    double v8[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) v8[q] = s_bpart[m & 1][q][l32];
+                    const double S = ((v8[0] + v8[1]) + (v8[2] + v8[3])) +
+                                     ((v8[4] + v8[5]) + (v8[6] + v8[7]));
+                    const double xi_k = s_bxi[wu][l32] + nhp.c * (S - nhp.NT);
+                    if (rb == 0 && half == 0) nhp.xi[rep] = xi_k;
+                }
+                break;
+            }
         }
         if constexpr (CANCEL) {
             if (cancel) {
@@ -949,8 +1008,21 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
         if (NPH > 1) load_stage(1);
         asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)" ::: "memory");
         if (NPH == 1) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();  // also publishes wg_abort
+        __syncthreads();  // also publishes wg_abort (and the thermostat's sums)
         if (wg_abort) break;
+        if constexpr (NH) {
+            // xi(t_m) = xi(t_{m-1}) + (dt/M)(sum_i y_i(t_{m-1})^2 - N T): the eight
+            // half-wave sums added pairwise, the same in every wave of the team
+            if (m > g.seg_k0) {
+                double v8[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v8[q] = s_bpart[m & 1][q][l32];
+                const double S = ((v8[0] + v8[1]) + (v8[2] + v8[3])) +
+                                 ((v8[4] + v8[5]) + (v8[6] + v8[7]));
+                const double xi_k = s_bxi[wu][l32] + nhp.c * (S - nhp.NT);
+                if (half == 0) s_bxi[wu][l32] = xi_k;
+            }
+        }
         v16f acc0, acc1;
         // the products of phase ph, operands from its buffer
         auto products = [&](const v4i(&src)[kPB][kXD][64], int ph) {
@@ -1007,12 +1079,24 @@ __global__ __launch_bounds__(256, 1) void k_bsb_fp4(
             if (ph + 1 < NPH) wait_stage(ph + 1);
         }
         mfma_drain(acc0, acc1);
+        float gdt = gdt_heat;
+        double t2 = 0.0;  // thermostat: this wave's sum of y_i(t_m)^2 (exact squares)
+        if constexpr (NH) {
+            gdt = (float)(-s_bxi[wu][l32]) * dt;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) t2 = __fma_rn((double)ys0[v], (double)ys0[v], t2);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) t2 = __fma_rn((double)ys1[v], (double)ys1[v], t2);
+            t2 += __shfl_xor(t2, 32);
+        }
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             sb_update(acc0[v], p, c0, dt, a0dt, gdt, xs0[v], ys0[v]);
             sb_update(acc1[v], p, c0, dt, a0dt, gdt, xs1[v], ys1[v]);
         }
-        if (m + 1 < g.seg_k1) publish(m + 1);
+        // with the thermostat the last step publishes too: its partials give
+        // xi(t_{k1}) at the segment's end
+        if (m + 1 < g.seg_k1 || NH) publish(m + 1, t2);
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -1212,24 +1296,25 @@ const void *pick_kernel(int nkb, int tile, bool cancel) {
 }
 
 template <int NKB>
-const void *bsb_ptr(int tile, bool cancel) {
+const void *bsb_ptr(int tile, bool cancel, bool nh) {
+    if (nh) return reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[0], false, true>);
     if (cancel)
-        return tile == 1 ? reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[1], true>)
-                         : reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[0], true>);
-    return tile == 1 ? reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[1], false>)
-                     : reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[0], false>);
+        return tile == 1 ? reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[1], true, false>)
+                         : reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[0], true, false>);
+    return tile == 1 ? reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[1], false, false>)
+                     : reinterpret_cast<const void *>(&k_bsb_fp4<NKB, kBsbPre[0], false, false>);
 }
 
-const void *pick_bsb_kernel(int nkb, int tile, bool cancel) {
+const void *pick_bsb_kernel(int nkb, int tile, bool cancel, bool nh) {
     switch (nkb) {
-    case 4: return bsb_ptr<4>(tile, cancel);
-    case 8: return bsb_ptr<8>(tile, cancel);
-    case 12: return bsb_ptr<12>(tile, cancel);
-    case 16: return bsb_ptr<16>(tile, cancel);
-    case 20: return bsb_ptr<20>(tile, cancel);
-    case 24: return bsb_ptr<24>(tile, cancel);
-    case 28: return bsb_ptr<28>(tile, cancel);
-    default: return bsb_ptr<32>(tile, cancel);
+    case 4: return bsb_ptr<4>(tile, cancel, nh);
+    case 8: return bsb_ptr<8>(tile, cancel, nh);
+    case 12: return bsb_ptr<12>(tile, cancel, nh);
+    case 16: return bsb_ptr<16>(tile, cancel, nh);
+    case 20: return bsb_ptr<20>(tile, cancel, nh);
+    case 24: return bsb_ptr<24>(tile, cancel, nh);
+    case 28: return bsb_ptr<28>(tile, cancel, nh);
+    default: return bsb_ptr<32>(tile, cancel, nh);
     }
 }
 
@@ -1338,7 +1423,7 @@ int persistent_work_create(PersistentWork **out) {
 void persistent_work_free(PersistentWork *w) {
     if (!w) return;
     void *ptrs[] = {w->xb, w->snap, w->ep, w->es, w->tp, w->ptab, w->err, w->xslot, w->epoch,
-                    w->teams, w->xd, w->xe, w->flags, w->tstop, w->ypart};
+                    w->teams, w->xd, w->xe, w->flags, w->tstop, w->ypart, w->bpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete w;
@@ -1348,7 +1433,7 @@ void persistent_free(PersistentJ *pj) {
     if (!pj) return;
     PersistentWork &w = pj->work;
     void *ptrs[] = {pj->jpk, w.xb, w.snap, w.ep, w.es, w.tp, w.ptab, w.err, w.xslot, w.epoch,
-                    w.teams, w.xd, w.xe, w.flags, w.tstop, w.ypart};
+                    w.teams, w.xd, w.xe, w.flags, w.tstop, w.ypart, w.bpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete pj;
@@ -1378,7 +1463,8 @@ int launch_shape(bool bsb, int nkb, int tile, bool cancel, int *teams_per_launch
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, bsb ? pick_bsb_kernel(nkb, tile, cancel) : pick_kernel(nkb, tile, cancel), 256, 0);
+            &nb, bsb ? pick_bsb_kernel(nkb, tile, cancel, tile < 0) : pick_kernel(nkb, tile, cancel),
+            256, 0);
     if (e != hipSuccess) return perr(HSB_EDEVICE, "FP4 path: %s", hipGetErrorString(e));
     const int nparts = bsb ? nkb : 2 * nkb;
     *wg_capacity = nb * ncu;
@@ -1412,10 +1498,12 @@ int run_segments(PersistentWork *pw, int variant, int nkb, int nteams_total, int
     if (e != hipSuccess) return perr(HSB_EDEVICE, "%s", hipGetErrorString(e));
     const float a0dt = run.a0 * run.dt;
     const bool nh = run.nh != nullptr;
-    const void *kfn = bsb ? pick_bsb_kernel(nkb, run.tile, run.cancel != nullptr)
+    const void *kfn = bsb ? pick_bsb_kernel(nkb, run.tile, run.cancel != nullptr, nh)
                           : pick_kernel(nkb, nh ? -1 : run.tile, run.cancel != nullptr);
     FP4NH nhp{};
-    if (nh) nhp = FP4NH{run.nh->xi, pw->ypart, run.nh->c, run.nh->NT};
+    BsbNH bnh{};
+    if (nh && !bsb) nhp = FP4NH{run.nh->xi, pw->ypart, run.nh->c, run.nh->NT};
+    if (nh && bsb) bnh = BsbNH{run.nh->xi, pw->bpart, run.nh->c, run.nh->NT};
     int a = run.k0;
     for (;;) {
         // segment [a, e]: at most seg_samples multiples of interval in (a, e]
@@ -1475,7 +1563,7 @@ int run_segments(PersistentWork *pw, int variant, int nkb, int nteams_total, int
                               (void *)&pw->ptab,
                               (void *)&b.bad,     (void *)&b.status,  (void *)&pw->err,
                               (void *)&pw->xslot, (void *)&pw->epoch, (void *)&local_ok,
-                              (void *)&cancel,    (void *)&pw->tstop,
+                              (void *)&cancel,    (void *)&pw->tstop, (void *)&bnh,
                               (void *)&nkb_v,     (void *)&nrb_v,     (void *)&Rpad_v,
                               (void *)&t0_v,      (void *)&nt_v,      (void *)&g,
                               (void *)&dt,        (void *)&a0dtv};
@@ -1529,7 +1617,8 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     const int Rpad = run.Rpad, nrb = nkb, nchunk = 2 * nrb;
     if (nteams_total * 32 > Rpad) return perr(HSB_EINVAL, "FP4 path: teams exceed the columns");
     int teams_per_launch = 0, wpt = 0, wg_capacity = 0;
-    if (run.nh && bsb) return perr(HSB_EUNSUPPORTED, "FP4 path: no thermostat for bSB");
+    if (run.nh && bsb && run.cancel)
+        return perr(HSB_EUNSUPPORTED, "FP4 path: no cancellable thermostat run for bSB");
     int rc = launch_shape(bsb, nkb, run.nh ? -1 : run.tile, run.cancel != nullptr, &teams_per_launch,
                           &wpt, &wg_capacity);
     if (rc) return rc;
@@ -1543,7 +1632,7 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     const bool traces = b.trace_e || b.trace_t;
     const void *const before[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->tp, pw->ptab, pw->err,
                                   pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch,
-                                  pw->tstop, pw->ypart};
+                                  pw->tstop, pw->ypart, pw->bpart};
     rc = grow(&pw->xb, &pw->xb_words, (size_t)2 * nchunk * Rpad);
     if (!rc) rc = grow(&pw->snap, &pw->snap_words, (seg_samples + 1) * snap_per_sample);
     if (!rc) rc = grow(&pw->ep, &pw->ep_elems, (seg_samples + 1) * (size_t)nparts * Rpad);
@@ -1569,7 +1658,8 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     if (!rc && bsb) rc = grow(&pw->xe, &pw->xe_n, (size_t)2 * 2 * Rpad * nkb);
     if (!rc && bsb) rc = grow(&pw->flags, &pw->flags_n, (size_t)nteams_total * nrb);
     if (!rc) rc = grow(&pw->tstop, &pw->tstop_n, (size_t)nteams_total);
-    if (!rc && run.nh) rc = grow(&pw->ypart, &pw->ypart_n, (size_t)4 * (nchunk / 4) * Rpad);
+    if (!rc && run.nh && !bsb) rc = grow(&pw->ypart, &pw->ypart_n, (size_t)4 * (nchunk / 4) * Rpad);
+    if (!rc && run.nh && bsb) rc = grow(&pw->bpart, &pw->bpart_n, (size_t)2 * nrb * Rpad);
     if (!rc && !pw->epoch) {
         rc = grow(&pw->epoch, &pw->epoch_n, 1);
         if (!rc) {
@@ -1589,7 +1679,7 @@ int persistent_run_teams(PersistentWork *pw, int variant, int nkb, const FP4Team
     {
         const void *const after[] = {pw->xb, pw->snap, pw->ep, pw->es, pw->tp, pw->ptab, pw->err,
                                      pw->teams, pw->xd, pw->xe, pw->flags, pw->xslot, pw->epoch,
-                                     pw->tstop, pw->ypart};
+                                     pw->tstop, pw->ypart, pw->bpart};
         if (std::memcmp(before, after, sizeof(before)) != 0) ++pw->gen;
     }
     // the team table, uploaded only when it differs from the last upload (a

@@ -139,6 +139,46 @@ def test_bsb_thermostat_within_bar(plan, N, seed, R, Ns, steps):
     np.testing.assert_allclose(g["xi"], o["xi"], rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("steps", [1, 50])
+def test_bsb_thermostat_on_fp4(steps):
+    """bSB with +-1 couplings on the FP4 plan, the thermostat inside the
+    persistent bSB kernel: the heated bar's configuration (N = 100, Ns = 2000)
+    within 1e-5 of FP64, xi to 1e-6."""
+    J = synth.sk_instance(100, 1)
+    say("bsb thermostat fp4", steps)
+    g = gpu(J, hsb.HSB_BSB, "mixed", steps, 16, schedule_steps=2000, amp=0.1)
+    assert g["plan"] == "fp4"
+    o = orc(J, oracle.BSB, oracle.FP64, steps, 16, schedule_steps=2000, amp=0.1)
+    assert rel_err(g["x"], o["x"]).max() <= 1e-5
+    assert rel_err(g["y"], o["y"]).max() <= 1e-5
+    np.testing.assert_allclose(g["xi"], o["xi"], rtol=1e-6, atol=0)
+
+
+def test_bsb_fp4_thermostat_split_run_and_cancellable_context():
+    """A bSB thermostat run on the FP4 plan split in two (x, y and xi_out of
+    the first part starting the second) equals one run bit for bit; at 700
+    spins the teams have 12 row blocks (several per half-wave's share of the
+    partials).  A cancellable context runs bSB with the thermostat on the
+    digit plan (the FP4 kernel's thermostat variant takes no cancel requests)."""
+    J = synth.sk_instance(700, 21)
+    say("bsb fp4 thermostat split")
+    nh = NH_LARGE
+    one = gpu(J, hsb.HSB_BSB, "mixed", 120, 40, nose_hoover=nh, amp=0.1, schedule_steps=400)
+    assert one["plan"] == "fp4" and np.all(np.isfinite(one["y"]))
+    a = gpu(J, hsb.HSB_BSB, "mixed", 50, 40, nose_hoover=nh, amp=0.1, schedule_steps=400)
+    dev = torch.device("cuda", 0)
+    b = gpu(J, hsb.HSB_BSB, "mixed", 70, 40, nose_hoover=nh, amp=0.1, start_step=50,
+            schedule_steps=400, x0=torch.from_numpy(a["x"]).to(dev),
+            y0=torch.from_numpy(a["y"]).to(dev), xi0=torch.from_numpy(a["xi"]).to(dev))
+    assert b["plan"] == "fp4"
+    for k in ("x", "y", "xi"):
+        assert np.array_equal(b[k], one[k]), k
+    with hsb.Context(J, precision="mixed", init_amp=0.1, energy_interval=50, cancellable=1) as ctx:
+        ctx.run_ex(hsb.HSB_BSB, 20, 40, 1.0, 0.5 / np.sqrt(700), 1.0, GAMMA, 1, nose_hoover=nh)
+        torch.cuda.synchronize()
+        assert ctx.last_plan() == "digits"
+
+
 @pytest.mark.parametrize("plan", ["fp32", "mixed"])
 def test_given_start_xi_and_per_replica_gamma(plan):
     N, R = 120, 12
