@@ -282,12 +282,15 @@ typedef struct {
  *                           explicit Euler on eq. (8) with the state before the
  *                           step.  xi starts at -gamma, so 1/M = 0 is exactly
  *                           heated SB.  The sum over all spins is formed every
- *                           step in FP64 from per-32-row partials in a fixed
- *                           order.  dSB runs it on every plan (on the FP4 plan
- *                           inside the persistent kernel: each workgroup's
- *                           partial is exchanged with the sign words); for bSB,
- *                           where AUTO or MIXED would take the FP4 plan, the
- *                           integer-digit plan runs instead.
+ *                           step in FP64 from per-wave partials in a fixed
+ *                           order.  Every plan runs it; on the FP4 plan inside
+ *                           the persistent kernels (dSB: each workgroup's
+ *                           partial is exchanged with the sign words; bSB: each
+ *                           wave's partial travels with its digits).  In a
+ *                           context with HSB_OPT_CANCELLABLE = 1, bSB thermostat
+ *                           runs that would take the FP4 plan take the
+ *                           integer-digit plan (the FP4 bSB kernel's thermostat
+ *                           variant takes no cancel requests).
  */
 typedef enum { HSB_THERMO_HEAT = 0, HSB_THERMO_NOSE_HOOVER = 1 } hsb_thermostat;
 
