@@ -407,7 +407,7 @@ def main() -> int:
         """The Nose-Hoover thermostat (eqs. (6)-(8)) on the bench instance: dSB,
         R = 1024, 10^4 steps, against the heated run on the same plan: on the
         FP4 plan (the thermostat inside the persistent kernel) and on the
-        integer-digit plan."""
+        integer-digit plan; and bSB on the FP4 plan."""
         # large mass (the paper's observation: xi kept negative, its rate small):
         # xi falls by at most N T / M per step, so it stays above -0.015 and
         # |xi| dt < 1 (a smaller M lets wall-pinned spins' y grow without bound)
@@ -434,6 +434,24 @@ def main() -> int:
             res[out["nose_hoover"][1]] = {
                 "ms_per_run": ms_n, "heated_ms_per_run": ms_h, "overhead": ms_n / ms_h - 1.0,
                 "runs_timed": reps, "xi_final_range": [float(xi.min()), float(xi.max())]}
+        # bSB on the same instance (the thermostat inside the persistent bSB kernel)
+        cb = hsb.Context(J, precision=args.plan, init_amp=0.1, energy_interval=100)
+        outb = {}
+        for name, kw in (("heated", {}), ("nose_hoover", {"nose_hoover": nh})):
+            o = cb.run_ex(hsb.HSB_BSB, Ns, R, A0, c0, DT, GAMMA, 1, **kw)
+            buf = {k: v for k, v in o.items() if hasattr(v, "data_ptr")}
+            cb.run_ex(hsb.HSB_BSB, Ns, R, A0, c0, DT, GAMMA, 1, out=buf, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = cb.run_ex(hsb.HSB_BSB, Ns, R, A0, c0, DT, GAMMA, 2, out=buf, **kw)
+            torch.cuda.synchronize()
+            outb[name] = (1e3 * (time.perf_counter() - t0), cb.last_plan(), o)
+        xib = outb["nose_hoover"][2]["xi"].cpu().numpy()
+        cb.close()
+        res["bsb_" + outb["nose_hoover"][1]] = {
+            "ms_per_run": outb["nose_hoover"][0], "heated_ms_per_run": outb["heated"][0],
+            "overhead": outb["nose_hoover"][0] / outb["heated"][0] - 1.0, "runs_timed": 1,
+            "xi_final_range": [float(xib.min()), float(xib.max())]}
         main = res.get("fp4") or next(iter(res.values()))
         plan_main = "fp4" if "fp4" in res else next(iter(res))
         return {"workload": f"SK +-1 N={N}, R={R}, {Ns} steps dSB, Nose-Hoover 1/M={nh[0]}, "
