@@ -468,22 +468,43 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
                 }
             }
         }
+        // Thermostat: xi(t_m) = xi(t_{m-1}) + (dt/M)(sum_i y_i(t_{m-1})^2 - N T):
+        // the eight half-wave sums (in LDS since the barrier) added pairwise in
+        // a fixed order, the same in every wave of the team.  The operations
+        // are spread between the products below, where a vector instruction
+        // issues while the matrix core works, and xi(t_m) goes to LDS after
+        // them (at the segment's first step it is the value read at launch).
+        double nva = 0.0, nvb = 0.0, nsa = 0.0, nsb = 0.0, nxi = 0.0;
         if constexpr (NH) {
-            // xi(t_m) = xi(t_{m-1}) + (dt/M)(sum_i y_i(t_{m-1})^2 - N T): the eight
-            // half-wave sums (in LDS since the barrier) added pairwise in a
-            // fixed order, the same in every wave of the team; formed before
-            // the products, so that only its use remains for the update after
-            // them
-            if (m > g.seg_k0) {
-                double v8[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) v8[q] = s_ysum[m & 1][q][l32];
-                const double S = ((v8[0] + v8[1]) + (v8[2] + v8[3])) +
-                                 ((v8[4] + v8[5]) + (v8[6] + v8[7]));
-                const double xi_k = s_xi[w][l32] + nhp.c * (S - nhp.NT);
-                if (half == 0) s_xi[w][l32] = xi_k;
-            }
+            nva = s_ysum[m & 1][0][l32];
+            nvb = s_ysum[m & 1][1][l32];
+            nxi = s_xi[w][l32];
         }
+        auto nh_slot = [&](int kb) {
+            if constexpr (NH) {
+                if (kb == 2) {  // a = v0 + v1
+                    nsa = nva + nvb;
+                    nva = s_ysum[m & 1][2][l32];
+                    nvb = s_ysum[m & 1][3][l32];
+                } else if (kb == 4) {  // a = (v0 + v1) + (v2 + v3)
+                    nsa = nsa + (nva + nvb);
+                    nva = s_ysum[m & 1][4][l32];
+                    nvb = s_ysum[m & 1][5][l32];
+                } else if (kb == 6) {  // b = v4 + v5
+                    nsb = nva + nvb;
+                    nva = s_ysum[m & 1][6][l32];
+                    nvb = s_ysum[m & 1][7][l32];
+                } else if (kb == 8) {  // b = (v4 + v5) + (v6 + v7)
+                    nsb = nsb + (nva + nvb);
+                } else if (kb == 10) {  // S = a + b, then S - N T
+                    nsa = (nsa + nsb) - nhp.NT;
+                } else if (kb == 12) {
+                    nsa = nhp.c * nsa;
+                } else if (kb == 14) {
+                    if (m > g.seg_k0) nxi = nxi + nsa;
+                }
+            }
+        };
         v16f acc;
         // The products run at the lowest issue priority and the rest of the
         // step at a raised one: while the other wave on this SIMD is in its
@@ -503,6 +524,14 @@ __global__ __launch_bounds__(256, 2) void k_dsb_fp4(
                 mfma_fp4_first(acc, jr[0], a, one);
             else
                 mfma_fp4(acc, jr[kb], a, one);
+            nh_slot(kb);
+        }
+        if constexpr (NH) {
+            if (NKB <= 14) {  // fewer products than slots: the rest of the chain
+#pragma unroll
+                for (int kb = NKB; kb <= 14; ++kb) nh_slot(kb);
+            }
+            if (half == 0) s_xi[w][l32] = nxi;
         }
         mfma_drain(acc);
         __builtin_amdgcn_s_setprio(3);
